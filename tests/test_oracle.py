@@ -1,0 +1,422 @@
+"""Pins for the FP64 CPU oracle (runs without a GPU).
+
+Each test ties the oracle to something other than itself: LAPACK routines
+with the same conventions (called through SciPy, never read), exact rational
+arithmetic, closed forms, and invariants that Agullo et al. state for TSQR:
+uniqueness of R with a positive diagonal (Sec. 2.2) and associativity /
+commutativity of the R-combine (Sec. 2.3).  A dropped term, a wrong sign or
+index, or a transposed operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg.lapack as lapack
+
+import oracle
+import synth
+
+U = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def signfix(R):
+    d = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return d[:, None] * R
+
+
+# ---------------------------------------------------------------- reflector
+
+@pytest.mark.parametrize("alpha,n", [(0.7, 9), (-1.3, 5), (0.0, 6), (2.5, 1)])
+def test_larfg_matches_lapack_and_annihilates(alpha, n):
+    rng = np.random.default_rng(11 + n)
+    x = rng.standard_normal(n)
+    beta, v, tau = oracle.larfg(alpha, x)
+    lb, lv, lt = lapack.dlarfg(n + 1, alpha, x.copy())
+    assert abs(beta - lb) <= 8 * U * abs(lb)
+    assert abs(tau - lt) <= 8 * U * max(abs(lt), 1e-300)
+    assert rel(v, lv) <= 8 * U
+    # H [alpha; x] = beta e_1 and H is orthogonal
+    vv = np.concatenate([[1.0], v])
+    H = np.eye(n + 1) - tau * np.outer(vv, vv)
+    y = H @ np.concatenate([[alpha], x])
+    assert abs(y[0] - beta) <= 16 * U * abs(beta)
+    assert np.linalg.norm(y[1:]) <= 16 * U * abs(beta)
+    assert np.linalg.norm(H.T @ H - np.eye(n + 1)) <= 32 * U
+
+
+def test_larfg_negative_zero_alpha_uses_plus_sign():
+    """sgn(0) = +1 for both signed zeros (reading of Sec. 2.2's reflector);
+    LAPACK's Fortran SIGN treats -0.0 as negative, so this case is pinned by
+    the reflector identity alone."""
+    x = np.array([3.0, 4.0])
+    beta, v, tau = oracle.larfg(-0.0, x)
+    assert beta == -5.0 and tau == 1.0
+    vv = np.concatenate([[1.0], v])
+    y = (np.eye(3) - tau * np.outer(vv, vv)) @ np.array([0.0, 3.0, 4.0])
+    assert np.allclose(y, [-5.0, 0.0, 0.0], atol=1e-15)
+
+
+def test_larfg_zero_tail_is_identity():
+    beta, v, tau = oracle.larfg(-3.0, np.zeros(4))
+    assert tau == 0.0 and beta == -3.0 and np.all(v == 0.0)
+
+
+# ------------------------------------------------------------- leaf (geqrt)
+
+@pytest.mark.parametrize("r,n", [(50, 8), (17, 17), (64, 5), (9, 12)])
+def test_geqrt_matches_lapack(r, n):
+    rng = np.random.default_rng(r * 100 + n)
+    A = rng.standard_normal((r, n))
+    W, tau, T = oracle.geqrt(A)
+    k = min(r, n)
+    la, lt, info = lapack.dgeqrt(k, np.asfortranarray(A.copy()))
+    assert info == 0
+    assert rel(np.triu(W), np.triu(la)) <= 50 * U
+    assert rel(np.tril(W, -1), np.tril(la, -1)) <= 200 * U
+    assert rel(T[:k, :k], lt[:k, :k]) <= 200 * U
+
+
+def test_geqrt_compact_wy_equals_product_of_reflectors():
+    rng = np.random.default_rng(5)
+    r, n = 40, 7
+    A = rng.standard_normal((r, n))
+    W, tau, T = oracle.geqrt(A)
+    V = np.tril(W, -1)[:, :n] + np.eye(r, n)
+    Q = np.eye(r)
+    for j in range(n):
+        v = V[:, j]
+        Q = Q @ (np.eye(r) - tau[j] * np.outer(v, v))
+    assert np.linalg.norm(Q - (np.eye(r) - V @ T @ V.T)) <= 64 * U
+    assert rel(Q[:, :n] @ np.triu(W[:n]), A) <= 64 * U
+
+
+# ---------------------------------------------------------- combine (tpqrt)
+
+@pytest.mark.parametrize("n", [1, 4, 16])
+def test_tpqrt_matches_lapack_and_dense_qr(n):
+    rng = np.random.default_rng(300 + n)
+    R1 = np.triu(rng.standard_normal((n, n)))
+    R2 = np.triu(rng.standard_normal((n, n)))
+    R, Uv, tau, T = oracle.tpqrt(R1, R2)
+    la, lb, lt, info = lapack.dtpqrt(n, n, np.asfortranarray(R1.copy()), np.asfortranarray(R2.copy()))
+    assert info == 0
+    assert rel(np.triu(R), np.triu(la)) <= 50 * U
+    assert rel(np.triu(Uv), np.triu(lb)) <= 200 * U
+    assert rel(T, lt[:n, :n]) <= 200 * U
+    # the structure-free computation: dense QR of the 2n x n stack
+    Rd = np.linalg.qr(np.vstack([R1, R2]))[1]
+    assert rel(signfix(np.triu(R)), signfix(Rd)) <= 50 * U
+    # the reflectors really are [e_j; u_j]: applying them reproduces [R; 0]
+    Y = np.vstack([np.eye(n), np.triu(Uv)])
+    Q = np.eye(2 * n) - Y @ T @ Y.T
+    assert rel(Q.T @ np.vstack([R1, R2]), np.vstack([np.triu(R), np.zeros((n, n))])) <= 64 * U
+
+
+# ------------------------------------------------------- partition / trees
+
+def test_partition_rule():
+    assert oracle.partition(1000, 16, 300) == [(0, 300), (300, 300), (600, 300), (900, 100)]
+    # a last domain shorter than n is merged into the one before it
+    assert oracle.partition(1010, 16, 500) == [(0, 500), (500, 510)]
+    assert oracle.partition(4096, 16, 1024) == [(0, 1024), (1024, 1024), (2048, 1024), (3072, 1024)]
+    assert oracle.partition(16, 16, 16) == [(0, 16)]
+
+
+def _depth(sched, P):
+    d = [0] * P
+    for l, r in sched:
+        d[l] = max(d[l], d[r]) + 1
+    return max(d) if P > 1 else 0
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 7, 8, 256, 1023])
+def test_tree_shapes(P):
+    b = oracle.schedule(P, oracle.TREE_BINARY)
+    assert len(b) == P - 1
+    assert _depth(b, P) == (math.ceil(math.log2(P)) if P > 1 else 0)
+    q = oracle.schedule(P, oracle.TREE_QUAD)
+    assert len(q) == P - 1
+    f = oracle.schedule(P, oracle.TREE_FLAT)
+    assert f == [(0, i) for i in range(1, P)]
+    for s in (b, q, f):     # every node is consumed once, results land left
+        assert sorted(r for _, r in s) == list(range(1, P))
+
+
+def test_paper_message_counts():
+    """Fig. 2 caption: on an M x 3 matrix spread over three clusters the
+    grid-tuned TSQR tree sends two inter-cluster messages, independent of the
+    number of columns; Table 1: a binary tree over P domains has log2(P)
+    messages on its critical path."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_counts.json")))
+    for case in g["tuned_tree_inter_cluster"]:
+        sizes = case["domains_per_cluster"]
+        start = np.cumsum([0] + sizes[:-1]).tolist()
+        sched = []
+        for s0, sz in zip(start, sizes):            # binary tree inside a cluster
+            sched += [(s0 + l, s0 + r) for l, r in oracle.schedule(sz, 2)]
+        roots = start
+        sched += [(roots[l], roots[r]) for l, r in oracle.schedule(len(roots), 2)]
+        cluster = np.repeat(np.arange(len(sizes)), sizes)
+        inter = sum(1 for l, r in sched if cluster[l] != cluster[r])
+        assert inter == case["inter_cluster_messages"]
+    for case in g["binary_tree_messages"]:
+        P = case["P"]
+        assert _depth(oracle.schedule(P, 2), P) == case["critical_path_messages"]
+
+
+# ------------------------------------------------------------- whole TSQR
+
+def test_single_domain_is_unpartitioned_householder():
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((3000, 20))
+    f = oracle.TSQR(A, mb=3000)
+    assert f.P == 1
+    R = f.R()
+    assert rel(R, signfix(np.linalg.qr(A)[1])) <= 1e-14
+    W, tau, _ = f.leaf()
+    la, ltau, _, info = lapack.dgeqrf(np.asfortranarray(A.copy()))
+    assert rel(tau, ltau) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,mb", [(4096, 16, 1024), (5003, 13, 700), (2000, 40, 64), (777, 1, 100)])
+def test_r_invariants_and_tree_independence(m, n, mb):
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    Rs = []
+    for tree in (oracle.TREE_BINARY, oracle.TREE_QUAD, oracle.TREE_FLAT, 3):
+        f = oracle.TSQR(A, mb=mb, tree=tree)
+        R = f.R()
+        assert np.all(np.tril(R, -1) == 0.0)
+        assert np.all(np.diag(R) >= 0.0)
+        assert np.linalg.norm(R.T @ R - A.T @ A) <= 64 * U * math.sqrt(m) * np.linalg.norm(A) ** 2
+        Rs.append(R)
+    # a shuffled pairing order is a valid tree too (commutativity, Sec. 2.3)
+    P = len(oracle.partition(m, n, mb))
+    order = [0] + (1 + rng.permutation(P - 1)).tolist()   # root stays slot 0
+    sched = []
+    live = order[:]
+    while len(live) > 1:
+        nxt = []
+        for i in range(0, len(live) - 1, 2):
+            a, b = live[i], live[i + 1]
+            sched.append((a, b))
+            nxt.append(a)
+        if len(live) % 2:
+            nxt.append(live[-1])
+        live = nxt
+    assert live[0] == 0
+    f = oracle.TSQR(A, mb=mb, sched=sched)
+    Rs.append(f.R())
+    Rref = signfix(np.linalg.qr(A)[1])
+    for R in Rs:
+        assert rel(R, Rref) <= 1e-13
+
+
+def test_shuffled_order_with_root_zero():
+    rng = np.random.default_rng(42)
+    A = rng.standard_normal((6400, 12))
+    P = len(oracle.partition(6400, 12, 400))
+    order = [0] + (1 + rng.permutation(P - 1)).tolist()
+    sched = [(0, o) for o in order[1:]]        # flat tree, shuffled order
+    R1 = oracle.TSQR(A, mb=400, sched=sched).R()
+    R2 = oracle.TSQR(A, mb=400).R()
+    assert rel(R1, R2) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,mb", [(4096, 16, 1024), (5003, 13, 700), (300, 30, 60)])
+def test_form_q_and_apply_qt(m, n, mb):
+    rng = np.random.default_rng(7 * m + n)
+    A = rng.standard_normal((m, n))
+    f = oracle.TSQR(A, mb=mb)
+    Q, R = f.form_q(), f.R()
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-13
+    assert rel(Q @ R, A) <= 1e-13
+    Qn, Rn = np.linalg.qr(A)
+    d = np.where(np.diag(Rn) < 0, -1.0, 1.0)
+    assert rel(Q, Qn * d) <= 1e-12
+    B = rng.standard_normal((m, 3))
+    C = f.apply_qt(B)
+    assert rel(C[:n], Q.T @ B) <= 1e-13
+    tail_expected = np.linalg.norm(B - Q @ (Q.T @ B), axis=0)
+    assert np.allclose(np.linalg.norm(C[n:], axis=0), tail_expected, rtol=1e-12)
+    # Q^T is orthogonal: column norms are preserved
+    assert np.allclose(np.linalg.norm(C, axis=0), np.linalg.norm(B, axis=0), rtol=1e-13)
+
+
+def test_lsq_against_lapack_and_consistent_rhs():
+    rng = np.random.default_rng(9)
+    m, n = 5000, 24
+    A = rng.standard_normal((m, n))
+    f = oracle.TSQR(A, mb=800)
+    B = rng.standard_normal((m, 2))
+    X, res, info = f.lsq(B)
+    assert info == 0
+    _, Xl, _ = lapack.dgels(np.asfortranarray(A.copy()), np.asfortranarray(B.copy()))[:3]
+    Xl = Xl[:n]
+    kappa = np.linalg.cond(A)
+    tan = np.linalg.norm(B - A @ Xl, axis=0) / np.linalg.norm(A @ Xl, axis=0)
+    kls = kappa + kappa ** 2 * tan
+    for c in range(2):
+        assert rel(X[:, c], Xl[:, c]) <= 10 * kls[c] * U
+        assert abs(res[c] - np.linalg.norm(B[:, c] - A @ X[:, c])) <= 1e-12 * res[c]
+        r = B[:, c] - A @ X[:, c]
+        eta = np.linalg.norm(A.T @ r) / (np.linalg.norm(A) * (np.linalg.norm(A) * np.linalg.norm(X[:, c]) + np.linalg.norm(B[:, c])))
+        assert eta <= 1e-14
+    xt = rng.standard_normal(n)
+    Xc, res_c, _ = f.lsq(A @ xt)
+    assert rel(Xc[:, 0], xt) <= 10 * kappa * U * math.sqrt(n)
+    assert res_c[0] <= 1e-13 * np.linalg.norm(A @ xt)
+
+
+# --------------------------------------------- exact rational brute force
+
+def _exact_checks(A, R, tol_rel=16 * U):
+    """R^T R = A^T A in exact rationals, entry by entry, with the floating R
+    converted exactly; tolerance relative to ||A||_F^2."""
+    Af = [[Fraction(float(x)) for x in row] for row in A]
+    Rf = [[Fraction(float(x)) for x in row] for row in R]
+    m, n = len(Af), len(Af[0])
+    nrm2 = sum(x * x for row in Af for x in row)
+    for i in range(n):
+        for j in range(n):
+            g = sum(Af[r][i] * Af[r][j] for r in range(m))
+            h = sum(Rf[q][i] * Rf[q][j] for q in range(n))
+            if abs(float(g - h)) > tol_rel * float(nrm2):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("mb", [2, 4])
+def test_brute_force_4x2_closed_form(mb):
+    rng = np.random.default_rng(123)
+    for _ in range(200):
+        A = rng.standard_normal((4, 2))
+        R = oracle.TSQR(A, mb=mb).R()
+        a1 = [Fraction(float(x)) for x in A[:, 0]]
+        a2 = [Fraction(float(x)) for x in A[:, 1]]
+        n11 = sum(x * x for x in a1)
+        n12 = sum(x * y for x, y in zip(a1, a2))
+        n22 = sum(x * x for x in a2)
+        r11, r12, r22 = (Fraction(float(R[0, 0])), Fraction(float(R[0, 1])), Fraction(float(R[1, 1])))
+        assert abs(float(r11 * r11 - n11)) <= 16 * U * float(n11)
+        assert abs(float(r11 * r12 - n12)) <= 16 * U * float(n11 + n22)
+        exact22 = n22 - n12 * n12 / n11
+        assert abs(float(r22 * r22 - exact22)) <= 16 * U * float(n11 + n22)
+
+
+def test_brute_force_integer_4x2_enumeration():
+    """A deterministic subset of the 5^8 integer matrices with entries in
+    {-2..2}; every full-rank one must give R^T R = A^T A exactly up to 16u."""
+    vals = [-2, -1, 0, 1, 2]
+    count = 0
+    for idx in range(0, 5 ** 8, 97):      # every 97th matrix: ~4000 cases
+        digits = []
+        t = idx
+        for _ in range(8):
+            digits.append(vals[t % 5])
+            t //= 5
+        A = np.array(digits, dtype=np.float64).reshape(4, 2)
+        if abs(np.linalg.det(A.T @ A)) < 0.5:   # integer Gram: singular iff det 0
+            continue
+        for mb in (2, 4):
+            R = oracle.TSQR(A, mb=mb).R()
+            assert _exact_checks(A, R)
+        count += 1
+    assert count > 3000
+
+
+@pytest.mark.parametrize("shape,mb", [((8, 2), 2), ((8, 2), 4), ((8, 4), 4), ((8, 4), 8)])
+def test_brute_force_8_rows(shape, mb):
+    rng = np.random.default_rng(shape[1] * 10 + mb)
+    for _ in range(50):
+        A = rng.standard_normal(shape)
+        f = oracle.TSQR(A, mb=mb)
+        assert f.P == shape[0] // mb
+        assert _exact_checks(A, f.R())
+
+
+# ------------------------------------------------- closed forms / specials
+
+def test_single_column_closed_form():
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((1000, 1))
+    f = oracle.TSQR(a, mb=128)
+    assert abs(f.R()[0, 0] - np.linalg.norm(a)) <= 8 * U * np.linalg.norm(a)
+    assert rel(f.form_q(), a / np.linalg.norm(a)) <= 16 * U * math.sqrt(1000)
+
+
+def test_orthonormal_input_gives_identity_and_triangular_input_gives_itself():
+    rng = np.random.default_rng(4)
+    Q0 = np.linalg.qr(rng.standard_normal((2048, 10)))[0]
+    assert np.linalg.norm(oracle.TSQR(Q0, mb=256).R() - np.eye(10)) <= 1e-14
+    R0 = np.triu(rng.standard_normal((10, 10))) + 5 * np.eye(10)
+    R0 = signfix(R0)
+    assert rel(oracle.TSQR(Q0 @ R0, mb=256).R(), R0) <= 1e-13
+
+
+def test_power_of_two_column_scaling_is_exact():
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((3000, 9))
+    d = 2.0 ** rng.integers(-20, 20, size=9)
+    R = oracle.TSQR(A, mb=500).R()
+    Rd = oracle.TSQR(A * d, mb=500).R()
+    assert np.array_equal(Rd, R * d)
+
+
+def test_row_permutation_invariance_and_square_case():
+    rng = np.random.default_rng(10)
+    A = rng.standard_normal((1200, 15))
+    p = rng.permutation(1200)
+    assert rel(oracle.TSQR(A[p], mb=300).R(), oracle.TSQR(A, mb=300).R()) <= 1e-13
+    S = rng.standard_normal((15, 15))
+    f = oracle.TSQR(S, mb=15)
+    assert rel(f.form_q() @ f.R(), S) <= 1e-14
+
+
+def test_exact_zero_column():
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((2000, 6))
+    A[:, 3] = 0.0
+    f = oracle.TSQR(A, mb=400)
+    R = f.R()
+    assert R[3, 3] == 0.0
+    W, tau, T = f.leaf()
+    assert np.all(tau[:, 3] == 0.0)
+    _, _, info = f.lsq(rng.standard_normal(2000))
+    assert info == 4
+
+
+def test_conditioned_construction_singular_values():
+    """A = U diag(s) V^T: the singular values of R equal s (closed form from
+    the construction), checked at a reduced row count."""
+    def orth(G):
+        return oracle.TSQR(G, mb=max(G.shape[1], 4096)).form_q()
+    A, b, bc, xt, s = synth.config_conditioned(16384, 128, orth, seed=0)
+    f = oracle.TSQR(A, mb=4096)
+    sv = np.linalg.svd(f.R(), compute_uv=False)
+    assert np.max(np.abs(sv - s)) <= 200 * U * math.sqrt(16384) * np.linalg.norm(A, 2)
+
+
+def test_refined_reference_converges_on_ill_conditioned_lsq():
+    rng = np.random.default_rng(13)
+    m, n = 6000, 20
+    Uq = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    Vq = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = synth.log_spaced_spectrum(n, -6)
+    A = (Uq * s) @ Vq.T
+    b = rng.standard_normal(m)
+    f = oracle.TSQR(A, mb=1000)
+    x, it = f.lsq_refined(A, b)
+    assert it >= 1
+    # normal equations hold to the accuracy of the data
+    r = b - A @ x
+    eta = np.linalg.norm(A.T @ r) / (np.linalg.norm(A) * (np.linalg.norm(A) * np.linalg.norm(x) + np.linalg.norm(b)))
+    assert eta <= 1e-15
