@@ -1,0 +1,170 @@
+/*
+ * tsqr.h -- C ABI of the MI355X (gfx950) TSQR library.
+ *
+ * The library factors a tall-and-skinny m x n FP64 matrix (m >= n) with TSQR,
+ * the panel factorization of Communication-Avoiding QR described in Sec. 2.3
+ * of Agullo, Coti, Dongarra, Herault and Langou, "QR Factorization of Tall and
+ * Skinny Matrices in a Grid Computing Environment" (arXiv 0912.2572):
+ *   1. the rows are split into P contiguous domains (block rows);
+ *   2. every domain gets a Householder QR (Sec. 2.2: H = I - tau v v^T,
+ *      blocked as H_1...H_b = I - V T V^T with T upper triangular);
+ *   3. the P triangular factors are reduced pairwise, R = qr([R_1; R_2]).R,
+ *      up a binary, 4-ary or flat tree (Sec. 2.3);
+ *   4. R is made unique by a nonnegative diagonal (Sec. 2.2: QR is unique
+ *      once diag(R) > 0), i.e. R <- D R and Q <- Q D, D = diag(sgn R_jj),
+ *      sgn(0) = +1.
+ * The same tree applies Q^T, applies Q, forms the thin Q, and solves least
+ * squares min ||A x - b||_2 (the paper notes QR as the first step toward
+ * least squares; the solve is the textbook x = R^{-1} Q_1^T b).
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major FP64 in DEVICE memory unless stated;
+ *   - the caller owns all device memory (A, B, X, Q, R and the workspace);
+ *     the library never allocates device memory in these calls except the
+ *     serving front-end, which documents its own allocations;
+ *   - calls are asynchronous and ordered on the given HIP stream, passed as
+ *     an opaque pointer (hipStream_t; NULL = the default stream);
+ *   - return value 0 = success; -i = argument i is invalid (1-based, LAPACK
+ *     style); TSQR_ERR_WORKSPACE when the workspace is too small;
+ *     -1000 - e for a HIP runtime error e.
+ *
+ * Scope limits: 1 <= n <= 256, n <= m <= 2^31 - 1, domain rows >= n.
+ */
+#ifndef TSQR_H_
+#define TSQR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSQR_API __attribute__((visibility("default")))
+
+/* Reduction-tree shapes (Sec. 2.3: binary and flat trees; the k-ary tree
+   generalises the binary one).  Results always land in the lower-index
+   child, so the root is domain 0 and its first n rows hold the top of Q^T B. */
+enum { TSQR_TREE_FLAT = 0, TSQR_TREE_BINARY = 2, TSQR_TREE_QUAD = 4 };
+
+/* Arithmetic of the factorization.  TSQR_F64: everything in FP64.
+   TSQR_MIXED: reflector generation (norms, beta, tau), the tree combines and
+   every residual in FP64; the trailing updates between 64-column panels and
+   the reflector storage in FP32 (MFMA); least squares is brought back to
+   FP64 accuracy by iterative refinement of the augmented system. */
+enum { TSQR_F64 = 0, TSQR_MIXED = 1 };
+
+/* Error codes beyond the LAPACK-style -i. */
+enum {
+    TSQR_ERR_WORKSPACE = -900,   /* workspace pointer NULL or too small      */
+    TSQR_ERR_STATE = -901,       /* handle not usable for this call (e.g. a */
+                                 /* factor made with keep_q = 0)             */
+    TSQR_ERR_UNSUPPORTED = -902  /* shape outside the documented scope       */
+};
+
+typedef struct {
+    int64_t row_block;       /* mb, rows per domain; 0 = library default.   */
+                             /* Must be >= n.  P = ceil(m / mb); a last     */
+                             /* domain shorter than n rows is merged into   */
+                             /* the one before it.                          */
+    int32_t tree;            /* TSQR_TREE_*                                  */
+    int32_t prec;            /* TSQR_F64 or TSQR_MIXED                       */
+    int32_t keep_q;          /* 1: store the reflectors (needed by apply/   */
+                             /* form_q/lsq); 0: R only, the paper's         */
+                             /* measured mode (Sec. 1).                     */
+    int32_t lsq_max_rhs;     /* largest k passed to tsqr_lsq_solve (>= 1)   */
+    int32_t refine_max_iter; /* mixed-precision refinement sweeps (cap)     */
+    int32_t reserved;
+    double refine_tol;       /* stop when ||dx|| <= tol ||x||               */
+} tsqr_opts;
+
+/* Opaque host handle describing one factorization.  It points into the
+   caller's workspace, which must outlive it and must not be reused by
+   another factorization while the handle is in use. */
+typedef struct tsqr_factors_s *tsqr_factors;
+
+/* Fill *o with the defaults: row_block 0 (library default), binary tree,
+   FP64, keep_q 1, lsq_max_rhs 8, refine_max_iter 30, refine_tol 1e-14. */
+TSQR_API void tsqr_default_opts(tsqr_opts *o);
+
+/* Bytes of device workspace tsqr_factor needs for an m x n problem with
+   options o (NULL = defaults).  Returns 0 for invalid arguments. */
+TSQR_API size_t tsqr_workspace_bytes(int64_t m, int64_t n, const tsqr_opts *o);
+
+/* Factor A (m x n, leading dimension lda >= m, device, not modified):
+   partition (step 1), leaf QR of every domain (step 2), tree (step 3) and
+   sign normalisation (step 4), all on `stream`.  dwork: device workspace of
+   at least tsqr_workspace_bytes() bytes, 256-byte aligned.  *out receives a
+   new host handle (free it with tsqr_free).
+   Errors: -1 m, -2 n, -3 A NULL, -4 lda, -5 opts (row_block < n, bad tree or
+   precision), TSQR_ERR_WORKSPACE, -1000-e on a HIP error. */
+TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda,
+                         const tsqr_opts *o, void *dwork, size_t work_bytes,
+                         void *stream, tsqr_factors *out);
+
+/* Copy the sign-normalised R (n x n upper triangular, zeros below the
+   diagonal, diag >= 0) to R (device, leading dimension ldr >= n). */
+TSQR_API int tsqr_get_r(tsqr_factors f, double *R, int64_t ldr, void *stream);
+
+/* B <- Q^T B for the factor's full m x m orthogonal Q (k columns, device,
+   ldb >= m).  Rows 0..n-1 of the result equal Q_1^T B for the
+   sign-normalised thin Q_1, whatever the tree or partition; rows n..m-1 are
+   a valid complement for this factor's Q and depend on its representation. */
+TSQR_API int tsqr_apply_qt(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream);
+
+/* B <- Q B, the inverse of tsqr_apply_qt (same representation). */
+TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream);
+
+/* Thin Q (m x n, device, ldq >= m), sign-normalised so that A = Q R with
+   diag(R) >= 0 and Q^T Q = I. */
+TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream);
+
+/* Least squares min ||A x_j - b_j||_2 for k <= opts.lsq_max_rhs right-hand
+   sides: X = R^{-1} (Q^T B)[0:n], resid[j] = ||(Q^T B)[n:m, j]||_2.
+   A (m x n, lda) is the matrix that was factored; it is read only by the
+   mixed-precision refinement.  B (m x k, ldb) is not modified.  X (n x k,
+   ldx >= n) and resid (k doubles, may be NULL) are device outputs.
+   dinfo (device int32, may be NULL) receives 0, or j+1 when R_jj == 0
+   exactly (X is then left untouched, LAPACK dtrtrs convention), or -2 when
+   a residual is not finite.  dinfo is valid after the stream synchronises. */
+TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_t k,
+                            const double *B, int64_t ldb, double *X, int64_t ldx,
+                            double *resid, int32_t *dinfo, void *stream);
+
+/* Number of refinement sweeps the last mixed-precision tsqr_lsq_solve on
+   this handle ran (0 for FP64 factors).  Reads a device counter, so it
+   synchronises `stream`. */
+TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream);
+
+/* Plan introspection (host only, no device work): number of domains, rows
+   per chunk of the leaf kernel and number of 64-column panels. */
+TSQR_API int tsqr_plan_info(int64_t m, int64_t n, const tsqr_opts *o,
+                            int64_t *num_domains, int64_t *chunk_rows, int64_t *num_panels);
+
+/* The reduction tree as a list of combines (left, right), in execution
+   order, for P domains and tree shape `tree` (host only).  Writes at most
+   `cap` pairs and returns the number of combines (P - 1), or a negative
+   argument code. */
+TSQR_API int64_t tsqr_tree_schedule(int64_t P, int tree, int64_t *left, int64_t *right, int64_t cap);
+
+/* Kernel timing with HIP events (for benchmarks).  While enabled, every
+   kernel the library enqueues is bracketed by a pair of events recorded on
+   the same stream, tagged with the kernel's name.  tsqr_prof_query
+   synchronises on the recorded events and returns, for the i-th distinct
+   tag (i = 0, 1, ...), its name, launch count and summed milliseconds; it
+   returns 0, or -1 once i is past the last tag.  tsqr_prof_enable(0)
+   disables and clears.  Not thread-safe; process-wide. */
+TSQR_API int tsqr_prof_enable(int on);
+TSQR_API int tsqr_prof_query(int i, const char **name, int64_t *launches, double *ms);
+
+/* Frees the host handle only (the workspace belongs to the caller). */
+TSQR_API int tsqr_free(tsqr_factors f);
+
+/* Static description of an error code. */
+TSQR_API const char *tsqr_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQR_H_ */

@@ -1,0 +1,266 @@
+"""MI355X-native TSQR (Agullo et al., arXiv 0912.2572, Sec. 2.3).
+
+Thin Python binding over the C ABI of ``libtsqr.so`` (see include/tsqr.h):
+argument marshalling only.  Every step of the factorization, the Q^T / Q
+applications, the thin Q and least squares runs in the library's HIP kernels
+for gfx950; PyTorch provides device memory and the stream.  There is no CPU
+fallback: if the library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtsqr.so")
+
+TREE_FLAT = 0
+TREE_BINARY = 2
+TREE_QUAD = 4
+F64 = 0
+MIXED = 1
+
+ERR_WORKSPACE = -900
+ERR_STATE = -901
+ERR_UNSUPPORTED = -902
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("row_block", ctypes.c_int64),
+        ("tree", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("keep_q", ctypes.c_int32),
+        ("lsq_max_rhs", ctypes.c_int32),
+        ("refine_max_iter", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("refine_tol", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtsqr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: build it with `python -m paper_0912_2572_amd.build`"
+            )
+        L = ctypes.CDLL(_LIB_PATH)
+        i64, i32, vp, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+        op = ctypes.POINTER(Opts)
+        L.tsqr_default_opts.argtypes = [op]
+        L.tsqr_default_opts.restype = None
+        L.tsqr_workspace_bytes.argtypes = [i64, i64, op]
+        L.tsqr_workspace_bytes.restype = sz
+        L.tsqr_factor.argtypes = [i64, i64, vp, i64, op, vp, sz, vp, ctypes.POINTER(vp)]
+        L.tsqr_get_r.argtypes = [vp, vp, i64, vp]
+        L.tsqr_apply_qt.argtypes = [vp, i64, vp, i64, vp]
+        L.tsqr_apply_q.argtypes = [vp, i64, vp, i64, vp]
+        L.tsqr_form_q.argtypes = [vp, vp, i64, vp]
+        L.tsqr_lsq_solve.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, vp, vp]
+        L.tsqr_last_refine_iters.argtypes = [vp, vp]
+        L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i64)]
+        L.tsqr_tree_schedule.argtypes = [i64, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
+        L.tsqr_tree_schedule.restype = i64
+        L.tsqr_prof_enable.argtypes = [ctypes.c_int]
+        L.tsqr_prof_enable.restype = ctypes.c_int
+        L.tsqr_prof_query.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+        L.tsqr_prof_query.restype = ctypes.c_int
+        L.tsqr_free.argtypes = [vp]
+        L.tsqr_strerror.argtypes = [ctypes.c_int]
+        L.tsqr_strerror.restype = ctypes.c_char_p
+        for name in ("tsqr_factor", "tsqr_get_r", "tsqr_apply_qt", "tsqr_apply_q", "tsqr_form_q",
+                     "tsqr_lsq_solve", "tsqr_last_refine_iters", "tsqr_plan_info", "tsqr_free"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class TSQRError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what} failed: {code} ({lib().tsqr_strerror(code).decode()})")
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise TSQRError(code, what)
+
+
+def opts(row_block: int = 0, tree: int = TREE_BINARY, prec: int = F64, keep_q: bool = True,
+         lsq_max_rhs: int = 8, refine_max_iter: int = 30, refine_tol: float = 1e-14) -> Opts:
+    o = Opts()
+    lib().tsqr_default_opts(ctypes.byref(o))
+    o.row_block = row_block
+    o.tree = tree
+    o.prec = prec
+    o.keep_q = 1 if keep_q else 0
+    o.lsq_max_rhs = lsq_max_rhs
+    o.refine_max_iter = refine_max_iter
+    o.refine_tol = refine_tol
+    return o
+
+
+def workspace_bytes(m: int, n: int, o: Opts | None = None) -> int:
+    return int(lib().tsqr_workspace_bytes(m, n, ctypes.byref(o) if o is not None else None))
+
+
+def plan_info(m: int, n: int, o: Opts | None = None):
+    P, c, npan = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().tsqr_plan_info(m, n, ctypes.byref(o) if o is not None else None,
+                                ctypes.byref(P), ctypes.byref(c), ctypes.byref(npan)), "tsqr_plan_info")
+    return P.value, c.value, npan.value
+
+
+def tree_schedule(P: int, tree: int):
+    """The library's reduction tree as (left, right) combines in order."""
+    cap = max(P - 1, 1)
+    left = (ctypes.c_int64 * cap)()
+    right = (ctypes.c_int64 * cap)()
+    cnt = int(lib().tsqr_tree_schedule(P, tree, left, right, cap))
+    if cnt < 0:
+        raise ValueError("invalid tree arguments")
+    return [(left[i], right[i]) for i in range(cnt)]
+
+
+def prof_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events (see tsqr.h)."""
+    lib().tsqr_prof_enable(1 if on else 0)
+
+
+def prof_query() -> dict:
+    """{kernel name: (launches, total ms)} of the launches timed so far."""
+    out = {}
+    i = 0
+    while True:
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        if lib().tsqr_prof_query(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)) != 0:
+            break
+        out[name.value.decode()] = (cnt.value, ms.value)
+        i += 1
+    return out
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _col_major(t: torch.Tensor, rows: int, name: str):
+    """(pointer, leading dimension) of a column-major float64 device matrix."""
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise ValueError(f"{name} must be contiguous")
+        return t.data_ptr(), max(rows, t.shape[0])
+    if t.stride(0) != 1:
+        raise ValueError(f"{name} must be column-major (use .t().contiguous().t() or "
+                         "torch.empty((n, m)).t())")
+    return t.data_ptr(), t.stride(1) if t.shape[1] > 1 else max(t.stride(1), t.shape[0])
+
+
+def empty_colmajor(m: int, n: int, device="cuda", dtype=torch.float64) -> torch.Tensor:
+    return torch.empty((n, m), device=device, dtype=dtype).t()
+
+
+def to_colmajor(x, device="cuda") -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.dim() == 1:
+        return t.to(device).contiguous()
+    return t.t().contiguous().t().to(device) if t.device.type == "cpu" else t.t().contiguous().t()
+
+
+class Factors:
+    """One TSQR factorization living in a caller-owned device workspace."""
+
+    def __init__(self, A: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = None,
+                 stream=None):
+        m, n = A.shape
+        self.m, self.n = m, n
+        self.opts = o if o is not None else opts()
+        need = workspace_bytes(m, n, self.opts)
+        if need == 0:
+            raise ValueError(f"invalid problem {m} x {n} for the given options")
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=A.device)
+        self.work = work
+        pa, lda = _col_major(A, m, "A")
+        h = ctypes.c_void_p()
+        _check(lib().tsqr_factor(m, n, ctypes.c_void_p(pa), lda, ctypes.byref(self.opts),
+                                 ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(stream),
+                                 ctypes.byref(h)), "tsqr_factor")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tsqr_free(h)
+            self._h = None
+
+    def R(self, stream=None) -> torch.Tensor:
+        R = empty_colmajor(self.n, self.n, device=self.work.device)
+        _check(lib().tsqr_get_r(self._h, ctypes.c_void_p(R.data_ptr()), self.n, _stream(stream)),
+               "tsqr_get_r")
+        return R
+
+    def apply_qt_(self, B: torch.Tensor, stream=None) -> torch.Tensor:
+        k = 1 if B.dim() == 1 else B.shape[1]
+        pb, ldb = _col_major(B, self.m, "B")
+        _check(lib().tsqr_apply_qt(self._h, k, ctypes.c_void_p(pb), ldb, _stream(stream)),
+               "tsqr_apply_qt")
+        return B
+
+    def apply_q_(self, B: torch.Tensor, stream=None) -> torch.Tensor:
+        k = 1 if B.dim() == 1 else B.shape[1]
+        pb, ldb = _col_major(B, self.m, "B")
+        _check(lib().tsqr_apply_q(self._h, k, ctypes.c_void_p(pb), ldb, _stream(stream)),
+               "tsqr_apply_q")
+        return B
+
+    def form_q(self, Q: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if Q is None:
+            Q = empty_colmajor(self.m, self.n, device=self.work.device)
+        pq, ldq = _col_major(Q, self.m, "Q")
+        _check(lib().tsqr_form_q(self._h, ctypes.c_void_p(pq), ldq, _stream(stream)), "tsqr_form_q")
+        return Q
+
+    def lsq(self, B: torch.Tensor, A: torch.Tensor | None = None, X: torch.Tensor | None = None,
+            resid: torch.Tensor | None = None, info: torch.Tensor | None = None, stream=None):
+        """Least squares through the factors.  Returns device tensors
+        (X, resid, info); info is an int32 scalar tensor."""
+        k = 1 if B.dim() == 1 else B.shape[1]
+        dev = self.work.device
+        if X is None:
+            X = empty_colmajor(self.n, k, device=dev)
+        if resid is None:
+            resid = torch.empty(k, dtype=torch.float64, device=dev)
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        pb, ldb = _col_major(B, self.m, "B")
+        px, ldx = _col_major(X, self.n, "X")
+        pa, lda = (0, self.m) if A is None else _col_major(A, self.m, "A")
+        _check(lib().tsqr_lsq_solve(self._h, ctypes.c_void_p(pa), lda, k, ctypes.c_void_p(pb), ldb,
+                                    ctypes.c_void_p(px), ldx, ctypes.c_void_p(resid.data_ptr()),
+                                    ctypes.c_void_p(info.data_ptr()), _stream(stream)),
+               "tsqr_lsq_solve")
+        return X, resid, info
+
+    def last_refine_iters(self, stream=None) -> int:
+        return int(lib().tsqr_last_refine_iters(self._h, _stream(stream)))
+
+
+def factor(A: torch.Tensor, **kw) -> Factors:
+    work = kw.pop("work", None)
+    stream = kw.pop("stream", None)
+    return Factors(A, opts(**kw), work=work, stream=stream)

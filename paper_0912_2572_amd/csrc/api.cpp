@@ -1,0 +1,317 @@
+// api.cpp -- the C ABI declared in include/tsqr.h.
+//
+// Every entry point validates its arguments on the host, then enqueues the
+// kernels of kernels.h on the caller's stream.  No device memory is
+// allocated here: the workspace, inputs and outputs belong to the caller.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "kernels.h"
+#include "plan.h"
+
+struct tsqr_factors_s {
+    tsqr::Plan plan;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int keep_q = 1;
+    int last_refine = 0;
+};
+
+namespace {
+
+using tsqr::Panel;
+using tsqr::PanelArgs;
+using tsqr::Plan;
+using tsqr::TreeArgs;
+
+inline int hip_code(hipError_t e) { return -1000 - (int)e; }
+
+PanelArgs panel_args(const Panel &p) {
+    PanelArgs a;
+    a.m = p.m;
+    a.mb = p.mb;
+    a.P = p.P;
+    a.cpd = p.cpd;
+    a.chunk = p.chunk;
+    a.n = p.n;
+    a.ns = p.ns;
+    return a;
+}
+
+template <typename T>
+T *at(const tsqr_factors_s *f, size_t off) {
+    return reinterpret_cast<T *>(f->ws + off);
+}
+
+#define TRY(call)                                  \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_code(e_); \
+    } while (0)
+
+// Q_p^T (trans = 1) or Q_p (trans = 0) of panel p on k columns; Bsrc/ldbs
+// address the panel's first row of the input, B/ldb of the output.
+int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int64_t ldbs, double *B,
+                int64_t ldb, int64_t k, int trans, hipStream_t st) {
+    const Plan &P = f->plan;
+    const PanelArgs pa = panel_args(p);
+    const double *V = at<double>(f, P.off_w) + p.row_off + (int64_t)p.col_off * P.m;
+    const double *Tc = at<double>(f, p.off_tc);
+    const double *Rdom = at<double>(f, p.off_rdom);
+    const double *Tnode = at<double>(f, p.off_tnode);
+    auto levels = tsqr::tree_levels(p.P, p.tree);
+    if (trans) {
+        TRY(tsqr::launch_leaf_apply(V, P.m, Tc, pa, Bsrc, ldbs, B, ldb, k, 1, st));
+        for (const auto &L : levels) {
+            TreeArgs ta{L.stride, L.span, L.chains};
+            TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 1, st));
+        }
+    } else {
+        if (Bsrc != B) TRY(tsqr::launch_copy(Bsrc, ldbs, B, ldb, p.m, k, st));
+        for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
+            TreeArgs ta{it->stride, it->span, it->chains};
+            TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 0, st));
+        }
+        TRY(tsqr::launch_leaf_apply(V, P.m, Tc, pa, B, ldb, B, ldb, k, 0, st));
+    }
+    return 0;
+}
+
+int validate_handle(const tsqr_factors_s *f, bool need_q) {
+    if (!f) return -1;
+    if (need_q && !f->keep_q) return TSQR_ERR_STATE;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+TSQR_API void tsqr_default_opts(tsqr_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->row_block = 0;
+    o->tree = TSQR_TREE_BINARY;
+    o->prec = TSQR_F64;
+    o->keep_q = 1;
+    o->lsq_max_rhs = 8;
+    o->refine_max_iter = 30;
+    o->refine_tol = 1e-14;
+}
+
+TSQR_API size_t tsqr_workspace_bytes(int64_t m, int64_t n, const tsqr_opts *o) {
+    Plan p;
+    if (tsqr::make_plan(m, n, o, &p) != 0) return 0;
+    return p.total;
+}
+
+TSQR_API int tsqr_plan_info(int64_t m, int64_t n, const tsqr_opts *o, int64_t *num_domains,
+                            int64_t *chunk_rows, int64_t *num_panels) {
+    Plan p;
+    int rc = tsqr::make_plan(m, n, o, &p);
+    if (rc) return rc;
+    if (num_domains) *num_domains = p.panels[0].P;
+    if (chunk_rows) *chunk_rows = p.panels[0].chunk;
+    if (num_panels) *num_panels = (int64_t)p.panels.size();
+    return 0;
+}
+
+TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, const tsqr_opts *o,
+                         void *dwork, size_t work_bytes, void *stream, tsqr_factors *out) {
+    if (!out) return -9;
+    *out = nullptr;
+    tsqr_opts defaults;
+    tsqr_default_opts(&defaults);
+    if (!o) o = &defaults;
+    Plan plan;
+    int rc = tsqr::make_plan(m, n, o, &plan);
+    if (rc) return rc;
+    if (!A) return -3;
+    if (lda < m) return -4;
+    if (!dwork || work_bytes < plan.total || (reinterpret_cast<uintptr_t>(dwork) % tsqr::kAlign))
+        return TSQR_ERR_WORKSPACE;
+    tsqr_factors_s *f = new (std::nothrow) tsqr_factors_s;
+    if (!f) return TSQR_ERR_WORKSPACE;
+    f->plan = plan;
+    f->ws = static_cast<char *>(dwork);
+    f->ws_bytes = work_bytes;
+    f->keep_q = o->keep_q ? 1 : 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *W = at<double>(f, plan.off_w);
+    double *R = at<double>(f, plan.off_r);
+    double *dsign = at<double>(f, plan.off_d);
+    const int np = (int)plan.panels.size();
+    int err = 0;
+    for (int q = 0; q < np && !err; ++q) {
+        const Panel &p = plan.panels[q];
+        const PanelArgs pa = panel_args(p);
+        const double *src = (q == 0) ? A : W;
+        const int64_t lds = (q == 0) ? lda : m;
+        const double *src_p = src + p.row_off + (int64_t)p.col_off * lds;
+        double *V = W + p.row_off + (int64_t)p.col_off * m;
+        const int keep = (f->keep_q || q < np - 1) ? 1 : 0;
+        double *Rdom = at<double>(f, p.off_rdom);
+        double *Tnode = at<double>(f, p.off_tnode);
+        hipError_t e = tsqr::launch_leaf(src_p, lds, V, m, at<double>(f, p.off_tc), Rdom, pa, keep, st);
+        for (const auto &L : tsqr::tree_levels(p.P, p.tree)) {
+            if (e != hipSuccess) break;
+            TreeArgs ta{L.stride, L.span, L.chains};
+            e = tsqr::launch_tree_level(Rdom, Tnode, pa, ta, keep, st);
+        }
+        if (e == hipSuccess)
+            e = tsqr::launch_sign_normalise(Rdom, p.n, R, n, p.row_off, p.col_off, dsign, st);
+        if (e != hipSuccess) {
+            err = hip_code(e);
+            break;
+        }
+        if (q < np - 1) {
+            // trailing update: Q_p^T on columns [col_off + w, n), rows [row_off, m)
+            const int64_t c1 = p.col_off + p.n;
+            const int64_t kt = n - c1;
+            const double *bsrc = src + p.row_off + c1 * lds;
+            double *bdst = W + p.row_off + c1 * m;
+            err = panel_apply(f, p, bsrc, lds, bdst, m, kt, 1, st);
+            if (err) break;
+            // R[row_off : row_off + w, c1 : n] = D_p * (top w rows of the result)
+            e = tsqr::launch_copy(bdst, m, R + p.row_off + c1 * n, n, p.n, kt, st);
+            if (e == hipSuccess) e = tsqr::launch_scale_rows(R + p.row_off + c1 * n, n, p.n, kt,
+                                                            dsign + p.row_off, st);
+            if (e != hipSuccess) err = hip_code(e);
+        }
+    }
+    if (err) {
+        delete f;
+        return err;
+    }
+    *out = f;
+    return 0;
+}
+
+TSQR_API int tsqr_get_r(tsqr_factors f, double *R, int64_t ldr, void *stream) {
+    int rc = validate_handle(f, false);
+    if (rc) return rc;
+    if (!R) return -2;
+    if (ldr < f->plan.n) return -3;
+    hipError_t e = tsqr::launch_copy(at<double>(f, f->plan.off_r), f->plan.n, R, ldr, f->plan.n,
+                                     f->plan.n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
+TSQR_API int tsqr_apply_qt(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream) {
+    int rc = validate_handle(f, true);
+    if (rc) return rc;
+    if (k < 0) return -2;
+    if (k == 0) return 0;
+    if (!B) return -3;
+    if (ldb < f->plan.m) return -4;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double *d = at<double>(f, f->plan.off_d);
+    for (const Panel &p : f->plan.panels) {
+        double *Bp = B + p.row_off;
+        rc = panel_apply(f, p, Bp, ldb, Bp, ldb, k, 1, st);
+        if (rc) return rc;
+        hipError_t e = tsqr::launch_scale_rows(Bp, ldb, p.n, k, d + p.row_off, st);
+        if (e != hipSuccess) return hip_code(e);
+    }
+    return 0;
+}
+
+static int apply_q_impl(tsqr_factors_s *f, int64_t k, double *B, int64_t ldb, bool scale,
+                        bool skip_left_cols, hipStream_t st) {
+    const double *d = at<double>(f, f->plan.off_d);
+    if (scale)
+        for (const Panel &p : f->plan.panels) {
+            hipError_t e = tsqr::launch_scale_rows(B + p.row_off, ldb, p.n, k, d + p.row_off, st);
+            if (e != hipSuccess) return hip_code(e);
+        }
+    for (auto it = f->plan.panels.rbegin(); it != f->plan.panels.rend(); ++it) {
+        const Panel &p = *it;
+        const int64_t c0 = skip_left_cols ? p.col_off : 0;
+        double *Bp = B + p.row_off + c0 * ldb;
+        int rc = panel_apply(f, p, Bp, ldb, Bp, ldb, k - c0, 0, st);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream) {
+    int rc = validate_handle(f, true);
+    if (rc) return rc;
+    if (k < 0) return -2;
+    if (k == 0) return 0;
+    if (!B) return -3;
+    if (ldb < f->plan.m) return -4;
+    return apply_q_impl(f, k, B, ldb, true, false, static_cast<hipStream_t>(stream));
+}
+
+TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
+    int rc = validate_handle(f, true);
+    if (rc) return rc;
+    if (!Q) return -2;
+    if (ldq < f->plan.m) return -3;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = tsqr::launch_fill_identity_signs(Q, ldq, f->plan.m, (int)f->plan.n,
+                                                    at<double>(f, f->plan.off_d), st);
+    if (e != hipSuccess) return hip_code(e);
+    return apply_q_impl(f, f->plan.n, Q, ldq, false, true, st);
+}
+
+TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_t k, const double *B,
+                            int64_t ldb, double *X, int64_t ldx, double *resid, int32_t *dinfo,
+                            void *stream) {
+    int rc = validate_handle(f, true);
+    if (rc) return rc;
+    const Plan &P = f->plan;
+    if (P.opts.prec == TSQR_MIXED && !A) return -2;
+    if (A && lda < P.m) return -3;
+    if (k < 1 || k > P.opts.lsq_max_rhs) return -4;
+    if (!B) return -5;
+    if (ldb < P.m) return -6;
+    if (!X) return -7;
+    if (ldx < P.n) return -8;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *C = at<double>(f, P.off_lsq);
+    hipError_t e = tsqr::launch_copy(B, ldb, C, P.m, P.m, k, st);
+    if (e != hipSuccess) return hip_code(e);
+    rc = tsqr_apply_qt(f, k, C, P.m, stream);
+    if (rc) return rc;
+    e = tsqr::launch_lsq_finish(at<double>(f, P.off_r), (int)P.n, C, P.m, P.m, k, X, ldx, resid, dinfo,
+                                at<double>(f, P.off_small), st);
+    f->last_refine = 0;
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
+TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream) {
+    (void)stream;
+    return f ? f->last_refine : -1;
+}
+
+TSQR_API int64_t tsqr_tree_schedule(int64_t P, int tree, int64_t *left, int64_t *right, int64_t cap) {
+    if (P < 1) return -1;
+    if (tree != TSQR_TREE_FLAT && tree != TSQR_TREE_BINARY && tree != TSQR_TREE_QUAD) return -2;
+    auto s = tsqr::tree_schedule(P, tree);
+    for (int64_t i = 0; i < (int64_t)s.size() && i < cap; ++i) {
+        if (left) left[i] = s[i].first;
+        if (right) right[i] = s[i].second;
+    }
+    return (int64_t)s.size();
+}
+
+TSQR_API int tsqr_free(tsqr_factors f) {
+    delete f;
+    return 0;
+}
+
+TSQR_API const char *tsqr_strerror(int code) {
+    if (code == 0) return "success";
+    if (code == TSQR_ERR_WORKSPACE) return "workspace missing, misaligned or too small";
+    if (code == TSQR_ERR_STATE) return "factor handle cannot serve this call (keep_q = 0?)";
+    if (code == TSQR_ERR_UNSUPPORTED) return "shape outside the supported scope (n <= 256)";
+    if (code <= -1000) return "HIP runtime error (code = -1000 - hipError_t)";
+    if (code < 0) return "invalid argument (code = -index of the argument)";
+    return "unknown";
+}
+
+}  // extern "C"

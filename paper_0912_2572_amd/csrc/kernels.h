@@ -1,0 +1,59 @@
+// kernels.h -- launch interface of the HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace tsqr {
+
+// Geometry of one panel TSQR as the kernels see it.
+struct PanelArgs {
+    int64_t m;      // rows of the panel
+    int64_t mb;     // rows per domain
+    int64_t P;      // domains
+    int64_t cpd;    // chunks per full domain
+    int64_t chunk;  // rows per chunk
+    int n;          // columns (<= 64)
+    int ns;         // column slots per thread of the leaf kernel
+};
+
+// One tree level: chains g = 0..chains-1 start at left = g * span and take
+// rights left + q * stride for q = 1.. while q * stride < span and < P.
+struct TreeArgs {
+    int64_t stride;
+    int64_t span;
+    int64_t chains;
+};
+
+size_t factor_smem_bytes();
+
+// factor.hip
+hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, double *Tc, double *Rdom,
+                       const PanelArgs &pa, int keep_q, hipStream_t st);
+hipError_t launch_tree_level(double *Rdom, double *Tnode, const PanelArgs &pa, const TreeArgs &ta,
+                             int keep_q, hipStream_t st);
+hipError_t launch_sign_normalise(const double *Rroot, int n, double *Rout, int64_t ldr, int row_off,
+                                 int col_off, double *dsign, hipStream_t st);
+
+// apply.hip: Q^T (trans = 1) or Q (trans = 0) of a panel's leaves / tree on
+// k columns.  Bsrc may differ from B (out of place) or equal it.
+hipError_t launch_leaf_apply(const double *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
+                             const double *Bsrc, int64_t ldbs, double *B, int64_t ldb, int64_t k,
+                             int trans, hipStream_t st);
+hipError_t launch_tree_apply(const double *Rdom, const double *Tnode, const PanelArgs &pa,
+                             const TreeArgs &ta, double *B, int64_t ldb, int64_t k, int trans,
+                             hipStream_t st);
+// Scale rows [0, n) of B (k columns) by the signs d.
+hipError_t launch_scale_rows(double *B, int64_t ldb, int n, int64_t k, const double *d, hipStream_t st);
+
+// misc.hip
+hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, const double *d,
+                                      hipStream_t st);
+hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                       int64_t cols, hipStream_t st);
+hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ldc, int64_t m, int64_t k,
+                             double *X, int64_t ldx, double *resid, int32_t *dinfo, double *partial,
+                             hipStream_t st);
+
+}  // namespace tsqr

@@ -1,0 +1,134 @@
+// misc.hip -- small kernels around the TSQR core: the [D; 0] seed of the
+// thin Q, 2-D copies, and the last steps of least squares (back substitution
+// with R and the residual norms ||(Q^T B)[n:m, j]||_2).
+#include "common.h"
+#include "kernels.h"
+#include "prof.h"
+
+namespace tsqr {
+
+// Q (m x n) = [D; 0], D = diag(d): the thin Q is Q_full [D; 0] (R <- D R,
+// Q <- Q D makes the factorization unique, Sec. 2.2).
+__global__ void k_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, const double *d) {
+    const int64_t total = m * (int64_t)n;
+    for (int64_t e = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; e < total;
+         e += (int64_t)blockDim.x * gridDim.x) {
+        const int64_t r = e % m, c = e / m;
+        Q[r + c * ldq] = (r == c) ? d[c] : 0.0;
+    }
+}
+
+__global__ void k_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                       int64_t cols) {
+    const int64_t total = rows * cols;
+    for (int64_t e = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; e < total;
+         e += (int64_t)blockDim.x * gridDim.x) {
+        const int64_t r = e % rows, c = e / rows;
+        dst[r + c * ldd] = src[r + c * lds];
+    }
+}
+
+constexpr int kResidBlocks = 512;
+
+// partial[b][c] = sum of C[r][c]^2 over the rows n..m-1 owned by block b
+// (contiguous row ranges, fixed summation order).
+__global__ __launch_bounds__(256) void k_resid_partial(const double *C, int64_t ldc, int64_t m, int n,
+                                                       int64_t k, double *partial) {
+    __shared__ double red[256];
+    const int64_t rows = m - n;
+    const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = n + (int64_t)blockIdx.x * per;
+    const int64_t hi = (lo + per < m) ? lo + per : m;
+    for (int64_t c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int64_t r = lo + threadIdx.x; r < hi; r += 256) {
+            const double v = C[r + c * ldc];
+            s = fma(v, v, s);
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x * k + c] = red[0];
+        __syncthreads();
+    }
+}
+
+// One workgroup: info from the diagonal of R, residual norms from the
+// partials, then X = R^{-1} C[0:n] by column-oriented back substitution.
+__global__ __launch_bounds__(256) void k_lsq_final(const double *R, int n, const double *C, int64_t ldc,
+                                                   int64_t k, double *X, int64_t ldx, double *resid,
+                                                   int32_t *dinfo, const double *partial, int nparts) {
+    __shared__ double xs[256];
+    __shared__ int info;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        info = 0;
+        for (int j = 0; j < n; ++j)
+            if (R[j + j * n] == 0.0) {
+                info = j + 1;
+                break;
+            }
+    }
+    __syncthreads();
+    bool bad = false;
+    if (tid < k) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; ++b) s += partial[b * k + tid];
+        const double rn = sqrt(s);
+        if (resid) resid[tid] = rn;
+        bad = !(rn - rn == 0.0);
+    }
+    const int anybad = __syncthreads_or(bad);
+    if (tid == 0 && dinfo) *dinfo = info ? info : (anybad ? -2 : 0);
+    if (info) return;
+    for (int64_t c = 0; c < k; ++c) {
+        for (int i = tid; i < n; i += 256) xs[i] = C[i + c * ldc];
+        __syncthreads();
+        for (int j = n - 1; j >= 0; --j) {
+            const double xj = xs[j] / R[j + j * n];
+            __syncthreads();
+            for (int i = tid; i < j; i += 256) xs[i] = fma(-R[i + j * n], xj, xs[i]);
+            if (tid == 0) xs[j] = xj;
+            __syncthreads();
+        }
+        for (int i = tid; i < n; i += 256) X[i + c * ldx] = xs[i];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, const double *d,
+                                      hipStream_t st) {
+    ProfScope ps("fill_identity", st);
+    hipLaunchKernelGGL(k_fill_identity_signs, dim3(2048), dim3(256), 0, st, Q, ldq, m, n, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                       int64_t cols, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    ProfScope ps("copy", st);
+    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, st, src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ldc, int64_t m, int64_t k,
+                             double *X, int64_t ldx, double *resid, int32_t *dinfo, double *partial,
+                             hipStream_t st) {
+    int blocks = kResidBlocks;
+    if (m - n < (int64_t)blocks * 256) blocks = (int)((m - n + 255) / 256);
+    if (blocks < 1) blocks = 1;
+    ProfScope ps("lsq_finish", st);
+    if (m > n) {
+        hipLaunchKernelGGL(k_resid_partial, dim3(blocks), dim3(256), 0, st, C, ldc, m, n, k, partial);
+    } else {
+        blocks = 0;
+    }
+    hipLaunchKernelGGL(k_lsq_final, dim3(1), dim3(256), 0, st, R, n, C, ldc, k, X, ldx, resid, dinfo,
+                       partial, blocks);
+    return hipGetLastError();
+}
+
+}  // namespace tsqr

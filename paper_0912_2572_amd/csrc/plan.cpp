@@ -1,0 +1,124 @@
+// plan.cpp -- domain partition, tree schedule, panels and workspace layout.
+//
+// Partition (Sec. 2.3, "the TS matrix is split in P block-rows, called
+// domains"): P = ceil(m / mb) contiguous domains; a last domain with fewer
+// than n rows is merged into the one before it so that every domain's QR has
+// n reflectors.  Trees (Sec. 2.3): binary (adjacent pairs per level), k-ary
+// (groups of k consecutive live nodes reduced left to right) and flat
+// (R <- comb(R, R_i) for i = 1..P-1); results stay in the lower index.
+// Matrices wider than 64 columns are factored in 64-column panels, each a
+// TSQR of the rows that remain below the previous panels, with the panel's
+// Q^T applied to the columns to its right in between: the factor-panel /
+// update-trailing-matrix structure of CAQR (Sec. 2.3), which is also how the
+// paper's ScaLAPACK domain kernel blocks its columns (block size 64, Sec. 5.2).
+#include "plan.h"
+
+#include <algorithm>
+
+namespace tsqr {
+
+static size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+std::vector<TreeLevel> tree_levels(int64_t P, int tree) {
+    std::vector<TreeLevel> lv;
+    if (P <= 1) return lv;
+    if (tree == TSQR_TREE_FLAT) {
+        lv.push_back(TreeLevel{1, P, 1, P - 1});
+        return lv;
+    }
+    int64_t k = (tree == TSQR_TREE_QUAD) ? 4 : 2;
+    for (int64_t stride = 1; stride < P; stride *= k) {
+        TreeLevel L;
+        L.stride = stride;
+        L.span = stride * k;
+        L.chains = (P - stride + L.span - 1) / L.span;
+        L.max_rights = k - 1;
+        lv.push_back(L);
+    }
+    return lv;
+}
+
+std::vector<std::pair<int64_t, int64_t>> tree_schedule(int64_t P, int tree) {
+    std::vector<std::pair<int64_t, int64_t>> s;
+    for (const TreeLevel &L : tree_levels(P, tree))
+        for (int64_t g = 0; g < L.chains; ++g) {
+            int64_t left = g * L.span;
+            for (int64_t q = 1; q * L.stride < L.span && left + q * L.stride < P; ++q)
+                s.emplace_back(left, left + q * L.stride);
+        }
+    return s;
+}
+
+static int64_t default_row_block(int64_t m, int64_t n) {
+    // Enough domains to give every one of the 256 compute units two
+    // workgroups, rounded up to whole chunks, within [max(n, chunk), 8192].
+    int64_t c = chunk_rows_for((int)std::min<int64_t>(n, kMaxPanel));
+    int64_t want = (m + 511) / 512;
+    int64_t mb = (want + c - 1) / c * c;
+    mb = std::min<int64_t>(mb, std::max<int64_t>(8192, c));
+    mb = std::max<int64_t>(mb, std::max<int64_t>(n, c));
+    return mb;
+}
+
+int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
+    tsqr_opts d;
+    tsqr_default_opts(&d);
+    if (!o) o = &d;
+    if (n < 1) return -2;
+    if (m < n || m > 2147483647LL) return -1;
+    if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
+    if (o->tree != TSQR_TREE_FLAT && o->tree != TSQR_TREE_BINARY && o->tree != TSQR_TREE_QUAD)
+        return -5;
+    if (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) return -5;
+    if (o->row_block != 0 && o->row_block < n) return -5;
+    if (o->lsq_max_rhs < 1 || o->refine_max_iter < 0) return -5;
+    Plan P;
+    P.m = m;
+    P.n = n;
+    P.opts = *o;
+    P.mb = o->row_block ? o->row_block : default_row_block(m, n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    P.off_w = take(sizeof(double) * (size_t)m * n);
+    if (o->prec == TSQR_MIXED) P.off_w32 = take(sizeof(float) * (size_t)m * n);
+    P.off_r = take(sizeof(double) * (size_t)n * n);
+    P.off_d = take(sizeof(double) * (size_t)n);
+    int np = (int)((n + kMaxPanel - 1) / kMaxPanel);
+    for (int q = 0; q < np; ++q) {
+        Panel pa;
+        pa.col_off = q * kMaxPanel;
+        pa.row_off = pa.col_off;
+        pa.n = (int)std::min<int64_t>(kMaxPanel, n - pa.col_off);
+        pa.m = m - pa.row_off;
+        pa.mb = P.mb;
+        if (pa.mb < pa.n) pa.mb = pa.n;
+        pa.P = (pa.m + pa.mb - 1) / pa.mb;
+        if (pa.P > 1 && pa.m - (pa.P - 1) * pa.mb < pa.n) pa.P -= 1;
+        pa.ns = slots_for(pa.n);
+        pa.chunk = chunk_rows_for(pa.n);
+        pa.cpd = (pa.mb + pa.chunk - 1) / pa.chunk;
+        pa.total_chunks = (pa.P - 1) * pa.cpd + pa.domain_chunks(pa.P - 1);
+        pa.tree = o->tree;
+        size_t nn = (size_t)pa.n * pa.n * sizeof(double);
+        pa.off_tc = take(nn * (size_t)pa.total_chunks);
+        pa.off_rdom = take(nn * (size_t)pa.P);
+        pa.off_tnode = take(nn * (size_t)pa.P);
+        pa.off_s = take(nn * (size_t)pa.P);
+        P.panels.push_back(pa);
+    }
+    P.off_lsq = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);
+    if (o->prec == TSQR_MIXED) P.off_lsq2 = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);
+    // small scratch: per-block partial sums (4096 blocks x rhs), a few
+    // n x rhs vectors, info words and counters
+    P.small_bytes = sizeof(double) * (size_t)(4096 + 8 * n) * o->lsq_max_rhs + 4096;
+    P.off_small = take(P.small_bytes);
+    P.total = off;
+    *p = P;
+    return 0;
+}
+
+}  // namespace tsqr

@@ -1,0 +1,89 @@
+// plan.h -- host-side plan of a TSQR factorization: domain partition, leaf
+// chunking, tree schedule, 64-column panels and the workspace layout.
+// Pure C++ (no device code), so the plan is testable on a machine without a
+// GPU through tsqr_plan_info / tsqr_workspace_bytes.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/tsqr.h"
+
+namespace tsqr {
+
+constexpr int kMaxPanel = 64;     // columns handled by one leaf/tree kernel
+constexpr int kMaxN = 256;        // documented scope
+constexpr int kThreads = 256;     // threads per workgroup of the leaf kernel
+constexpr size_t kAlign = 256;
+
+// Column slots per thread of the leaf kernel for a panel of width w:
+// 8 column groups x ns slots must cover w.  Rows per thread = 64 / ns (32
+// for ns = 1), and a chunk holds 32 row groups x rows-per-thread rows.
+inline int slots_for(int w) {
+    int need = (w + 7) / 8;
+    int ns = 1;
+    while (ns < need) ns <<= 1;
+    return ns;
+}
+inline int chunk_rows_for(int w) {
+    int ns = slots_for(w);
+    return 32 * (ns >= 2 ? 64 / ns : 32);   // 32 row groups x rows per thread
+}
+
+// One TSQR over rows [row_off, row_off + m) and columns [col_off, col_off+n)
+// of the working matrix (n <= 64).
+struct Panel {
+    int64_t m = 0, row_off = 0;
+    int n = 0, col_off = 0;
+    int64_t mb = 0, P = 0;          // domains of mb rows (the last one ragged)
+    int ns = 0;                     // slots per thread (1, 2, 4, 8)
+    int64_t chunk = 0;              // rows per chunk of the leaf kernel
+    int64_t cpd = 0;                // chunks in a full domain
+    int64_t total_chunks = 0;
+    int tree = TSQR_TREE_BINARY;
+    // workspace offsets (bytes from the workspace base)
+    size_t off_tc = 0;              // total_chunks x n x n   (chunk T factors)
+    size_t off_rdom = 0;            // P x n x n              (domain R / node U)
+    size_t off_tnode = 0;           // P x n x n              (node T, by right child)
+    size_t off_s = 0;               // P x n x n              (top-down blocks)
+
+    int64_t domain_row0(int64_t i) const { return i * mb; }
+    int64_t domain_rows(int64_t i) const { return (i == P - 1) ? m - i * mb : mb; }
+    int64_t domain_chunk0(int64_t i) const { return i * cpd; }
+    int64_t domain_chunks(int64_t i) const { return (domain_rows(i) + chunk - 1) / chunk; }
+};
+
+// Tree levels: one kernel launch per level, one workgroup per chain.  A chain
+// is (left, right_1, ..., right_c): the rights are combined into left one
+// after the other (binary: c = 1, k-ary: c = k - 1, flat: one chain of P - 1).
+struct TreeLevel {
+    int64_t stride = 0;    // distance between consecutive rights of a chain
+    int64_t span = 0;      // distance between the lefts of consecutive chains
+    int64_t chains = 0;
+    int64_t max_rights = 0;
+};
+std::vector<TreeLevel> tree_levels(int64_t P, int tree);
+// The flat list of (left, right) combines in execution order, for tests.
+std::vector<std::pair<int64_t, int64_t>> tree_schedule(int64_t P, int tree);
+
+struct Plan {
+    int64_t m = 0, n = 0;
+    tsqr_opts opts{};
+    int64_t mb = 0;
+    std::vector<Panel> panels;
+    size_t off_w = 0;       // m x n FP64 working matrix (reflectors, trailing updates)
+    size_t off_w32 = 0;     // m x n FP32 copy of the reflectors (mixed only)
+    size_t off_r = 0;       // n x n final R
+    size_t off_d = 0;       // n signs
+    size_t off_lsq = 0;     // m x lsq_max_rhs scratch (Q^T B)
+    size_t off_lsq2 = 0;    // m x lsq_max_rhs scratch (refinement residual)
+    size_t off_small = 0;   // small scratch: partial sums, x corrections, info words
+    size_t small_bytes = 0;
+    size_t total = 0;
+};
+
+// Returns 0 and fills *p, or a negative argument code.
+int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p);
+
+}  // namespace tsqr

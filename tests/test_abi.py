@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/tsqr.h declares, plans like the oracle partitions,
+and rejects invalid arguments before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsqr.h")
+LIB = os.path.join(ROOT, "paper_0912_2572_amd", "libtsqr.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"TSQR_API\s+[\w\s\*]+?\b(tsqr_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def tl():
+    if not os.path.exists(LIB):
+        import paper_0912_2572_amd.build as b
+        b.build()
+    import paper_0912_2572_amd as t
+    return t
+
+
+def test_header_declares_the_four_calls():
+    syms = declared_symbols()
+    for s in ("tsqr_factor", "tsqr_apply_qt", "tsqr_form_q", "tsqr_lsq_solve"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(tl):
+    L = ctypes.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_plan_matches_oracle_partition(tl):
+    for m, n, mb in [(4096, 16, 1024), (1 << 20, 64, 4096), (1010, 16, 500), (5003, 13, 700),
+                     (777, 1, 100), (64, 64, 64)]:
+        P, chunk, npan = tl.plan_info(m, n, tl.opts(row_block=mb))
+        assert P == len(oracle.partition(m, n, mb))
+        assert npan == 1
+        assert chunk >= n
+
+
+def test_wide_problems_are_split_in_64_column_panels(tl):
+    for n, want in [(64, 1), (65, 2), (128, 2), (200, 4), (256, 4)]:
+        assert tl.plan_info(100000, n, tl.opts(row_block=4096))[2] == want
+
+
+@pytest.mark.parametrize("tree", [0, 2, 4])
+@pytest.mark.parametrize("P", [1, 2, 5, 8, 17, 256])
+def test_tree_schedule_matches_oracle(tl, tree, P):
+    assert tl.tree_schedule(P, tree) == oracle.schedule(P, tree)
+
+
+def test_workspace_bytes(tl):
+    o = tl.opts(row_block=4096)
+    w = tl.workspace_bytes(1 << 20, 64, o)
+    # at least the reflectors (m x n) plus the chunk T factors
+    assert w >= 8 * (1 << 20) * 64
+    assert w < 8 * (1 << 20) * 64 * 1.6
+    assert tl.workspace_bytes(10, 20, o) == 0          # m < n
+    assert tl.workspace_bytes(100, 300, o) == 0        # n above scope
+
+
+def test_invalid_arguments_rejected_on_host(tl):
+    L = tl.lib()
+    o = tl.opts(row_block=64)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    assert L.tsqr_factor(10, 20, dummy, 10, ctypes.byref(o), dummy, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.tsqr_factor(100, 0, dummy, 100, ctypes.byref(o), dummy, 1 << 20, None, ctypes.byref(h)) == -2
+    assert L.tsqr_factor(100, 4, None, 100, ctypes.byref(tl.opts(row_block=64)), dummy, 1 << 30, None,
+                         ctypes.byref(h)) == -3
+    assert L.tsqr_factor(100, 4, dummy, 99, ctypes.byref(o), dummy, 1 << 30, None, ctypes.byref(h)) == -4
+    bad = tl.opts(row_block=3)
+    assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
+    bad = tl.opts(tree=3)
+    assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
+    assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(o), None, 1 << 30, None,
+                         ctypes.byref(h)) == tl.ERR_WORKSPACE
+    assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(o), dummy, 16, None,
+                         ctypes.byref(h)) == tl.ERR_WORKSPACE
+    assert L.tsqr_factor(1000, 300, dummy, 1000, ctypes.byref(o), dummy, 1 << 30, None,
+                         ctypes.byref(h)) == tl.ERR_UNSUPPORTED
+    assert not h.value
+    assert L.tsqr_strerror(-900).decode().startswith("workspace")
