@@ -144,6 +144,11 @@ TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, con
     double *dsign = at<double>(f, plan.off_d);
     const int np = (int)plan.panels.size();
     int err = 0;
+    if (np > 1) {
+        // the panels write R block by block; its lower-left part stays zero
+        hipError_t e = tsqr::launch_fill(R, n * n, 0.0, st);
+        if (e != hipSuccess) err = hip_code(e);
+    }
     for (int q = 0; q < np && !err; ++q) {
         const Panel &p = plan.panels[q];
         const PanelArgs pa = panel_args(p);
@@ -252,8 +257,24 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
     if (!Q) return -2;
     if (ldq < f->plan.m) return -3;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = tsqr::launch_fill_identity_signs(Q, ldq, f->plan.m, (int)f->plan.n,
-                                                    at<double>(f, f->plan.off_d), st);
+    const double *dsign = at<double>(f, f->plan.off_d);
+    if (f->plan.panels.size() == 1) {
+        // single panel: top-down tree on n x n blocks, then the MFMA leaf
+        const Panel &p = f->plan.panels[0];
+        const PanelArgs pa = panel_args(p);
+        double *S = at<double>(f, p.off_s);
+        TRY(tsqr::launch_seed_root(S, p.n, dsign, st));
+        auto levels = tsqr::tree_levels(p.P, p.tree);
+        for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
+            TreeArgs ta{it->stride, it->span, it->chains};
+            TRY(tsqr::launch_tree_down(at<double>(f, p.off_rdom), at<double>(f, p.off_tnode), S, pa, ta,
+                                       st));
+        }
+        TRY(tsqr::launch_form_leaf(at<double>(f, f->plan.off_w), f->plan.m, at<double>(f, p.off_tc), S,
+                                   pa, Q, ldq, st));
+        return 0;
+    }
+    hipError_t e = tsqr::launch_fill_identity_signs(Q, ldq, f->plan.m, (int)f->plan.n, dsign, st);
     if (e != hipSuccess) return hip_code(e);
     return apply_q_impl(f, f->plan.n, Q, ldq, false, true, st);
 }

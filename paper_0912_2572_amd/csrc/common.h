@@ -15,13 +15,38 @@ constexpr int kLdsStride = 65;
 // broadcast copy of one column stays in registers.
 __host__ __device__ constexpr int rows_per_thread(int ns) { return ns >= 2 ? 64 / ns : 32; }
 
+// 64-bit lane permutations built from 32-bit DPP / swizzle primitives.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int PATTERN>
+__device__ __forceinline__ double swizzle_f64(double v) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PATTERN);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PATTERN);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowRor8 = 0x128;     // lane i <- lane (i + 8) mod 16 of its row = i ^ 8
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kSwizzleXor16 = 0x401F;  // bit mode: and 0x1f, xor 0x10
+
 // Sum over the 8 lanes that share a column group (lane = rg * 8 + cg), i.e.
 // across lane bits 3..5.  Butterfly with commutative pairwise adds, so every
 // participating lane ends with the bitwise-identical sum.
 __device__ __forceinline__ double sum_rowgroups(double v) {
-    v += __shfl_xor(v, 8);
-    v += __shfl_xor(v, 16);
+    v += dpp_f64<kDppRowRor8>(v);
+    v += swizzle_f64<kSwizzleXor16>(v);
     v += __shfl_xor(v, 32);
+    return v;
+}
+
+// Sum over the 4 lanes of a quad (lane bits 0..1), identical in all four.
+__device__ __forceinline__ double sum_quad(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
     return v;
 }
 

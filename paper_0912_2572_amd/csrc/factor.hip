@@ -22,6 +22,8 @@
 // ||x||^2 (k = j), the update coefficients (k > j) and, for k < j, the entries
 // v_k . v_j of the Gram matrix that builds T -- so the step has exactly one
 // workgroup barrier.
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 #include "prof.h"
@@ -46,10 +48,148 @@ __device__ __forceinline__ void t_column(FactorSmem &sm, int jj, double tau_jj) 
         const double *z = sm.z[jj & 1];
         for (int q = i + part; q < jj; q += 4) acc = fma(sm.T[i * kLdsStride + q], z[q], acc);
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
+    acc = sum_quad(acc);
     if (part == 0 && i < jj) sm.T[i * kLdsStride + jj] = -tau_jj * acc;
     if (tid == 0) sm.T[jj * kLdsStride + jj] = tau_jj;
+}
+
+// State carried across the column steps of one chunk.
+template <int NS>
+struct StepState {
+    double tau_prev = 0.0;
+    double rnew[NS];     // new R row, written one step late (see below)
+    int jprev = -1;
+};
+
+// Column steps j = 8 TJ .. 8 TJ + 7 (< n) of chunk_qr.  TJ is a template
+// parameter so that the slot index of column j is known at compile time.
+template <int NS, int TJ>
+__device__ __forceinline__ void qr_steps(double (&c)[rows_per_thread(NS)][NS], const int n,
+                                         const bool first, FactorSmem &sm, const bool want_t,
+                                         StepState<NS> &ss) {
+    constexpr int RPT = rows_per_thread(NS);
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63, cg = lane & 7, rgl = lane >> 3;
+    const int rg = w * 8 + rgl;
+    for (int q = 0; q < 8; ++q) {
+        const int j = TJ * 8 + q;
+        if (j >= n) return;
+        const int par = j & 1;
+        // x = column j of this thread's rows (owner lane rg*8 + q)
+        double x[RPT];
+        const int src = (rgl << 3) | q;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) x[i] = __shfl(c[i][TJ], src);
+        // first chunk: row j is the pivot row; its values go to the R row
+        // (reduced as qv) and it is left out of the dots.
+        const bool own_j = first && (rg == (j & 31));
+        const int ij = j >> 5;
+        double qv[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) qv[t] = 0.0;
+        if (own_j) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (i == ij) {
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) qv[t] = c[i][t];
+                    x[i] = 0.0;
+                }
+        }
+        double p[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) s = fma(x[i], c[i][t], s);
+            p[t] = s;
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) p[t] = sum_rowgroups(p[t]);
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            if (rgl == t) sm.red[par][w][cg + 8 * t] = p[t];
+        if (first) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) qv[t] = sum_rowgroups(qv[t]);
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                if (rgl == t) sm.redq[par][w][cg + 8 * t] = qv[t];
+        }
+        __syncthreads();
+        // deferred write of the previous step's R row: every thread has
+        // read that row before this barrier.
+        if (ss.jprev >= 0 && rg == 0) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const int k = cg + 8 * t;
+                if (k >= ss.jprev) sm.R[ss.jprev * kLdsStride + k] = ss.rnew[t];
+            }
+        }
+        double d[NS], e[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int k = cg + 8 * t;
+            d[t] = ((sm.red[par][0][k] + sm.red[par][1][k]) + sm.red[par][2][k]) + sm.red[par][3][k];
+        }
+        const double sig2 =
+            ((sm.red[par][0][j] + sm.red[par][1][j]) + sm.red[par][2][j]) + sm.red[par][3][j];
+        double alpha;
+        if (first) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const int k = cg + 8 * t;
+                e[t] = ((sm.redq[par][0][k] + sm.redq[par][1][k]) + sm.redq[par][2][k]) +
+                       sm.redq[par][3][k];
+            }
+            alpha = ((sm.redq[par][0][j] + sm.redq[par][1][j]) + sm.redq[par][2][j]) +
+                    sm.redq[par][3][j];
+        } else {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) e[t] = sm.R[j * kLdsStride + cg + 8 * t];
+            alpha = sm.R[j * kLdsStride + j];
+        }
+        double beta, tau, s;
+        householder_scalars(alpha, sig2, beta, tau, s);
+        if (want_t && j > 0) t_column(sm, j - 1, ss.tau_prev);
+        // trailing update (k > j), reflector (k == j), Gram entries (k < j)
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int k = cg + 8 * t;
+            if (t < TJ) {
+                if (want_t && rg == 0) sm.z[par][k] = (first ? e[t] : 0.0) + s * d[t];
+                continue;
+            }
+            if (k > j) {
+                const double wv = e[t] + s * d[t];
+                const double f = tau * wv * s;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
+                if (own_j) {
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i)
+                        if (i == ij) c[i][t] = 0.0;
+                }
+                ss.rnew[t] = e[t] - tau * wv;
+            } else if (k == j) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) c[i][t] = s * x[i];
+                ss.rnew[t] = beta;
+            } else {
+                if (want_t && rg == 0) sm.z[par][k] = (first ? e[t] : 0.0) + s * d[t];
+            }
+        }
+        ss.tau_prev = tau;
+        ss.jprev = j;
+    }
+}
+
+template <int NS, int... TJ>
+__device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
+                                             double (&c)[rows_per_thread(NS)][NS], const int n,
+                                             const bool first, FactorSmem &sm, const bool want_t,
+                                             StepState<NS> &ss) {
+    (qr_steps<NS, TJ>(c, n, first, sm, want_t, ss), ...);
 }
 
 // Householder QR of [R; C] (first == false) or of C alone (first == true,
@@ -57,136 +197,22 @@ __device__ __forceinline__ void t_column(FactorSmem &sm, int jj, double tau_jj) 
 // on and above the diagonal of a first chunk, whose unit diagonal is
 // implicit), sm.R the updated triangle and, if want_t, sm.T the chunk's T.
 template <int NS>
-__device__ __forceinline__ void chunk_qr(double (&c)[rows_per_thread(NS)][NS], const int n, const bool first,
-                                         FactorSmem &sm, const bool want_t) {
-    constexpr int RPT = rows_per_thread(NS);
+__device__ __forceinline__ void chunk_qr(double (&c)[rows_per_thread(NS)][NS], const int n,
+                                         const bool first, FactorSmem &sm, const bool want_t) {
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, cg = lane & 7, rgl = lane >> 3;
     const int rg = w * 8 + rgl;
-    double tau_prev = 0.0;
-    double rnew[NS];           // new R row, written one step late (see below)
-    int jprev = -1;
-#pragma unroll
-    for (int tj = 0; tj < NS; ++tj) {
-        for (int q = 0; q < 8; ++q) {
-            const int j = tj * 8 + q;
-            if (j >= n) break;
-            const int par = j & 1;
-            // x = column j of this thread's rows (owner lane rg*8 + q)
-            double x[RPT];
-            const int src = (rgl << 3) | q;
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) x[i] = __shfl(c[i][tj], src);
-            // first chunk: row j is the pivot row; its values go to the R row
-            // (reduced as qv) and it is left out of the dots.
-            const bool own_j = first && (rg == (j & 31));
-            const int ij = j >> 5;
-            double qv[NS];
-#pragma unroll
-            for (int t = 0; t < NS; ++t) qv[t] = 0.0;
-            if (own_j) {
-#pragma unroll
-                for (int i = 0; i < RPT; ++i)
-                    if (i == ij) {
-#pragma unroll
-                        for (int t = 0; t < NS; ++t) qv[t] = c[i][t];
-                        x[i] = 0.0;
-                    }
-            }
-            double p[NS];
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) s = fma(x[i], c[i][t], s);
-                p[t] = sum_rowgroups(s);
-            }
-#pragma unroll
-            for (int t = 0; t < NS; ++t)
-                if (rgl == t) sm.red[par][w][cg + 8 * t] = p[t];
-            if (first) {
-#pragma unroll
-                for (int t = 0; t < NS; ++t) qv[t] = sum_rowgroups(qv[t]);
-#pragma unroll
-                for (int t = 0; t < NS; ++t)
-                    if (rgl == t) sm.redq[par][w][cg + 8 * t] = qv[t];
-            }
-            __syncthreads();
-            // deferred write of the previous step's R row: every thread has
-            // read that row before this barrier.
-            if (jprev >= 0 && rg == 0) {
-#pragma unroll
-                for (int t = 0; t < NS; ++t) {
-                    const int k = cg + 8 * t;
-                    if (k >= jprev) sm.R[jprev * kLdsStride + k] = rnew[t];
-                }
-            }
-            double d[NS], e[NS];
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                const int k = cg + 8 * t;
-                d[t] = ((sm.red[par][0][k] + sm.red[par][1][k]) + sm.red[par][2][k]) + sm.red[par][3][k];
-            }
-            const double sig2 =
-                ((sm.red[par][0][j] + sm.red[par][1][j]) + sm.red[par][2][j]) + sm.red[par][3][j];
-            double alpha;
-            if (first) {
-#pragma unroll
-                for (int t = 0; t < NS; ++t) {
-                    const int k = cg + 8 * t;
-                    e[t] = ((sm.redq[par][0][k] + sm.redq[par][1][k]) + sm.redq[par][2][k]) +
-                           sm.redq[par][3][k];
-                }
-                alpha = ((sm.redq[par][0][j] + sm.redq[par][1][j]) + sm.redq[par][2][j]) +
-                        sm.redq[par][3][j];
-            } else {
-#pragma unroll
-                for (int t = 0; t < NS; ++t) e[t] = sm.R[j * kLdsStride + cg + 8 * t];
-                alpha = sm.R[j * kLdsStride + j];
-            }
-            double beta, tau, s;
-            householder_scalars(alpha, sig2, beta, tau, s);
-            if (want_t && j > 0) t_column(sm, j - 1, tau_prev);
-            // trailing update (k > j), reflector (k == j), Gram entries (k < j)
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                const int k = cg + 8 * t;
-                if (t < tj) {
-                    if (want_t && rg == 0) sm.z[par][k] = (first ? e[t] : 0.0) + s * d[t];
-                    continue;
-                }
-                if (k > j) {
-                    const double wv = e[t] + s * d[t];
-                    const double f = tau * wv * s;
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
-                    if (own_j) {
-#pragma unroll
-                        for (int i = 0; i < RPT; ++i)
-                            if (i == ij) c[i][t] = 0.0;
-                    }
-                    rnew[t] = e[t] - tau * wv;
-                } else if (k == j) {
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i) c[i][t] = s * x[i];
-                    rnew[t] = beta;
-                } else {
-                    if (want_t && rg == 0) sm.z[par][k] = (first ? e[t] : 0.0) + s * d[t];
-                }
-            }
-            tau_prev = tau;
-            jprev = j;
-        }
-    }
+    StepState<NS> ss;
+    qr_all_steps<NS>(std::make_integer_sequence<int, NS>{}, c, n, first, sm, want_t, ss);
     __syncthreads();
-    if (jprev >= 0 && rg == 0) {
+    if (ss.jprev >= 0 && rg == 0) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             const int k = cg + 8 * t;
-            if (k >= jprev) sm.R[jprev * kLdsStride + k] = rnew[t];
+            if (k >= ss.jprev) sm.R[ss.jprev * kLdsStride + k] = ss.rnew[t];
         }
     }
-    if (want_t && jprev >= 0) t_column(sm, jprev, tau_prev);
+    if (want_t && ss.jprev >= 0) t_column(sm, ss.jprev, ss.tau_prev);
     __syncthreads();
 }
 

@@ -1,0 +1,207 @@
+// formq.hip -- the thin Q of a single-panel TSQR (n <= 64) on matrix cores.
+//
+// Q_1 D = Q_full [D; 0] (Sec. 2.2 uniqueness, sign matrix D).  The tree is
+// applied top-down first (Sec. 2.3: the reduction tree is reused for Q):
+// the root block is S_0 = D, and a node (l, r) with reflector block
+// [I; U] and factor T maps its parent block S_l to
+//     S_r = -U T S_l,    S_l <- S_l - T S_l.
+// Each domain then expands its n x n block S_i through its chunks, last
+// chunk first.  A chunk k >= 1 with reflectors [I; V_k] and factor T_k
+// turns the running block X (the domain's top rows) into
+//     rows of chunk k = -V_k (T_k X),   X <- X - T_k X,
+// and the first chunk (unit lower trapezoidal V_0) gives
+//     rows of chunk 0 = [X; 0] - V_0 T_0 (V_0top^T X).
+// The chunk products run as FP64 MFMA tiles in the transposed form
+// Q^T-tile = Z^T V^T, so that every store writes 16 consecutive rows of a
+// column of the column-major Q.
+#include "common.h"
+#include "kernels.h"
+#include "mfma.h"
+#include "prof.h"
+
+namespace tsqr {
+
+constexpr int LD = 64;     // row stride of the 64 x 64 LDS matrices
+
+struct FormSmem {
+    double X[64 * LD];
+    double Z[64 * LD];
+    double T[64 * LD];
+    double W[64 * LD];
+};
+
+// Loads an n x n column-major matrix into a zero-padded 64 x 64 row-major
+// LDS matrix (optionally as a unit-lower-trapezoidal block: diagonal 1,
+// zeros above).
+__device__ __forceinline__ void load_nn(double *dst, const double *__restrict__ src, int64_t lds,
+                                        int n, bool unit_lower) {
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int r = e & 63, c = e >> 6;
+        double v = 0.0;
+        if (r < n && c < n) {
+            v = src[r + (int64_t)c * lds];
+            if (unit_lower) v = (r == c) ? 1.0 : (r > c ? v : 0.0);
+        }
+        dst[r * LD + c] = v;
+    }
+}
+
+__device__ __forceinline__ void store_nn(double *__restrict__ dst, const double *src, int n) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e % n, c = e / n;
+        dst[e] = src[r * LD + c];
+    }
+}
+
+// Top-down tree level for the thin Q: one workgroup per chain.
+__global__ __launch_bounds__(256) void k_tree_down(const double *__restrict__ Rdom,
+                                                   const double *__restrict__ Tnode,
+                                                   double *__restrict__ S, PanelArgs pa, TreeArgs ta) {
+    extern __shared__ double smem_raw[];
+    FormSmem &sm = *reinterpret_cast<FormSmem *>(smem_raw);
+    const int n = pa.n;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t left = (int64_t)blockIdx.x * ta.span;
+    int64_t nr = 0;
+    for (int64_t q = 1; q * ta.stride < ta.span && left + q * ta.stride < pa.P; ++q) ++nr;
+    load_nn(sm.X, S + left * nn, n, n, false);
+    for (int64_t q = nr; q >= 1; --q) {
+        const int64_t right = left + q * ta.stride;
+        __syncthreads();
+        load_nn(sm.T, Tnode + right * nn, n, n, false);
+        load_nn(sm.W, Rdom + right * nn, n, n, false);   // U (upper triangular)
+        __syncthreads();
+        lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);       // Z = T S_l
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) sm.X[e] -= sm.Z[e];
+        lds_gemm64(sm.W, sm.Z, sm.T, LD, true, false, -1.0);      // S_r = -U Z
+        __syncthreads();
+        store_nn(S + right * nn, sm.T, n);
+    }
+    __syncthreads();
+    store_nn(S + left * nn, sm.X, n);
+}
+
+// S_0 = D (n x n, column-major).
+__global__ void k_seed_root(double *S, int n, const double *d) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e % n, c = e / n;
+        S[e] = (r == c) ? d[r] : 0.0;
+    }
+}
+
+// Q = -V Z (+ [X; 0] on a first chunk) for the rows of one chunk; wave w
+// takes the 16-row tiles 4 w .. 4 w + 3 of every 256-row block.
+__device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__restrict__ Vc, int64_t ldv,
+                                          double *__restrict__ Qc, int64_t ldq, int64_t valid, int n,
+                                          bool first) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kbn = (n + 3) >> 2;
+    for (int64_t tile = 4 * w; 16 * tile < valid; tile += (tile % 4 == 3) ? 13 : 1) {
+        const int64_t row = 16 * tile + (lane & 15);
+        double vb[16];
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) {
+            const int col = 4 * kb + (lane >> 4);
+            double v = 0.0;
+            if (kb < kbn && row < valid && col < n) {
+                v = Vc[row + (int64_t)col * ldv];
+                if (first && row <= col) v = (row == col) ? 1.0 : 0.0;
+            }
+            vb[kb] = v;
+        }
+        d4 acc[4];
+#pragma unroll
+        for (int CT = 0; CT < 4; ++CT) acc[CT] = d4_zero();
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) {
+            if (kb >= kbn) break;
+            const double *zr = sm.Z + (4 * kb + (lane >> 4)) * LD + (lane & 15);
+#pragma unroll
+            for (int CT = 0; CT < 4; ++CT) acc[CT] = mfma_f64(zr[16 * CT], vb[kb], acc[CT]);
+        }
+#pragma unroll
+        for (int CT = 0; CT < 4; ++CT)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = 16 * CT + 4 * r + (lane >> 4);
+                if (row < valid && col < n) {
+                    double val = -acc[CT][r];
+                    if (first && row < n) val += sm.X[row * LD + col];
+                    Qc[row + (int64_t)col * ldq] = val;
+                }
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_form_leaf(const double *__restrict__ V, int64_t ldv,
+                                                   const double *__restrict__ Tc,
+                                                   const double *__restrict__ S, PanelArgs pa,
+                                                   double *__restrict__ Q, int64_t ldq) {
+    extern __shared__ double smem_raw[];
+    FormSmem &sm = *reinterpret_cast<FormSmem *>(smem_raw);
+    const int n = pa.n;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t dom = blockIdx.x;
+    const int64_t row0 = dom * pa.mb;
+    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
+    load_nn(sm.X, S + dom * nn, n, n, false);
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+        const int64_t r0 = row0 + ch * pa.chunk;
+        const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
+        const double *Tk = Tc + (dom * pa.cpd + ch) * nn;
+        __syncthreads();
+        if (ch > 0) {
+            load_nn(sm.T, Tk, n, n, false);
+            __syncthreads();
+            lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);    // Z = T_k X
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) sm.X[e] -= sm.Z[e];
+            // chunk_out reads only Z; X is not read for ch > 0
+            chunk_out(sm, V + r0, ldv, Q + r0, ldq, valid, n, false);
+        } else {
+            load_nn(sm.T, V + r0, ldv, n, true);                     // V_0top (unit lower)
+            __syncthreads();
+            lds_gemm64(sm.T, sm.X, sm.W, LD, true, true, 1.0);     // W = V_0top^T X
+            __syncthreads();
+            load_nn(sm.T, Tk, n, n, false);
+            __syncthreads();
+            lds_gemm64(sm.T, sm.W, sm.Z, LD, true, false, 1.0);    // Z = T_0 W
+            __syncthreads();
+            chunk_out(sm, V + r0, ldv, Q + r0, ldq, valid, n, true);
+        }
+    }
+}
+
+static hipError_t set_smem(const void *k) {
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(FormSmem));
+}
+
+hipError_t launch_seed_root(double *S, int n, const double *dsign, hipStream_t st) {
+    ProfScope ps("seed_root", st);
+    hipLaunchKernelGGL(k_seed_root, dim3(1), dim3(256), 0, st, S, n, dsign);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_down(const double *Rdom, const double *Tnode, double *S, const PanelArgs &pa,
+                            const TreeArgs &ta, hipStream_t st) {
+    hipError_t e = set_smem((const void *)k_tree_down);
+    if (e != hipSuccess) return e;
+    ProfScope ps("tree_down", st);
+    hipLaunchKernelGGL(k_tree_down, dim3((unsigned)ta.chains), dim3(256), sizeof(FormSmem), st, Rdom,
+                       Tnode, S, pa, ta);
+    return hipGetLastError();
+}
+
+hipError_t launch_form_leaf(const double *V, int64_t ldv, const double *Tc, const double *S,
+                            const PanelArgs &pa, double *Q, int64_t ldq, hipStream_t st) {
+    hipError_t e = set_smem((const void *)k_form_leaf);
+    if (e != hipSuccess) return e;
+    ProfScope ps("form_leaf", st);
+    hipLaunchKernelGGL(k_form_leaf, dim3((unsigned)pa.P), dim3(256), sizeof(FormSmem), st, V, ldv, Tc, S,
+                       pa, Q, ldq);
+    return hipGetLastError();
+}
+
+}  // namespace tsqr

@@ -47,9 +47,18 @@ hipError_t launch_tree_apply(const double *Rdom, const double *Tnode, const Pane
 // Scale rows [0, n) of B (k columns) by the signs d.
 hipError_t launch_scale_rows(double *B, int64_t ldb, int n, int64_t k, const double *d, hipStream_t st);
 
+// formq.hip: thin Q of a single-panel factorization (n <= 64).
+hipError_t launch_seed_root(double *S, int n, const double *dsign, hipStream_t st);
+hipError_t launch_tree_down(const double *Rdom, const double *Tnode, double *S, const PanelArgs &pa,
+                            const TreeArgs &ta, hipStream_t st);
+hipError_t launch_form_leaf(const double *V, int64_t ldv, const double *Tc, const double *S,
+                            const PanelArgs &pa, double *Q, int64_t ldq, hipStream_t st);
+
 // misc.hip
 hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, const double *d,
                                       hipStream_t st);
+// p[0..count) = value (a kernel, so it is safe inside captured graphs).
+hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t st);
 hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
                        int64_t cols, hipStream_t st);
 hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ldc, int64_t m, int64_t k,

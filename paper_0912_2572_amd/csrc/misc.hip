@@ -18,6 +18,12 @@ __global__ void k_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, 
     }
 }
 
+__global__ void k_fill(double *p, int64_t count, double value) {
+    for (int64_t e = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; e < count;
+         e += (int64_t)blockDim.x * gridDim.x)
+        p[e] = value;
+}
+
 __global__ void k_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
                        int64_t cols) {
     const int64_t total = rows * cols;
@@ -103,6 +109,14 @@ hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, 
                                       hipStream_t st) {
     ProfScope ps("fill_identity", st);
     hipLaunchKernelGGL(k_fill_identity_signs, dim3(2048), dim3(256), 0, st, Q, ldq, m, n, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    ProfScope ps("fill", st);
+    unsigned blocks = (unsigned)((count + 255) / 256 < 2048 ? (count + 255) / 256 : 2048);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, p, count, value);
     return hipGetLastError();
 }
 
