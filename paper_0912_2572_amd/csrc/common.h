@@ -10,10 +10,12 @@ namespace tsqr {
 // reads down a column of the row-major copy hit distinct banks.
 constexpr int kLdsStride = 65;
 
-// Rows per thread of the leaf kernel's register tile for `ns` column slots
-// per thread (8 * ns columns): 64 / ns, capped at 32 so the tile plus its
-// broadcast copy of one column stays in registers.
-__host__ __device__ constexpr int rows_per_thread(int ns) { return ns >= 2 ? 64 / ns : 32; }
+// Leaf register tile: 16 column groups x 4 row groups per wave (lane =
+// 16 rg + cg), `ns` column slots per thread (16 ns columns) and
+// rows_per_thread(ns) rows per thread; 16 row groups per 256-thread
+// workgroup, so a chunk has 16 * rows_per_thread(ns) rows.
+__host__ __device__ constexpr int rows_per_thread(int ns) { return ns >= 2 ? 16 : 32; }
+__host__ __device__ constexpr int chunk_rows(int ns) { return 16 * rows_per_thread(ns); }
 
 // 64-bit lane permutations built from 32-bit DPP / swizzle primitives.
 template <int CTRL>
@@ -33,13 +35,27 @@ constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
 constexpr int kSwizzleXor16 = 0x401F;  // bit mode: and 0x1f, xor 0x10
 
+// v[l & ~16] + v[l | 16] for every lane (exchange across lane bit 4), the
+// same sum in the same order on both lanes of a pair.
+__device__ __forceinline__ double pair_sum16(double v) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+// v[l & ~32] + v[l | 32] (exchange across lane bit 5).
+__device__ __forceinline__ double pair_sum32(double v) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
 // Sum over the 8 lanes that share a column group (lane = rg * 8 + cg), i.e.
-// across lane bits 3..5.  Butterfly with commutative pairwise adds, so every
-// participating lane ends with the bitwise-identical sum.
+// across lane bits 3..5, entirely in the VALU (DPP and permlane swaps).
+// Every participating lane ends with the bitwise-identical sum.
 __device__ __forceinline__ double sum_rowgroups(double v) {
     v += dpp_f64<kDppRowRor8>(v);
-    v += swizzle_f64<kSwizzleXor16>(v);
-    v += __shfl_xor(v, 32);
+    v = pair_sum16(v);
+    v = pair_sum32(v);
     return v;
 }
 

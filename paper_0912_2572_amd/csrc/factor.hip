@@ -2,89 +2,176 @@
 //
 // Leaf (Sec. 2.3, "the factorization of a domain is the operation performed
 // on the leaves"): one 256-thread workgroup per domain.  The domain is
-// streamed from HBM in chunks of `rows` rows that live in registers; the
-// domain's triangle R lives in LDS.  The first chunk gets a plain Householder
-// QR (its top n rows become R); every later chunk C gets the structured QR of
-// [R; C] -- the paper's flat tree (Sec. 2.3) applied inside the domain, so A
-// is read exactly once.  Each chunk leaves its reflectors V in place of the
-// chunk and its compact-WY factor T (Sec. 2.2: H_1...H_n = I - V T V^T).
+// streamed from HBM in chunks that live in registers; the domain's triangle
+// R lives in LDS.  The first chunk gets a plain Householder QR (its top n
+// rows become R); every later chunk C gets the structured QR of [R; C] --
+// the paper's flat tree (Sec. 2.3) applied inside the domain, so A is read
+// exactly once.  Each chunk leaves its reflectors V in place of the chunk
+// and its compact-WY factor T (Sec. 2.2: H_1...H_n = I - V T V^T).
 //
 // Tree (Sec. 2.3): the same structured QR of [R_l; R_r] on the domain
 // triangles, one launch per tree level, one workgroup per chain of combines.
 // The right child's triangle is overwritten by the combine's reflectors and
 // its T is stored under the right child's index.
 //
-// Register layout of a chunk: lane = rg * 8 + cg (cg = column group 0..7,
-// rg = row group 0..7 inside the wave, 32 row groups per workgroup).  A
-// thread owns rows {i * 32 + rg_wg : i < RPT} and columns {cg + 8 t : t < NS},
-// RPT = 64 / NS.  One column step j of Householder QR needs a single
-// reduction: with x = column j, the dots d_k = x . c_k for every column k give
-// ||x||^2 (k = j), the update coefficients (k > j) and, for k < j, the entries
-// v_k . v_j of the Gram matrix that builds T -- so the step has exactly one
-// workgroup barrier.
+// Register tile of a chunk: 256 threads (4 waves); lane = 16 rg + cg (cg =
+// column group 0..15, rg = row group 0..3 inside the wave, 16 row groups per
+// workgroup).  A thread owns rows {16 i + 4 w + rg : i < RPT} and columns
+// {cg + 16 t : t < NS}.  Column step j of Householder QR needs one reduction: with x = column
+// j, the dots d_k = x . c_k for every column k give ||x||^2 (k = j), the
+// update coefficients (k > j) and, for k < j, the Gram entries y_k . y_j
+// that build T.  The reduction over the 4 row groups of a wave runs in the
+// VALU (lane permutes); the 4 waves meet at one barrier per step.
 #include <utility>
 
 #include "common.h"
 #include "kernels.h"
+#include "mfma.h"
 #include "prof.h"
 
 namespace tsqr {
 
+constexpr int kWaves = 4;                  // waves per leaf/tree workgroup
+constexpr int kFactorThreads = 64 * kWaves;
+constexpr int kRowGroups = 4 * kWaves;     // row groups per workgroup
+
+// LDS of the leaf and tree kernels (about 75 KiB).
 struct FactorSmem {
     double R[64 * kLdsStride];   // running triangle, row-major
-    double T[64 * kLdsStride];   // compact-WY T of the current chunk, row-major
-    double red[2][4][64];        // per-wave partial dots, double-buffered
-    double redq[2][4][64];       // per-wave row-j values (first chunk only)
-    double z[2][64];             // Gram column for T, double-buffered
+    double T[64 * kLdsStride];   // upper: T of the chunk; strictly lower: Gram G^T
+    union {
+        struct {
+            double red[2][64][kWaves];    // per-wave partial dots, double-buffered
+            double redq[2][64][kWaves];   // per-wave pivot-row values (first chunk only)
+        } s;
+        double P[64 * 16];                // scratch of the blocked T build
+    } u;
+    double tau[64];
 };
 
-// T[i][jj] = -tau_jj * sum_{q=i}^{jj-1} T[i][q] z_q (Schreiber-Van Loan
-// accumulation of the compact-WY factor, Sec. 2.2).  Four threads per row i.
-__device__ __forceinline__ void t_column(FactorSmem &sm, int jj, double tau_jj) {
-    const int tid = threadIdx.x;
-    const int i = tid >> 2, part = tid & 3;
-    double acc = 0.0;
-    if (i < jj) {
-        const double *z = sm.z[jj & 1];
-        for (int q = i + part; q < jj; q += 4) acc = fma(sm.T[i * kLdsStride + q], z[q], acc);
+// Gram entry G[k][j] = y_k . y_j (k < j), kept in the lower triangle of T.
+__device__ __forceinline__ double &gram(FactorSmem &sm, int k, int j) { return sm.T[j * kLdsStride + k]; }
+
+// Compact-WY factor T of the chunk (Sec. 2.2: H_1...H_n = I - V T V^T),
+// built once per chunk from tau and the Gram matrix G = Y^T Y by the
+// forward (Schreiber-Van Loan) recurrence T[0:j, j] = -tau_j T[0:j, 0:j]
+// G[0:j, j], T_jj = tau_j, in 16-column blocks: wave J runs the recurrence
+// inside diagonal block J in registers, then the off-diagonal blocks follow
+// from the block form of the same recurrence,
+//     T[0:16J, J] = -T[0:16J, 0:16J] (G[0:16J, J] T_JJ),
+// as FP64 MFMA tiles.
+__device__ __forceinline__ void build_t(FactorSmem &sm, const int n) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j0 = 16 * w;
+    double trow[16];
+    const int i = lane & 15;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) trow[q] = 0.0;
+    if (j0 < n) {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = j0 + jj;
+            if (j < n) {
+                const double tj = sm.tau[j];
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < jj; ++q) acc = fma(trow[q], gram(sm, j0 + q, j), acc);
+                trow[jj] = (i < jj) ? -tj * acc : ((i == jj) ? tj : 0.0);
+            }
+        }
     }
-    acc = sum_quad(acc);
-    if (part == 0 && i < jj) sm.T[i * kLdsStride + jj] = -tau_jj * acc;
-    if (tid == 0) sm.T[jj * kLdsStride + jj] = tau_jj;
+    __syncthreads();   // every wave has read its Gram block before T overwrites
+    if (j0 < n && lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (q >= i) sm.T[(j0 + i) * kLdsStride + j0 + q] = trow[q];
+    }
+    __syncthreads();
+    for (int J = 1; J < 4 && 16 * J < n; ++J) {
+        if (w < J) {   // P[16w : 16w + 16, :] = G[16w.., J block] T_JJ
+            d4 acc = d4_zero();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const int kk = 4 * kb + (lane >> 4), jj = lane & 15;
+                const int k = 16 * J + kk;
+                const double t = (kk <= jj) ? sm.T[k * kLdsStride + 16 * J + jj] : 0.0;
+                acc = mfma_f64(gram(sm, 16 * w + (lane & 15), k), t, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.u.P[(16 * w + d_row(r, lane)) * 16 + d_col(lane)] = acc[r];
+        }
+        __syncthreads();
+        if (w < J) {   // T[16w.., J block] = -T[16w.., 0:16J] P
+            d4 acc = d4_zero();
+            const int row = 16 * w + (lane & 15);
+            for (int kb = 4 * w; kb < 4 * J; ++kb) {
+                const int k = 4 * kb + (lane >> 4);
+                const double t = (k >= row) ? sm.T[row * kLdsStride + k] : 0.0;
+                acc = mfma_f64(t, sm.u.P[k * 16 + (lane & 15)], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sm.T[(16 * w + d_row(r, lane)) * kLdsStride + 16 * J + d_col(lane)] = -acc[r];
+        }
+        __syncthreads();
+    }
 }
 
 // State carried across the column steps of one chunk.
 template <int NS>
 struct StepState {
-    double tau_prev = 0.0;
-    double rnew[NS];     // new R row, written one step late (see below)
+    double rnew[NS];                    // new R row, written one step late
+    double xa[rows_per_thread(NS)];     // current / next column (ping-pong)
+    double xb[rows_per_thread(NS)];
     int jprev = -1;
 };
 
-// Column steps j = 8 TJ .. 8 TJ + 7 (< n) of chunk_qr.  TJ is a template
-// parameter so that the slot index of column j is known at compile time.
-template <int NS, int TJ>
-__device__ __forceinline__ void qr_steps(double (&c)[rows_per_thread(NS)][NS], const int n,
-                                         const bool first, FactorSmem &sm, const bool want_t,
-                                         StepState<NS> &ss) {
+// Sum over the waves' partials of column k, in a fixed order.  The
+// scheduling barrier keeps the compiler from hoisting every column's loads
+// at once (which would spill the register tile).
+__device__ __forceinline__ double sum_waves(const double (&a)[2][64][kWaves], int par, int k) {
+    const double2 *p = reinterpret_cast<const double2 *>(&a[par][k][0]);
+    double2 v[kWaves / 2];
+#pragma unroll
+    for (int h = 0; h < kWaves / 2; ++h) v[h] = p[h];
+    double s = v[0].x + v[0].y;
+#pragma unroll
+    for (int h = 1; h < kWaves / 2; ++h) s = (s + v[h].x) + v[h].y;
+    __builtin_amdgcn_sched_barrier(0);
+    return s;
+}
+
+// Column step j (= 16 TJ + q) of chunk_qr.  TJ is a template parameter so
+// that the slot index of column j is known at compile time.
+//
+// With x = column j (rows of a first chunk above the pivot are 0, the pivot
+// row itself is left out), one reduction gives d_k = x . c_k for every
+// column k; then with alpha (the R entry or the pivot value) the Householder
+// scalars follow and
+//     k > j:  w = e_k + s d_k,  c_k -= tau w s x,  R[j][k] = e_k - tau w
+//     k = j:  v_j = s x,  R[j][j] = beta
+//     k < j:  G[k][j] = y_k . y_j = (pivot-row value) + s d_k.
+// The next column's pre-update values are fetched into xn from their owner
+// lanes before the barrier, and every thread applies step j's update to
+// them itself (the same fma as the owner), so the next step needs no
+// shuffle on its critical path.
+template <int NS, int TJ, bool FIRST>
+__device__ __forceinline__ void one_step(const int j, const int q, double (&c)[rows_per_thread(NS)][NS],
+                                         const int n, FactorSmem &sm, const bool want_t,
+                                         double (&x)[rows_per_thread(NS)],
+                                         double (&xn)[rows_per_thread(NS)], double (&rnew)[NS],
+                                         int &jprev) {
     constexpr int RPT = rows_per_thread(NS);
     const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63, cg = lane & 7, rgl = lane >> 3;
-    const int rg = w * 8 + rgl;
-    for (int q = 0; q < 8; ++q) {
-        const int j = TJ * 8 + q;
-        if (j >= n) return;
-        const int par = j & 1;
-        // x = column j of this thread's rows (owner lane rg*8 + q)
-        double x[RPT];
-        const int src = (rgl << 3) | q;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) x[i] = __shfl(c[i][TJ], src);
-        // first chunk: row j is the pivot row; its values go to the R row
-        // (reduced as qv) and it is left out of the dots.
-        const bool own_j = first && (rg == (j & 31));
-        const int ij = j >> 5;
-        double qv[NS];
+    const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int rgw = w * 4 + rg;
+    const int par = j & 1;
+    // first chunk: row j is the pivot row, reduced separately (qv) and left
+    // out of the dots.
+    const bool own_j = FIRST && (rgw == (j % kRowGroups));
+    const int ij = j / kRowGroups;
+    double qv[NS];
+    if (FIRST) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) qv[t] = 0.0;
         if (own_j) {
@@ -96,164 +183,206 @@ __device__ __forceinline__ void qr_steps(double (&c)[rows_per_thread(NS)][NS], c
                     x[i] = 0.0;
                 }
         }
-        double p[NS];
+    }
+    // prefetch column j + 1 (pre-update) from its owner lane
+    if (q < 15) {
+        const int src = (rg << 4) | (q + 1);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) xn[i] = __shfl(c[i][TJ], src);
+    } else if constexpr (TJ + 1 < NS) {
+        const int src = rg << 4;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) xn[i] = __shfl(c[i][TJ + 1], src);
+    } else {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) xn[i] = 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; i += 2) {
+            s0 = fma(x[i], c[i][t], s0);
+            s1 = fma(x[i + 1], c[i + 1][t], s1);
+        }
+        const double p = pair_sum32(pair_sum16(s0 + s1));
+        if (rg == t) sm.u.s.red[par][cg + 16 * t][w] = p;
+    }
+    if (FIRST) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) s = fma(x[i], c[i][t], s);
-            p[t] = s;
+            const double p = pair_sum32(pair_sum16(qv[t]));
+            if (rg == t) sm.u.s.redq[par][cg + 16 * t][w] = p;
         }
-#pragma unroll
-        for (int t = 0; t < NS; ++t) p[t] = sum_rowgroups(p[t]);
-#pragma unroll
-        for (int t = 0; t < NS; ++t)
-            if (rgl == t) sm.red[par][w][cg + 8 * t] = p[t];
-        if (first) {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) qv[t] = sum_rowgroups(qv[t]);
-#pragma unroll
-            for (int t = 0; t < NS; ++t)
-                if (rgl == t) sm.redq[par][w][cg + 8 * t] = qv[t];
-        }
-        __syncthreads();
-        // deferred write of the previous step's R row: every thread has
-        // read that row before this barrier.
-        if (ss.jprev >= 0 && rg == 0) {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                const int k = cg + 8 * t;
-                if (k >= ss.jprev) sm.R[ss.jprev * kLdsStride + k] = ss.rnew[t];
-            }
-        }
-        double d[NS], e[NS];
+    }
+    __syncthreads();
+    // deferred write of the previous step's R row: every thread has read
+    // that row before this barrier.
+    if (jprev >= 0 && rgw == 0) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            const int k = cg + 8 * t;
-            d[t] = ((sm.red[par][0][k] + sm.red[par][1][k]) + sm.red[par][2][k]) + sm.red[par][3][k];
+            const int k = cg + 16 * t;
+            if (k >= jprev) sm.R[jprev * kLdsStride + k] = rnew[t];
         }
-        const double sig2 =
-            ((sm.red[par][0][j] + sm.red[par][1][j]) + sm.red[par][2][j]) + sm.red[par][3][j];
-        double alpha;
-        if (first) {
+    }
+    const double sig2 = sum_waves(sm.u.s.red, par, j);
+    const bool has_next = j + 1 < n;
+    const double dn = has_next ? sum_waves(sm.u.s.red, par, j + 1) : 0.0;
+    double alpha, en = 0.0;
+    if (FIRST) {
+        alpha = sum_waves(sm.u.s.redq, par, j);
+        if (has_next) en = sum_waves(sm.u.s.redq, par, j + 1);
+    } else {
+        alpha = sm.R[j * kLdsStride + j];
+        if (has_next) en = sm.R[j * kLdsStride + j + 1];
+    }
+    double beta, tau, s;
+    householder_scalars(alpha, sig2, beta, tau, s);
+    // the next column after this step's update (same fma as its owner)
+    {
+        const double fn = (tau * fma(s, dn, en)) * s;
 #pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                const int k = cg + 8 * t;
-                e[t] = ((sm.redq[par][0][k] + sm.redq[par][1][k]) + sm.redq[par][2][k]) +
-                       sm.redq[par][3][k];
+        for (int i = 0; i < RPT; ++i) xn[i] = fma(-fn, x[i], xn[i]);
+        if (own_j) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (i == ij) xn[i] = 0.0;
+        }
+    }
+    // trailing update (k > j), reflector (k == j), Gram entries (k < j)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int k = cg + 16 * t;
+        const double d = sum_waves(sm.u.s.red, par, k);
+        const double e = FIRST ? sum_waves(sm.u.s.redq, par, k) : sm.R[j * kLdsStride + k];
+        if (t < TJ) {
+            if (want_t && rgw == 0) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
+            continue;
+        }
+        if (k > j) {
+            const double wv = fma(s, d, e);
+            const double f = (tau * wv) * s;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
+            if (own_j) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (i == ij) c[i][t] = 0.0;
             }
-            alpha = ((sm.redq[par][0][j] + sm.redq[par][1][j]) + sm.redq[par][2][j]) +
-                    sm.redq[par][3][j];
+            rnew[t] = e - tau * wv;
+        } else if (k == j) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) c[i][t] = s * x[i];
+            rnew[t] = beta;
         } else {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) e[t] = sm.R[j * kLdsStride + cg + 8 * t];
-            alpha = sm.R[j * kLdsStride + j];
+            if (want_t && rgw == 0) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
         }
-        double beta, tau, s;
-        householder_scalars(alpha, sig2, beta, tau, s);
-        if (want_t && j > 0) t_column(sm, j - 1, ss.tau_prev);
-        // trailing update (k > j), reflector (k == j), Gram entries (k < j)
-#pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            const int k = cg + 8 * t;
-            if (t < TJ) {
-                if (want_t && rg == 0) sm.z[par][k] = (first ? e[t] : 0.0) + s * d[t];
-                continue;
-            }
-            if (k > j) {
-                const double wv = e[t] + s * d[t];
-                const double f = tau * wv * s;
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
-                if (own_j) {
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i)
-                        if (i == ij) c[i][t] = 0.0;
-                }
-                ss.rnew[t] = e[t] - tau * wv;
-            } else if (k == j) {
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) c[i][t] = s * x[i];
-                ss.rnew[t] = beta;
-            } else {
-                if (want_t && rg == 0) sm.z[par][k] = (first ? e[t] : 0.0) + s * d[t];
-            }
-        }
-        ss.tau_prev = tau;
-        ss.jprev = j;
+    }
+    if (tid == 0) sm.tau[j] = tau;
+    jprev = j;
+}
+
+// Column steps j = 16 TJ .. 16 TJ + 15 (< n), two at a time so that the
+// current and next column buffers swap roles without copies.
+template <int NS, int TJ, bool FIRST>
+__device__ __forceinline__ void qr_steps(double (&c)[rows_per_thread(NS)][NS], const int n,
+                                         FactorSmem &sm, const bool want_t, StepState<NS> &ss) {
+#pragma unroll 1
+    for (int q = 0; q < 16; q += 2) {
+        const int j = TJ * 16 + q;
+        if (j >= n) return;
+        one_step<NS, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
+        if (j + 1 >= n) return;
+        one_step<NS, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
     }
 }
 
-template <int NS, int... TJ>
+template <int NS, bool FIRST, int... TJ>
 __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
                                              double (&c)[rows_per_thread(NS)][NS], const int n,
-                                             const bool first, FactorSmem &sm, const bool want_t,
-                                             StepState<NS> &ss) {
-    (qr_steps<NS, TJ>(c, n, first, sm, want_t, ss), ...);
+                                             FactorSmem &sm, const bool want_t, StepState<NS> &ss) {
+    (qr_steps<NS, TJ, FIRST>(c, n, sm, want_t, ss), ...);
 }
 
-// Householder QR of [R; C] (first == false) or of C alone (first == true,
+// Householder QR of [R; C] (FIRST == false) or of C alone (FIRST == true,
 // rows 0..n-1 of C become R).  On exit c holds the reflector tails V (zeros
 // on and above the diagonal of a first chunk, whose unit diagonal is
-// implicit), sm.R the updated triangle and, if want_t, sm.T the chunk's T.
-template <int NS>
+// implicit), sm.R the updated triangle and, if want_t, the upper triangle
+// of sm.T the chunk's T.
+template <int NS, bool FIRST>
 __device__ __forceinline__ void chunk_qr(double (&c)[rows_per_thread(NS)][NS], const int n,
-                                         const bool first, FactorSmem &sm, const bool want_t) {
+                                         FactorSmem &sm, const bool want_t) {
+    constexpr int RPT = rows_per_thread(NS);
     const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63, cg = lane & 7, rgl = lane >> 3;
-    const int rg = w * 8 + rgl;
+    const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int rgw = w * 4 + rg;
     StepState<NS> ss;
-    qr_all_steps<NS>(std::make_integer_sequence<int, NS>{}, c, n, first, sm, want_t, ss);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
+    qr_all_steps<NS, FIRST>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss);
     __syncthreads();
-    if (ss.jprev >= 0 && rg == 0) {
+    if (ss.jprev >= 0 && rgw == 0) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            const int k = cg + 8 * t;
+            const int k = cg + 16 * t;
             if (k >= ss.jprev) sm.R[ss.jprev * kLdsStride + k] = ss.rnew[t];
         }
     }
-    if (want_t && ss.jprev >= 0) t_column(sm, ss.jprev, ss.tau_prev);
-    __syncthreads();
 }
 
-// Loads rows [0, valid) x columns [0, n) of a chunk at src (ld) into c.
+// Loads rows [0, valid) x columns [0, n) of a chunk at src (ld) into c
+// (zeros elsewhere).  A full chunk takes one base address per column slot
+// plus immediate row offsets, so no per-element address stays live.
 template <int NS>
-__device__ __forceinline__ void load_chunk(double (&c)[rows_per_thread(NS)][NS], const double *__restrict__ src,
-                                           int64_t ld, int64_t valid, int n) {
+__device__ __forceinline__ void load_chunk(double (&c)[rows_per_thread(NS)][NS],
+                                           const double *__restrict__ src, int64_t ld, int64_t valid,
+                                           int n) {
     constexpr int RPT = rows_per_thread(NS);
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 7, rgl = lane >> 3;
-    const int rg = w * 8 + rgl;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int rgw = w * 4 + rg;
+    const bool full = valid >= (int64_t)RPT * kRowGroups;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int64_t r = (int64_t)i * 32 + rg;
+    for (int t = 0; t < NS; ++t) {
+        const int k = cg + 16 * t;
+        const double *p = src + rgw + (int64_t)k * ld;
+        if (k < n && full) {
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            const int k = cg + 8 * t;
-            c[i][t] = (r < valid && k < n) ? src[r + (int64_t)k * ld] : 0.0;
+            for (int i = 0; i < RPT; ++i) c[i][t] = __builtin_nontemporal_load(p + i * kRowGroups);
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                c[i][t] = (k < n && i * kRowGroups + rgw < valid) ? p[i * kRowGroups] : 0.0;
         }
     }
 }
 
 template <int NS>
-__device__ __forceinline__ void store_chunk(const double (&c)[rows_per_thread(NS)][NS], double *__restrict__ dst,
-                                            int64_t ld, int64_t valid, int n) {
+__device__ __forceinline__ void store_chunk(const double (&c)[rows_per_thread(NS)][NS],
+                                            double *__restrict__ dst, int64_t ld, int64_t valid, int n) {
     constexpr int RPT = rows_per_thread(NS);
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 7, rgl = lane >> 3;
-    const int rg = w * 8 + rgl;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int rgw = w * 4 + rg;
+    const bool full = valid >= (int64_t)RPT * kRowGroups;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int64_t r = (int64_t)i * 32 + rg;
+    for (int t = 0; t < NS; ++t) {
+        const int k = cg + 16 * t;
+        double *p = dst + rgw + (int64_t)k * ld;
+        if (k < n && full) {
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            const int k = cg + 8 * t;
-            if (r < valid && k < n) dst[r + (int64_t)k * ld] = c[i][t];
+            for (int i = 0; i < RPT; ++i) p[i * kRowGroups] = c[i][t];
+        } else if (k < n) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (i * kRowGroups + rgw < valid) p[i * kRowGroups] = c[i][t];
         }
     }
 }
 
+// Upper triangle of an LDS matrix (row-major) -> column-major n x n with
+// zeros below the diagonal.
 __device__ __forceinline__ void store_tri(const double *lds, double *__restrict__ dst, int n) {
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e % n, k = e / n;     // column-major n x n
+        const int r = e % n, k = e / n;
         dst[e] = (r <= k) ? lds[r * kLdsStride + k] : 0.0;
     }
 }
@@ -263,18 +392,19 @@ __device__ __forceinline__ void zero_lds(double *lds) {
 }
 
 template <int NS>
-__global__ __launch_bounds__(256) void k_leaf(const double *__restrict__ A, int64_t lda,
-                                              double *__restrict__ V, int64_t ldv,
-                                              double *__restrict__ Tc, double *__restrict__ Rdom,
-                                              PanelArgs pa, int keep_q) {
+__global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restrict__ A, int64_t lda,
+                                                 double *__restrict__ V, int64_t ldv,
+                                                 double *__restrict__ Tc, double *__restrict__ Rdom,
+                                                 PanelArgs pa, int keep_q) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
-    constexpr int ROWS = 32 * rows_per_thread(NS);
+    constexpr int ROWS = chunk_rows(NS);
     const int64_t dom = blockIdx.x;
     const int64_t row0 = dom * pa.mb;
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
     const int64_t nch = (nrows + ROWS - 1) / ROWS;
     const int n = pa.n;
+    const bool want_t = keep_q != 0;
     zero_lds(sm.R);
     zero_lds(sm.T);
     __syncthreads();
@@ -283,12 +413,14 @@ __global__ __launch_bounds__(256) void k_leaf(const double *__restrict__ A, int6
         const int64_t r0 = row0 + ch * ROWS;
         const int64_t valid = (nrows - ch * ROWS < ROWS) ? nrows - ch * ROWS : ROWS;
         load_chunk<NS>(c, A + r0, lda, valid, n);
-        chunk_qr<NS>(c, n, ch == 0, sm, keep_q != 0);
-        if (keep_q) {
+        if (ch == 0) chunk_qr<NS, true>(c, n, sm, want_t);
+        else chunk_qr<NS, false>(c, n, sm, want_t);
+        if (want_t) {
             store_chunk<NS>(c, V + r0, ldv, valid, n);
+            build_t(sm, n);
             store_tri(sm.T, Tc + (dom * pa.cpd + ch) * (int64_t)n * n, n);
-            __syncthreads();
         }
+        __syncthreads();
     }
     store_tri(sm.R, Rdom + dom * (int64_t)n * n, n);
 }
@@ -296,13 +428,14 @@ __global__ __launch_bounds__(256) void k_leaf(const double *__restrict__ A, int6
 // One chain of combines per workgroup: left <- qr([R_left; R_right]) for
 // every right of the chain, in order.
 template <int NS>
-__global__ __launch_bounds__(256) void k_tree(double *__restrict__ Rdom, double *__restrict__ Tnode,
-                                              PanelArgs pa, TreeArgs ta, int keep_q) {
+__global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rdom, double *__restrict__ Tnode,
+                                                 PanelArgs pa, TreeArgs ta, int keep_q) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
     const int n = pa.n;
     const int64_t nn = (int64_t)n * n;
     const int64_t left = (int64_t)blockIdx.x * ta.span;
+    const bool want_t = keep_q != 0;
     zero_lds(sm.R);
     zero_lds(sm.T);
     __syncthreads();
@@ -316,10 +449,13 @@ __global__ __launch_bounds__(256) void k_tree(double *__restrict__ Rdom, double 
         const int64_t right = left + q * ta.stride;
         if (right >= pa.P) break;
         load_chunk<NS>(c, Rdom + right * nn, n, n, n);
-        chunk_qr<NS>(c, n, false, sm, keep_q != 0);
+        chunk_qr<NS, false>(c, n, sm, want_t);
         // the right triangle becomes the node's reflector block U
         store_chunk<NS>(c, Rdom + right * nn, n, n, n);
-        if (keep_q) store_tri(sm.T, Tnode + right * nn, n);
+        if (want_t) {
+            build_t(sm, n);
+            store_tri(sm.T, Tnode + right * nn, n);
+        }
         __syncthreads();
     }
     store_tri(sm.R, Rdom + left * nn, n);
@@ -327,15 +463,13 @@ __global__ __launch_bounds__(256) void k_tree(double *__restrict__ Rdom, double 
 
 // R_out = D R_root with D = diag(sgn R_jj), sgn(0) = +1; d_out = diag(D).
 __global__ void k_sign_normalise(const double *__restrict__ Rroot, int n, double *__restrict__ Rout,
-                                 int64_t ldr, int row_off, int col_off, int nfull,
-                                 double *__restrict__ dsign) {
+                                 int64_t ldr, int row_off, int col_off, double *__restrict__ dsign) {
     for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < n * n; e += blockDim.x * gridDim.x) {
         const int r = e % n, k = e / n;
         const double dr = (Rroot[r + r * n] < 0.0) ? -1.0 : 1.0;
         Rout[(row_off + r) + (int64_t)(col_off + k) * ldr] = (r <= k) ? dr * Rroot[e] : 0.0;
         if (k == 0) dsign[row_off + r] = dr;
     }
-    (void)nfull;
 }
 
 size_t factor_smem_bytes() { return sizeof(FactorSmem); }
@@ -348,7 +482,7 @@ static hipError_t launch_leaf_ns(const double *A, int64_t lda, double *V, int64_
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     ProfScope ps("leaf_factor", st);
-    hipLaunchKernelGGL(k_leaf<NS>, dim3((unsigned)pa.P), dim3(256), sh, st, A, lda, V, ldv, Tc, Rdom,
+    hipLaunchKernelGGL(k_leaf<NS>, dim3((unsigned)pa.P), dim3(kFactorThreads), sh, st, A, lda, V, ldv, Tc, Rdom,
                        pa, keep_q);
     return hipGetLastError();
 }
@@ -358,8 +492,7 @@ hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, dou
     switch (pa.ns) {
         case 1: return launch_leaf_ns<1>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
         case 2: return launch_leaf_ns<2>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
-        case 4: return launch_leaf_ns<4>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
-        default: return launch_leaf_ns<8>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
+        default: return launch_leaf_ns<4>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
     }
 }
 
@@ -371,19 +504,18 @@ static hipError_t launch_tree_ns(double *Rdom, double *Tnode, const PanelArgs &p
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     ProfScope ps("tree_factor", st);
-    hipLaunchKernelGGL(k_tree<NS>, dim3((unsigned)ta.chains), dim3(256), sh, st, Rdom, Tnode, pa, ta,
+    hipLaunchKernelGGL(k_tree<NS>, dim3((unsigned)ta.chains), dim3(kFactorThreads), sh, st, Rdom, Tnode, pa, ta,
                        keep_q);
     return hipGetLastError();
 }
 
 hipError_t launch_tree_level(double *Rdom, double *Tnode, const PanelArgs &pa, const TreeArgs &ta,
                              int keep_q, hipStream_t st) {
-    // the tree tile must hold n rows: 32 * rows_per_thread(NS) >= 64 >= n
+    // the tree tile must hold n rows: chunk_rows(NS) >= 256 > 64 >= n
     switch (pa.ns) {
         case 1: return launch_tree_ns<1>(Rdom, Tnode, pa, ta, keep_q, st);
         case 2: return launch_tree_ns<2>(Rdom, Tnode, pa, ta, keep_q, st);
-        case 4: return launch_tree_ns<4>(Rdom, Tnode, pa, ta, keep_q, st);
-        default: return launch_tree_ns<8>(Rdom, Tnode, pa, ta, keep_q, st);
+        default: return launch_tree_ns<4>(Rdom, Tnode, pa, ta, keep_q, st);
     }
 }
 
@@ -391,7 +523,7 @@ hipError_t launch_sign_normalise(const double *Rroot, int n, double *Rout, int64
                                  int col_off, double *dsign, hipStream_t st) {
     ProfScope ps("sign_normalise", st);
     hipLaunchKernelGGL(k_sign_normalise, dim3(16), dim3(256), 0, st, Rroot, n, Rout, ldr, row_off,
-                       col_off, 0, dsign);
+                       col_off, dsign);
     return hipGetLastError();
 }
 

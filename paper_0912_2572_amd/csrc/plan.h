@@ -17,18 +17,19 @@ constexpr int kMaxN = 256;        // documented scope
 constexpr int kThreads = 256;     // threads per workgroup of the leaf kernel
 constexpr size_t kAlign = 256;
 
-// Column slots per thread of the leaf kernel for a panel of width w:
-// 8 column groups x ns slots must cover w.  Rows per thread = 64 / ns (32
-// for ns = 1), and a chunk holds 32 row groups x rows-per-thread rows.
+// Column slots per thread of the leaf kernel for a panel of width w: 16
+// column groups x ns slots must cover w (ns = 1, 2 or 4).  Rows per thread
+// are 32 for ns = 1 and 16 otherwise; a chunk holds 16 row groups x rows
+// per thread (the same constants as the device tile in common.h).
 inline int slots_for(int w) {
-    int need = (w + 7) / 8;
+    int need = (w + 15) / 16;
     int ns = 1;
     while (ns < need) ns <<= 1;
     return ns;
 }
 inline int chunk_rows_for(int w) {
     int ns = slots_for(w);
-    return 32 * (ns >= 2 ? 64 / ns : 32);   // 32 row groups x rows per thread
+    return 16 * (ns >= 2 ? 16 : 32);
 }
 
 // One TSQR over rows [row_off, row_off + m) and columns [col_off, col_off+n)
