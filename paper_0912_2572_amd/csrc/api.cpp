@@ -63,7 +63,7 @@ int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int
     const double *Tnode = at<double>(f, p.off_tnode);
     auto levels = tsqr::tree_levels(p.P, p.tree);
     if (trans) {
-        TRY(tsqr::launch_leaf_apply(V, P.m, Tc, pa, Bsrc, ldbs, B, ldb, k, 1, st));
+        TRY(tsqr::launch_leaf_apply_m(V, P.m, Tc, pa, Bsrc, ldbs, B, ldb, k, 1, st));
         for (const auto &L : levels) {
             TreeArgs ta{L.stride, L.span, L.chains};
             TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 1, st));
@@ -74,7 +74,7 @@ int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int
             TreeArgs ta{it->stride, it->span, it->chains};
             TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 0, st));
         }
-        TRY(tsqr::launch_leaf_apply(V, P.m, Tc, pa, B, ldb, B, ldb, k, 0, st));
+        TRY(tsqr::launch_leaf_apply_m(V, P.m, Tc, pa, B, ldb, B, ldb, k, 0, st));
     }
     return 0;
 }

@@ -118,11 +118,11 @@ __device__ __forceinline__ void build_t(FactorSmem &sm, const int n) {
 }
 
 // State carried across the column steps of one chunk.
-template <int NS>
+template <int NS, int RPT>
 struct StepState {
-    double rnew[NS];                    // new R row, written one step late
-    double xa[rows_per_thread(NS)];     // current / next column (ping-pong)
-    double xb[rows_per_thread(NS)];
+    double rnew[NS];     // new R row, written one step late
+    double xa[RPT];      // current / next column (ping-pong)
+    double xb[RPT];
     int jprev = -1;
 };
 
@@ -155,13 +155,11 @@ __device__ __forceinline__ double sum_waves(const double (&a)[2][64][kWaves], in
 // lanes before the barrier, and every thread applies step j's update to
 // them itself (the same fma as the owner), so the next step needs no
 // shuffle on its critical path.
-template <int NS, int TJ, bool FIRST>
-__device__ __forceinline__ void one_step(const int j, const int q, double (&c)[rows_per_thread(NS)][NS],
+template <int NS, int RPT, int TJ, bool FIRST>
+__device__ __forceinline__ void one_step(const int j, const int q, double (&c)[RPT][NS],
                                          const int n, FactorSmem &sm, const bool want_t,
-                                         double (&x)[rows_per_thread(NS)],
-                                         double (&xn)[rows_per_thread(NS)], double (&rnew)[NS],
+                                         double (&x)[RPT], double (&xn)[RPT], double (&rnew)[NS],
                                          int &jprev) {
-    constexpr int RPT = rows_per_thread(NS);
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
@@ -284,24 +282,24 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[r
 
 // Column steps j = 16 TJ .. 16 TJ + 15 (< n), two at a time so that the
 // current and next column buffers swap roles without copies.
-template <int NS, int TJ, bool FIRST>
-__device__ __forceinline__ void qr_steps(double (&c)[rows_per_thread(NS)][NS], const int n,
-                                         FactorSmem &sm, const bool want_t, StepState<NS> &ss) {
+template <int NS, int RPT, int TJ, bool FIRST>
+__device__ __forceinline__ void qr_steps(double (&c)[RPT][NS], const int n, FactorSmem &sm,
+                                         const bool want_t, StepState<NS, RPT> &ss) {
 #pragma unroll 1
     for (int q = 0; q < 16; q += 2) {
         const int j = TJ * 16 + q;
         if (j >= n) return;
-        one_step<NS, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
+        one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
         if (j + 1 >= n) return;
-        one_step<NS, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
+        one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
     }
 }
 
-template <int NS, bool FIRST, int... TJ>
+template <int NS, int RPT, bool FIRST, int... TJ>
 __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
-                                             double (&c)[rows_per_thread(NS)][NS], const int n,
-                                             FactorSmem &sm, const bool want_t, StepState<NS> &ss) {
-    (qr_steps<NS, TJ, FIRST>(c, n, sm, want_t, ss), ...);
+                                             double (&c)[RPT][NS], const int n, FactorSmem &sm,
+                                             const bool want_t, StepState<NS, RPT> &ss) {
+    (qr_steps<NS, RPT, TJ, FIRST>(c, n, sm, want_t, ss), ...);
 }
 
 // Householder QR of [R; C] (FIRST == false) or of C alone (FIRST == true,
@@ -309,17 +307,16 @@ __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
 // on and above the diagonal of a first chunk, whose unit diagonal is
 // implicit), sm.R the updated triangle and, if want_t, the upper triangle
 // of sm.T the chunk's T.
-template <int NS, bool FIRST>
-__device__ __forceinline__ void chunk_qr(double (&c)[rows_per_thread(NS)][NS], const int n,
+template <int NS, int RPT, bool FIRST>
+__device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
                                          FactorSmem &sm, const bool want_t) {
-    constexpr int RPT = rows_per_thread(NS);
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
-    StepState<NS> ss;
+    StepState<NS, RPT> ss;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
-    qr_all_steps<NS, FIRST>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss);
+    qr_all_steps<NS, RPT, FIRST>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss);
     __syncthreads();
     if (ss.jprev >= 0 && rgw == 0) {
 #pragma unroll
@@ -333,11 +330,10 @@ __device__ __forceinline__ void chunk_qr(double (&c)[rows_per_thread(NS)][NS], c
 // Loads rows [0, valid) x columns [0, n) of a chunk at src (ld) into c
 // (zeros elsewhere).  A full chunk takes one base address per column slot
 // plus immediate row offsets, so no per-element address stays live.
-template <int NS>
-__device__ __forceinline__ void load_chunk(double (&c)[rows_per_thread(NS)][NS],
+template <int NS, int RPT>
+__device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
                                            const double *__restrict__ src, int64_t ld, int64_t valid,
                                            int n) {
-    constexpr int RPT = rows_per_thread(NS);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
@@ -356,10 +352,9 @@ __device__ __forceinline__ void load_chunk(double (&c)[rows_per_thread(NS)][NS],
     }
 }
 
-template <int NS>
-__device__ __forceinline__ void store_chunk(const double (&c)[rows_per_thread(NS)][NS],
+template <int NS, int RPT>
+__device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
                                             double *__restrict__ dst, int64_t ld, int64_t valid, int n) {
-    constexpr int RPT = rows_per_thread(NS);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
@@ -408,15 +403,16 @@ __global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restric
     zero_lds(sm.R);
     zero_lds(sm.T);
     __syncthreads();
-    double c[rows_per_thread(NS)][NS];
+    constexpr int RPT = rows_per_thread(NS);
+    double c[RPT][NS];
     for (int64_t ch = 0; ch < nch; ++ch) {
         const int64_t r0 = row0 + ch * ROWS;
         const int64_t valid = (nrows - ch * ROWS < ROWS) ? nrows - ch * ROWS : ROWS;
-        load_chunk<NS>(c, A + r0, lda, valid, n);
-        if (ch == 0) chunk_qr<NS, true>(c, n, sm, want_t);
-        else chunk_qr<NS, false>(c, n, sm, want_t);
+        load_chunk<NS, RPT>(c, A + r0, lda, valid, n);
+        if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t);
+        else chunk_qr<NS, RPT, false>(c, n, sm, want_t);
         if (want_t) {
-            store_chunk<NS>(c, V + r0, ldv, valid, n);
+            store_chunk<NS, RPT>(c, V + r0, ldv, valid, n);
             build_t(sm, n);
             store_tri(sm.T, Tc + (dom * pa.cpd + ch) * (int64_t)n * n, n);
         }
@@ -444,14 +440,15 @@ __global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rd
         if (r <= k) sm.R[r * kLdsStride + k] = Rdom[left * nn + e];
     }
     __syncthreads();
-    double c[rows_per_thread(NS)][NS];
+    constexpr int RPT = 64 / kRowGroups;   // the right triangle has n <= 64 rows
+    double c[RPT][NS];
     for (int64_t q = 1; q * ta.stride < ta.span; ++q) {
         const int64_t right = left + q * ta.stride;
         if (right >= pa.P) break;
-        load_chunk<NS>(c, Rdom + right * nn, n, n, n);
-        chunk_qr<NS, false>(c, n, sm, want_t);
+        load_chunk<NS, RPT>(c, Rdom + right * nn, n, n, n);
+        chunk_qr<NS, RPT, false>(c, n, sm, want_t);
         // the right triangle becomes the node's reflector block U
-        store_chunk<NS>(c, Rdom + right * nn, n, n, n);
+        store_chunk<NS, RPT>(c, Rdom + right * nn, n, n, n);
         if (want_t) {
             build_t(sm, n);
             store_tri(sm.T, Tnode + right * nn, n);
@@ -511,7 +508,7 @@ static hipError_t launch_tree_ns(double *Rdom, double *Tnode, const PanelArgs &p
 
 hipError_t launch_tree_level(double *Rdom, double *Tnode, const PanelArgs &pa, const TreeArgs &ta,
                              int keep_q, hipStream_t st) {
-    // the tree tile must hold n rows: chunk_rows(NS) >= 256 > 64 >= n
+    // the tree tile holds 64 >= n rows
     switch (pa.ns) {
         case 1: return launch_tree_ns<1>(Rdom, Tnode, pa, ta, keep_q, st);
         case 2: return launch_tree_ns<2>(Rdom, Tnode, pa, ta, keep_q, st);

@@ -41,6 +41,11 @@ hipError_t launch_sign_normalise(const double *Rroot, int n, double *Rout, int64
 hipError_t launch_leaf_apply(const double *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
                              const double *Bsrc, int64_t ldbs, double *B, int64_t ldb, int64_t k,
                              int trans, hipStream_t st);
+// apply_mfma.hip: the same leaf application on FP64 matrix cores
+// (16 columns of B per workgroup).
+hipError_t launch_leaf_apply_m(const double *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
+                               const double *Bsrc, int64_t ldbs, double *B, int64_t ldb, int64_t k,
+                               int trans, hipStream_t st);
 hipError_t launch_tree_apply(const double *Rdom, const double *Tnode, const PanelArgs &pa,
                              const TreeArgs &ta, double *B, int64_t ldb, int64_t k, int trans,
                              hipStream_t st);
