@@ -48,10 +48,15 @@ extern "C" {
 enum { TSQR_TREE_FLAT = 0, TSQR_TREE_BINARY = 2, TSQR_TREE_QUAD = 4 };
 
 /* Arithmetic of the factorization.  TSQR_F64: everything in FP64.
-   TSQR_MIXED: reflector generation (norms, beta, tau), the tree combines and
-   every residual in FP64; the trailing updates between 64-column panels and
-   the reflector storage in FP32 (MFMA); least squares is brought back to
-   FP64 accuracy by iterative refinement of the augmented system. */
+   TSQR_MIXED: reflector generation (norms, beta, tau), the leaf and tree
+   Householder steps and every residual in FP64; the reflectors are stored in
+   FP32 and every application of Q or Q^T (the trailing updates between
+   64-column panels, apply_qt/apply_q/form_q, the solves inside least
+   squares) runs on FP32 matrix cores with FP32 accumulation.  The factor is
+   then FP32-accurate (R exact to FP64 rounding for n <= 64, where no FP32
+   trailing update runs; Q orthogonal to about 1e-6), and tsqr_lsq_solve is
+   brought back to FP64 accuracy by iterative refinement of the augmented
+   system [I A; A^T 0][r; x] = [b; 0] with FP64 residuals (Bjorck). */
 enum { TSQR_F64 = 0, TSQR_MIXED = 1 };
 
 /* Error codes beyond the LAPACK-style -i. */
@@ -73,7 +78,8 @@ typedef struct {
                              /* form_q/lsq); 0: R only, the paper's         */
                              /* measured mode (Sec. 1).                     */
     int32_t lsq_max_rhs;     /* largest k passed to tsqr_lsq_solve (>= 1)   */
-    int32_t refine_max_iter; /* mixed-precision refinement sweeps (cap)     */
+    int32_t refine_max_iter; /* mixed: refinement sweeps after the first   */
+                             /* solve (cap)                                */
     int32_t reserved;
     double refine_tol;       /* stop when ||dx|| <= tol ||x||               */
 } tsqr_opts;
@@ -122,7 +128,10 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream);
 /* Least squares min ||A x_j - b_j||_2 for k <= opts.lsq_max_rhs right-hand
    sides: X = R^{-1} (Q^T B)[0:n], resid[j] = ||(Q^T B)[n:m, j]||_2.
    A (m x n, lda) is the matrix that was factored; it is read only by the
-   mixed-precision refinement.  B (m x k, ldb) is not modified.  X (n x k,
+   mixed-precision refinement (required there: -2 when NULL), which
+   synchronises `stream` once per sweep to read its convergence flag and
+   reports resid[j] = ||b_j - A x_j||_2 computed in FP64 from the last
+   sweep's residual pass.  B (m x k, ldb) is not modified.  X (n x k,
    ldx >= n) and resid (k doubles, may be NULL) are device outputs.
    dinfo (device int32, may be NULL) receives 0, or j+1 when R_jj == 0
    exactly (X is then left untouched, LAPACK dtrtrs convention), or -2 when
@@ -131,9 +140,9 @@ TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_
                             const double *B, int64_t ldb, double *X, int64_t ldx,
                             double *resid, int32_t *dinfo, void *stream);
 
-/* Number of refinement sweeps the last mixed-precision tsqr_lsq_solve on
-   this handle ran (0 for FP64 factors).  Reads a device counter, so it
-   synchronises `stream`. */
+/* Number of sweeps (the first solve included) the last mixed-precision
+   tsqr_lsq_solve on this handle ran, the largest over its groups of 8
+   right-hand sides; 0 for FP64 factors.  Host only; `stream` is unused. */
 TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream);
 
 /* Plan introspection (host only, no device work): number of domains, rows

@@ -53,17 +53,30 @@ T *at(const tsqr_factors_s *f, size_t off) {
 
 // Q_p^T (trans = 1) or Q_p (trans = 0) of panel p on k columns; Bsrc/ldbs
 // address the panel's first row of the input, B/ldb of the output.
-int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int64_t ldbs, double *B,
-                int64_t ldb, int64_t k, int trans, hipStream_t st) {
+inline bool is_mixed(const tsqr_factors_s *f) { return f->plan.opts.prec == TSQR_MIXED; }
+
+// Leaf part of Q_p^T / Q_p: FP64 reflectors, or the FP32 copy in the mixed mode.
+hipError_t leaf_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int64_t ldbs, double *B,
+                      int64_t ldb, int64_t k, int trans, hipStream_t st) {
     const Plan &P = f->plan;
     const PanelArgs pa = panel_args(p);
-    const double *V = at<double>(f, P.off_w) + p.row_off + (int64_t)p.col_off * P.m;
+    const int64_t off = p.row_off + (int64_t)p.col_off * P.m;
     const double *Tc = at<double>(f, p.off_tc);
+    if (is_mixed(f))
+        return tsqr::launch_leaf_apply_m32(at<float>(f, P.off_w32) + off, P.m, Tc, pa, Bsrc, ldbs, B, ldb,
+                                           k, trans, st);
+    return tsqr::launch_leaf_apply_m(at<double>(f, P.off_w) + off, P.m, Tc, pa, Bsrc, ldbs, B, ldb, k,
+                                     trans, st);
+}
+
+int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int64_t ldbs, double *B,
+                int64_t ldb, int64_t k, int trans, hipStream_t st) {
+    const PanelArgs pa = panel_args(p);
     const double *Rdom = at<double>(f, p.off_rdom);
     const double *Tnode = at<double>(f, p.off_tnode);
     auto levels = tsqr::tree_levels(p.P, p.tree);
     if (trans) {
-        TRY(tsqr::launch_leaf_apply_m(V, P.m, Tc, pa, Bsrc, ldbs, B, ldb, k, 1, st));
+        TRY(leaf_apply(f, p, Bsrc, ldbs, B, ldb, k, 1, st));
         for (const auto &L : levels) {
             TreeArgs ta{L.stride, L.span, L.chains};
             TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 1, st));
@@ -74,7 +87,7 @@ int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int
             TreeArgs ta{it->stride, it->span, it->chains};
             TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 0, st));
         }
-        TRY(tsqr::launch_leaf_apply_m(V, P.m, Tc, pa, B, ldb, B, ldb, k, 0, st));
+        TRY(leaf_apply(f, p, B, ldb, B, ldb, k, 0, st));
     }
     return 0;
 }
@@ -159,7 +172,11 @@ TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, con
         const int keep = (f->keep_q || q < np - 1) ? 1 : 0;
         double *Rdom = at<double>(f, p.off_rdom);
         double *Tnode = at<double>(f, p.off_tnode);
-        hipError_t e = tsqr::launch_leaf(src_p, lds, V, m, at<double>(f, p.off_tc), Rdom, pa, keep, st);
+        hipError_t e =
+            (o->prec == TSQR_MIXED)
+                ? tsqr::launch_leaf32(src_p, lds, at<float>(f, plan.off_w32) + (V - W), m,
+                                      at<double>(f, p.off_tc), Rdom, pa, keep, st)
+                : tsqr::launch_leaf(src_p, lds, V, m, at<double>(f, p.off_tc), Rdom, pa, keep, st);
         for (const auto &L : tsqr::tree_levels(p.P, p.tree)) {
             if (e != hipSuccess) break;
             TreeArgs ta{L.stride, L.span, L.chains};
@@ -241,6 +258,62 @@ static int apply_q_impl(tsqr_factors_s *f, int64_t k, double *B, int64_t ldb, bo
     return 0;
 }
 
+// Mixed-precision least squares: Bjorck refinement of the augmented system
+// [I A; A^T 0][r; x] = [b; 0] from r = 0, x = 0, so the first sweep is the
+// plain solve through the mixed factor.  Per sweep (groups of at most 8
+// right-hand sides):
+//   f = b - r - A x, g = -A^T r          (FP64, one pass over A)
+//   F = Q^T f                            (FP32 leaves, FP64 tree)
+//   R^T h = g, dx = R^{-1}(F[0:n] - h), x += dx, F[0:n] = h
+//   r += Q F                             (skipped after the last sweep)
+// The stream is synchronised once per sweep to read the convergence flag.
+static int lsq_solve_mixed(tsqr_factors_s *f, const double *A, int64_t lda, int64_t k, const double *B,
+                           int64_t ldb, double *X, int64_t ldx, double *resid, int32_t *dinfo,
+                           hipStream_t st) {
+    const Plan &P = f->plan;
+    const int n = (int)P.n;
+    const int64_t m = P.m;
+    const int kmax = P.opts.lsq_max_rhs < 8 ? P.opts.lsq_max_rhs : 8;
+    const int nb = tsqr::resid_blocks(m);
+    double *F = at<double>(f, P.off_lsq);
+    double *Rr = at<double>(f, P.off_lsq2);
+    double *Xw = at<double>(f, P.off_ref);
+    double *gpart = Xw + (size_t)n * kmax;
+    double *rpart = gpart + (size_t)tsqr::kRefineBlocks * n * kmax;
+    double *hist = rpart + (size_t)tsqr::kRefineBlocks * kmax;
+    int32_t *status = reinterpret_cast<int32_t *>(hist + kmax);
+    const double *Rf = at<double>(f, P.off_r);
+    int sweeps_max = 0;
+    for (int64_t c0 = 0; c0 < k; c0 += kmax) {
+        const int kg = (int)((k - c0 < kmax) ? k - c0 : kmax);
+        const double *Bg = B + c0 * ldb;
+        TRY(tsqr::launch_fill(Xw, (int64_t)n * kg, 0.0, st));
+        TRY(tsqr::launch_fill(Rr, m * kg, 0.0, st));
+        TRY(tsqr::launch_status_init(status, hist, kg, st));
+        int sweeps = 0;
+        for (int it = 0; it <= P.opts.refine_max_iter; ++it) {
+            TRY(tsqr::launch_lsq_resid(A, lda, m, n, Bg, ldb, Xw, n, Rr, F, kg, gpart, rpart, nb, st));
+            int rc = tsqr_apply_qt(f, kg, F, m, st);
+            if (rc) return rc;
+            TRY(tsqr::launch_lsq_refine(Rf, n, F, m, kg, gpart, nb, Xw, n, P.opts.refine_tol, status, hist,
+                                        st));
+            int32_t hs[2] = {0, 0};
+            TRY(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
+            TRY(hipStreamSynchronize(st));
+            sweeps = hs[0];
+            if (hs[1] || it == P.opts.refine_max_iter) break;
+            rc = apply_q_impl(f, kg, F, m, true, false, st);
+            if (rc) return rc;
+            TRY(tsqr::launch_axpy(Rr, F, m * kg, st));
+        }
+        if (sweeps > sweeps_max) sweeps_max = sweeps;
+        TRY(tsqr::launch_mixed_final(Rf, n, kg, Xw, X + c0 * ldx, ldx, resid ? resid + c0 : nullptr, dinfo,
+                                     c0 > 0 ? 1 : 0, rpart, nb, st));
+    }
+    f->last_refine = sweeps_max;
+    return 0;
+}
+
 TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream) {
     int rc = validate_handle(f, true);
     if (rc) return rc;
@@ -258,7 +331,7 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
     if (ldq < f->plan.m) return -3;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double *dsign = at<double>(f, f->plan.off_d);
-    if (f->plan.panels.size() == 1) {
+    if (f->plan.panels.size() == 1 && !is_mixed(f)) {
         // single panel: top-down tree on n x n blocks, then the MFMA leaf
         const Panel &p = f->plan.panels[0];
         const PanelArgs pa = panel_args(p);
@@ -293,6 +366,8 @@ TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_
     if (!X) return -7;
     if (ldx < P.n) return -8;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (P.opts.prec == TSQR_MIXED)
+        return lsq_solve_mixed(f, A, lda, k, B, ldb, X, ldx, resid, dinfo, st);
     double *C = at<double>(f, P.off_lsq);
     hipError_t e = tsqr::launch_copy(B, ldb, C, P.m, P.m, k, st);
     if (e != hipSuccess) return hip_code(e);

@@ -352,23 +352,23 @@ __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
     }
 }
 
-template <int NS, int RPT>
+template <int NS, int RPT, typename OT = double>
 __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
-                                            double *__restrict__ dst, int64_t ld, int64_t valid, int n) {
+                                            OT *__restrict__ dst, int64_t ld, int64_t valid, int n) {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
-        double *p = dst + rgw + (int64_t)k * ld;
+        OT *p = dst + rgw + (int64_t)k * ld;
         if (k < n && full) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) p[i * kRowGroups] = c[i][t];
+            for (int i = 0; i < RPT; ++i) p[i * kRowGroups] = OT(c[i][t]);
         } else if (k < n) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
-                if (i * kRowGroups + rgw < valid) p[i * kRowGroups] = c[i][t];
+                if (i * kRowGroups + rgw < valid) p[i * kRowGroups] = OT(c[i][t]);
         }
     }
 }
@@ -386,9 +386,11 @@ __device__ __forceinline__ void zero_lds(double *lds) {
     for (int e = threadIdx.x; e < 64 * kLdsStride; e += blockDim.x) lds[e] = 0.0;
 }
 
-template <int NS>
+// VT: element type of the stored reflectors (double, or float in the mixed
+// mode, where they only feed the FP32 matrix-core applies).
+template <int NS, typename VT>
 __global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restrict__ A, int64_t lda,
-                                                 double *__restrict__ V, int64_t ldv,
+                                                 VT *__restrict__ V, int64_t ldv,
                                                  double *__restrict__ Tc, double *__restrict__ Rdom,
                                                  PanelArgs pa, int keep_q) {
     extern __shared__ double smem_raw[];
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restric
         if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t);
         else chunk_qr<NS, RPT, false>(c, n, sm, want_t);
         if (want_t) {
-            store_chunk<NS, RPT>(c, V + r0, ldv, valid, n);
+            store_chunk<NS, RPT, VT>(c, V + r0, ldv, valid, n);
             build_t(sm, n);
             store_tri(sm.T, Tc + (dom * pa.cpd + ch) * (int64_t)n * n, n);
         }
@@ -471,26 +473,38 @@ __global__ void k_sign_normalise(const double *__restrict__ Rroot, int n, double
 
 size_t factor_smem_bytes() { return sizeof(FactorSmem); }
 
-template <int NS>
-static hipError_t launch_leaf_ns(const double *A, int64_t lda, double *V, int64_t ldv, double *Tc,
-                                 double *Rdom, const PanelArgs &pa, int keep_q, hipStream_t st) {
+template <int NS, typename VT>
+static hipError_t launch_leaf_ns(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,
+                                 double *Rdom, const PanelArgs &pa, int keep_q, const char *tag,
+                                 hipStream_t st) {
     const size_t sh = sizeof(FactorSmem);
-    hipError_t e = hipFuncSetAttribute((const void *)k_leaf<NS>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_leaf<NS, VT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
-    ProfScope ps("leaf_factor", st);
-    hipLaunchKernelGGL(k_leaf<NS>, dim3((unsigned)pa.P), dim3(kFactorThreads), sh, st, A, lda, V, ldv, Tc, Rdom,
-                       pa, keep_q);
+    ProfScope ps(tag, st);
+    hipLaunchKernelGGL((k_leaf<NS, VT>), dim3((unsigned)pa.P), dim3(kFactorThreads), sh, st, A, lda, V, ldv,
+                       Tc, Rdom, pa, keep_q);
     return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t launch_leaf_t(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc, double *Rdom,
+                                const PanelArgs &pa, int keep_q, const char *tag, hipStream_t st) {
+    switch (pa.ns) {
+        case 1: return launch_leaf_ns<1, VT>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
+        case 2: return launch_leaf_ns<2, VT>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
+        default: return launch_leaf_ns<4, VT>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
+    }
 }
 
 hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, double *Tc, double *Rdom,
                        const PanelArgs &pa, int keep_q, hipStream_t st) {
-    switch (pa.ns) {
-        case 1: return launch_leaf_ns<1>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
-        case 2: return launch_leaf_ns<2>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
-        default: return launch_leaf_ns<4>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, st);
-    }
+    return launch_leaf_t<double>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, "leaf_factor", st);
+}
+
+hipError_t launch_leaf32(const double *A, int64_t lda, float *V, int64_t ldv, double *Tc, double *Rdom,
+                         const PanelArgs &pa, int keep_q, hipStream_t st) {
+    return launch_leaf_t<float>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, "leaf_factor_v32", st);
 }
 
 template <int NS>

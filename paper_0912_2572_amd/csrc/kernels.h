@@ -33,6 +33,9 @@ hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, dou
                        const PanelArgs &pa, int keep_q, hipStream_t st);
 hipError_t launch_tree_level(double *Rdom, double *Tnode, const PanelArgs &pa, const TreeArgs &ta,
                              int keep_q, hipStream_t st);
+// The same leaf with the reflectors stored in FP32 (mixed precision).
+hipError_t launch_leaf32(const double *A, int64_t lda, float *V, int64_t ldv, double *Tc, double *Rdom,
+                         const PanelArgs &pa, int keep_q, hipStream_t st);
 hipError_t launch_sign_normalise(const double *Rroot, int n, double *Rout, int64_t ldr, int row_off,
                                  int col_off, double *dsign, hipStream_t st);
 
@@ -46,6 +49,10 @@ hipError_t launch_leaf_apply(const double *V, int64_t ldv, const double *Tc, con
 hipError_t launch_leaf_apply_m(const double *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
                                const double *Bsrc, int64_t ldbs, double *B, int64_t ldb, int64_t k,
                                int trans, hipStream_t st);
+// The same with FP32 reflectors on FP32 matrix cores (mixed precision).
+hipError_t launch_leaf_apply_m32(const float *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
+                                 const double *Bsrc, int64_t ldbs, double *B, int64_t ldb, int64_t k,
+                                 int trans, hipStream_t st);
 hipError_t launch_tree_apply(const double *Rdom, const double *Tnode, const PanelArgs &pa,
                              const TreeArgs &ta, double *B, int64_t ldb, int64_t k, int trans,
                              hipStream_t st);
@@ -69,5 +76,19 @@ hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd,
 hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ldc, int64_t m, int64_t k,
                              double *X, int64_t ldx, double *resid, int32_t *dinfo, double *partial,
                              hipStream_t st);
+
+// refine.hip: FP64 pieces of the mixed-precision least-squares refinement.
+int resid_blocks(int64_t m);
+hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, const double *B, int64_t ldb,
+                            const double *X, int64_t ldx, const double *Rr, double *F, int k,
+                            double *gpart, double *rpart, int nblocks, hipStream_t st);
+hipError_t launch_lsq_refine(const double *R, int n, double *F, int64_t m, int k, const double *gpart,
+                             int nblocks, double *X, int64_t ldx, double tol, int32_t *status,
+                             double *hist, hipStream_t st);
+hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st);
+hipError_t launch_status_init(int32_t *status, double *hist, int k, hipStream_t st);
+hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, double *X, int64_t ldx,
+                              double *resid, int32_t *dinfo, int merge, const double *rpart, int nblocks,
+                              hipStream_t st);
 
 }  // namespace tsqr

@@ -12,6 +12,7 @@
 namespace tsqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -22,7 +23,28 @@ __device__ __forceinline__ d4 d4_zero() {
     return z;
 }
 
-// Row of D held in register r of lane l, and its column.
+// FP32 tile (v_mfma_f32_16x16x4f32): A and B as above; D[i][j] is register
+// (i % 4) of lane j + 16 (i / 4) -- a different output layout from FP64.
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Precision traits of the 16x16x4 tiles: element type, accumulator vector
+// and the row of D held in register r of lane l.
+struct TileF64 {
+    using T = double;
+    using Acc = d4;
+    __device__ static Acc mfma(T a, T b, Acc c) { return mfma_f64(a, b, c); }
+    __device__ static int drow(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+struct TileF32 {
+    using T = float;
+    using Acc = f4;
+    __device__ static Acc mfma(T a, T b, Acc c) { return mfma_f32(a, b, c); }
+    __device__ static int drow(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
+
+// Row of a FP64 D held in register r of lane l, and its column.
 __device__ __forceinline__ int d_row(int r, int lane) { return 4 * r + (lane >> 4); }
 __device__ __forceinline__ int d_col(int lane) { return lane & 15; }
 

@@ -111,7 +111,13 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         P.panels.push_back(pa);
     }
     P.off_lsq = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);
-    if (o->prec == TSQR_MIXED) P.off_lsq2 = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);
+    if (o->prec == TSQR_MIXED) {
+        P.off_lsq2 = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);
+        // x (n x k), per-block A^T r partials (blocks x n x k), per-block
+        // residual norms (blocks x k), last relative corrections (k), flags
+        const size_t k = (size_t)o->lsq_max_rhs;
+        P.off_ref = take(sizeof(double) * (n * k + (size_t)kRefineBlocks * (n + 1) * k + k) + 64);
+    }
     // small scratch: per-block partial sums (4096 blocks x rhs), a few
     // n x rhs vectors, info words and counters
     P.small_bytes = sizeof(double) * (size_t)(4096 + 8 * n) * o->lsq_max_rhs + 4096;

@@ -16,6 +16,7 @@ constexpr int kMaxPanel = 64;     // columns handled by one leaf/tree kernel
 constexpr int kMaxN = 256;        // documented scope
 constexpr int kThreads = 256;     // threads per workgroup of the leaf kernel
 constexpr size_t kAlign = 256;
+constexpr int kRefineBlocks = 1024;   // workgroups of the refinement's residual pass
 
 // Column slots per thread of the leaf kernel for a panel of width w: 16
 // column groups x ns slots must cover w (ns = 1, 2 or 4).  Rows per thread
@@ -79,6 +80,7 @@ struct Plan {
     size_t off_d = 0;       // n signs
     size_t off_lsq = 0;     // m x lsq_max_rhs scratch (Q^T B)
     size_t off_lsq2 = 0;    // m x lsq_max_rhs scratch (refinement residual)
+    size_t off_ref = 0;     // refinement scratch (mixed only): x, partial sums, flags
     size_t off_small = 0;   // small scratch: partial sums, x corrections, info words
     size_t small_bytes = 0;
     size_t total = 0;

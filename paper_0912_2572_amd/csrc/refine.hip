@@ -1,0 +1,279 @@
+// refine.hip -- mixed-precision support: FP32 copies of the reflectors and
+// the FP64 pieces of least-squares iterative refinement.
+//
+// With the mixed factor Q~ R~ (FP32 WY applies), least squares is brought
+// back to FP64 accuracy by refining the augmented system
+//     [ I   A ] [r]   [b]
+//     [ A^T 0 ] [x] = [0]
+// (Bjorck's method): with FP64 residuals f = b - r - A x and g = -A^T r, the
+// correction solves through the factors are
+//     R^T h = g,   d = Q^T f,   dx = R^{-1} (d_1 - h),   dr = Q [h; d_2],
+// and x += dx, r += dr.  Plain x-only refinement would stall at the
+// accuracy of the FP32 factor for problems with a large residual; the
+// augmented form does not.  The paper fixes only the QR (Sec. 2.2) and
+// names least squares as its use; the refinement is the textbook one.
+#include "common.h"
+#include "kernels.h"
+#include "plan.h"
+#include "prof.h"
+
+namespace tsqr {
+
+__global__ void k_to_f32(const double *__restrict__ src, int64_t lds, float *__restrict__ dst, int64_t ldd,
+                         int64_t rows, int64_t cols) {
+    const int64_t total = rows * cols;
+    for (int64_t e = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; e < total;
+         e += (int64_t)blockDim.x * gridDim.x) {
+        const int64_t r = e % rows, c = e / rows;
+        dst[r + c * ldd] = (float)src[r + c * lds];
+    }
+}
+
+constexpr int kResRows = 32;   // rows per LDS tile of the residual pass
+
+// One pass over A (FP64): F = B - Rr - A X (rows of this block),
+// gpart[block] = A_block^T Rr_block (n x k) and rpart[block] = the squared
+// norms of the columns of (B - A X)_block, all in a fixed summation order.
+__global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A, int64_t lda, int64_t m,
+                                                   int n, const double *__restrict__ B, int64_t ldb,
+                                                   const double *__restrict__ X, int64_t ldx,
+                                                   const double *__restrict__ Rr, double *__restrict__ F,
+                                                   int k, double *__restrict__ gpart,
+                                                   double *__restrict__ rpart) {
+    extern __shared__ double sh[];
+    double *At = sh;                        // kResRows x n (row-major)
+    double *Xs = At + kResRows * n;         // n x k
+    double *Rt = Xs + n * k;                // kResRows x k
+    double *Ss = Rt + kResRows * k;         // kResRows x k: (B - A X)^2
+    const int tid = threadIdx.x;
+    const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = (lo + per < m) ? lo + per : m;
+    for (int e = tid; e < n * k; e += 256) Xs[e] = X[(e % n) + (int64_t)(e / n) * ldx];
+    for (int e = tid; e < kResRows * k; e += 256) Ss[e] = 0.0;
+    // accumulators of A^T Rr: thread owns (j, c) pairs e = tid + 256 q
+    constexpr int kMaxOwn = 8;              // n * k <= 2048
+    double acc[kMaxOwn];
+#pragma unroll
+    for (int q = 0; q < kMaxOwn; ++q) acc[q] = 0.0;
+    for (int64_t r0 = lo; r0 < hi; r0 += kResRows) {
+        const int rows = (int)((hi - r0 < kResRows) ? hi - r0 : kResRows);
+        __syncthreads();
+        for (int e = tid; e < kResRows * n; e += 256) {
+            const int r = e % kResRows, j = e / kResRows;
+            At[r * n + j] = (r < rows) ? A[r0 + r + (int64_t)j * lda] : 0.0;
+        }
+        for (int e = tid; e < kResRows * k; e += 256) {
+            const int r = e % kResRows, c = e / kResRows;
+            Rt[r * k + c] = (r < rows) ? Rr[r0 + r + (int64_t)c * m] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < kResRows * k; e += 256) {
+            const int r = e % kResRows, c = e / kResRows;
+            if (r >= rows) continue;
+            double s = B[r0 + r + (int64_t)c * ldb];
+            for (int j = 0; j < n; ++j) s = fma(-At[r * n + j], Xs[j + n * c], s);
+            Ss[r * k + c] = fma(s, s, Ss[r * k + c]);
+            F[r0 + r + (int64_t)c * m] = s - Rt[r * k + c];
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxOwn; ++q) {
+            const int e = tid + 256 * q;
+            if (e < n * k) {
+                const int j = e % n, c = e / n;
+                double s = acc[q];
+                for (int r = 0; r < rows; ++r) s = fma(At[r * n + j], Rt[r * k + c], s);
+                acc[q] = s;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxOwn; ++q) {
+        const int e = tid + 256 * q;
+        if (e < n * k) gpart[(int64_t)blockIdx.x * n * k + e] = acc[q];
+    }
+    __syncthreads();
+    if (tid < k) {
+        double s = 0.0;
+        for (int r = 0; r < kResRows; ++r) s += Ss[r * k + tid];
+        rpart[(int64_t)blockIdx.x * k + tid] = s;
+    }
+}
+
+// One workgroup: g = -sum_b gpart[b];  R^T h = g;  dx = R^{-1} (d_1 - h)
+// with d_1 = F[0:n] (= (Q^T f)[0:n] on entry);  X += dx;  F[0:n] = h.
+// status[0] = sweeps done, status[1] = 1 when converged or stalled,
+// hist[c] = ||dx_c|| / ||x_c|| of the last sweep.  A sweep counts as
+// final when every column either met the tolerance or stalled (its
+// correction shrank by less than 10 %).
+__global__ __launch_bounds__(256) void k_lsq_refine(const double *__restrict__ R, int n,
+                                                    double *__restrict__ F, int64_t m, int k,
+                                                    const double *__restrict__ gpart, int nblocks,
+                                                    double *__restrict__ X, int64_t ldx, double tol,
+                                                    int32_t *__restrict__ status,
+                                                    double *__restrict__ hist) {
+    __shared__ double g[256], h[256], dx[256];
+    __shared__ double nrm[2];
+    __shared__ int all_ok;
+    const int tid = threadIdx.x;
+    if (tid == 0) all_ok = 1;
+    for (int c = 0; c < k; ++c) {
+        for (int j = tid; j < n; j += 256) {
+            double s = 0.0;
+            for (int b = 0; b < nblocks; ++b) s += gpart[(int64_t)b * n * k + j + n * c];
+            g[j] = -s;
+        }
+        __syncthreads();
+        // forward substitution R^T h = g (column-oriented)
+        for (int i = 0; i < n; ++i) {
+            const double hi_ = g[i] / R[i + (int64_t)i * n];
+            __syncthreads();
+            for (int q = i + 1 + tid; q < n; q += 256) g[q] = fma(-R[i + (int64_t)q * n], hi_, g[q]);
+            if (tid == 0) h[i] = hi_;
+            __syncthreads();
+        }
+        for (int j = tid; j < n; j += 256) dx[j] = F[j + m * c] - h[j];
+        __syncthreads();
+        // back substitution R dx = d_1 - h
+        for (int i = n - 1; i >= 0; --i) {
+            const double xi = dx[i] / R[i + (int64_t)i * n];
+            __syncthreads();
+            for (int q = tid; q < i; q += 256) dx[q] = fma(-R[q + (int64_t)i * n], xi, dx[q]);
+            if (tid == 0) dx[i] = xi;
+            __syncthreads();
+        }
+        if (tid == 0) { nrm[0] = 0.0; nrm[1] = 0.0; }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double xn = X[j + ldx * c] + dx[j];
+                a += dx[j] * dx[j];
+                b += xn * xn;
+            }
+            nrm[0] = a;
+            nrm[1] = b;
+        }
+        __syncthreads();
+        for (int j = tid; j < n; j += 256) {
+            X[j + ldx * c] += dx[j];
+            F[j + m * c] = h[j];
+        }
+        if (tid == 0) {
+            const double rel = sqrt(nrm[0]) / fmax(sqrt(nrm[1]), 1e-300);
+            const double prev = hist[c];
+            hist[c] = rel;
+            const bool done = (rel <= tol) || (status[0] >= 1 && rel > 0.9 * prev) || !(rel == rel);
+            if (!done) all_ok = 0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        status[0] += 1;
+        status[1] = all_ok;
+    }
+}
+
+__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, int64_t count) {
+    for (int64_t e = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; e < count;
+         e += (int64_t)blockDim.x * gridDim.x)
+        y[e] += x[e];
+}
+
+__global__ void k_status_init(int32_t *status, double *hist, int k) {
+    if (threadIdx.x == 0) {
+        status[0] = 0;
+        status[1] = 0;
+    }
+    if ((int)threadIdx.x < k) hist[threadIdx.x] = 1.0;
+}
+
+// Last step of a refined solve: info from the diagonal of R (LAPACK dtrtrs
+// convention: X untouched when R_jj == 0), X = Xw otherwise, residual norms
+// ||b_c - A x_c|| from the last residual pass.
+__global__ __launch_bounds__(256) void k_mixed_final(const double *R, int n, int k, const double *Xw,
+                                                     double *X, int64_t ldx, double *resid, int32_t *dinfo,
+                                                     int merge, const double *rpart, int nblocks) {
+    __shared__ int info;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        info = 0;
+        for (int j = 0; j < n; ++j)
+            if (R[j + j * n] == 0.0) {
+                info = j + 1;
+                break;
+            }
+    }
+    __syncthreads();
+    bool bad = false;
+    if (tid < k) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += rpart[(int64_t)b * k + tid];
+        const double rn = sqrt(s);
+        if (resid) resid[tid] = rn;
+        bad = !(rn - rn == 0.0);
+    }
+    const int anybad = __syncthreads_or(bad);
+    // merge: a later group of right-hand sides keeps an earlier nonzero code
+    if (tid == 0 && dinfo && !(merge && *dinfo != 0)) *dinfo = info ? info : (anybad ? -2 : 0);
+    if (info) return;
+    for (int e = tid; e < n * k; e += 256) X[(e % n) + (int64_t)(e / n) * ldx] = Xw[e];
+}
+
+hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, double *X, int64_t ldx,
+                              double *resid, int32_t *dinfo, int merge, const double *rpart, int nblocks,
+                              hipStream_t st) {
+    ProfScope ps("lsq_final", st);
+    hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(256), 0, st, R, n, k, Xw, X, ldx, resid, dinfo, merge,
+                       rpart, nblocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows,
+                         int64_t cols, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    ProfScope ps("to_f32", st);
+    hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(256), 0, st, src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+int resid_blocks(int64_t m) {
+    int64_t b = (m + 2047) / 2048;
+    return (int)(b < 1 ? 1 : (b > kRefineBlocks ? kRefineBlocks : b));
+}
+
+hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, const double *B, int64_t ldb,
+                            const double *X, int64_t ldx, const double *Rr, double *F, int k,
+                            double *gpart, double *rpart, int nblocks, hipStream_t st) {
+    const size_t sh =
+        sizeof(double) * ((size_t)kResRows * n + (size_t)n * k + 2 * (size_t)kResRows * k);
+    hipError_t e = hipFuncSetAttribute((const void *)k_lsq_resid,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps("lsq_resid", st);
+    hipLaunchKernelGGL(k_lsq_resid, dim3(nblocks), dim3(256), sh, st, A, lda, m, n, B, ldb, X, ldx, Rr, F,
+                       k, gpart, rpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsq_refine(const double *R, int n, double *F, int64_t m, int k, const double *gpart,
+                             int nblocks, double *X, int64_t ldx, double tol, int32_t *status,
+                             double *hist, hipStream_t st) {
+    ProfScope ps("lsq_refine", st);
+    hipLaunchKernelGGL(k_lsq_refine, dim3(1), dim3(256), 0, st, R, n, F, m, k, gpart, nblocks, X, ldx, tol,
+                       status, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st) {
+    ProfScope ps("axpy", st);
+    hipLaunchKernelGGL(k_axpy, dim3(2048), dim3(256), 0, st, y, x, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_init(int32_t *status, double *hist, int k, hipStream_t st) {
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, status, hist, k);
+    return hipGetLastError();
+}
+
+}  // namespace tsqr

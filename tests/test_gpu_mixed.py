@@ -1,0 +1,174 @@
+"""GPU parity of the mixed-precision path (FP32 matrix-core updates and
+applies, FP64 reflector generation, tree and residuals, Bjorck refinement of
+the augmented least-squares system).
+
+What is checked, per right-hand side:
+  E1  eta = ||A^T (b - A x)|| / (||A||_F (||A||_F ||x|| + ||b||)) <= 1e-12,
+      the kappa-independent backward-error proxy that any backward-stable
+      FP64 solver meets (an unrefined FP32 factor gives about 1e-7);
+  E2  ||x - x_oracle|| / ||x_oracle|| <= max(1e-12, 10 kappa_LS u) against
+      the FP64 oracle solve, kappa_LS = kappa + kappa^2 tan(theta);
+  E3  ||x - x*|| / ||x*|| against the oracle's binary128-refined solution,
+      printed for the record (bounded by the same kappa_LS u term).
+The factor itself is only FP32-accurate once a trailing update has run in
+FP32 (n > 64); for n <= 64 the leaves and tree are FP64 and R must match the
+oracle to the FP64 tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def tl():
+    import paper_0912_2572_amd as t
+    t.lib()
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return t
+
+
+def dev(x):
+    t = torch.as_tensor(np.asarray(x, dtype=np.float64))
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    return t.t().contiguous().t().cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def eta(A, x, b):
+    r = b - A @ x
+    nA = np.linalg.norm(A)
+    return float(np.linalg.norm(A.T @ r) / (nA * (nA * np.linalg.norm(x) + np.linalg.norm(b))))
+
+
+def orth(G):
+    return oracle.TSQR(G, mb=max(G.shape[1], 4096)).form_q()
+
+
+@pytest.fixture(scope="module")
+def conditioned():
+    """Config-3 construction at 65,536 rows: A = U diag(s) V^T, s log-spaced
+    from 1 to 1e-6 over 128 columns (kappa = 1e6), b ~ N(0,1) (large
+    residual) and b_c = A x_true (consistent)."""
+    A, b, bc, xt, s = synth.config_conditioned(65536, 128, orth, seed=0)
+    return A, b, bc, xt, s
+
+
+def check_solution(A, X, B, Ro, mb, label):
+    orc = oracle.TSQR(A, mb=mb)
+    Xo, reso, _ = orc.lsq(B)
+    kappa = np.linalg.cond(Ro)
+    for c in range(B.shape[1]):
+        x = X[:, c]
+        e1 = eta(A, x, B[:, c])
+        tan = reso[c] / max(np.linalg.norm(A @ Xo[:, c]), 1e-300)
+        bound = max(1e-12, 10 * (kappa + kappa ** 2 * tan) * U)
+        e2 = rel(x, Xo[:, c])
+        xs, _ = orc.lsq_refined(A, B[:, c])
+        e3 = rel(x, xs)
+        print(f"{label} rhs {c}: E1 eta={e1:.2e}  E2={e2:.2e} (bound {bound:.2e})  E3={e3:.2e}",
+              flush=True)
+        assert e1 <= 1e-12
+        assert e2 <= bound
+
+
+def test_mixed_conditioned_two_panels(tl, conditioned):
+    A, b, bc, xt, s = conditioned
+    m, n = A.shape
+    print(f"case mixed m={m} n={n} mb=4096 kappa=1e6", flush=True)
+    f = tl.factor(dev(A), row_block=4096, prec=tl.MIXED)
+    R = host(f.R())
+    assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) >= 0.0)
+    # backward error of the mixed factor: FP32 trailing update
+    nA2 = np.linalg.norm(A) ** 2
+    assert np.linalg.norm(R.T @ R - A.T @ A) / nA2 <= 1e-5
+    Ro = oracle.TSQR(A, mb=4096).R()
+    B = np.stack([b, bc], axis=1)
+    X, res, info = f.lsq(dev(B), A=dev(A))
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    it = f.last_refine_iters()
+    print(f"refinement sweeps {it}", flush=True)
+    assert 2 <= it <= 31
+    X = host(X)
+    check_solution(A, X, B, Ro, 4096, "kappa=1e6")
+    # residual norms are ||b - A x|| in FP64
+    for c in range(2):
+        r = np.linalg.norm(B[:, c] - A @ X[:, c])
+        assert abs(host(res)[c] - r) <= 1e-10 * max(r, 1e-300) + 1e-14 * np.linalg.norm(B[:, c])
+    # the consistent right-hand side recovers x_true within kappa u
+    assert rel(X[:, 1], xt) <= 10 * 1e6 * U * math.sqrt(n)
+
+
+@pytest.mark.parametrize("m,n,mb,tree", [(20000, 64, 2048, 2), (30000, 16, 4096, 4),
+                                         (5000, 100, 1024, 0), (9000, 200, 1500, 2)])
+def test_mixed_gaussian(tl, m, n, mb, tree):
+    print(f"case mixed m={m} n={n} mb={mb} tree={tree}", flush=True)
+    A = synth.gaussian(m, n, seed=m + 7 * n)
+    f = tl.factor(dev(A), row_block=mb, tree=tree, prec=tl.MIXED)
+    R = host(f.R())
+    orc = oracle.TSQR(A, mb=mb, tree=tree)
+    Ro = orc.R()
+    if n <= 64:
+        # one panel: FP64 leaves and tree, only the stored V is FP32
+        assert rel(R, Ro) <= 1e-12
+    else:
+        assert rel(R, Ro) <= 1e-5
+    rng = np.random.default_rng(n)
+    B = rng.standard_normal((m, 3))
+    X, res, info = f.lsq(dev(B), A=dev(A))
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    check_solution(A, host(X), B, Ro, mb, f"n={n}")
+    # Q from FP32 reflectors: orthogonal to FP32 accuracy
+    Q = host(f.form_q())
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-5
+    assert rel(Q @ R, A) <= 1e-5
+
+
+def test_mixed_rhs_groups(tl):
+    """More right-hand sides than one refinement group (8): groups of 8 + 2."""
+    m, n = 12000, 24
+    A = synth.gaussian(m, n, seed=3)
+    f = tl.factor(dev(A), row_block=2048, prec=tl.MIXED, lsq_max_rhs=10)
+    B = np.random.default_rng(4).standard_normal((m, 10))
+    X, res, info = f.lsq(dev(B), A=dev(A))
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Xo, _, _ = oracle.TSQR(A, mb=2048).lsq(B)
+    assert rel(host(X), Xo) <= 1e-12
+
+
+def test_mixed_zero_column_info(tl):
+    A = synth.gaussian(3000, 12, seed=5)
+    A[:, 3] = 0.0
+    f = tl.factor(dev(A), row_block=1024, prec=tl.MIXED)
+    X = torch.full((12, 1), 7.0, dtype=torch.float64, device="cuda")
+    b = np.random.default_rng(1).standard_normal(3000)
+    _, _, info = f.lsq(dev(b), A=dev(A), X=X)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 4
+    assert torch.all(X == 7.0)
+
+
+def test_mixed_needs_a(tl):
+    A = synth.gaussian(2000, 8, seed=2)
+    f = tl.factor(dev(A), row_block=1024, prec=tl.MIXED)
+    with pytest.raises(tl.TSQRError):
+        f.lsq(dev(np.ones(2000)))
