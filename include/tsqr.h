@@ -166,6 +166,97 @@ TSQR_API int64_t tsqr_tree_schedule(int64_t P, int tree, int64_t *left, int64_t 
 TSQR_API int tsqr_prof_enable(int on);
 TSQR_API int tsqr_prof_query(int i, const char **name, int64_t *launches, double *ms);
 
+/* ------------------------------------------------------------------------
+   Batched TSQR + least squares.  Many independent matrices (n <= 64, one
+   right-hand side each, FP64 or mixed per matrix) are factored and solved
+   together: every step of the path (leaf QR, each tree level, sign
+   normalisation, Q^T b, the solve and the mixed matrices' refinement
+   sweeps) is one launch over all matrices at once, and the whole sequence
+   is captured once into a HIP graph and replayed.  Row-block size and tree
+   arity come from a tuning table (tsqr_autotune) keyed by (n, precision):
+   a matrix's plan depends only on its own (m, n, precision), never on the
+   rest of the batch.
+   ------------------------------------------------------------------------ */
+
+/* One tuning-table entry: applies to matrices of precision `prec` with
+   n <= n_max (the entry with the smallest such n_max wins). */
+typedef struct {
+    int32_t n_max;
+    int32_t prec;
+    int64_t row_block;   /* rows per domain (raised to n when smaller)     */
+    int32_t tree;        /* TSQR_TREE_*                                    */
+    int32_t reserved;
+} tsqr_tune_entry;
+
+/* One matrix of a batch.  All pointers are device pointers the caller owns;
+   A (m x n, lda >= m) and b (m) are read only. */
+typedef struct {
+    int64_t m, n;        /* 1 <= n <= 64, n <= m <= 2^31 - 1                */
+    int32_t prec;        /* TSQR_F64 or TSQR_MIXED                          */
+    int32_t reserved;
+    const double *A;
+    int64_t lda;
+    const double *b;
+    double *R;           /* n x n output (leading dimension n), diag >= 0   */
+    double *x;           /* n output: argmin ||A x - b||_2                  */
+    double *resid;       /* 1 output: ||b - A x||_2 (FP64 matrices: the    */
+                         /* norm of (Q^T b)[n:m])                           */
+    int32_t *info;       /* 1 output: 0, j+1 for R_jj == 0 (x untouched),  */
+                         /* -2 for a non-finite residual                    */
+} tsqr_batch_item;
+
+typedef struct tsqr_batch_s *tsqr_batch;
+
+/* Default row block and tree of the batched path when no table is given. */
+#define TSQR_BATCH_DEFAULT_ROW_BLOCK 4096
+
+/* Device workspace for a batch (only m, n, prec of the items are read).
+   tune == NULL: the largest over the whole autotuning space, so the same
+   workspace serves tsqr_autotune and any table it returns.  0 on error. */
+TSQR_API size_t tsqr_batch_workspace_bytes(int count, const tsqr_batch_item *items,
+                                           const tsqr_tune_entry *tune, int ntune);
+
+/* Plans the batch (host), writes its device descriptors into dwork (256-byte
+   aligned, >= tsqr_batch_workspace_bytes) on `stream`, and returns a host
+   handle.  refine_sweeps: refinement sweeps after the first solve for the
+   mixed matrices (each stops early on its own once ||dx|| <= refine_tol ||x||
+   or it stalls; the sweeps are part of the captured graph, so no host
+   synchronisation happens inside a run).  Errors: -1 count, -2 items (an
+   item out of scope: its index is reported by tsqr_batch_bad_item), -3 tune,
+   -5 refine arguments, TSQR_ERR_WORKSPACE, -1000-e. */
+TSQR_API int tsqr_batch_create(int count, const tsqr_batch_item *items, const tsqr_tune_entry *tune,
+                               int ntune, int refine_sweeps, double refine_tol, void *dwork,
+                               size_t work_bytes, void *stream, tsqr_batch *out);
+
+/* Index of the first invalid item seen by the last failed
+   tsqr_batch_create / tsqr_batch_workspace_bytes, or -1. */
+TSQR_API int tsqr_batch_bad_item(void);
+
+/* Runs the whole batch on `stream`.  use_graph = 1: the first call captures
+   the launch sequence into a HIP graph bound to this handle (stream must
+   not be NULL), later calls replay it; use_graph = 0: plain launches. */
+TSQR_API int tsqr_batch_run(tsqr_batch b, int use_graph, void *stream);
+
+/* Plan of item i (host): rows per domain, tree and number of domains. */
+TSQR_API int tsqr_batch_plan(tsqr_batch b, int i, int64_t *row_block, int32_t *tree,
+                             int64_t *domains);
+
+/* Number of launches one run of the batch enqueues (graph nodes). */
+TSQR_API int tsqr_batch_launches(tsqr_batch b);
+
+TSQR_API int tsqr_batch_free(tsqr_batch b);
+
+/* Autotuner: times the batch (plain launches, `reps` timed runs after one
+   warm-up, HIP events on `stream`) over row_block in {512, 1024, 2048,
+   4096, 8192} x tree in {binary, 4-ary, flat}: first one setting for all
+   matrices, then each (n class, precision) class on its own with the others
+   held at the best so far.  n classes are n <= 8, 16, 32, 64.  Writes at
+   most `cap` entries to out and returns the number written (< 0: error).
+   dwork must hold tsqr_batch_workspace_bytes(count, items, NULL, 0); the
+   items' outputs are overwritten. */
+TSQR_API int tsqr_autotune(int count, const tsqr_batch_item *items, int reps, void *dwork,
+                           size_t work_bytes, void *stream, tsqr_tune_entry *out, int cap);
+
 /* Frees the host handle only (the workspace belongs to the caller). */
 TSQR_API int tsqr_free(tsqr_factors f);
 

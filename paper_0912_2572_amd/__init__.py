@@ -40,6 +40,34 @@ class Opts(ctypes.Structure):
     ]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("n_max", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("row_block", ctypes.c_int64),
+        ("tree", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("prec", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("A", ctypes.c_void_p),
+        ("lda", ctypes.c_int64),
+        ("b", ctypes.c_void_p),
+        ("R", ctypes.c_void_p),
+        ("x", ctypes.c_void_p),
+        ("resid", ctypes.c_void_p),
+        ("info", ctypes.c_void_p),
+    ]
+
+
+BATCH_DEFAULT_ROW_BLOCK = 4096
+
 _lib = None
 
 
@@ -77,8 +105,22 @@ def lib():
         L.tsqr_free.argtypes = [vp]
         L.tsqr_strerror.argtypes = [ctypes.c_int]
         L.tsqr_strerror.restype = ctypes.c_char_p
+        bip, tep = ctypes.POINTER(BatchItem), ctypes.POINTER(TuneEntry)
+        L.tsqr_batch_workspace_bytes.argtypes = [ctypes.c_int, bip, tep, ctypes.c_int]
+        L.tsqr_batch_workspace_bytes.restype = sz
+        L.tsqr_batch_create.argtypes = [ctypes.c_int, bip, tep, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                        vp, sz, vp, ctypes.POINTER(vp)]
+        L.tsqr_batch_bad_item.argtypes = []
+        L.tsqr_batch_run.argtypes = [vp, ctypes.c_int, vp]
+        L.tsqr_batch_plan.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i64)]
+        L.tsqr_batch_launches.argtypes = [vp]
+        L.tsqr_batch_free.argtypes = [vp]
+        L.tsqr_autotune.argtypes = [ctypes.c_int, bip, ctypes.c_int, vp, sz, vp, tep, ctypes.c_int]
         for name in ("tsqr_factor", "tsqr_get_r", "tsqr_apply_qt", "tsqr_apply_q", "tsqr_form_q",
-                     "tsqr_lsq_solve", "tsqr_last_refine_iters", "tsqr_plan_info", "tsqr_free"):
+                     "tsqr_lsq_solve", "tsqr_last_refine_iters", "tsqr_plan_info", "tsqr_free",
+                     "tsqr_batch_create", "tsqr_batch_bad_item", "tsqr_batch_run", "tsqr_batch_plan",
+                     "tsqr_batch_launches", "tsqr_batch_free", "tsqr_autotune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -264,3 +306,133 @@ def factor(A: torch.Tensor, **kw) -> Factors:
     work = kw.pop("work", None)
     stream = kw.pop("stream", None)
     return Factors(A, opts(**kw), work=work, stream=stream)
+
+
+# ---------------------------------------------------------------------------
+# Batched path
+
+
+def tune_table(entries) -> tuple:
+    """(ctypes array, count) from a list of dicts {n_max, prec, row_block, tree}."""
+    if not entries:
+        return None, 0
+    arr = (TuneEntry * len(entries))()
+    for i, e in enumerate(entries):
+        arr[i].n_max, arr[i].prec = int(e["n_max"]), int(e["prec"])
+        arr[i].row_block, arr[i].tree = int(e["row_block"]), int(e["tree"])
+    return arr, len(entries)
+
+
+def _items(As, bs, precs, outs):
+    cnt = len(As)
+    arr = (BatchItem * cnt)()
+    for i in range(cnt):
+        A = As[i]
+        m, n = A.shape
+        pa, lda = _col_major(A, m, "A")
+        arr[i].m, arr[i].n, arr[i].prec = m, n, int(precs[i])
+        arr[i].A, arr[i].lda = pa, lda
+        if outs is not None:
+            R, x, res, info = outs[i]
+            arr[i].b = bs[i].data_ptr()
+            arr[i].R, arr[i].x = R.data_ptr(), x.data_ptr()
+            arr[i].resid, arr[i].info = res.data_ptr(), info.data_ptr()
+    return arr
+
+
+class Batch:
+    """Many independent least-squares problems (n <= 64, one right-hand side
+    each), factored and solved together by tsqr_batch_run.  Outputs per
+    matrix: R (n x n), x (n), resid (1), info (1), all device tensors."""
+
+    def __init__(self, As, bs, precs, tune=None, refine_sweeps: int = 4, refine_tol: float = 1e-14,
+                 work: torch.Tensor | None = None, stream=None):
+        dev = As[0].device
+        self.count = len(As)
+        self.As, self.bs = As, [b.reshape(-1).contiguous() for b in bs]
+        self.outs = []
+        for A in As:
+            n = A.shape[1]
+            self.outs.append((torch.empty((n, n), dtype=torch.float64, device=dev),
+                              torch.empty(n, dtype=torch.float64, device=dev),
+                              torch.empty(1, dtype=torch.float64, device=dev),
+                              torch.empty(1, dtype=torch.int32, device=dev)))
+        self._items = _items(As, self.bs, precs, self.outs)
+        self._tune, ntune = tune_table(tune)
+        need = lib().tsqr_batch_workspace_bytes(self.count, self._items, self._tune, ntune)
+        if need == 0:
+            raise ValueError(f"invalid batch item {lib().tsqr_batch_bad_item()}")
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.work = work
+        h = ctypes.c_void_p()
+        _check(lib().tsqr_batch_create(self.count, self._items, self._tune, ntune, refine_sweeps,
+                                       refine_tol, ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                       _stream(stream), ctypes.byref(h)), "tsqr_batch_create")
+        self._h = h
+
+    def run(self, use_graph: bool = True, stream=None):
+        _check(lib().tsqr_batch_run(self._h, 1 if use_graph else 0, _stream(stream)), "tsqr_batch_run")
+
+    def plan(self, i: int):
+        mb, tr, P = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().tsqr_batch_plan(self._h, i, ctypes.byref(mb), ctypes.byref(tr), ctypes.byref(P)),
+               "tsqr_batch_plan")
+        return mb.value, tr.value, P.value
+
+    def launches(self) -> int:
+        return int(lib().tsqr_batch_launches(self._h))
+
+    def R(self, i):
+        # the library writes R column-major with leading dimension n
+        return self.outs[i][0].t()
+
+    def x(self, i):
+        return self.outs[i][1]
+
+    def resid(self, i):
+        return self.outs[i][2]
+
+    def info(self, i):
+        return self.outs[i][3]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tsqr_batch_free(h)
+            self._h = None
+
+
+def batch_workspace_bytes(shapes, precs, tune=None) -> int:
+    """Workspace for a batch of (m, n) shapes (tune None: the autotuning
+    space's maximum)."""
+    cnt = len(shapes)
+    arr = (BatchItem * cnt)()
+    for i, (m, n) in enumerate(shapes):
+        arr[i].m, arr[i].n, arr[i].prec, arr[i].lda = m, n, int(precs[i]), m
+    t, nt = tune_table(tune)
+    return int(lib().tsqr_batch_workspace_bytes(cnt, arr, t, nt))
+
+
+def autotune(As, bs, precs, reps: int = 2, stream=None):
+    """Runs the C++ autotuner on this batch; returns the table as a list of
+    dicts (save it as JSON to reuse it)."""
+    dev = As[0].device
+    outs = [(torch.empty((A.shape[1], A.shape[1]), dtype=torch.float64, device=dev),
+             torch.empty(A.shape[1], dtype=torch.float64, device=dev),
+             torch.empty(1, dtype=torch.float64, device=dev),
+             torch.empty(1, dtype=torch.int32, device=dev)) for A in As]
+    bs = [b.reshape(-1).contiguous() for b in bs]
+    items = _items(As, bs, precs, outs)
+    need = lib().tsqr_batch_workspace_bytes(len(As), items, None, 0)
+    if need == 0:
+        raise ValueError(f"invalid batch item {lib().tsqr_batch_bad_item()}")
+    work = torch.empty(need, dtype=torch.uint8, device=dev)
+    cap = 16
+    out = (TuneEntry * cap)()
+    rc = lib().tsqr_autotune(len(As), items, reps, ctypes.c_void_p(work.data_ptr()), work.numel(),
+                             _stream(stream), out, cap)
+    if rc < 0:
+        raise TSQRError(rc, "tsqr_autotune")
+    return [{"n_max": out[i].n_max, "prec": out[i].prec, "row_block": out[i].row_block,
+             "tree": out[i].tree} for i in range(rc)]

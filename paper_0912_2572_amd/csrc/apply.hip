@@ -199,29 +199,29 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const double *__restrict__ V
 
 // Tree level: chain g combines rights into left; Y blocks are the top n rows
 // of the domains involved.
-__global__ __launch_bounds__(256) void k_tree_apply(const double *__restrict__ Rdom,
-                                                    const double *__restrict__ Tnode, PanelArgs pa,
-                                                    TreeArgs ta, double *__restrict__ B, int64_t ldb,
-                                                    int64_t k, int trans) {
-    extern __shared__ double smem_raw[];
-    ApplySmem &sm = *reinterpret_cast<ApplySmem *>(smem_raw);
+// One chain of the tree for the KB-column block cblk of B: the chain's
+// nodes (left, right) in order (Q^T) or in reverse order (Q).
+__device__ __forceinline__ void tree_apply_chain(ApplySmem &sm, const double *__restrict__ Rdom,
+                                                 const double *__restrict__ Tnode, const PanelArgs &pa,
+                                                 int64_t left, int64_t stride, int64_t span,
+                                                 double *__restrict__ B, int64_t ldb, int64_t k, int trans,
+                                                 int64_t cblk) {
     const int n = pa.n;
     const int64_t nn = (int64_t)n * n;
-    const int64_t left = (int64_t)blockIdx.x * ta.span;
-    const int64_t c0 = (int64_t)blockIdx.y * KB;
+    const int64_t c0 = cblk * KB;
     const int kc = (int)((k - c0 < KB) ? k - c0 : KB);
     double *B0 = B + c0 * ldb;
     const int tid = threadIdx.x;
     const int wi = tid & 63, wc = tid >> 6;
     int64_t nr = 0;
-    for (int64_t q = 1; q * ta.stride < ta.span && left + q * ta.stride < pa.P; ++q) ++nr;
+    for (int64_t q = 1; q * stride < span && left + q * stride < pa.P; ++q) ++nr;
     for (int e = tid; e < 64 * KB; e += 256) {
         const int r = e & 63, c = e >> 6;
         sm.Ys[r][c] = (r < n && c < kc) ? B0[left * pa.mb + r + (int64_t)c * ldb] : 0.0;
     }
     for (int64_t qq = 0; qq < nr; ++qq) {
         const int64_t q = trans ? qq + 1 : nr - qq;
-        const int64_t right = left + q * ta.stride;
+        const int64_t right = left + q * stride;
         const double *U = Rdom + right * nn;
         const double *T = Tnode + right * nn;
         double *Yr = B0 + right * pa.mb;
@@ -288,6 +288,38 @@ __global__ __launch_bounds__(256) void k_tree_apply(const double *__restrict__ R
     }
 }
 
+__global__ __launch_bounds__(256) void k_tree_apply(const double *__restrict__ Rdom,
+                                                    const double *__restrict__ Tnode, PanelArgs pa,
+                                                    TreeArgs ta, double *__restrict__ B, int64_t ldb,
+                                                    int64_t k, int trans) {
+    extern __shared__ double smem_raw[];
+    ApplySmem &sm = *reinterpret_cast<ApplySmem *>(smem_raw);
+    tree_apply_chain(sm, Rdom, Tnode, pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, B, ldb, k,
+                     trans, blockIdx.y);
+}
+
+// Batched: level `step` from the bottom (Q^T) or from the top (Q) of each
+// listed matrix's own tree, on its vector F.
+__global__ __launch_bounds__(256) void k_tree_apply_b(const BMat *__restrict__ mats,
+                                                      const int *__restrict__ list, int trans, int step,
+                                                      int sweep) {
+    extern __shared__ double smem_raw[];
+    ApplySmem &sm = *reinterpret_cast<ApplySmem *>(smem_raw);
+    const BMat &M = mats[list[blockIdx.y]];
+    if (step >= M.nlev) return;
+    if (sweep > 0 && M.status[1]) return;
+    const TreeArgs ta = M.lev[trans ? step : M.nlev - 1 - step];
+    if ((int64_t)blockIdx.x >= ta.chains) return;
+    tree_apply_chain(sm, M.Rdom, M.Tnode, M.pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, M.F,
+                     M.pa.m, 1, trans, 0);
+}
+
+__global__ void k_scale_b(const BMat *__restrict__ mats, const int *__restrict__ list, int sweep) {
+    const BMat &M = mats[list[blockIdx.x]];
+    if (sweep > 0 && M.status[1]) return;
+    for (int r = threadIdx.x; r < M.pa.n; r += blockDim.x) M.F[r] *= M.dsign[r];
+}
+
 __global__ void k_scale_rows(double *B, int64_t ldb, int n, int64_t k, const double *d) {
     for (int64_t e = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; e < (int64_t)n * k;
          e += (int64_t)blockDim.x * gridDim.x) {
@@ -330,6 +362,27 @@ hipError_t launch_scale_rows(double *B, int64_t ldb, int n, int64_t k, const dou
     if (k <= 0) return hipSuccess;
     ProfScope ps("scale_rows", st);
     hipLaunchKernelGGL(k_scale_rows, dim3(8), dim3(256), 0, st, B, ldb, n, k, d);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_tree_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int step,
+                               int sweep, hipStream_t st) {
+    if (cnt <= 0 || gx <= 0) return hipSuccess;
+    const size_t sh = sizeof(ApplySmem);
+    hipError_t e = hipFuncSetAttribute((const void *)k_tree_apply_b,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps(trans ? "batch_tree_apply_qt" : "batch_tree_apply_q", st);
+    hipLaunchKernelGGL(k_tree_apply_b, dim3((unsigned)gx, (unsigned)cnt), dim3(256), sh, st, mats, list,
+                       trans, step, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_b(const BMat *mats, const int *list, int cnt, int sweep, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    ProfScope ps("batch_scale_rows", st);
+    hipLaunchKernelGGL(k_scale_b, dim3((unsigned)cnt), dim3(64), 0, st, mats, list, sweep);
     return hipGetLastError();
 }
 

@@ -151,16 +151,14 @@ __device__ void chunk_apply_m(ApplyMSmem<Tile> &sm, const typename Tile::T *__re
     __syncthreads();
 }
 
+// Leaf part for domain `dom` and the 16-column block `cblk` of B.
 template <typename Tile>
-__global__ __launch_bounds__(256) void k_leaf_apply_m(const typename Tile::T *__restrict__ V, int64_t ldv,
-                                                      const double *__restrict__ Tc, PanelArgs pa,
-                                                      const double *__restrict__ Bsrc, int64_t ldbs,
-                                                      double *__restrict__ B, int64_t ldb, int64_t k,
-                                                      int trans) {
-    extern __shared__ double smem_raw[];
-    ApplyMSmem<Tile> &sm = *reinterpret_cast<ApplyMSmem<Tile> *>(smem_raw);
-    const int64_t dom = blockIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.y * KBM;
+__device__ __forceinline__ void leaf_apply_domain(ApplyMSmem<Tile> &sm, const typename Tile::T *__restrict__ V,
+                                                  int64_t ldv, const double *__restrict__ Tc,
+                                                  const PanelArgs &pa, const double *__restrict__ Bsrc,
+                                                  int64_t ldbs, double *__restrict__ B, int64_t ldb, int64_t k,
+                                                  int trans, int64_t dom, int64_t cblk) {
+    const int64_t c0 = cblk * KBM;
     const int kc = (int)((k - c0 < KBM) ? k - c0 : KBM);
     const int n = pa.n;
     const int64_t row0 = dom * pa.mb;
@@ -194,6 +192,48 @@ __global__ __launch_bounds__(256) void k_leaf_apply_m(const typename Tile::T *__
                                 ldb, valid, n, kc, ch == 0, 0);
         }
     }
+}
+
+template <typename Tile>
+__global__ __launch_bounds__(256) void k_leaf_apply_m(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                                      const double *__restrict__ Tc, PanelArgs pa,
+                                                      const double *__restrict__ Bsrc, int64_t ldbs,
+                                                      double *__restrict__ B, int64_t ldb, int64_t k,
+                                                      int trans) {
+    extern __shared__ double smem_raw[];
+    ApplyMSmem<Tile> &sm = *reinterpret_cast<ApplyMSmem<Tile> *>(smem_raw);
+    leaf_apply_domain<Tile>(sm, V, ldv, Tc, pa, Bsrc, ldbs, B, ldb, k, trans, blockIdx.x, blockIdx.y);
+}
+
+// Batched form on each listed matrix's vector F (one column), FP64 or FP32
+// tiles by the matrix's precision; sweep > 0 skips converged matrices.
+__global__ __launch_bounds__(256) void k_leaf_apply_b(const BMat *__restrict__ mats,
+                                                      const int *__restrict__ list, int trans, int sweep) {
+    extern __shared__ double smem_raw[];
+    const BMat &M = mats[list[blockIdx.y]];
+    const int64_t dom = blockIdx.x;
+    if (dom >= M.pa.P) return;
+    if (sweep > 0 && M.status[1]) return;
+    if (M.prec) {
+        ApplyMSmem<TileF32> &sm = *reinterpret_cast<ApplyMSmem<TileF32> *>(smem_raw);
+        leaf_apply_domain<TileF32>(sm, M.V32, M.pa.m, M.Tc, M.pa, M.F, M.pa.m, M.F, M.pa.m, 1, trans, dom, 0);
+    } else {
+        ApplyMSmem<TileF64> &sm = *reinterpret_cast<ApplyMSmem<TileF64> *>(smem_raw);
+        leaf_apply_domain<TileF64>(sm, M.V, M.pa.m, M.Tc, M.pa, M.F, M.pa.m, M.F, M.pa.m, 1, trans, dom, 0);
+    }
+}
+
+hipError_t launch_leaf_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int sweep,
+                               hipStream_t st) {
+    if (cnt <= 0 || gx <= 0) return hipSuccess;
+    const size_t sh = sizeof(ApplyMSmem<TileF64>);
+    hipError_t e = hipFuncSetAttribute((const void *)k_leaf_apply_b,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps(trans ? "batch_leaf_apply_qt" : "batch_leaf_apply_q", st);
+    hipLaunchKernelGGL(k_leaf_apply_b, dim3((unsigned)gx, (unsigned)cnt), dim3(256), sh, st, mats, list, trans,
+                       sweep);
+    return hipGetLastError();
 }
 
 template <typename Tile>

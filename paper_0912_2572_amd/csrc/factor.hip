@@ -386,17 +386,16 @@ __device__ __forceinline__ void zero_lds(double *lds) {
     for (int e = threadIdx.x; e < 64 * kLdsStride; e += blockDim.x) lds[e] = 0.0;
 }
 
+// Leaf QR of domain `dom` (step 2): the chunks of the domain in order, a
+// geqrt of the first and a tpqrt of [R; chunk] for each later one.
 // VT: element type of the stored reflectors (double, or float in the mixed
 // mode, where they only feed the FP32 matrix-core applies).
 template <int NS, typename VT>
-__global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restrict__ A, int64_t lda,
-                                                 VT *__restrict__ V, int64_t ldv,
-                                                 double *__restrict__ Tc, double *__restrict__ Rdom,
-                                                 PanelArgs pa, int keep_q) {
-    extern __shared__ double smem_raw[];
-    FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+__device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__restrict__ A, int64_t lda,
+                                            VT *__restrict__ V, int64_t ldv, double *__restrict__ Tc,
+                                            double *__restrict__ Rdom, const PanelArgs &pa, int keep_q,
+                                            int64_t dom) {
     constexpr int ROWS = chunk_rows(NS);
-    const int64_t dom = blockIdx.x;
     const int64_t row0 = dom * pa.mb;
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
     const int64_t nch = (nrows + ROWS - 1) / ROWS;
@@ -423,16 +422,25 @@ __global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restric
     store_tri(sm.R, Rdom + dom * (int64_t)n * n, n);
 }
 
-// One chain of combines per workgroup: left <- qr([R_left; R_right]) for
-// every right of the chain, in order.
-template <int NS>
-__global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rdom, double *__restrict__ Tnode,
-                                                 PanelArgs pa, TreeArgs ta, int keep_q) {
+template <int NS, typename VT>
+__global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restrict__ A, int64_t lda,
+                                                 VT *__restrict__ V, int64_t ldv,
+                                                 double *__restrict__ Tc, double *__restrict__ Rdom,
+                                                 PanelArgs pa, int keep_q) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    leaf_domain<NS, VT>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x);
+}
+
+// One chain of combines (step 3): left <- qr([R_left; R_right]) for every
+// right = left + q stride (q = 1, 2, ... while q stride < span and right < P),
+// in order.
+template <int NS>
+__device__ __forceinline__ void tree_chain(FactorSmem &sm, double *__restrict__ Rdom,
+                                           double *__restrict__ Tnode, const PanelArgs &pa,
+                                           int64_t left, int64_t stride, int64_t span, int keep_q) {
     const int n = pa.n;
     const int64_t nn = (int64_t)n * n;
-    const int64_t left = (int64_t)blockIdx.x * ta.span;
     const bool want_t = keep_q != 0;
     zero_lds(sm.R);
     zero_lds(sm.T);
@@ -444,8 +452,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rd
     __syncthreads();
     constexpr int RPT = 64 / kRowGroups;   // the right triangle has n <= 64 rows
     double c[RPT][NS];
-    for (int64_t q = 1; q * ta.stride < ta.span; ++q) {
-        const int64_t right = left + q * ta.stride;
+    for (int64_t q = 1; q * stride < span; ++q) {
+        const int64_t right = left + q * stride;
         if (right >= pa.P) break;
         load_chunk<NS, RPT>(c, Rdom + right * nn, n, n, n);
         chunk_qr<NS, RPT, false>(c, n, sm, want_t);
@@ -460,6 +468,14 @@ __global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rd
     store_tri(sm.R, Rdom + left * nn, n);
 }
 
+template <int NS>
+__global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rdom, double *__restrict__ Tnode,
+                                                 PanelArgs pa, TreeArgs ta, int keep_q) {
+    extern __shared__ double smem_raw[];
+    FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    tree_chain<NS>(sm, Rdom, Tnode, pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, keep_q);
+}
+
 // R_out = D R_root with D = diag(sgn R_jj), sgn(0) = +1; d_out = diag(D).
 __global__ void k_sign_normalise(const double *__restrict__ Rroot, int n, double *__restrict__ Rout,
                                  int64_t ldr, int row_off, int col_off, double *__restrict__ dsign) {
@@ -472,6 +488,96 @@ __global__ void k_sign_normalise(const double *__restrict__ Rroot, int n, double
 }
 
 size_t factor_smem_bytes() { return sizeof(FactorSmem); }
+
+// ---- batched forms: grid.y walks the matrix list, grid.x the domains /
+// chains of the listed matrix (a workgroup past its matrix's count returns).
+template <int NS>
+__global__ __launch_bounds__(kFactorThreads) void k_leaf_b(const BMat *__restrict__ mats,
+                                                   const int *__restrict__ list) {
+    extern __shared__ double smem_raw[];
+    FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    const BMat &M = mats[list[blockIdx.y]];
+    const int64_t dom = blockIdx.x;
+    if (dom >= M.pa.P) return;
+    if (M.prec)
+        leaf_domain<NS, float>(sm, M.A, M.lda, M.V32, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+    else
+        leaf_domain<NS, double>(sm, M.A, M.lda, M.V, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+}
+
+template <int NS>
+__global__ __launch_bounds__(kFactorThreads) void k_tree_b(const BMat *__restrict__ mats,
+                                                   const int *__restrict__ list, int level) {
+    extern __shared__ double smem_raw[];
+    FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    const BMat &M = mats[list[blockIdx.y]];
+    if (level >= M.nlev) return;
+    const TreeArgs ta = M.lev[level];
+    if ((int64_t)blockIdx.x >= ta.chains) return;
+    tree_chain<NS>(sm, M.Rdom, M.Tnode, M.pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, 1);
+}
+
+__global__ void k_sign_b(const BMat *__restrict__ mats, const int *__restrict__ list) {
+    const BMat &M = mats[list[blockIdx.x]];
+    const int n = M.pa.n;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e % n, k = e / n;
+        const double dr = (M.Rdom[r + r * n] < 0.0) ? -1.0 : 1.0;
+        M.R[e] = (r <= k) ? dr * M.Rdom[e] : 0.0;
+        if (k == 0) M.dsign[r] = dr;
+    }
+}
+
+template <int NS>
+static hipError_t launch_leaf_b_ns(const BMat *mats, const int *list, int cnt, int64_t gx, hipStream_t st) {
+    const size_t sh = sizeof(FactorSmem);
+    hipError_t e = hipFuncSetAttribute((const void *)k_leaf_b<NS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps("batch_leaf_factor", st);
+    hipLaunchKernelGGL(k_leaf_b<NS>, dim3((unsigned)gx, (unsigned)cnt), dim3(kFactorThreads), sh, st, mats,
+                       list);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, hipStream_t st) {
+    if (cnt <= 0 || gx <= 0) return hipSuccess;
+    switch (ns) {
+        case 1: return launch_leaf_b_ns<1>(mats, list, cnt, gx, st);
+        case 2: return launch_leaf_b_ns<2>(mats, list, cnt, gx, st);
+        default: return launch_leaf_b_ns<4>(mats, list, cnt, gx, st);
+    }
+}
+
+template <int NS>
+static hipError_t launch_tree_b_ns(const BMat *mats, const int *list, int cnt, int64_t gx, int level,
+                                   hipStream_t st) {
+    const size_t sh = sizeof(FactorSmem);
+    hipError_t e = hipFuncSetAttribute((const void *)k_tree_b<NS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps("batch_tree_factor", st);
+    hipLaunchKernelGGL(k_tree_b<NS>, dim3((unsigned)gx, (unsigned)cnt), dim3(kFactorThreads), sh, st, mats,
+                       list, level);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, int level,
+                         hipStream_t st) {
+    if (cnt <= 0 || gx <= 0) return hipSuccess;
+    switch (ns) {
+        case 1: return launch_tree_b_ns<1>(mats, list, cnt, gx, level, st);
+        case 2: return launch_tree_b_ns<2>(mats, list, cnt, gx, level, st);
+        default: return launch_tree_b_ns<4>(mats, list, cnt, gx, level, st);
+    }
+}
+
+hipError_t launch_sign_b(const BMat *mats, const int *list, int cnt, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    ProfScope ps("batch_sign_normalise", st);
+    hipLaunchKernelGGL(k_sign_b, dim3((unsigned)cnt), dim3(256), 0, st, mats, list);
+    return hipGetLastError();
+}
 
 template <int NS, typename VT>
 static hipError_t launch_leaf_ns(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,

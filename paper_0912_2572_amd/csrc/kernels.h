@@ -28,6 +28,42 @@ struct TreeArgs {
 
 size_t factor_smem_bytes();
 
+// ---------------------------------------------------------------------------
+// Batched path: one descriptor per matrix (single panel, n <= 64, one
+// right-hand side), resident in device memory.  Batched kernels take a list
+// of matrix indices and run grid.y = list length, grid.x = the largest count
+// of work items (domains, chains, row blocks) of any listed matrix; a
+// workgroup whose item does not exist for its matrix returns at once.
+constexpr int kMaxLevels = 32;
+
+struct BMat {
+    // caller's memory
+    const double *A;
+    int64_t lda;
+    const double *b;      // one right-hand side (m)
+    double *R;            // n x n output, leading dimension n
+    double *x;            // n output
+    double *resid;        // one double
+    int32_t *info;        // one int32
+    // workspace
+    double *V;            // m x n reflectors (FP64 matrices)
+    float *V32;           // m x n reflectors (mixed matrices)
+    double *Tc, *Rdom, *Tnode, *dsign;
+    double *F;            // m: Q^T f / correction vector
+    double *Rr;           // m: refined residual (mixed)
+    double *Xw;           // n: running solution
+    double *gpart;        // nb x n partial A^T r
+    double *rpart;        // nb partial ||b - A x||^2
+    double *hist;         // [0] last relative correction, [1] residual norm (FP64)
+    int32_t *status;      // [0] sweeps done, [1] converged
+    PanelArgs pa;
+    int prec;             // 0 FP64, 1 mixed
+    int nlev;             // tree levels
+    int nb;               // row blocks of the residual pass
+    int pad;
+    TreeArgs lev[kMaxLevels];
+};
+
 // factor.hip
 hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, double *Tc, double *Rdom,
                        const PanelArgs &pa, int keep_q, hipStream_t st);
@@ -90,5 +126,25 @@ hipError_t launch_status_init(int32_t *status, double *hist, int k, hipStream_t 
 hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, double *X, int64_t ldx,
                               double *resid, int32_t *dinfo, int merge, const double *rpart, int nblocks,
                               hipStream_t st);
+
+// batched launches (device descriptor array `mats`, index list `list` of
+// `cnt` entries, `gx` = grid.x as described above)
+hipError_t launch_leaf_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, hipStream_t st);
+hipError_t launch_tree_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, int level,
+                         hipStream_t st);
+hipError_t launch_sign_b(const BMat *mats, const int *list, int cnt, hipStream_t st);
+// Q^T (trans = 1) or Q (trans = 0) on F, leaves; sweep > 0 skips converged
+// matrices.
+hipError_t launch_leaf_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int sweep,
+                               hipStream_t st);
+// one tree level; step counts from the bottom (trans = 1) or the top (0)
+hipError_t launch_tree_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int step,
+                               int sweep, hipStream_t st);
+hipError_t launch_scale_b(const BMat *mats, const int *list, int cnt, int sweep, hipStream_t st);
+hipError_t launch_lsq_init_b(const BMat *mats, const int *list, int cnt, int64_t gx, hipStream_t st);
+hipError_t launch_resid_b(const BMat *mats, const int *list, int cnt, int64_t gx, int sweep, hipStream_t st);
+hipError_t launch_refine_b(const BMat *mats, const int *list, int cnt, int sweep, double tol, hipStream_t st);
+hipError_t launch_axpy_b(const BMat *mats, const int *list, int cnt, int64_t gx, int sweep, hipStream_t st);
+hipError_t launch_final_b(const BMat *mats, const int *list, int cnt, hipStream_t st);
 
 }  // namespace tsqr

@@ -16,6 +16,7 @@ struct Rec {
 };
 
 bool g_on = false;
+int g_suspend = 0;    // > 0 while a stream is being captured into a graph
 std::vector<Rec> g_recs;       // events recorded since the last query
 std::vector<hipEvent_t> g_pool;
 struct Agg {
@@ -59,8 +60,10 @@ void drain() {
 
 }  // namespace
 
+void prof_suspend(bool on) { g_suspend += on ? 1 : -1; }
+
 int prof_begin(const char *tag, hipStream_t st) {
-    if (!g_on) return -1;
+    if (!g_on || g_suspend > 0) return -1;
     if (g_recs.size() > 20000) drain();
     Rec r{tag, get_event(), get_event()};
     if (r.a) hipEventRecord(r.a, st);

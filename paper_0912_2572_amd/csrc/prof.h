@@ -9,6 +9,9 @@ namespace tsqr {
 // slot id for prof_end (or -1 when profiling is off).
 int prof_begin(const char *tag, hipStream_t st);
 void prof_end(int slot, hipStream_t st);
+// No events are recorded between prof_suspend(true) and prof_suspend(false)
+// (used while a stream is captured into a graph).
+void prof_suspend(bool on);
 
 // RAII bracket around one launch.
 struct ProfScope {

@@ -34,20 +34,19 @@ constexpr int kResRows = 32;   // rows per LDS tile of the residual pass
 // One pass over A (FP64): F = B - Rr - A X (rows of this block),
 // gpart[block] = A_block^T Rr_block (n x k) and rpart[block] = the squared
 // norms of the columns of (B - A X)_block, all in a fixed summation order.
-__global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A, int64_t lda, int64_t m,
-                                                   int n, const double *__restrict__ B, int64_t ldb,
-                                                   const double *__restrict__ X, int64_t ldx,
-                                                   const double *__restrict__ Rr, double *__restrict__ F,
-                                                   int k, double *__restrict__ gpart,
-                                                   double *__restrict__ rpart) {
-    extern __shared__ double sh[];
+__device__ __forceinline__ void resid_block(const double *__restrict__ A, int64_t lda, int64_t m, int n,
+                                            const double *__restrict__ B, int64_t ldb,
+                                            const double *__restrict__ X, int64_t ldx,
+                                            const double *__restrict__ Rr, double *__restrict__ F, int k,
+                                            double *__restrict__ gpart, double *__restrict__ rpart,
+                                            int64_t blk, int64_t nblk, double *sh) {
     double *At = sh;                        // kResRows x n (row-major)
     double *Xs = At + kResRows * n;         // n x k
     double *Rt = Xs + n * k;                // kResRows x k
     double *Ss = Rt + kResRows * k;         // kResRows x k: (B - A X)^2
     const int tid = threadIdx.x;
-    const int64_t per = (m + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t per = (m + nblk - 1) / nblk;
+    const int64_t lo = blk * per;
     const int64_t hi = (lo + per < m) ? lo + per : m;
     for (int e = tid; e < n * k; e += 256) Xs[e] = X[(e % n) + (int64_t)(e / n) * ldx];
     for (int e = tid; e < kResRows * k; e += 256) Ss[e] = 0.0;
@@ -90,14 +89,24 @@ __global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A,
 #pragma unroll
     for (int q = 0; q < kMaxOwn; ++q) {
         const int e = tid + 256 * q;
-        if (e < n * k) gpart[(int64_t)blockIdx.x * n * k + e] = acc[q];
+        if (e < n * k) gpart[blk * n * k + e] = acc[q];
     }
     __syncthreads();
     if (tid < k) {
         double s = 0.0;
         for (int r = 0; r < kResRows; ++r) s += Ss[r * k + tid];
-        rpart[(int64_t)blockIdx.x * k + tid] = s;
+        rpart[blk * k + tid] = s;
     }
+}
+
+__global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A, int64_t lda, int64_t m,
+                                                   int n, const double *__restrict__ B, int64_t ldb,
+                                                   const double *__restrict__ X, int64_t ldx,
+                                                   const double *__restrict__ Rr, double *__restrict__ F,
+                                                   int k, double *__restrict__ gpart,
+                                                   double *__restrict__ rpart) {
+    extern __shared__ double sh[];
+    resid_block(A, lda, m, n, B, ldb, X, ldx, Rr, F, k, gpart, rpart, blockIdx.x, gridDim.x, sh);
 }
 
 // One workgroup: g = -sum_b gpart[b];  R^T h = g;  dx = R^{-1} (d_1 - h)
@@ -106,12 +115,10 @@ __global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A,
 // hist[c] = ||dx_c|| / ||x_c|| of the last sweep.  A sweep counts as
 // final when every column either met the tolerance or stalled (its
 // correction shrank by less than 10 %).
-__global__ __launch_bounds__(256) void k_lsq_refine(const double *__restrict__ R, int n,
-                                                    double *__restrict__ F, int64_t m, int k,
-                                                    const double *__restrict__ gpart, int nblocks,
-                                                    double *__restrict__ X, int64_t ldx, double tol,
-                                                    int32_t *__restrict__ status,
-                                                    double *__restrict__ hist) {
+__device__ __forceinline__ void refine_step(const double *__restrict__ R, int n, double *__restrict__ F,
+                                            int64_t m, int k, const double *__restrict__ gpart, int nblocks,
+                                            double *__restrict__ X, int64_t ldx, double tol,
+                                            int32_t *__restrict__ status, double *__restrict__ hist) {
     __shared__ double g[256], h[256], dx[256];
     __shared__ double nrm[2];
     __shared__ int all_ok;
@@ -120,7 +127,8 @@ __global__ __launch_bounds__(256) void k_lsq_refine(const double *__restrict__ R
     for (int c = 0; c < k; ++c) {
         for (int j = tid; j < n; j += 256) {
             double s = 0.0;
-            for (int b = 0; b < nblocks; ++b) s += gpart[(int64_t)b * n * k + j + n * c];
+            if (gpart)
+                for (int b = 0; b < nblocks; ++b) s += gpart[(int64_t)b * n * k + j + n * c];
             g[j] = -s;
         }
         __syncthreads();
@@ -172,6 +180,15 @@ __global__ __launch_bounds__(256) void k_lsq_refine(const double *__restrict__ R
         status[0] += 1;
         status[1] = all_ok;
     }
+}
+
+__global__ __launch_bounds__(256) void k_lsq_refine(const double *__restrict__ R, int n,
+                                                    double *__restrict__ F, int64_t m, int k,
+                                                    const double *__restrict__ gpart, int nblocks,
+                                                    double *__restrict__ X, int64_t ldx, double tol,
+                                                    int32_t *__restrict__ status,
+                                                    double *__restrict__ hist) {
+    refine_step(R, n, F, m, k, gpart, nblocks, X, ldx, tol, status, hist);
 }
 
 __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, int64_t count) {
@@ -226,6 +243,137 @@ hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, d
     ProfScope ps("lsq_final", st);
     hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(256), 0, st, R, n, k, Xw, X, ldx, resid, dinfo, merge,
                        rpart, nblocks);
+    return hipGetLastError();
+}
+
+// ---- batched refinement (one right-hand side per matrix) ----
+
+// F = b, Rr = 0, x = 0, flags cleared.
+__global__ void k_lsq_init_b(const BMat *__restrict__ mats, const int *__restrict__ list) {
+    const BMat &M = mats[list[blockIdx.y]];
+    const int64_t m = M.pa.m;
+    for (int64_t r = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; r < m;
+         r += (int64_t)blockDim.x * gridDim.x) {
+        M.F[r] = M.b[r];
+        if (M.prec) M.Rr[r] = 0.0;
+    }
+    if (blockIdx.x == 0) {
+        for (int j = threadIdx.x; j < M.pa.n; j += blockDim.x) M.Xw[j] = 0.0;
+        if (threadIdx.x == 0) {
+            M.status[0] = 0;
+            M.status[1] = 0;
+            M.hist[0] = 1.0;
+            M.hist[1] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_resid_b(const BMat *__restrict__ mats, const int *__restrict__ list,
+                                                 int sweep) {
+    extern __shared__ double sh[];
+    const BMat &M = mats[list[blockIdx.y]];
+    if ((int)blockIdx.x >= M.nb) return;
+    if (sweep > 0 && M.status[1]) return;
+    resid_block(M.A, M.lda, M.pa.m, M.pa.n, M.b, M.pa.m, M.Xw, M.pa.n, M.Rr, M.F, 1, M.gpart, M.rpart,
+                blockIdx.x, M.nb, sh);
+}
+
+// One workgroup per matrix.  Sweep 0 is the plain solve (g = 0); an FP64
+// matrix stops there, with ||(Q^T b)[n:m]|| as its residual norm.
+__global__ __launch_bounds__(256) void k_refine_b(const BMat *__restrict__ mats, const int *__restrict__ list,
+                                                  int sweep, double tol) {
+    __shared__ double red[256];
+    const BMat &M = mats[list[blockIdx.x]];
+    if (sweep > 0 && M.status[1]) return;
+    const int n = M.pa.n;
+    const int64_t m = M.pa.m;
+    if (!M.prec) {
+        double s = 0.0;
+        for (int64_t r = n + threadIdx.x; r < m; r += 256) s = fma(M.F[r], M.F[r], s);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) M.hist[1] = sqrt(red[0]);
+        __syncthreads();
+    }
+    refine_step(M.R, n, M.F, m, 1, sweep > 0 ? M.gpart : nullptr, M.nb, M.Xw, n, tol, M.status, M.hist);
+    if (!M.prec && threadIdx.x == 0) M.status[1] = 1;
+}
+
+__global__ void k_axpy_b(const BMat *__restrict__ mats, const int *__restrict__ list, int sweep) {
+    const BMat &M = mats[list[blockIdx.y]];
+    if (sweep > 0 && M.status[1]) return;
+    for (int64_t r = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; r < M.pa.m;
+         r += (int64_t)blockDim.x * gridDim.x)
+        M.Rr[r] += M.F[r];
+}
+
+__global__ void k_final_b(const BMat *__restrict__ mats, const int *__restrict__ list) {
+    __shared__ int info;
+    const BMat &M = mats[list[blockIdx.x]];
+    const int n = M.pa.n;
+    if (threadIdx.x == 0) {
+        info = 0;
+        for (int j = 0; j < n; ++j)
+            if (M.R[j + j * n] == 0.0) {
+                info = j + 1;
+                break;
+            }
+        double rn;
+        if (M.prec) {
+            double s = 0.0;
+            for (int b = 0; b < M.nb; ++b) s += M.rpart[b];
+            rn = sqrt(s);
+        } else {
+            rn = M.hist[1];
+        }
+        *M.resid = rn;
+        *M.info = info ? info : (!(rn - rn == 0.0) ? -2 : 0);
+    }
+    __syncthreads();
+    if (info) return;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) M.x[j] = M.Xw[j];
+}
+
+static unsigned rows_grid(int64_t gx) { return (unsigned)(gx < 1 ? 1 : (gx > 1024 ? 1024 : gx)); }
+
+hipError_t launch_lsq_init_b(const BMat *mats, const int *list, int cnt, int64_t gx, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    ProfScope ps("batch_lsq_init", st);
+    hipLaunchKernelGGL(k_lsq_init_b, dim3(rows_grid(gx), (unsigned)cnt), dim3(256), 0, st, mats, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_b(const BMat *mats, const int *list, int cnt, int64_t gx, int sweep, hipStream_t st) {
+    if (cnt <= 0 || gx <= 0) return hipSuccess;
+    // n <= 64, k = 1
+    const size_t sh = sizeof(double) * ((size_t)kResRows * 64 + 64 + 2 * (size_t)kResRows);
+    ProfScope ps("batch_lsq_resid", st);
+    hipLaunchKernelGGL(k_resid_b, dim3((unsigned)gx, (unsigned)cnt), dim3(256), sh, st, mats, list, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_b(const BMat *mats, const int *list, int cnt, int sweep, double tol, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    ProfScope ps("batch_lsq_refine", st);
+    hipLaunchKernelGGL(k_refine_b, dim3((unsigned)cnt), dim3(256), 0, st, mats, list, sweep, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_b(const BMat *mats, const int *list, int cnt, int64_t gx, int sweep, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    ProfScope ps("batch_axpy", st);
+    hipLaunchKernelGGL(k_axpy_b, dim3(rows_grid(gx), (unsigned)cnt), dim3(256), 0, st, mats, list, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_b(const BMat *mats, const int *list, int cnt, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    ProfScope ps("batch_lsq_final", st);
+    hipLaunchKernelGGL(k_final_b, dim3((unsigned)cnt), dim3(64), 0, st, mats, list);
     return hipGetLastError();
 }
 

@@ -93,3 +93,37 @@ def test_invalid_arguments_rejected_on_host(tl):
                          ctypes.byref(h)) == tl.ERR_UNSUPPORTED
     assert not h.value
     assert L.tsqr_strerror(-900).decode().startswith("workspace")
+
+
+def test_batch_workspace_and_item_checks(tl):
+    L = tl.lib()
+    shapes = [(5000, 8), (20000, 64), (1000, 16)]
+    w_default = tl.batch_workspace_bytes(shapes, [0, 1, 0],
+                                         tune=[{"n_max": 64, "prec": 0, "row_block": 4096, "tree": 2},
+                                               {"n_max": 64, "prec": 1, "row_block": 4096, "tree": 2}])
+    w_space = tl.batch_workspace_bytes(shapes, [0, 1, 0])
+    # reflectors: FP64 for matrices 0 and 2, FP32 for the mixed one
+    assert w_default >= 8 * (5000 * 8 + 1000 * 16) + 4 * 20000 * 64
+    assert w_space >= w_default
+    # out of scope: n > 64 (batched matrices are single-panel), m < n
+    assert tl.batch_workspace_bytes([(5000, 65)], [0]) == 0
+    assert L.tsqr_batch_bad_item() == 0
+    assert tl.batch_workspace_bytes([(100, 8), (10, 20)], [0, 0]) == 0
+    assert L.tsqr_batch_bad_item() == 1
+    assert tl.batch_workspace_bytes([(100, 8)], [2]) == 0   # unknown precision
+
+
+def test_batch_create_rejects_on_host(tl):
+    L = tl.lib()
+    items = (tl.BatchItem * 1)()
+    items[0].m, items[0].n, items[0].prec, items[0].lda = 1000, 8, 0, 1000
+    h = ctypes.c_void_p()
+    # NULL device pointers in the item: rejected before any device work
+    assert L.tsqr_batch_create(1, items, None, 0, 2, 1e-14, ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(h)) == -2
+    assert L.tsqr_batch_create(0, items, None, 0, 2, 1e-14, ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(h)) == -1
+    assert L.tsqr_batch_create(1, items, None, 0, -1, 1e-14, ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(h)) == -5
+    assert not h.value
+    assert L.tsqr_autotune(1, items, 0, None, 0, None, None, 0) == -3
