@@ -1,7 +1,8 @@
 """Throughput benchmark of the TSQR hot path on one MI355X.
 
-A step is one pass of the single-matrix path over a 1,048,576 x 64 FP64
-matrix (iid N(0,1), seed 0) split into 4096-row domains with a binary tree:
+Default workload (--workload single): one pass of the single-matrix path over
+a 1,048,576 x 64 FP64 matrix (iid N(0,1), seed 0) split into 4096-row
+domains with a binary tree:
     partition + leaf QR + tree + sign normalisation   (tsqr_factor, keep Q)
     thin Q                                             (tsqr_form_q)
     least squares for one right-hand side              (tsqr_lsq_solve)
@@ -9,8 +10,17 @@ The metric is useful Gflop/s: (2mn^2 - 2n^3/3) for R, the same again for Q
 (Table 2 of the paper counts Q + R as twice R), plus 4mn + n^2 for the
 solve.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
-one GPU; the sharding design is described in the design doc.
+Other workloads, one JSON line each:
+  --workload mixed  4,194,304 x 128, A = U diag(s) V^T with s log-spaced
+                    from 1 to 1e-6; factor + least squares (b ~ N(0,1) and a
+                    consistent b), mixed precision beside FP64, with the
+                    backward error of every solution;
+  --workload batch  512 matrices, m ~ U[1000, 200000], n in {8,16,32,64},
+                    odd ones mixed, one b each: autotuned plan, one captured
+                    graph per run, beside 512 sequential single calls;
+  --workload copy   a plain 1 GiB device copy (calibrates HBM counters).
+
+--gpus N > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -58,6 +68,7 @@ def cpu_baseline(m: int, n: int, mb: int, passes: int):
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="single", choices=["single", "mixed", "batch", "copy"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -71,7 +82,10 @@ def main():
         print("bench.py runs on exactly one GPU; multi-GPU sharding of TSQR is a design "
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
+    {"single": run_single, "mixed": run_mixed, "batch": run_batch, "copy": run_copy}[args.workload](args)
 
+
+def run_single(args):
     import torch
     import paper_0912_2572_amd as tl
     import synth
@@ -154,6 +168,188 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(m, n, mb, args.cpu_passes)
     print(json.dumps(line), flush=True)
+
+
+def _eta(A, x, b):
+    """Backward-error proxy ||A^T (b - A x)|| / (||A||_F (||A||_F ||x|| + ||b||)), FP64 on the GPU."""
+    import torch
+    r = b - A @ x
+    nA = torch.linalg.norm(A)
+    return float(torch.linalg.norm(A.t() @ r) / (nA * (nA * torch.linalg.norm(x) + torch.linalg.norm(b))))
+
+
+def run_mixed(args):
+    """Config with kappa = 1e6: FP64 path vs mixed path, factor + 2-RHS solve."""
+    import torch
+    import paper_0912_2572_amd as tl
+    import synth
+    m, n = 4194304, 128
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    G1 = torch.randn((n, m), generator=g, device=dev, dtype=torch.float64).t()
+    G2 = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64)
+    U, _ = torch.linalg.qr(G1)
+    V, _ = torch.linalg.qr(G2)
+    s = torch.as_tensor(synth.log_spaced_spectrum(n, -6.0), device=dev)
+    A = ((U * s) @ V.t()).t().contiguous().t()
+    del G1, U
+    b = torch.randn(m, generator=g, device=dev, dtype=torch.float64)
+    xt = torch.randn(n, generator=g, device=dev, dtype=torch.float64)
+    bc = A @ xt
+    B = torch.stack([b, bc], dim=1).t().contiguous().t()
+    flops = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0 + 2 * (4.0 * m * n + n * n)
+    out = {}
+    for name, prec in (("f64", tl.F64), ("mixed", tl.MIXED)):
+        o = tl.opts(row_block=4096, prec=prec, lsq_max_rhs=2)
+        work = torch.empty(tl.workspace_bytes(m, n, o), dtype=torch.uint8, device=dev)
+        X = tl.empty_colmajor(n, 2, device=dev)
+        res = torch.empty(2, dtype=torch.float64, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+
+        def step():
+            f = tl.Factors(A, o, work=work)
+            f.lsq(B, A=A, X=X, resid=res, info=info)
+            return f
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        tl.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            f = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        kern = tl.prof_query()
+        tl.prof_enable(False)
+        sweeps = f.last_refine_iters()
+        e1 = [_eta(A, X[:, c], B[:, c]) for c in range(2)]
+        out[name] = {"ms": ms, "gflops": flops / (ms * 1e-3) / 1e9, "eta": e1, "sweeps": sweeps,
+                     "x": X.clone(),
+                     "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kern.items()}}
+        del work
+    xf, xm = out["f64"]["x"], out["mixed"]["x"]
+    e2 = [float(torch.linalg.norm(xm[:, c] - xf[:, c]) / torch.linalg.norm(xf[:, c])) for c in range(2)]
+    e_true = float(torch.linalg.norm(xm[:, 1] - xt) / torch.linalg.norm(xt))
+    line = {
+        "metric": "TSQR least squares Gflop/s (factor + 2-RHS solve), mixed vs FP64 at kappa 1e6",
+        "value": round(out["mixed"]["gflops"], 2),
+        "unit": "Gflop/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(out["mixed"]["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic U diag(s) V^T, U, V from QR of torch N(0,1) draws (Philox, seed 0)",
+        "config": {"workload": f"tsqr_lsq_conditioned {m}x{n}", "m": m, "n": n, "row_block": 4096,
+                   "tree": "binary", "rhs": 2, "kappa": 1e6},
+        "f64": {k: v for k, v in out["f64"].items() if k != "x"},
+        "mixed": {k: v for k, v in out["mixed"].items() if k != "x"},
+        "mixed_vs_f64_rel_x": e2,
+        "mixed_consistent_rhs_rel_err_x_true": e_true,
+        "speedup_mixed_over_f64": round(out["f64"]["ms"] / out["mixed"]["ms"], 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_batch(args):
+    """512 independent least-squares problems through the batched path."""
+    import numpy as np
+    import torch
+    import paper_0912_2572_amd as tl
+    import synth
+    dev = torch.device("cuda:0")
+    shapes = synth.batch_shapes(512, seed=0)
+    precs = [j % 2 for j in range(len(shapes))]
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    As, bs = [], []
+    for m, n in shapes:
+        As.append(torch.randn((n, m), generator=g, device=dev, dtype=torch.float64).t())
+        bs.append(torch.randn(m, generator=g, device=dev, dtype=torch.float64))
+    torch.cuda.synchronize()
+    # the table depends only on the (n class, precision) classes, so it is
+    # tuned on every 4th matrix of the batch
+    t0 = time.perf_counter()
+    table = tl.autotune(As[::4], bs[::4], precs[::4], reps=1)
+    tune_s = time.perf_counter() - t0
+    B = tl.Batch(As, bs, precs, tune=table, refine_sweeps=4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(max(args.warmup, 1)):
+            B.run(use_graph=True, stream=stream)
+        stream.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            B.run(use_graph=True, stream=stream)
+        ev1.record(stream)
+    stream.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    flops = sum(2.0 * m * n * n - 2.0 * n ** 3 / 3.0 + 4.0 * m * n + n * n for m, n in shapes)
+    # algorithmic HBM bytes of one run: read A, write V (e = 8 or 4), read V
+    # and b for Q^T b; the mixed matrices' refinement sweeps are not counted
+    alg = sum(8.0 * m * n + 2 * (8 if p == 0 else 4) * m * n + 16.0 * m
+              for (m, n), p in zip(shapes, precs))
+    eta = []
+    infos = 0
+    for i in range(0, len(shapes), 16):
+        infos += int(B.info(i).item() != 0)
+        eta.append(_eta(As[i], B.x(i), bs[i]))
+    # the launch-bound baseline: the same problems as 512 sequential single calls
+    fs = []
+    work = None
+
+    def seq():
+        nonlocal work
+        for i, (m, n) in enumerate(shapes):
+            mb, tree, P = B.plan(i)
+            o = tl.opts(row_block=mb, tree=tree, prec=precs[i], lsq_max_rhs=1)
+            need = tl.workspace_bytes(m, n, o)
+            if work is None or work.numel() < need:
+                work = torch.empty(max(need, 1 << 30), dtype=torch.uint8, device=dev)
+            f = tl.Factors(As[i], o, work=work)
+            f.lsq(bs[i].reshape(-1, 1), A=As[i])
+    seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    line = {
+        "metric": "batched TSQR + least squares Gflop/s (512 matrices, half mixed)",
+        "value": round(flops / (ms * 1e-3) / 1e9, 2),
+        "unit": "Gflop/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic iid N(0,1), torch Philox seed 1; shapes from numpy PCG64 seed 0",
+        "config": {"workload": "tsqr_batch_512", "count": len(shapes),
+                   "total_rows": int(sum(m for m, n in shapes)),
+                   "mixed": int(sum(precs)), "graph_launches": B.launches(), "refine_sweeps": 4},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_run": alg, "kernel": "whole graph"},
+        "solves_per_s": round(len(shapes) / (ms * 1e-3), 1),
+        "sequential_single_calls_ms": round(seq_ms, 3),
+        "speedup_vs_sequential": round(seq_ms / ms, 2),
+        "autotune_s": round(tune_s, 2),
+        "autotune_sample": "every 4th matrix (128)",
+        "tune_table": table,
+        "sampled_eta_max": max(eta),
+        "sampled_info_nonzero": infos,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_copy(args):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup + args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "launches": args.warmup + args.steps}), flush=True)
 
 
 if __name__ == "__main__":

@@ -250,12 +250,82 @@ TSQR_API int tsqr_batch_free(tsqr_batch b);
    warm-up, HIP events on `stream`) over row_block in {512, 1024, 2048,
    4096, 8192} x tree in {binary, 4-ary, flat}: first one setting for all
    matrices, then each (n class, precision) class on its own with the others
-   held at the best so far.  n classes are n <= 8, 16, 32, 64.  Writes at
+   held at the best so far (its row block, then its tree; a change is kept
+   when it saves at least 1 %).  n classes are n <= 8, 16, 32, 64.  Writes at
    most `cap` entries to out and returns the number written (< 0: error).
    dwork must hold tsqr_batch_workspace_bytes(count, items, NULL, 0); the
    items' outputs are overwritten. */
 TSQR_API int tsqr_autotune(int count, const tsqr_batch_item *items, int reps, void *dwork,
                            size_t work_bytes, void *stream, tsqr_tune_entry *out, int cap);
+
+/* ------------------------------------------------------------------------
+   Serving: a request loop for least-squares solves of different sizes.
+   Requests arrive with HOST matrices; the server admits them while its
+   device memory budget and slot count allow (continuous batching: requests
+   admitted while others run share the GPU through several HIP streams),
+   copies A and B in, factors A (tsqr_factor) unless a factor of the same
+   matrix is cached, solves (tsqr_lsq_solve) and copies X, the residual norms
+   and info back.  Factors of finished requests stay cached (LRU) while the
+   budget allows, so a repeated matrix costs only the solve.
+   Allocation: tsqr_server_create allocates ONE device arena of hbm_budget
+   bytes (hipMalloc) and creates the streams and events; everything else is
+   carved from the arena.  tsqr_server_free releases them.  Host buffers
+   should be pinned (hipHostMalloc) for the copies to overlap.
+   Not thread-safe: one host thread drives a server.
+   ------------------------------------------------------------------------ */
+typedef struct tsqr_server_s *tsqr_server;
+
+typedef struct {
+    size_t hbm_budget;      /* device bytes of the arena                     */
+    int32_t streams;        /* HIP streams (>= 1)                            */
+    int32_t max_inflight;   /* requests admitted at once (>= 1)              */
+    int32_t cache;          /* 1: keep factors of finished requests          */
+    int32_t prec;           /* TSQR_F64 or TSQR_MIXED for every request      */
+    int32_t tree;           /* TSQR_TREE_*                                   */
+    int32_t reserved;
+} tsqr_server_opts;
+
+typedef struct {
+    int64_t matrix_id;      /* requests with equal ids share A (same m, n)   */
+    int64_t m, n, k;        /* 1 <= n <= 256, n <= m, 1 <= k <= 8            */
+    const double *A;        /* host, m x n column-major (lda = m); read at   */
+                            /* admission unless the factor is cached         */
+    const double *B;        /* host, m x k column-major (ldb = m)            */
+    double *X;              /* host output, n x k (ldx = n)                  */
+    double *resid;          /* host output, k residual norms                 */
+    int32_t *info;          /* host output, tsqr_lsq_solve's dinfo           */
+} tsqr_request;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t cache_hits, evictions;
+    size_t bytes_in_use, bytes_peak;
+    double busy_seconds;            /* time with >= 1 request admitted       */
+    double byte_seconds;            /* integral of bytes in use over time    */
+} tsqr_server_stats;
+
+TSQR_API void tsqr_server_default_opts(tsqr_server_opts *o);
+TSQR_API int tsqr_server_create(const tsqr_server_opts *o, tsqr_server *out);
+/* Queues a request (the descriptor is copied; its host buffers must stay
+   valid until the request is done).  Returns a ticket >= 0 or an error:
+   -2 shape out of scope, -3 NULL buffer, -4 matrix_id reused with another
+   shape, TSQR_ERR_WORKSPACE when it can never fit the budget. */
+TSQR_API int64_t tsqr_server_submit(tsqr_server s, const tsqr_request *r);
+/* Retires finished requests and admits queued ones (FIFO; a request that
+   does not fit waits, after evicting idle cached factors, until memory
+   frees up).  wait = 1 blocks until at least one request finishes when
+   any is running.  Returns the number of requests queued or running. */
+TSQR_API int tsqr_server_progress(tsqr_server s, int wait);
+/* 1 when the request's outputs are written, 0 while pending, < 0 on error. */
+TSQR_API int tsqr_server_status(tsqr_server s, int64_t ticket);
+/* Steady-clock times (s) of submission, admission and completion. */
+TSQR_API int tsqr_server_times(tsqr_server s, int64_t ticket, double *t_submit, double *t_admit,
+                               double *t_done);
+TSQR_API int tsqr_server_get_stats(tsqr_server s, tsqr_server_stats *st);
+/* Finishes every request, then frees the arena, streams and handle. */
+TSQR_API int tsqr_server_free(tsqr_server s);
+/* Seconds on the server's steady clock (for arrival schedules). */
+TSQR_API double tsqr_server_now(void);
 
 /* Frees the host handle only (the workspace belongs to the caller). */
 TSQR_API int tsqr_free(tsqr_factors f);

@@ -68,6 +68,46 @@ class BatchItem(ctypes.Structure):
 
 BATCH_DEFAULT_ROW_BLOCK = 4096
 
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("streams", ctypes.c_int32),
+        ("max_inflight", ctypes.c_int32),
+        ("cache", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("tree", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("matrix_id", ctypes.c_int64),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int64),
+        ("A", ctypes.c_void_p),
+        ("B", ctypes.c_void_p),
+        ("X", ctypes.c_void_p),
+        ("resid", ctypes.c_void_p),
+        ("info", ctypes.c_void_p),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("cache_hits", ctypes.c_int64),
+        ("evictions", ctypes.c_int64),
+        ("bytes_in_use", ctypes.c_size_t),
+        ("bytes_peak", ctypes.c_size_t),
+        ("busy_seconds", ctypes.c_double),
+        ("byte_seconds", ctypes.c_double),
+    ]
+
 _lib = None
 
 
@@ -117,6 +157,23 @@ def lib():
         L.tsqr_batch_launches.argtypes = [vp]
         L.tsqr_batch_free.argtypes = [vp]
         L.tsqr_autotune.argtypes = [ctypes.c_int, bip, ctypes.c_int, vp, sz, vp, tep, ctypes.c_int]
+        sop = ctypes.POINTER(ServerOpts)
+        L.tsqr_server_default_opts.argtypes = [sop]
+        L.tsqr_server_default_opts.restype = None
+        L.tsqr_server_create.argtypes = [sop, ctypes.POINTER(vp)]
+        L.tsqr_server_submit.argtypes = [vp, ctypes.POINTER(Request)]
+        L.tsqr_server_submit.restype = i64
+        L.tsqr_server_progress.argtypes = [vp, ctypes.c_int]
+        L.tsqr_server_status.argtypes = [vp, i64]
+        L.tsqr_server_times.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.tsqr_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.tsqr_server_free.argtypes = [vp]
+        L.tsqr_server_now.argtypes = []
+        L.tsqr_server_now.restype = ctypes.c_double
+        for name in ("tsqr_server_create", "tsqr_server_progress", "tsqr_server_status",
+                     "tsqr_server_times", "tsqr_server_get_stats", "tsqr_server_free"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("tsqr_factor", "tsqr_get_r", "tsqr_apply_qt", "tsqr_apply_q", "tsqr_form_q",
                      "tsqr_lsq_solve", "tsqr_last_refine_iters", "tsqr_plan_info", "tsqr_free",
                      "tsqr_batch_create", "tsqr_batch_bad_item", "tsqr_batch_run", "tsqr_batch_plan",
@@ -436,3 +493,93 @@ def autotune(As, bs, precs, reps: int = 2, stream=None):
         raise TSQRError(rc, "tsqr_autotune")
     return [{"n_max": out[i].n_max, "prec": out[i].prec, "row_block": out[i].row_block,
              "tree": out[i].tree} for i in range(rc)]
+
+
+# ---------------------------------------------------------------------------
+# Serving
+
+
+def _host_colmajor_ptr(t: torch.Tensor, name: str) -> int:
+    if t.device.type != "cpu" or t.dtype not in (torch.float64, torch.int32):
+        raise TypeError(f"{name} must be a host float64/int32 tensor")
+    if t.dim() == 2 and not (t.stride(0) == 1 and (t.shape[1] == 1 or t.stride(1) == t.shape[0])):
+        raise ValueError(f"{name} must be dense column-major")
+    if t.dim() == 1 and t.stride(0) != 1:
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+class Server:
+    """Least-squares request server (tsqr_server_* in the C ABI).  Host
+    tensors passed to submit() must stay alive until the request is done;
+    the server keeps references to them."""
+
+    def __init__(self, hbm_budget: int = 8 << 30, streams: int = 4, max_inflight: int = 16,
+                 cache: bool = True, prec: int = F64, tree: int = TREE_BINARY):
+        o = ServerOpts()
+        lib().tsqr_server_default_opts(ctypes.byref(o))
+        o.hbm_budget, o.streams, o.max_inflight = hbm_budget, streams, max_inflight
+        o.cache, o.prec, o.tree = 1 if cache else 0, prec, tree
+        h = ctypes.c_void_p()
+        _check(lib().tsqr_server_create(ctypes.byref(o), ctypes.byref(h)), "tsqr_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, matrix_id: int, A: torch.Tensor, B: torch.Tensor, X: torch.Tensor,
+               resid: torch.Tensor, info: torch.Tensor) -> int:
+        m, n = A.shape
+        k = 1 if B.dim() == 1 else B.shape[1]
+        r = Request()
+        r.matrix_id, r.m, r.n, r.k = matrix_id, m, n, k
+        r.A = _host_colmajor_ptr(A, "A")
+        r.B = _host_colmajor_ptr(B, "B")
+        r.X = _host_colmajor_ptr(X, "X")
+        r.resid = _host_colmajor_ptr(resid, "resid")
+        r.info = _host_colmajor_ptr(info, "info")
+        t = int(lib().tsqr_server_submit(self._h, ctypes.byref(r)))
+        if t < 0:
+            raise TSQRError(t, "tsqr_server_submit")
+        self._keep[t] = (A, B, X, resid, info)
+        return t
+
+    def progress(self, wait: bool = False) -> int:
+        rc = int(lib().tsqr_server_progress(self._h, 1 if wait else 0))
+        if rc < 0:
+            raise TSQRError(rc, "tsqr_server_progress")
+        return rc
+
+    def drain(self):
+        while self.progress(wait=True) > 0:
+            pass
+
+    def status(self, t: int) -> int:
+        return int(lib().tsqr_server_status(self._h, t))
+
+    def times(self, t: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().tsqr_server_times(self._h, t, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "tsqr_server_times")
+        return a.value, b.value, c.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().tsqr_server_get_stats(self._h, ctypes.byref(st)), "tsqr_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def release(self, t: int):
+        """Drops the references kept for a finished request."""
+        self._keep.pop(t, None)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tsqr_server_free(h)
+            self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        self.close()
+
+
+def server_now() -> float:
+    return float(lib().tsqr_server_now())

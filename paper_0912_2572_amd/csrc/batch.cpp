@@ -508,21 +508,31 @@ TSQR_API int tsqr_autotune(int count, const tsqr_batch_item *items, int reps, vo
                 first = false;
             }
         }
-    // stage 2: each class on its own
-    for (size_t c = 0; c < cur.size(); ++c)
-        for (int64_t mb : kTuneMb)
-            for (int tr : kTuneTree) {
-                if (cur[c].row_block == mb && cur[c].tree == tr) continue;
-                std::vector<tsqr_tune_entry> t = cur;
-                t[c].row_block = mb;
-                t[c].tree = tr;
-                float ms = 0.f;
-                if ((rc = time_table(t, &ms))) goto done;
-                if (ms < 0.99f * best) {
-                    best = ms;
-                    cur = t;
-                }
+    // stage 2: each class's row block on its own, then its tree
+    for (size_t c = 0; c < cur.size(); ++c) {
+        for (int64_t mb : kTuneMb) {
+            if (cur[c].row_block == mb) continue;
+            std::vector<tsqr_tune_entry> t = cur;
+            t[c].row_block = mb;
+            float ms = 0.f;
+            if ((rc = time_table(t, &ms))) goto done;
+            if (ms < 0.99f * best) {
+                best = ms;
+                cur = t;
             }
+        }
+        for (int tr : kTuneTree) {
+            if (cur[c].tree == tr) continue;
+            std::vector<tsqr_tune_entry> t = cur;
+            t[c].tree = tr;
+            float ms = 0.f;
+            if ((rc = time_table(t, &ms))) goto done;
+            if (ms < 0.99f * best) {
+                best = ms;
+                cur = t;
+            }
+        }
+    }
     for (size_t c = 0; c < cur.size(); ++c) out[c] = cur[c];
     rc = (int)cur.size();
 done:

@@ -127,3 +127,21 @@ def test_batch_create_rejects_on_host(tl):
                                ctypes.byref(h)) == -5
     assert not h.value
     assert L.tsqr_autotune(1, items, 0, None, 0, None, None, 0) == -3
+
+
+def test_server_options_checked_on_host(tl):
+    L = tl.lib()
+    o = tl.ServerOpts()
+    L.tsqr_server_default_opts(ctypes.byref(o))
+    assert o.streams >= 1 and o.max_inflight >= 1 and o.cache == 1
+    h = ctypes.c_void_p()
+    o.streams = 0
+    assert L.tsqr_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    L.tsqr_server_default_opts(ctypes.byref(o))
+    o.hbm_budget = 1000
+    assert L.tsqr_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    L.tsqr_server_default_opts(ctypes.byref(o))
+    o.prec = 5
+    assert L.tsqr_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    assert not h.value
+    assert L.tsqr_server_submit(None, None) == -1
