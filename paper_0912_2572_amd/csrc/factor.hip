@@ -165,21 +165,20 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     const int rgw = w * 4 + rg;
     const int par = j & 1;
     // first chunk: row j is the pivot row, reduced separately (qv) and left
-    // out of the dots.
+    // out of the dots.  Lane-dependent choices below are selects, not
+    // branches, so the wave keeps one execution mask.
     const bool own_j = FIRST && (rgw == (j % kRowGroups));
     const int ij = j / kRowGroups;
     double qv[NS];
     if (FIRST) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) qv[t] = 0.0;
-        if (own_j) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
-                if (i == ij) {
+        for (int i = 0; i < RPT; ++i) {
+            const bool piv = own_j && (i == ij);
 #pragma unroll
-                    for (int t = 0; t < NS; ++t) qv[t] = c[i][t];
-                    x[i] = 0.0;
-                }
+            for (int t = 0; t < NS; ++t) qv[t] = piv ? c[i][t] : qv[t];
+            x[i] = piv ? 0.0 : x[i];
         }
     }
     // prefetch column j + 1 (pre-update) from its owner lane
@@ -195,22 +194,27 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
 #pragma unroll
         for (int i = 0; i < RPT; ++i) xn[i] = 0.0;
     }
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPT; i += 2) {
-            s0 = fma(x[i], c[i][t], s0);
-            s1 = fma(x[i + 1], c[i + 1][t], s1);
-        }
-        const double p = pair_sum32(pair_sum16(s0 + s1));
-        if (rg == t) sm.u.s.red[par][cg + 16 * t][w] = p;
-    }
-    if (FIRST) {
+    // dots; lane (cg, rg) publishes the wave's partial of column cg + 16 rg
+    {
+        double pub = 0.0, pubq = 0.0;
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            const double p = pair_sum32(pair_sum16(qv[t]));
-            if (rg == t) sm.u.s.redq[par][cg + 16 * t][w] = p;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; i += 2) {
+                s0 = fma(x[i], c[i][t], s0);
+                s1 = fma(x[i + 1], c[i + 1][t], s1);
+            }
+            const double p = pair_sum32(pair_sum16(s0 + s1));
+            pub = (rg == t) ? p : pub;
+            if (FIRST) {
+                const double pq = pair_sum32(pair_sum16(qv[t]));
+                pubq = (rg == t) ? pq : pubq;
+            }
+        }
+        if (rg < NS) {
+            sm.u.s.red[par][cg + 16 * rg][w] = pub;
+            if (FIRST) sm.u.s.redq[par][cg + 16 * rg][w] = pubq;
         }
     }
     __syncthreads();
@@ -240,14 +244,14 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     {
         const double fn = (tau * fma(s, dn, en)) * s;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) xn[i] = fma(-fn, x[i], xn[i]);
-        if (own_j) {
-#pragma unroll
-            for (int i = 0; i < RPT; ++i)
-                if (i == ij) xn[i] = 0.0;
+        for (int i = 0; i < RPT; ++i) {
+            const double u = fma(-fn, x[i], xn[i]);
+            xn[i] = (FIRST && own_j && i == ij) ? 0.0 : u;
         }
     }
-    // trailing update (k > j), reflector (k == j), Gram entries (k < j)
+    // trailing update (k > j), reflector (k == j), Gram entries (k < j).
+    // Slots t < TJ hold only columns k < j and slots t > TJ only k > j
+    // (both known at compile time); slot TJ mixes all three by lane.
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
@@ -257,23 +261,26 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
             if (want_t && rgw == 0) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
             continue;
         }
-        if (k > j) {
-            const double wv = fma(s, d, e);
+        const double wv = fma(s, d, e);
+        if (t > TJ) {
             const double f = (tau * wv) * s;
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
-            if (own_j) {
-#pragma unroll
-                for (int i = 0; i < RPT; ++i)
-                    if (i == ij) c[i][t] = 0.0;
+            for (int i = 0; i < RPT; ++i) {
+                const double u = fma(-f, x[i], c[i][t]);
+                c[i][t] = (FIRST && own_j && i == ij) ? 0.0 : u;
             }
             rnew[t] = e - tau * wv;
-        } else if (k == j) {
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) c[i][t] = s * x[i];
-            rnew[t] = beta;
         } else {
-            if (want_t && rgw == 0) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
+            const bool upd = cg > q, refl = cg == q;
+            const double f = upd ? (tau * wv) * s : 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const double u = fma(-f, x[i], c[i][t]);
+                const double r = refl ? s * x[i] : u;
+                c[i][t] = (FIRST && own_j && upd && i == ij) ? 0.0 : r;
+            }
+            rnew[t] = upd ? e - tau * wv : beta;
+            if (want_t && rgw == 0 && cg < q) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
         }
     }
     if (tid == 0) sm.tau[j] = tau;
