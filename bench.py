@@ -92,6 +92,23 @@ def main():
      "copy": run_copy}[args.workload](args)
 
 
+def counted_traffic(kernel: str, m: int, n: int, mb: int):
+    """HBM bytes per launch from the committed counter record of this kernel
+    and workload (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None
+    when there is none or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{m}x{n}_hbm.json")
+    if not os.path.exists(path) or mb != 4096:
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def run_single(args):
     import torch
     import paper_0912_2572_amd as tl
@@ -151,7 +168,8 @@ def run_single(args):
     if ab is not None:
         gbs = ab / avg_s / 1e9
         roof = {"kernel": dom_name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "traffic": counted_traffic(dom_name, m, n, mb),
                 "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": ab}
     line = {
         "metric": "TSQR Gflop/s (factor + thin Q + LSQ), FP64",
