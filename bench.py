@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--row-block", type=int, default=4096)
-    ap.add_argument("--cpu-passes", type=int, default=5)
+    ap.add_argument("--cpu-passes", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

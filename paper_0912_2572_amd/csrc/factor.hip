@@ -126,19 +126,26 @@ struct StepState {
     int jprev = -1;
 };
 
-// Sum over the waves' partials of column k, in a fixed order.  The
-// scheduling barrier keeps the compiler from hoisting every column's loads
-// at once (which would spill the register tile).
-__device__ __forceinline__ double sum_waves(const double (&a)[2][64][kWaves], int par, int k) {
-    const double2 *p = reinterpret_cast<const double2 *>(&a[par][k][0]);
+// Total of column `lane` over the waves' partials, in a fixed order (every
+// wave computes the same bits).  Lane k of each wave then holds column k's
+// total; a thread takes the totals of its own columns from those lanes.
+__device__ __forceinline__ double col_total(const double (&a)[2][64][kWaves], int par) {
+    const int lane = threadIdx.x & 63;
+    const double2 *p = reinterpret_cast<const double2 *>(&a[par][lane][0]);
     double2 v[kWaves / 2];
 #pragma unroll
     for (int h = 0; h < kWaves / 2; ++h) v[h] = p[h];
     double s = v[0].x + v[0].y;
 #pragma unroll
     for (int h = 1; h < kWaves / 2; ++h) s = (s + v[h].x) + v[h].y;
-    __builtin_amdgcn_sched_barrier(0);
     return s;
+}
+
+// Value of v in lane `src` (uniform across the wave).
+__device__ __forceinline__ double read_lane(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
 }
 
 // Column step j (= 16 TJ + q) of chunk_qr.  TJ is a template parameter so
@@ -194,23 +201,39 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
 #pragma unroll
         for (int i = 0; i < RPT; ++i) xn[i] = 0.0;
     }
-    // dots; lane (cg, rg) publishes the wave's partial of column cg + 16 rg
+    // dots, the NS slots' accumulator chains interleaved; lane (cg, rg)
+    // publishes the wave's partial of column cg + 16 rg
     {
-        double pub = 0.0, pubq = 0.0;
+        double s0[NS], s1[NS], p[NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            double s0 = 0.0, s1 = 0.0;
+            s0[t] = 0.0;
+            s1[t] = 0.0;
+        }
 #pragma unroll
-            for (int i = 0; i < RPT; i += 2) {
-                s0 = fma(x[i], c[i][t], s0);
-                s1 = fma(x[i + 1], c[i + 1][t], s1);
+        for (int i = 0; i < RPT; i += 2) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                s0[t] = fma(x[i], c[i][t], s0[t]);
+                s1[t] = fma(x[i + 1], c[i + 1][t], s1[t]);
             }
-            const double p = pair_sum32(pair_sum16(s0 + s1));
-            pub = (rg == t) ? p : pub;
-            if (FIRST) {
-                const double pq = pair_sum32(pair_sum16(qv[t]));
-                pubq = (rg == t) ? pq : pubq;
-            }
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) p[t] = pair_sum16(s0[t] + s1[t]);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) p[t] = pair_sum32(p[t]);
+        double pub = p[0], pubq = 0.0;
+#pragma unroll
+        for (int t = 1; t < NS; ++t) pub = (rg == t) ? p[t] : pub;
+        if (FIRST) {
+            double pq[NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) pq[t] = pair_sum16(qv[t]);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) pq[t] = pair_sum32(pq[t]);
+            pubq = pq[0];
+#pragma unroll
+            for (int t = 1; t < NS; ++t) pubq = (rg == t) ? pq[t] : pubq;
         }
         if (rg < NS) {
             sm.u.s.red[par][cg + 16 * rg][w] = pub;
@@ -227,13 +250,22 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
             if (k >= jprev) sm.R[jprev * kLdsStride + k] = rnew[t];
         }
     }
-    const double sig2 = sum_waves(sm.u.s.red, par, j);
+    const double tot = col_total(sm.u.s.red, par);
+    const double totq = FIRST ? col_total(sm.u.s.redq, par) : 0.0;
+    // this thread's columns: dots d and the pivot-row entries e
+    double dv[NS], ev[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        dv[t] = __shfl(tot, cg + 16 * t);
+        ev[t] = FIRST ? __shfl(totq, cg + 16 * t) : sm.R[j * kLdsStride + cg + 16 * t];
+    }
+    const double sig2 = read_lane(tot, j);
     const bool has_next = j + 1 < n;
-    const double dn = has_next ? sum_waves(sm.u.s.red, par, j + 1) : 0.0;
+    const double dn = has_next ? read_lane(tot, j + 1) : 0.0;
     double alpha, en = 0.0;
     if (FIRST) {
-        alpha = sum_waves(sm.u.s.redq, par, j);
-        if (has_next) en = sum_waves(sm.u.s.redq, par, j + 1);
+        alpha = read_lane(totq, j);
+        if (has_next) en = read_lane(totq, j + 1);
     } else {
         alpha = sm.R[j * kLdsStride + j];
         if (has_next) en = sm.R[j * kLdsStride + j + 1];
@@ -255,8 +287,8 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
-        const double d = sum_waves(sm.u.s.red, par, k);
-        const double e = FIRST ? sum_waves(sm.u.s.redq, par, k) : sm.R[j * kLdsStride + k];
+        const double d = dv[t];
+        const double e = ev[t];
         if (t < TJ) {
             if (want_t && rgw == 0) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
             continue;
