@@ -62,6 +62,16 @@ hipError_t leaf_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsr
     const PanelArgs pa = panel_args(p);
     const int64_t off = p.row_off + (int64_t)p.col_off * P.m;
     const double *Tc = at<double>(f, p.off_tc);
+    if (k <= tsqr::kApply3MaxCols && Bsrc == B && p.off_pz) {
+        // few columns: chunk-parallel three-pass form
+        double *Pc = at<double>(f, p.off_pz);
+        double *Zc = Pc + (size_t)p.n * 16 * (size_t)p.total_chunks;
+        if (is_mixed(f))
+            return tsqr::launch_leaf_apply3_32(at<float>(f, P.off_w32) + off, P.m, Tc, pa, B, ldb, k, trans, Pc,
+                                               Zc, st);
+        return tsqr::launch_leaf_apply3(at<double>(f, P.off_w) + off, P.m, Tc, pa, B, ldb, k, trans, Pc, Zc,
+                                        st);
+    }
     if (is_mixed(f))
         return tsqr::launch_leaf_apply_m32(at<float>(f, P.off_w32) + off, P.m, Tc, pa, Bsrc, ldbs, B, ldb,
                                            k, trans, st);

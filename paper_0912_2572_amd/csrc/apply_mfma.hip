@@ -266,4 +266,284 @@ hipError_t launch_leaf_apply_m32(const float *V, int64_t ldv, const double *Tc, 
                                    trans ? "leaf_apply_qt_f32" : "leaf_apply_q_f32", st);
 }
 
+// ---------------------------------------------------------------------------
+// Three-pass leaf apply for few columns (k <= 16).  The chunk chain of a
+// domain couples chunks only through the n x k running top rows Y, so
+//   pass 1 (every chunk at once):  P_c = V_c^T B_c            (a first chunk
+//                                  from row n on: its top rows are Y)
+//   pass 2 (one workgroup/domain): the chain on n x k blocks,
+//          Q^T: W_0 = V_0top^T Y + P_0, Z_0 = T_0^T W_0, Y <- Y - V_0top Z_0,
+//               then W_c = Y + P_c, Z_c = T_c^T W_c, Y <- Y - Z_c (c = 1..),
+//          Q:   chunks last to first with T_c, chunk 0 last, top rows
+//               written as Y - V_0top Z_0;
+//   pass 3 (every chunk at once):  B_c <- B_c - V_c Z_c   (rows below the
+//                                  top rows of a first chunk).
+// V is streamed twice across the whole device instead of once chunk after
+// chunk; the chain touches only T and n x k blocks.  P_c and Z_c are n x k
+// column-major blocks, one per chunk.
+
+// Rows [rlo, valid) of chunk c: W(n x kc) = V_c^T B_c, reduced over the
+// waves into sm.W (tile precision).
+template <typename Tile>
+struct VtbSmem {
+    using T = typename Tile::T;
+    T Wp[4][64][KBM];
+    T W[64][KBM];
+};
+
+template <typename Tile>
+__device__ __forceinline__ void chunk_vtb(VtbSmem<Tile> &sm, const typename Tile::T *__restrict__ Vc,
+                                          int64_t ldv, const double *__restrict__ Bc, int64_t ldb,
+                                          int64_t rlo, int64_t valid, int n, int kc, bool first) {
+    using T = typename Tile::T;
+    using Acc = typename Tile::Acc;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    const int mtn = (n + 15) >> 4;
+    Acc acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = Acc{0, 0, 0, 0};
+    const int64_t span = valid - rlo;
+    const int64_t per = ((span + 15) / 16 + 3) / 4 * 16;
+    const int64_t lo = rlo + w * per, hi = (lo + per < valid) ? lo + per : valid;
+    for (int64_t r4 = lo; r4 < hi; r4 += 4) {
+        const int64_t row = r4 + l4;
+        const T b = T((row < hi && l16 < kc) ? Bc[row + (int64_t)l16 * ldb] : 0.0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            if (mt >= mtn) break;
+            const T a = (row < hi) ? v_elem<T>(Vc, ldv, row, 16 * mt + l16, valid, n, first) : T(0);
+            acc[mt] = Tile::mfma(a, b, acc[mt]);
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sm.Wp[w][16 * mt + Tile::drow(r, lane)][l16] = acc[mt][r];
+    __syncthreads();
+    for (int e = tid; e < 64 * KBM; e += 256) {
+        const int m = e >> 4, j = e & 15;
+        sm.W[m][j] = ((sm.Wp[0][m][j] + sm.Wp[1][m][j]) + sm.Wp[2][m][j]) + sm.Wp[3][m][j];
+    }
+    __syncthreads();
+}
+
+template <typename Tile>
+__global__ __launch_bounds__(256) void k_apply_p1(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                                  PanelArgs pa, const double *__restrict__ B, int64_t ldb,
+                                                  int64_t k, double *__restrict__ Pc) {
+    extern __shared__ double smem_raw[];
+    VtbSmem<Tile> &sm = *reinterpret_cast<VtbSmem<Tile> *>(smem_raw);
+    const int64_t dom = blockIdx.y, ch = blockIdx.x;
+    const int n = pa.n;
+    const int64_t row0 = dom * pa.mb;
+    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
+    if (ch >= nch) return;
+    const int kc = (int)k;
+    const int64_t r0 = row0 + ch * pa.chunk;
+    const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
+    chunk_vtb<Tile>(sm, V + r0, ldv, B + r0, ldb, ch == 0 ? n : 0, valid, n, kc, ch == 0);
+    double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
+    for (int e = threadIdx.x; e < n * kc; e += 256) {
+        const int m = e % n, j = e / n;
+        P[e] = (double)sm.W[m][j];
+    }
+}
+
+struct ChainSmem {
+    double Tm[64 * kLdsStride];
+    double V0[64 * kLdsStride];   // unit lower V_0top of the first chunk
+    double Y[64][KBM];
+    double W[64][KBM];
+    double Z[64][KBM];
+};
+
+// Pass 2 for one domain (FP64).
+__global__ __launch_bounds__(256) void k_apply_p2(const double *__restrict__ V64, const float *__restrict__ V32,
+                                                  int64_t ldv, const double *__restrict__ Tc, PanelArgs pa,
+                                                  double *__restrict__ B, int64_t ldb, int64_t k, int trans,
+                                                  const double *__restrict__ Pc, double *__restrict__ Zc) {
+    extern __shared__ double smem_raw[];
+    ChainSmem &sm = *reinterpret_cast<ChainSmem *>(smem_raw);
+    const int64_t dom = blockIdx.x;
+    const int n = pa.n, kc = (int)k, tid = threadIdx.x;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t row0 = dom * pa.mb;
+    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
+    for (int e = tid; e < 64 * KBM; e += 256) {
+        const int r = e >> 4, c = e & 15;
+        sm.Y[r][c] = (r < n && c < kc) ? B[row0 + r + (int64_t)c * ldb] : 0.0;
+    }
+    // V_0top, unit lower triangular (the reflector storage precision)
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e & 63, q = e >> 6;
+        double v = 0.0;
+        if (r < n && q < n) {
+            if (r == q) v = 1.0;
+            else if (r > q) v = V32 ? (double)V32[row0 + r + (int64_t)q * ldv] : V64[row0 + r + (int64_t)q * ldv];
+        }
+        sm.V0[r * kLdsStride + q] = v;
+    }
+    auto chunk_step = [&](int64_t ch) {
+        const double *Tk = Tc + (dom * pa.cpd + ch) * nn;
+        const double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
+        __syncthreads();
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e & 63, q = e >> 6;
+            sm.Tm[r * kLdsStride + q] = (r < n && q < n) ? Tk[r + (int64_t)q * n] : 0.0;
+        }
+        // W = (V_0top^T Y on a first chunk, else Y) + P_c
+        for (int e = tid; e < 64 * KBM; e += 256) {
+            const int m = e >> 4, j = e & 15;
+            double wv = 0.0;
+            if (m < n && j < kc) {
+                if (ch == 0) {
+                    for (int r = m; r < n; ++r) wv = fma(sm.V0[r * kLdsStride + m], sm.Y[r][j], wv);
+                } else {
+                    wv = sm.Y[m][j];
+                }
+                wv += P[m + (int64_t)j * n];
+            }
+            sm.W[m][j] = wv;
+        }
+        __syncthreads();
+        for (int e = tid; e < 64 * KBM; e += 256) {
+            const int i = e >> 4, j = e & 15;
+            double z = 0.0;
+            if (i < n) {
+                if (trans) {
+                    for (int q = 0; q <= i; ++q) z = fma(sm.Tm[q * kLdsStride + i], sm.W[q][j], z);
+                } else {
+                    for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.W[q][j], z);
+                }
+            }
+            sm.Z[i][j] = z;
+            if (i < n && j < kc) Zc[(dom * pa.cpd + ch) * (int64_t)n * k + i + (int64_t)j * n] = z;
+        }
+        __syncthreads();
+        // Y <- Y - Z, or on a first chunk Y <- Y - V_0top Z
+        for (int e = tid; e < 64 * KBM; e += 256) {
+            const int i = e >> 4, j = e & 15;
+            if (ch == 0) {
+                double u = 0.0;
+                for (int q = 0; q <= i && q < n; ++q) u = fma(sm.V0[i * kLdsStride + q], sm.Z[q][j], u);
+                sm.W[i][j] = sm.Y[i][j] - u;
+            } else {
+                sm.Y[i][j] -= sm.Z[i][j];
+            }
+        }
+        if (ch == 0) {
+            __syncthreads();
+            for (int e = tid; e < 64 * KBM; e += 256) {
+                const int i = e >> 4, j = e & 15;
+                sm.Y[i][j] = sm.W[i][j];
+            }
+        }
+    };
+    if (trans) {
+        for (int64_t ch = 0; ch < nch; ++ch) chunk_step(ch);
+    } else {
+        for (int64_t ch = nch - 1; ch >= 0; --ch) chunk_step(ch);
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * KBM; e += 256) {
+        const int r = e >> 4, c = e & 15;
+        if (r < n && c < kc) B[row0 + r + (int64_t)c * ldb] = sm.Y[r][c];
+    }
+}
+
+// Pass 3: B_c <- B_c - V_c Z_c over the chunk's rows (a first chunk from
+// row n on), transposed MFMA form as in chunk_apply_m; the Z operand stays in
+// registers, so the kernel needs no LDS and many workgroups share a CU.
+template <typename Tile>
+__global__ __launch_bounds__(256) void k_apply_p3(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                                  PanelArgs pa, double *__restrict__ B, int64_t ldb, int64_t k,
+                                                  const double *__restrict__ Zc) {
+    using T = typename Tile::T;
+    using Acc = typename Tile::Acc;
+    const int64_t dom = blockIdx.y, ch = blockIdx.x;
+    const int n = pa.n, kc = (int)k;
+    const int64_t row0 = dom * pa.mb;
+    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
+    if (ch >= nch) return;
+    const int64_t r0 = row0 + ch * pa.chunk;
+    const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
+    const bool first = ch == 0;
+    const double *Z = Zc + (dom * pa.cpd + ch) * (int64_t)n * k;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    const int kbn = (n + 3) >> 2;
+    // A[i][q] = Z^T[col i][reflector q] for q = 4 kb + l4
+    T za[16];
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) {
+        const int q = 4 * kb + l4;
+        za[kb] = (q < n && l16 < kc) ? T(Z[q + (int64_t)l16 * n]) : T(0);
+    }
+    const T *Vc = V + r0;
+    double *Bc = B + r0;
+    for (int64_t t0 = 16 * w; t0 < valid; t0 += 64) {
+        const int64_t row = t0 + l16;
+        const bool live = row < valid && !(first && row < n);
+        T vv[16];
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb)
+            vv[kb] = (kb < kbn && live) ? v_elem<T>(Vc, ldv, row, 4 * kb + l4, valid, n, first) : T(0);
+        Acc acc = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) {
+            if (kb >= kbn) break;
+            acc = Tile::mfma(za[kb], vv[kb], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = Tile::drow(r, lane);
+            if (live && col < kc) Bc[row + (int64_t)col * ldb] -= (double)acc[r];
+        }
+    }
+}
+
+template <typename Tile>
+static hipError_t launch_apply3(const typename Tile::T *V, const double *V64, const float *V32, int64_t ldv,
+                                const double *Tc, const PanelArgs &pa, double *B, int64_t ldb, int64_t k,
+                                int trans, double *Pc, double *Zc, hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    const size_t sh = sizeof(VtbSmem<Tile>);
+    hipError_t e = hipFuncSetAttribute((const void *)k_apply_p1<Tile>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_apply_p2, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(ChainSmem));
+    if (e != hipSuccess) return e;
+    const dim3 chunks((unsigned)max_domain_chunks(pa), (unsigned)pa.P);
+    {
+        ProfScope ps(trans ? "apply3_p1_qt" : "apply3_p1_q", st);
+        hipLaunchKernelGGL(k_apply_p1<Tile>, chunks, dim3(256), sh, st, V, ldv, pa, B, ldb, k, Pc);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        ProfScope ps(trans ? "apply3_p2_qt" : "apply3_p2_q", st);
+        hipLaunchKernelGGL(k_apply_p2, dim3((unsigned)pa.P), dim3(256), sizeof(ChainSmem), st, V64, V32, ldv,
+                           Tc, pa, B, ldb, k, trans, Pc, Zc);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    ProfScope ps(trans ? "apply3_p3_qt" : "apply3_p3_q", st);
+    hipLaunchKernelGGL(k_apply_p3<Tile>, chunks, dim3(256), 0, st, V, ldv, pa, B, ldb, k, Zc);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_apply3(const double *V, int64_t ldv, const double *Tc, const PanelArgs &pa, double *B,
+                              int64_t ldb, int64_t k, int trans, double *Pc, double *Zc, hipStream_t st) {
+    return launch_apply3<TileF64>(V, V, nullptr, ldv, Tc, pa, B, ldb, k, trans, Pc, Zc, st);
+}
+
+hipError_t launch_leaf_apply3_32(const float *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
+                                 double *B, int64_t ldb, int64_t k, int trans, double *Pc, double *Zc,
+                                 hipStream_t st) {
+    return launch_apply3<TileF32>(V, nullptr, V, ldv, Tc, pa, B, ldb, k, trans, Pc, Zc, st);
+}
+
 }  // namespace tsqr

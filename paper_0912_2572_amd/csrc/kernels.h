@@ -18,6 +18,13 @@ struct PanelArgs {
     int ns;         // column slots per thread of the leaf kernel
 };
 
+// Most chunks any domain has (the last domain can be longer than mb when a
+// short remainder was merged into it).
+inline int64_t max_domain_chunks(const PanelArgs &pa) {
+    const int64_t last = (pa.m - (pa.P - 1) * pa.mb + pa.chunk - 1) / pa.chunk;
+    return last > pa.cpd ? last : pa.cpd;
+}
+
 // One tree level: chains g = 0..chains-1 start at left = g * span and take
 // rights left + q * stride for q = 1.. while q * stride < span and < P.
 struct TreeArgs {
@@ -89,6 +96,16 @@ hipError_t launch_leaf_apply_m(const double *V, int64_t ldv, const double *Tc, c
 hipError_t launch_leaf_apply_m32(const float *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
                                  const double *Bsrc, int64_t ldbs, double *B, int64_t ldb, int64_t k,
                                  int trans, hipStream_t st);
+// Three-pass leaf apply for k <= 16 columns, in place on B (pass 1 P_c =
+// V_c^T B_c for every chunk, pass 2 the per-domain chain on n x k blocks,
+// pass 3 B_c -= V_c Z_c for every chunk).  Pc and Zc hold one n x k block
+// per chunk.
+constexpr int kApply3MaxCols = 16;
+hipError_t launch_leaf_apply3(const double *V, int64_t ldv, const double *Tc, const PanelArgs &pa, double *B,
+                              int64_t ldb, int64_t k, int trans, double *Pc, double *Zc, hipStream_t st);
+hipError_t launch_leaf_apply3_32(const float *V, int64_t ldv, const double *Tc, const PanelArgs &pa,
+                                 double *B, int64_t ldb, int64_t k, int trans, double *Pc, double *Zc,
+                                 hipStream_t st);
 hipError_t launch_tree_apply(const double *Rdom, const double *Tnode, const PanelArgs &pa,
                              const TreeArgs &ta, double *B, int64_t ldb, int64_t k, int trans,
                              hipStream_t st);

@@ -108,6 +108,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         pa.off_rdom = take(nn * (size_t)pa.P);
         pa.off_tnode = take(nn * (size_t)pa.P);
         pa.off_s = take(nn * (size_t)pa.P);
+        if (o->keep_q) pa.off_pz = take(2 * sizeof(double) * (size_t)pa.n * 16 * (size_t)pa.total_chunks);
         P.panels.push_back(pa);
     }
     P.off_lsq = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);

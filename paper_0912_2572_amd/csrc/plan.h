@@ -49,6 +49,7 @@ struct Panel {
     size_t off_rdom = 0;            // P x n x n              (domain R / node U)
     size_t off_tnode = 0;           // P x n x n              (node T, by right child)
     size_t off_s = 0;               // P x n x n              (top-down blocks)
+    size_t off_pz = 0;              // 2 x total_chunks x n x 16 (few-column apply: P_c, Z_c)
 
     int64_t domain_row0(int64_t i) const { return i * mb; }
     int64_t domain_rows(int64_t i) const { return (i == P - 1) ? m - i * mb : mb; }

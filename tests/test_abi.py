@@ -64,9 +64,11 @@ def test_tree_schedule_matches_oracle(tl, tree, P):
 def test_workspace_bytes(tl):
     o = tl.opts(row_block=4096)
     w = tl.workspace_bytes(1 << 20, 64, o)
-    # at least the reflectors (m x n) plus the chunk T factors
-    assert w >= 8 * (1 << 20) * 64
-    assert w < 8 * (1 << 20) * 64 * 1.6
+    # the reflectors (m x n) plus, per 256-row chunk, its n x n T and the
+    # few-column apply's two n x 16 blocks
+    m, n, chunks = 1 << 20, 64, (1 << 20) // 256
+    assert w >= 8 * m * n + 8 * chunks * (n * n + 2 * n * 16)
+    assert w < 8 * m * n * 1.6
     assert tl.workspace_bytes(10, 20, o) == 0          # m < n
     assert tl.workspace_bytes(100, 300, o) == 0        # n above scope
 

@@ -123,8 +123,10 @@ def test_batch_replays_and_plain_launches_agree(tl, small_batch):
 
 
 def test_batch_equals_single_calls(tl, small_batch):
-    """Each matrix's result equals a single tsqr_factor + tsqr_lsq_solve with
-    the same plan (the batched launches run the same per-domain code)."""
+    """Each matrix's R equals (bitwise) a single tsqr_factor with the same
+    plan: the batched factor runs the same per-domain and per-chain code.
+    The solves apply Q^T in different work splits (chunk chain in one
+    workgroup vs. chunk-parallel passes), so x agrees to rounding."""
     shapes, mats = small_batch
     print("case batch vs single calls", flush=True)
     B = make(tl, shapes, mats)
@@ -136,10 +138,7 @@ def test_batch_equals_single_calls(tl, small_batch):
         assert np.array_equal(host(f.R()), host(B.R(i))), f"matrix {i}"
         X, res, info = f.lsq(dev(b.reshape(-1, 1)), A=dev(A))
         torch.cuda.synchronize()
-        if prec == tl.F64:
-            assert np.array_equal(host(X)[:, 0], host(B.x(i)))
-        else:
-            assert rel(host(X)[:, 0], host(B.x(i))) <= 1e-13
+        assert rel(host(X)[:, 0], host(B.x(i))) <= 1e-13
 
 
 def test_batch_tuned_plans(tl, small_batch):
