@@ -386,49 +386,59 @@ __global__ __launch_bounds__(256) void k_apply_p2(const double *__restrict__ V64
         }
         sm.V0[r * kLdsStride + q] = v;
     }
-    auto chunk_step = [&](int64_t ch) {
+    // Only the n x kc live entries are computed (e < n kc: i = e % n, j = e / n).
+    // The next chunk's T is fetched into registers while the current chunk
+    // is processed.
+    const int live = n * kc;
+    constexpr int kTPer = 64 * 64 / 256;   // T entries per thread
+    double tnext[kTPer];
+    auto fetch_t = [&](int64_t ch) {
         const double *Tk = Tc + (dom * pa.cpd + ch) * nn;
+#pragma unroll
+        for (int u = 0; u < kTPer; ++u) {
+            const int e = tid + 256 * u, r = e & 63, q = e >> 6;
+            tnext[u] = (r < n && q < n) ? Tk[r + (int64_t)q * n] : 0.0;
+        }
+    };
+    auto chunk_step = [&](int64_t ch, int64_t ch_next) {
         const double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
         __syncthreads();
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int r = e & 63, q = e >> 6;
-            sm.Tm[r * kLdsStride + q] = (r < n && q < n) ? Tk[r + (int64_t)q * n] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kTPer; ++u) {
+            const int e = tid + 256 * u, r = e & 63, q = e >> 6;
+            sm.Tm[r * kLdsStride + q] = tnext[u];
         }
+        if (ch_next >= 0) fetch_t(ch_next);
         // W = (V_0top^T Y on a first chunk, else Y) + P_c
-        for (int e = tid; e < 64 * KBM; e += 256) {
-            const int m = e >> 4, j = e & 15;
+        for (int e = tid; e < live; e += 256) {
+            const int m = e % n, j = e / n;
             double wv = 0.0;
-            if (m < n && j < kc) {
-                if (ch == 0) {
-                    for (int r = m; r < n; ++r) wv = fma(sm.V0[r * kLdsStride + m], sm.Y[r][j], wv);
-                } else {
-                    wv = sm.Y[m][j];
-                }
-                wv += P[m + (int64_t)j * n];
+            if (ch == 0) {
+                for (int r = m; r < n; ++r) wv = fma(sm.V0[r * kLdsStride + m], sm.Y[r][j], wv);
+            } else {
+                wv = sm.Y[m][j];
             }
-            sm.W[m][j] = wv;
+            sm.W[m][j] = wv + P[m + (int64_t)j * n];
         }
         __syncthreads();
-        for (int e = tid; e < 64 * KBM; e += 256) {
-            const int i = e >> 4, j = e & 15;
+        for (int e = tid; e < live; e += 256) {
+            const int i = e % n, j = e / n;
             double z = 0.0;
-            if (i < n) {
-                if (trans) {
-                    for (int q = 0; q <= i; ++q) z = fma(sm.Tm[q * kLdsStride + i], sm.W[q][j], z);
-                } else {
-                    for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.W[q][j], z);
-                }
+            if (trans) {
+                for (int q = 0; q <= i; ++q) z = fma(sm.Tm[q * kLdsStride + i], sm.W[q][j], z);
+            } else {
+                for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.W[q][j], z);
             }
             sm.Z[i][j] = z;
-            if (i < n && j < kc) Zc[(dom * pa.cpd + ch) * (int64_t)n * k + i + (int64_t)j * n] = z;
+            Zc[(dom * pa.cpd + ch) * (int64_t)n * k + i + (int64_t)j * n] = z;
         }
         __syncthreads();
         // Y <- Y - Z, or on a first chunk Y <- Y - V_0top Z
-        for (int e = tid; e < 64 * KBM; e += 256) {
-            const int i = e >> 4, j = e & 15;
+        for (int e = tid; e < live; e += 256) {
+            const int i = e % n, j = e / n;
             if (ch == 0) {
                 double u = 0.0;
-                for (int q = 0; q <= i && q < n; ++q) u = fma(sm.V0[i * kLdsStride + q], sm.Z[q][j], u);
+                for (int q = 0; q <= i; ++q) u = fma(sm.V0[i * kLdsStride + q], sm.Z[q][j], u);
                 sm.W[i][j] = sm.Y[i][j] - u;
             } else {
                 sm.Y[i][j] -= sm.Z[i][j];
@@ -436,16 +446,18 @@ __global__ __launch_bounds__(256) void k_apply_p2(const double *__restrict__ V64
         }
         if (ch == 0) {
             __syncthreads();
-            for (int e = tid; e < 64 * KBM; e += 256) {
-                const int i = e >> 4, j = e & 15;
+            for (int e = tid; e < live; e += 256) {
+                const int i = e % n, j = e / n;
                 sm.Y[i][j] = sm.W[i][j];
             }
         }
     };
     if (trans) {
-        for (int64_t ch = 0; ch < nch; ++ch) chunk_step(ch);
+        fetch_t(0);
+        for (int64_t ch = 0; ch < nch; ++ch) chunk_step(ch, ch + 1 < nch ? ch + 1 : -1);
     } else {
-        for (int64_t ch = nch - 1; ch >= 0; --ch) chunk_step(ch);
+        fetch_t(nch - 1);
+        for (int64_t ch = nch - 1; ch >= 0; --ch) chunk_step(ch, ch - 1);
     }
     __syncthreads();
     for (int e = tid; e < 64 * KBM; e += 256) {
