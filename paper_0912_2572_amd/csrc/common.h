@@ -85,4 +85,81 @@ __device__ __forceinline__ void householder_scalars(double alpha, double sig2, d
     s = 1.0 / (alpha - beta);
 }
 
+// ---- one-wave triangular solves for n <= 256 (column-major R, ld n) ----
+// Lane l holds entries l + 64 q in xr[q], q < 4.  No barrier: the wave
+// broadcasts each solved entry with a lane read, and the next column (or
+// row) of R is fetched one step ahead.
+
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double pick4(const double (&xr)[4], int q) {
+    return q == 0 ? xr[0] : (q == 1 ? xr[1] : (q == 2 ? xr[2] : xr[3]));
+}
+
+// Back substitution R x = b (b in xr on entry, x on exit).
+__device__ __forceinline__ void wave_backsub(const double *__restrict__ R, int n, double (&xr)[4]) {
+    const int lane = threadIdx.x & 63;
+    double col[4], nxt[4];
+    auto fetch = [&](int j, double (&cc)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = lane + 64 * q;
+            cc[q] = (i < j) ? R[i + (int64_t)j * n] : 0.0;
+        }
+    };
+    if (n > 0) fetch(n - 1, col);
+    for (int j = n - 1; j >= 0; --j) {
+        if (j > 0) fetch(j - 1, nxt);
+        const int qj = j >> 6, lj = j & 63;
+        const double xj = wave_bcast(pick4(xr, qj), lj) / R[j + (int64_t)j * n];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xr[q] = fma(-col[q], xj, xr[q]);
+            if (q == qj && lane == lj) xr[q] = xj;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) col[q] = nxt[q];
+    }
+}
+
+// Forward substitution R^T h = g (g in xr on entry, h on exit).
+__device__ __forceinline__ void wave_fwdsub_t(const double *__restrict__ R, int n, double (&xr)[4]) {
+    const int lane = threadIdx.x & 63;
+    double row[4], nxt[4];
+    auto fetch = [&](int i, double (&rr)[4]) {   // R[i][q] for q > i
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            rr[q] = (c > i && c < n) ? R[i + (int64_t)c * n] : 0.0;
+        }
+    };
+    if (n > 0) fetch(0, row);
+    for (int i = 0; i < n; ++i) {
+        if (i + 1 < n) fetch(i + 1, nxt);
+        const int qi = i >> 6, li = i & 63;
+        const double hi = wave_bcast(pick4(xr, qi), li) / R[i + (int64_t)i * n];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xr[q] = fma(-row[q], hi, xr[q]);
+            if (q == qi && lane == li) xr[q] = hi;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) row[q] = nxt[q];
+    }
+}
+
+// Sum over the 64 lanes, identical in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = sum_quad(v);                      // lanes within 4
+    v += __shfl_xor(v, 4);                // the two quads of 8 lanes
+    v += dpp_f64<kDppRowRor8>(v);         // the two halves of a 16-lane row
+    v = pair_sum16(v);
+    v = pair_sum32(v);
+    return v;
+}
+
 }  // namespace tsqr

@@ -62,47 +62,49 @@ __global__ __launch_bounds__(256) void k_resid_partial(const double *C, int64_t 
     }
 }
 
-// One workgroup: info from the diagonal of R, residual norms from the
-// partials, then X = R^{-1} C[0:n] by column-oriented back substitution.
-__global__ __launch_bounds__(256) void k_lsq_final(const double *R, int n, const double *C, int64_t ldc,
-                                                   int64_t k, double *X, int64_t ldx, double *resid,
-                                                   int32_t *dinfo, const double *partial, int nparts) {
-    __shared__ double xs[256];
-    __shared__ int info;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        info = 0;
-        for (int j = 0; j < n; ++j)
-            if (R[j + j * n] == 0.0) {
-                info = j + 1;
-                break;
-            }
+// One wave per right-hand side: info from the diagonal of R, the residual
+// norm from the partials, then X = R^{-1} C[0:n] by back substitution.
+__global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const double *C, int64_t ldc,
+                                                  int64_t k, double *X, int64_t ldx, double *resid,
+                                                  int32_t *dinfo, const double *partial, int nparts) {
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    int info = 0;
+    for (int j0 = 0; j0 < n && !info; j0 += 64) {
+        const int j = j0 + lane;
+        const bool zero = j < n && R[j + (int64_t)j * n] == 0.0;
+        const unsigned long long mask = __ballot(zero);
+        if (mask) info = j0 + __ffsll((long long)mask);
     }
-    __syncthreads();
-    bool bad = false;
-    if (tid < k) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += partial[b * k + tid];
-        const double rn = sqrt(s);
-        if (resid) resid[tid] = rn;
-        bad = !(rn - rn == 0.0);
-    }
-    const int anybad = __syncthreads_or(bad);
-    if (tid == 0 && dinfo) *dinfo = info ? info : (anybad ? -2 : 0);
-    if (info) return;
-    for (int64_t c = 0; c < k; ++c) {
-        for (int i = tid; i < n; i += 256) xs[i] = C[i + c * ldc];
-        __syncthreads();
-        for (int j = n - 1; j >= 0; --j) {
-            const double xj = xs[j] / R[j + j * n];
-            __syncthreads();
-            for (int i = tid; i < j; i += 256) xs[i] = fma(-R[i + j * n], xj, xs[i]);
-            if (tid == 0) xs[j] = xj;
-            __syncthreads();
+    double s = 0.0;
+    for (int b = lane; b < nparts; b += 64) s += partial[(int64_t)b * k + c];
+    const double rn = sqrt(wave_sum(s));
+    if (lane == 0) {
+        if (resid) resid[c] = rn;
+        // the lowest code over the columns: info first, then -2
+        if (dinfo) {
+            const int32_t code = info ? info : (!(rn - rn == 0.0) ? -2 : 0);
+            if (code > 0) atomicMax(dinfo, code);   // info is the same for every column
+            else if (code < 0) atomicMin(dinfo, code);
         }
-        for (int i = tid; i < n; i += 256) X[i + c * ldx] = xs[i];
-        __syncthreads();
     }
+    if (info) return;
+    double xr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        xr[q] = (i < n) ? C[i + c * ldc] : 0.0;
+    }
+    wave_backsub(R, n, xr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n) X[i + c * ldx] = xr[q];
+    }
+}
+
+__global__ void k_info_clear(int32_t *dinfo) {
+    if (threadIdx.x == 0) *dinfo = 0;
 }
 
 hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, const double *d,
@@ -140,7 +142,8 @@ hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ld
     } else {
         blocks = 0;
     }
-    hipLaunchKernelGGL(k_lsq_final, dim3(1), dim3(256), 0, st, R, n, C, ldc, k, X, ldx, resid, dinfo,
+    if (dinfo) hipLaunchKernelGGL(k_info_clear, dim3(1), dim3(64), 0, st, dinfo);
+    hipLaunchKernelGGL(k_lsq_final, dim3((unsigned)k), dim3(64), 0, st, R, n, C, ldc, k, X, ldx, resid, dinfo,
                        partial, blocks);
     return hipGetLastError();
 }

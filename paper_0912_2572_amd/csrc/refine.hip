@@ -119,66 +119,63 @@ __device__ __forceinline__ void refine_step(const double *__restrict__ R, int n,
                                             int64_t m, int k, const double *__restrict__ gpart, int nblocks,
                                             double *__restrict__ X, int64_t ldx, double tol,
                                             int32_t *__restrict__ status, double *__restrict__ hist) {
-    __shared__ double g[256], h[256], dx[256];
-    __shared__ double nrm[2];
-    __shared__ int all_ok;
-    const int tid = threadIdx.x;
-    if (tid == 0) all_ok = 1;
+    __shared__ double g[256];
+    const int tid = threadIdx.x, lane = tid & 63;
+    bool all_ok = true;
     for (int c = 0; c < k; ++c) {
-        for (int j = tid; j < n; j += 256) {
-            double s = 0.0;
-            if (gpart)
-                for (int b = 0; b < nblocks; ++b) s += gpart[(int64_t)b * n * k + j + n * c];
-            g[j] = -s;
-        }
+        // g = -sum_b gpart[b] (every thread), in a fixed order per entry
         __syncthreads();
-        // forward substitution R^T h = g (column-oriented)
-        for (int i = 0; i < n; ++i) {
-            const double hi_ = g[i] / R[i + (int64_t)i * n];
-            __syncthreads();
-            for (int q = i + 1 + tid; q < n; q += 256) g[q] = fma(-R[i + (int64_t)q * n], hi_, g[q]);
-            if (tid == 0) h[i] = hi_;
-            __syncthreads();
-        }
-        for (int j = tid; j < n; j += 256) dx[j] = F[j + m * c] - h[j];
-        __syncthreads();
-        // back substitution R dx = d_1 - h
-        for (int i = n - 1; i >= 0; --i) {
-            const double xi = dx[i] / R[i + (int64_t)i * n];
-            __syncthreads();
-            for (int q = tid; q < i; q += 256) dx[q] = fma(-R[q + (int64_t)i * n], xi, dx[q]);
-            if (tid == 0) dx[i] = xi;
-            __syncthreads();
-        }
-        if (tid == 0) { nrm[0] = 0.0; nrm[1] = 0.0; }
-        __syncthreads();
-        if (tid == 0) {
-            double a = 0.0, b = 0.0;
-            for (int j = 0; j < n; ++j) {
-                const double xn = X[j + ldx * c] + dx[j];
-                a += dx[j] * dx[j];
-                b += xn * xn;
+        for (int j = tid; j < n; j += blockDim.x) {
+            double s0 = 0.0, s1 = 0.0;
+            if (gpart) {
+                int b = 0;
+                for (; b + 1 < nblocks; b += 2) {
+                    s0 += gpart[(int64_t)b * n * k + j + n * c];
+                    s1 += gpart[(int64_t)(b + 1) * n * k + j + n * c];
+                }
+                if (b < nblocks) s0 += gpart[(int64_t)b * n * k + j + n * c];
             }
-            nrm[0] = a;
-            nrm[1] = b;
+            g[j] = -(s0 + s1);
         }
         __syncthreads();
-        for (int j = tid; j < n; j += 256) {
-            X[j + ldx * c] += dx[j];
-            F[j + m * c] = h[j];
-        }
-        if (tid == 0) {
-            const double rel = sqrt(nrm[0]) / fmax(sqrt(nrm[1]), 1e-300);
+        if (tid < 64) {   // the solves run on one wave
+            double h[4], dx[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane + 64 * q;
+                h[q] = (i < n) ? g[i] : 0.0;
+            }
+            wave_fwdsub_t(R, n, h);                       // R^T h = g
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane + 64 * q;
+                dx[q] = (i < n) ? F[i + m * c] - h[q] : 0.0;
+            }
+            wave_backsub(R, n, dx);                       // R dx = d_1 - h
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane + 64 * q;
+                if (i < n) {
+                    const double xn = X[i + ldx * c] + dx[q];
+                    a = fma(dx[q], dx[q], a);
+                    b = fma(xn, xn, b);
+                    X[i + ldx * c] = xn;
+                    F[i + m * c] = h[q];
+                }
+            }
+            a = wave_sum(a);
+            b = wave_sum(b);
+            const double rel = sqrt(a) / fmax(sqrt(b), 1e-300);
             const double prev = hist[c];
-            hist[c] = rel;
             const bool done = (rel <= tol) || (status[0] >= 1 && rel > 0.9 * prev) || !(rel == rel);
-            if (!done) all_ok = 0;
+            all_ok = all_ok && done;
+            if (lane == 0) hist[c] = rel;
         }
-        __syncthreads();
     }
     if (tid == 0) {
         status[0] += 1;
-        status[1] = all_ok;
+        status[1] = all_ok ? 1 : 0;
     }
 }
 
