@@ -309,6 +309,12 @@ def run_batch(args):
         ev1.record(stream)
     stream.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
+    # per-kernel breakdown of one run with plain launches (HIP events per launch)
+    tl.prof_enable(True)
+    B.run(use_graph=False)
+    torch.cuda.synchronize()
+    kern = tl.prof_query()
+    tl.prof_enable(False)
     flops = sum(2.0 * m * n * n - 2.0 * n ** 3 / 3.0 + 4.0 * m * n + n * n for m, n in shapes)
     # algorithmic HBM bytes of one run: read A, write V (e = 8 or 4), read V
     # and b for Q^T b; the mixed matrices' refinement sweeps are not counted
@@ -355,6 +361,7 @@ def run_batch(args):
         "solves_per_s": round(len(shapes) / (ms * 1e-3), 1),
         "sequential_single_calls_ms": round(seq_ms, 3),
         "speedup_vs_sequential": round(seq_ms / ms, 2),
+        "kernels_ms_plain_run": {k: round(v[1], 3) for k, v in kern.items()},
         "autotune_s": round(tune_s, 2),
         "autotune_sample": "every 3rd matrix (171)",
         "tune_table": table,

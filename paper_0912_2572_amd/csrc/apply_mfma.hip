@@ -205,37 +205,6 @@ __global__ __launch_bounds__(256) void k_leaf_apply_m(const typename Tile::T *__
     leaf_apply_domain<Tile>(sm, V, ldv, Tc, pa, Bsrc, ldbs, B, ldb, k, trans, blockIdx.x, blockIdx.y);
 }
 
-// Batched form on each listed matrix's vector F (one column), FP64 or FP32
-// tiles by the matrix's precision; sweep > 0 skips converged matrices.
-__global__ __launch_bounds__(256) void k_leaf_apply_b(const BMat *__restrict__ mats,
-                                                      const int *__restrict__ list, int trans, int sweep) {
-    extern __shared__ double smem_raw[];
-    const BMat &M = mats[list[blockIdx.y]];
-    const int64_t dom = blockIdx.x;
-    if (dom >= M.pa.P) return;
-    if (sweep > 0 && M.status[1]) return;
-    if (M.prec) {
-        ApplyMSmem<TileF32> &sm = *reinterpret_cast<ApplyMSmem<TileF32> *>(smem_raw);
-        leaf_apply_domain<TileF32>(sm, M.V32, M.pa.m, M.Tc, M.pa, M.F, M.pa.m, M.F, M.pa.m, 1, trans, dom, 0);
-    } else {
-        ApplyMSmem<TileF64> &sm = *reinterpret_cast<ApplyMSmem<TileF64> *>(smem_raw);
-        leaf_apply_domain<TileF64>(sm, M.V, M.pa.m, M.Tc, M.pa, M.F, M.pa.m, M.F, M.pa.m, 1, trans, dom, 0);
-    }
-}
-
-hipError_t launch_leaf_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int sweep,
-                               hipStream_t st) {
-    if (cnt <= 0 || gx <= 0) return hipSuccess;
-    const size_t sh = sizeof(ApplyMSmem<TileF64>);
-    hipError_t e = hipFuncSetAttribute((const void *)k_leaf_apply_b,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    if (e != hipSuccess) return e;
-    ProfScope ps(trans ? "batch_leaf_apply_qt" : "batch_leaf_apply_q", st);
-    hipLaunchKernelGGL(k_leaf_apply_b, dim3((unsigned)gx, (unsigned)cnt), dim3(256), sh, st, mats, list, trans,
-                       sweep);
-    return hipGetLastError();
-}
-
 template <typename Tile>
 static hipError_t launch_apply_m(const typename Tile::T *V, int64_t ldv, const double *Tc,
                                  const PanelArgs &pa, const double *Bsrc, int64_t ldbs, double *B,
@@ -329,12 +298,11 @@ __device__ __forceinline__ void chunk_vtb(VtbSmem<Tile> &sm, const typename Tile
 }
 
 template <typename Tile>
-__global__ __launch_bounds__(256) void k_apply_p1(const typename Tile::T *__restrict__ V, int64_t ldv,
-                                                  PanelArgs pa, const double *__restrict__ B, int64_t ldb,
-                                                  int64_t k, double *__restrict__ Pc) {
+__device__ __forceinline__ void apply_p1_body(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                              const PanelArgs &pa, const double *__restrict__ B, int64_t ldb,
+                                              int64_t k, double *__restrict__ Pc, int64_t dom, int64_t ch) {
     extern __shared__ double smem_raw[];
     VtbSmem<Tile> &sm = *reinterpret_cast<VtbSmem<Tile> *>(smem_raw);
-    const int64_t dom = blockIdx.y, ch = blockIdx.x;
     const int n = pa.n;
     const int64_t row0 = dom * pa.mb;
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
@@ -351,6 +319,13 @@ __global__ __launch_bounds__(256) void k_apply_p1(const typename Tile::T *__rest
     }
 }
 
+template <typename Tile>
+__global__ __launch_bounds__(256) void k_apply_p1(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                                  PanelArgs pa, const double *__restrict__ B, int64_t ldb,
+                                                  int64_t k, double *__restrict__ Pc) {
+    apply_p1_body<Tile>(V, ldv, pa, B, ldb, k, Pc, blockIdx.y, blockIdx.x);
+}
+
 struct ChainSmem {
     double Tm[64 * kLdsStride];
     double V0[64 * kLdsStride];   // unit lower V_0top of the first chunk
@@ -360,13 +335,13 @@ struct ChainSmem {
 };
 
 // Pass 2 for one domain (FP64).
-__global__ __launch_bounds__(256) void k_apply_p2(const double *__restrict__ V64, const float *__restrict__ V32,
-                                                  int64_t ldv, const double *__restrict__ Tc, PanelArgs pa,
-                                                  double *__restrict__ B, int64_t ldb, int64_t k, int trans,
-                                                  const double *__restrict__ Pc, double *__restrict__ Zc) {
+__device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, const float *__restrict__ V32,
+                                              int64_t ldv, const double *__restrict__ Tc, const PanelArgs &pa,
+                                              double *__restrict__ B, int64_t ldb, int64_t k, int trans,
+                                              const double *__restrict__ Pc, double *__restrict__ Zc,
+                                              int64_t dom) {
     extern __shared__ double smem_raw[];
     ChainSmem &sm = *reinterpret_cast<ChainSmem *>(smem_raw);
-    const int64_t dom = blockIdx.x;
     const int n = pa.n, kc = (int)k, tid = threadIdx.x;
     const int64_t nn = (int64_t)n * n;
     const int64_t row0 = dom * pa.mb;
@@ -466,16 +441,22 @@ __global__ __launch_bounds__(256) void k_apply_p2(const double *__restrict__ V64
     }
 }
 
+__global__ __launch_bounds__(256) void k_apply_p2(const double *__restrict__ V64, const float *__restrict__ V32,
+                                                  int64_t ldv, const double *__restrict__ Tc, PanelArgs pa,
+                                                  double *__restrict__ B, int64_t ldb, int64_t k, int trans,
+                                                  const double *__restrict__ Pc, double *__restrict__ Zc) {
+    apply_p2_body(V64, V32, ldv, Tc, pa, B, ldb, k, trans, Pc, Zc, blockIdx.x);
+}
+
 // Pass 3: B_c <- B_c - V_c Z_c over the chunk's rows (a first chunk from
 // row n on), transposed MFMA form as in chunk_apply_m; the Z operand stays in
 // registers, so the kernel needs no LDS and many workgroups share a CU.
 template <typename Tile>
-__global__ __launch_bounds__(256) void k_apply_p3(const typename Tile::T *__restrict__ V, int64_t ldv,
-                                                  PanelArgs pa, double *__restrict__ B, int64_t ldb, int64_t k,
-                                                  const double *__restrict__ Zc) {
+__device__ __forceinline__ void apply_p3_body(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                              const PanelArgs &pa, double *__restrict__ B, int64_t ldb, int64_t k,
+                                              const double *__restrict__ Zc, int64_t dom, int64_t ch) {
     using T = typename Tile::T;
     using Acc = typename Tile::Acc;
-    const int64_t dom = blockIdx.y, ch = blockIdx.x;
     const int n = pa.n, kc = (int)k;
     const int64_t row0 = dom * pa.mb;
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
@@ -516,6 +497,80 @@ __global__ __launch_bounds__(256) void k_apply_p3(const typename Tile::T *__rest
             if (live && col < kc) Bc[row + (int64_t)col * ldb] -= (double)acc[r];
         }
     }
+}
+
+template <typename Tile>
+__global__ __launch_bounds__(256) void k_apply_p3(const typename Tile::T *__restrict__ V, int64_t ldv,
+                                                  PanelArgs pa, double *__restrict__ B, int64_t ldb, int64_t k,
+                                                  const double *__restrict__ Zc) {
+    apply_p3_body<Tile>(V, ldv, pa, B, ldb, k, Zc, blockIdx.y, blockIdx.x);
+}
+
+// ---- batched forms on each listed matrix's vector F (k = 1); grid.x walks
+// the matrix's chunks (pass 1, 3) or domains (pass 2); sweep > 0 skips
+// converged matrices.
+__device__ __forceinline__ bool chunk_of(const BMat &M, int64_t g, int64_t &dom, int64_t &ch) {
+    if (g >= M.tchunks) return false;
+    dom = g / M.pa.cpd;
+    if (dom > M.pa.P - 1) dom = M.pa.P - 1;
+    ch = g - dom * M.pa.cpd;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_apply_p1_b(const BMat *__restrict__ mats, const int *__restrict__ list,
+                                                    int sweep) {
+    const BMat &M = mats[list[blockIdx.y]];
+    int64_t dom, ch;
+    if (!chunk_of(M, blockIdx.x, dom, ch)) return;
+    if (sweep > 0 && M.status[1]) return;
+    if (M.prec) apply_p1_body<TileF32>(M.V32, M.pa.m, M.pa, M.F, M.pa.m, 1, M.Pc, dom, ch);
+    else apply_p1_body<TileF64>(M.V, M.pa.m, M.pa, M.F, M.pa.m, 1, M.Pc, dom, ch);
+}
+
+__global__ __launch_bounds__(256) void k_apply_p2_b(const BMat *__restrict__ mats, const int *__restrict__ list,
+                                                    int trans, int sweep) {
+    const BMat &M = mats[list[blockIdx.y]];
+    if ((int64_t)blockIdx.x >= M.pa.P) return;
+    if (sweep > 0 && M.status[1]) return;
+    apply_p2_body(M.V, M.V32, M.pa.m, M.Tc, M.pa, M.F, M.pa.m, 1, trans, M.Pc, M.Zc, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_apply_p3_b(const BMat *__restrict__ mats, const int *__restrict__ list,
+                                                    int sweep) {
+    const BMat &M = mats[list[blockIdx.y]];
+    int64_t dom, ch;
+    if (!chunk_of(M, blockIdx.x, dom, ch)) return;
+    if (sweep > 0 && M.status[1]) return;
+    if (M.prec) apply_p3_body<TileF32>(M.V32, M.pa.m, M.pa, M.F, M.pa.m, 1, M.Zc, dom, ch);
+    else apply_p3_body<TileF64>(M.V, M.pa.m, M.pa, M.F, M.pa.m, 1, M.Zc, dom, ch);
+}
+
+hipError_t launch_apply3_b(const BMat *mats, const int *list, int cnt, int64_t max_chunks, int64_t max_p,
+                           int trans, int sweep, hipStream_t st) {
+    if (cnt <= 0 || max_chunks <= 0) return hipSuccess;
+    const size_t sh = sizeof(VtbSmem<TileF64>);
+    hipError_t e = hipFuncSetAttribute((const void *)k_apply_p1_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sh);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_apply_p2_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(ChainSmem));
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(trans ? "batch_apply3_p1_qt" : "batch_apply3_p1_q", st);
+        hipLaunchKernelGGL(k_apply_p1_b, dim3((unsigned)max_chunks, (unsigned)cnt), dim3(256), sh, st, mats, list,
+                           sweep);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        ProfScope ps(trans ? "batch_apply3_p2_qt" : "batch_apply3_p2_q", st);
+        hipLaunchKernelGGL(k_apply_p2_b, dim3((unsigned)max_p, (unsigned)cnt), dim3(256), sizeof(ChainSmem), st,
+                           mats, list, trans, sweep);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    ProfScope ps(trans ? "batch_apply3_p3_qt" : "batch_apply3_p3_q", st);
+    hipLaunchKernelGGL(k_apply_p3_b, dim3((unsigned)max_chunks, (unsigned)cnt), dim3(256), 0, st, mats, list,
+                       sweep);
+    return hipGetLastError();
 }
 
 template <typename Tile>

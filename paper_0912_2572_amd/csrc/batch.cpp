@@ -89,6 +89,7 @@ int plan_matrix(const tsqr_batch_item &it, int64_t mb, int tree, MatPlan *mp) {
     if (it.prec) b += align_up(sizeof(double) * nb * n);                     // gpart
     b += align_up(sizeof(double) * nb);                                      // rpart
     b += align_up(sizeof(double) * 2 + sizeof(int32_t) * 2);                 // hist, status
+    b += 2 * align_up(sizeof(double) * n * (size_t)p.total_chunks);         // Pc, Zc
     mp->bytes = b;
     return 0;
 }
@@ -102,7 +103,7 @@ struct Group {
     int list_off = 0;            // offset (in ints) of its index list
     int cnt = 0;
     int ns = 0;
-    int64_t maxP = 0, maxNb = 0, maxM = 0;
+    int64_t maxP = 0, maxNb = 0, maxM = 0, maxChunks = 0;
     int maxLev = 0;
     std::vector<int64_t> up;     // per bottom-up step: largest chain count
     std::vector<int64_t> down;   // per top-down step
@@ -137,6 +138,7 @@ void fill_group(Group &g, const std::vector<int> &idx, const tsqr_batch_s &B, in
         g.maxP = std::max(g.maxP, M.pa.P);
         g.maxNb = std::max<int64_t>(g.maxNb, M.nb);
         g.maxM = std::max(g.maxM, M.pa.m);
+        g.maxChunks = std::max(g.maxChunks, M.tchunks);
         g.maxLev = std::max(g.maxLev, M.nlev);
     }
     g.up.assign(g.maxLev, 0);
@@ -172,8 +174,8 @@ int enqueue(tsqr_batch_s *B, hipStream_t st, int *launches) {
     const Group &A = B->all;
     TRYB(tsqr::launch_sign_b(D, L(A), A.cnt, st));
     TRYB(tsqr::launch_lsq_init_b(D, L(A), A.cnt, (A.maxM + 2047) / 2048, st));
-    TRYB(tsqr::launch_leaf_apply_b(D, L(A), A.cnt, A.maxP, 1, 0, st));
-    nl += 3;
+    TRYB(tsqr::launch_apply3_b(D, L(A), A.cnt, A.maxChunks, A.maxP, 1, 0, st));
+    nl += 5;
     for (int s = 0; s < A.maxLev; ++s) {
         TRYB(tsqr::launch_tree_apply_b(D, L(A), A.cnt, A.up[s], 1, s, 0, st));
         ++nl;
@@ -188,16 +190,16 @@ int enqueue(tsqr_batch_s *B, hipStream_t st, int *launches) {
             TRYB(tsqr::launch_scale_b(D, L(X), X.cnt, sw, st));
             for (int s = 0; s < X.maxLev; ++s)
                 TRYB(tsqr::launch_tree_apply_b(D, L(X), X.cnt, X.down[s], 0, s, sw, st));
-            TRYB(tsqr::launch_leaf_apply_b(D, L(X), X.cnt, X.maxP, 0, sw, st));
+            TRYB(tsqr::launch_apply3_b(D, L(X), X.cnt, X.maxChunks, X.maxP, 0, sw, st));
             TRYB(tsqr::launch_axpy_b(D, L(X), X.cnt, (X.maxM + 2047) / 2048, sw, st));
             // f = b - r - A x, g = -A^T r (FP64), then Q^T f and the solve
             TRYB(tsqr::launch_resid_b(D, L(X), X.cnt, X.maxNb, sw, st));
-            TRYB(tsqr::launch_leaf_apply_b(D, L(X), X.cnt, X.maxP, 1, sw, st));
+            TRYB(tsqr::launch_apply3_b(D, L(X), X.cnt, X.maxChunks, X.maxP, 1, sw, st));
             for (int s = 0; s < X.maxLev; ++s)
                 TRYB(tsqr::launch_tree_apply_b(D, L(X), X.cnt, X.up[s], 1, s, sw, st));
             TRYB(tsqr::launch_scale_b(D, L(X), X.cnt, sw, st));
             TRYB(tsqr::launch_refine_b(D, L(X), X.cnt, sw, B->tol, st));
-            nl += 8 + 2 * X.maxLev;
+            nl += 12 + 2 * X.maxLev;
         }
     TRYB(tsqr::launch_final_b(D, L(A), A.cnt, st));
     ++nl;
@@ -333,6 +335,9 @@ TSQR_API int tsqr_batch_create(int count, const tsqr_batch_item *items, const ts
         char *hs = take(sizeof(double) * 2 + sizeof(int32_t) * 2);
         M.hist = reinterpret_cast<double *>(hs);
         M.status = reinterpret_cast<int32_t *>(hs + 2 * sizeof(double));
+        M.Pc = reinterpret_cast<double *>(take(sizeof(double) * n * (size_t)p.total_chunks));
+        M.Zc = reinterpret_cast<double *>(take(sizeof(double) * n * (size_t)p.total_chunks));
+        M.tchunks = p.total_chunks;
         off += mp.bytes;
         M.pa.m = p.m;
         M.pa.mb = p.mb;
@@ -435,8 +440,8 @@ TSQR_API int tsqr_batch_launches(tsqr_batch B) {
         // count without launching: the sequence is fixed by the plan
         int nl = (int)B->cls.size();
         for (const Group &g : B->cls) nl += g.maxLev;
-        nl += 5 + B->all.maxLev + 1;
-        if (B->mixed.cnt > 0) nl += B->sweeps * (8 + 2 * B->mixed.maxLev);
+        nl += 7 + B->all.maxLev + 1;
+        if (B->mixed.cnt > 0) nl += B->sweeps * (12 + 2 * B->mixed.maxLev);
         return nl;
     }
     return B->launches;

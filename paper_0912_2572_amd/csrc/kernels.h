@@ -64,6 +64,8 @@ struct BMat {
     double *hist;         // [0] last relative correction, [1] residual norm (FP64)
     int32_t *status;      // [0] sweeps done, [1] converged
     PanelArgs pa;
+    double *Pc, *Zc;      // per chunk n x 1 blocks of the few-column apply
+    int64_t tchunks;      // chunks over all domains
     int prec;             // 0 FP64, 1 mixed
     int nlev;             // tree levels
     int nb;               // row blocks of the residual pass
@@ -150,10 +152,11 @@ hipError_t launch_leaf_b(const BMat *mats, const int *list, int cnt, int64_t gx,
 hipError_t launch_tree_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, int level,
                          hipStream_t st);
 hipError_t launch_sign_b(const BMat *mats, const int *list, int cnt, hipStream_t st);
-// Q^T (trans = 1) or Q (trans = 0) on F, leaves; sweep > 0 skips converged
-// matrices.
-hipError_t launch_leaf_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int sweep,
-                               hipStream_t st);
+// Q^T (trans = 1) or Q (trans = 0) on F, leaves, in three chunk-parallel
+// passes (grid.x: max_chunks for passes 1 and 3, max_p for pass 2); sweep > 0
+// skips converged matrices.
+hipError_t launch_apply3_b(const BMat *mats, const int *list, int cnt, int64_t max_chunks, int64_t max_p,
+                           int trans, int sweep, hipStream_t st);
 // one tree level; step counts from the bottom (trans = 1) or the top (0)
 hipError_t launch_tree_apply_b(const BMat *mats, const int *list, int cnt, int64_t gx, int trans, int step,
                                int sweep, hipStream_t st);
