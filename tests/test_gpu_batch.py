@@ -210,3 +210,35 @@ def test_batch_zero_column(tl):
     assert torch.all(B.x(0) == 7.0) and torch.all(B.x(1) == 7.0)
     assert int(B.info(2).item()) == 0
     assert eta(A1, host(B.x(2)), mats[2][1]) <= 1e-12
+
+
+def test_batch_full_config_sampled(tl):
+    """The full 512-matrix workload in the configuration the benchmark times
+    (autotuned table, captured graph), checked against the oracle on a sample
+    of matrices (the oracle factors them one by one)."""
+    shapes = synth.batch_shapes(512, seed=0)
+    precs = [j % 2 for j in range(len(shapes))]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    As, bs = [], []
+    for m, n in shapes:
+        As.append(torch.randn((n, m), generator=g, device="cuda", dtype=torch.float64).t())
+        bs.append(torch.randn(m, generator=g, device="cuda", dtype=torch.float64))
+    print("case batch 512 matrices, autotuned, graph", flush=True)
+    table = tl.autotune(As[::3], bs[::3], precs[::3], reps=1)
+    B = tl.Batch(As, bs, precs, tune=table, refine_sweeps=4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B.run(use_graph=True, stream=stream)
+    stream.synchronize()
+    for i in list(range(0, 512, 37)) + [511]:
+        A, b = host(As[i]), host(bs[i])
+        mb, tree, P = B.plan(i)
+        orc = oracle.TSQR(A, mb=mb, tree=tree)
+        Ro = orc.R()
+        assert rel(host(B.R(i)), Ro) <= 1e-12, f"matrix {i}"
+        Xo, reso, _ = orc.lsq(b)
+        x = host(B.x(i))
+        assert int(B.info(i).item()) == 0
+        assert rel(x, Xo[:, 0]) <= 1e-12, f"matrix {i}"
+        assert eta(A, x, b) <= 1e-12, f"matrix {i}"

@@ -172,3 +172,40 @@ def test_mixed_needs_a(tl):
     f = tl.factor(dev(A), row_block=1024, prec=tl.MIXED)
     with pytest.raises(tl.TSQRError):
         f.lsq(dev(np.ones(2000)))
+
+
+def test_mixed_full_size_properties(tl):
+    """The 4,194,304 x 128 conditioned workload at full size, built on the
+    device as the benchmark builds it: the oracle cannot factor it, so the
+    mixed solve is checked through properties that hold at any size (the
+    backward-error proxy of each solution, the consistent right-hand side
+    recovering x_true, R against the FP64 path's R)."""
+    m, n = 4194304, 128
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    G1 = torch.randn((n, m), generator=g, device="cuda", dtype=torch.float64).t()
+    G2 = torch.randn((n, n), generator=g, device="cuda", dtype=torch.float64)
+    Uq, _ = torch.linalg.qr(G1)
+    Vq, _ = torch.linalg.qr(G2)
+    s = torch.as_tensor(synth.log_spaced_spectrum(n, -6.0), device="cuda")
+    A = ((Uq * s) @ Vq.t()).t().contiguous().t()
+    del G1, Uq
+    b = torch.randn(m, generator=g, device="cuda", dtype=torch.float64)
+    xt = torch.randn(n, generator=g, device="cuda", dtype=torch.float64)
+    B = torch.stack([b, A @ xt], dim=1).t().contiguous().t()
+    print("case mixed full size 4194304 x 128", flush=True)
+    f = tl.factor(A, row_block=4096, prec=tl.MIXED, lsq_max_rhs=2)
+    X, res, info = f.lsq(B, A=A)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    nA = torch.linalg.norm(A)
+    for c in range(2):
+        x = X[:, c]
+        r = B[:, c] - A @ x
+        e1 = float(torch.linalg.norm(A.t() @ r) / (nA * (nA * torch.linalg.norm(x) + torch.linalg.norm(B[:, c]))))
+        print(f"rhs {c}: eta {e1:.2e}", flush=True)
+        assert e1 <= 1e-12
+    assert float(torch.linalg.norm(X[:, 1] - xt) / torch.linalg.norm(xt)) <= 10 * 1e6 * U * math.sqrt(n)
+    f64 = tl.factor(A, row_block=4096)
+    R64, Rm = f64.R(), f.R()
+    assert float(torch.linalg.norm(Rm - R64) / torch.linalg.norm(R64)) <= 1e-4
