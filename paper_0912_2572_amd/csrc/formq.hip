@@ -91,18 +91,26 @@ __global__ void k_seed_root(double *S, int n, const double *d) {
 }
 
 // Q = -V Z (+ [X; 0] on a first chunk) for the rows of one chunk; wave w
-// takes the 16-row tiles 4 w .. 4 w + 3 of every 256-row block.
+// takes the 16-row tiles 4 w .. 4 w + 3 of every 256-row block.  The wave
+// keeps its Z operands in registers for the whole chunk and fetches the next
+// tile's V while the current tile's products run.
 __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__restrict__ Vc, int64_t ldv,
                                           double *__restrict__ Qc, int64_t ldq, int64_t valid, int n,
                                           bool first) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
     const int kbn = (n + 3) >> 2;
-    for (int64_t tile = 4 * w; 16 * tile < valid; tile += (tile % 4 == 3) ? 13 : 1) {
-        const int64_t row = 16 * tile + (lane & 15);
-        double vb[16];
+    double za[16][4];
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb)
+#pragma unroll
+        for (int CT = 0; CT < 4; ++CT)
+            za[kb][CT] = (kb < kbn) ? sm.Z[(4 * kb + l4) * LD + 16 * CT + l16] : 0.0;
+    auto load_v = [&](int64_t tile, double (&vb)[16]) {
+        const int64_t row = 16 * tile + l16;
 #pragma unroll
         for (int kb = 0; kb < 16; ++kb) {
-            const int col = 4 * kb + (lane >> 4);
+            const int col = 4 * kb + l4;
             double v = 0.0;
             if (kb < kbn && row < valid && col < n) {
                 v = Vc[row + (int64_t)col * ldv];
@@ -110,27 +118,36 @@ __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__re
             }
             vb[kb] = v;
         }
+    };
+    int64_t tile = 4 * w;
+    double vb[16], vn[16];
+    if (16 * tile < valid) load_v(tile, vb);
+    while (16 * tile < valid) {
+        const int64_t next = tile + ((tile % 4 == 3) ? 13 : 1);
+        if (16 * next < valid) load_v(next, vn);
+        const int64_t row = 16 * tile + l16;
         d4 acc[4];
 #pragma unroll
         for (int CT = 0; CT < 4; ++CT) acc[CT] = d4_zero();
 #pragma unroll
-        for (int kb = 0; kb < 16; ++kb) {
-            if (kb >= kbn) break;
-            const double *zr = sm.Z + (4 * kb + (lane >> 4)) * LD + (lane & 15);
+        for (int kb = 0; kb < 16; ++kb)
 #pragma unroll
-            for (int CT = 0; CT < 4; ++CT) acc[CT] = mfma_f64(zr[16 * CT], vb[kb], acc[CT]);
-        }
+            for (int CT = 0; CT < 4; ++CT)
+                if (kb < kbn) acc[CT] = mfma_f64(za[kb][CT], vb[kb], acc[CT]);
 #pragma unroll
         for (int CT = 0; CT < 4; ++CT)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int col = 16 * CT + 4 * r + (lane >> 4);
+                const int col = 16 * CT + 4 * r + l4;
                 if (row < valid && col < n) {
                     double val = -acc[CT][r];
                     if (first && row < n) val += sm.X[row * LD + col];
                     Qc[row + (int64_t)col * ldq] = val;
                 }
             }
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) vb[kb] = vn[kb];
+        tile = next;
     }
 }
 
