@@ -80,9 +80,18 @@ __device__ __forceinline__ void householder_scalars(double alpha, double sig2, d
         return;
     }
     const double sgn = (alpha < 0.0) ? -1.0 : 1.0;
-    beta = -sgn * sqrt(alpha * alpha + sig2);
-    tau = (beta - alpha) / beta;
-    s = 1.0 / (alpha - beta);
+    beta = -sgn * sqrt(fma(alpha, alpha, sig2));
+    // s = 1 / (alpha - beta) and tau = (beta - alpha) / beta = -(alpha - beta) / beta
+    // from two independent reciprocals, each v_rcp_f64 refined by two Newton
+    // steps r <- r + r (1 - x r) (within an ulp of the quotient)
+    const double d = alpha - beta;
+    double rd = __builtin_amdgcn_rcp(d), rb = __builtin_amdgcn_rcp(beta);
+    rd = fma(rd, fma(-d, rd, 1.0), rd);
+    rb = fma(rb, fma(-beta, rb, 1.0), rb);
+    rd = fma(rd, fma(-d, rd, 1.0), rd);
+    rb = fma(rb, fma(-beta, rb, 1.0), rb);
+    s = rd;
+    tau = -d * rb;
 }
 
 // ---- one-wave triangular solves for n <= 256 (column-major R, ld n) ----

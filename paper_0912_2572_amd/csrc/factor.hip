@@ -240,6 +240,16 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
             if (FIRST) sm.u.s.redq[par][cg + 16 * rg][w] = pubq;
         }
     }
+    // non-first chunk: row j of the running R is final until this step's
+    // deferred write (after the next barrier), so it is read before the
+    // barrier, off the critical path
+    double alpha = 0.0, en = 0.0, ev[NS];
+    if (!FIRST) {
+        alpha = sm.R[j * kLdsStride + j];
+        en = (j + 1 < n) ? sm.R[j * kLdsStride + j + 1] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) ev[t] = sm.R[j * kLdsStride + cg + 16 * t];
+    }
     __syncthreads();
     // deferred write of the previous step's R row: every thread has read
     // that row before this barrier.
@@ -252,23 +262,19 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     }
     const double tot = col_total(sm.u.s.red, par);
     const double totq = FIRST ? col_total(sm.u.s.redq, par) : 0.0;
-    // this thread's columns: dots d and the pivot-row entries e
-    double dv[NS], ev[NS];
+    // this thread's columns: dots d and (first chunk) the pivot-row entries e
+    double dv[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         dv[t] = __shfl(tot, cg + 16 * t);
-        ev[t] = FIRST ? __shfl(totq, cg + 16 * t) : sm.R[j * kLdsStride + cg + 16 * t];
+        if (FIRST) ev[t] = __shfl(totq, cg + 16 * t);
     }
     const double sig2 = read_lane(tot, j);
     const bool has_next = j + 1 < n;
     const double dn = has_next ? read_lane(tot, j + 1) : 0.0;
-    double alpha, en = 0.0;
     if (FIRST) {
         alpha = read_lane(totq, j);
         if (has_next) en = read_lane(totq, j + 1);
-    } else {
-        alpha = sm.R[j * kLdsStride + j];
-        if (has_next) en = sm.R[j * kLdsStride + j + 1];
     }
     double beta, tau, s;
     householder_scalars(alpha, sig2, beta, tau, s);
