@@ -46,14 +46,42 @@ __device__ __forceinline__ VT v_elem(const VT *__restrict__ Vc, int64_t ldv, int
     return Vc[row + (int64_t)col * ldv];
 }
 
+// Four consecutive entries p[0..3] as 16-byte loads (p 16-byte aligned),
+// or zeros when !ok; FP64 reads two double2, FP32 one float4, and the
+// entries are converted to T.
+template <typename T, typename S>
+__device__ __forceinline__ void load4(const S *__restrict__ p, bool ok, T (&v)[4]) {
+    if constexpr (sizeof(S) == 8) {
+        double2 x0 = {0.0, 0.0}, x1 = {0.0, 0.0};
+        if (ok) {
+            x0 = reinterpret_cast<const double2 *>(p)[0];
+            x1 = reinterpret_cast<const double2 *>(p)[1];
+        }
+        v[0] = T(x0.x); v[1] = T(x0.y); v[2] = T(x1.x); v[3] = T(x1.y);
+    } else {
+        float4 x = {0.f, 0.f, 0.f, 0.f};
+        if (ok) x = *reinterpret_cast<const float4 *>(p);
+        v[0] = T(x.x); v[1] = T(x.y); v[2] = T(x.z); v[3] = T(x.w);
+    }
+}
+
+// A wave's row range [r, r + rows) of V and B can be read 4 rows at a time
+// with 16-byte loads: whole 16-row blocks, every column start 16-byte aligned.
+template <typename VT>
+__device__ __forceinline__ bool wide_rows_ok(const VT *v, int64_t ldv, const double *b, int64_t ldb, int64_t rows) {
+    return rows > 0 && rows % 16 == 0 && (reinterpret_cast<uintptr_t>(v) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(b) & 15) == 0 && (ldv * (int64_t)sizeof(VT)) % 16 == 0 &&
+           (ldb * 8) % 16 == 0;
+}
+
 template <typename Tile>
-__device__ void chunk_apply_m(ApplyMSmem<Tile> &sm, const typename Tile::T *__restrict__ Vc, int64_t ldv,
+__device__ __forceinline__ void chunk_apply_m(ApplyMSmem<Tile> &sm, const typename Tile::T *__restrict__ Vc, int64_t ldv,
                               const double *__restrict__ Tk, const double *__restrict__ Bin, int64_t ldbi,
                               double *__restrict__ Bout, int64_t ldbo, int64_t valid, int n, int kc,
                               bool first, int trans) {
     using T = typename Tile::T;
     using Acc = typename Tile::Acc;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     const int mtn = (n + 15) >> 4;             // 16-reflector tiles
     for (int e = tid; e < 64 * 64; e += 256) {
@@ -67,19 +95,37 @@ __device__ void chunk_apply_m(ApplyMSmem<Tile> &sm, const typename Tile::T *__re
         for (int mt = 0; mt < 4; ++mt) acc[mt] = Acc{0, 0, 0, 0};
         const int64_t per = ((valid + 15) / 16 + 3) / 4 * 16;   // rows per wave, multiple of 16
         const int64_t lo = w * per, hi = (lo + per < valid) ? lo + per : valid;
-        for (int64_t r4 = lo; r4 < hi; r4 += 4) {
-            const int64_t row = r4 + l4;
-            double bv = 0.0;
-            if (row < hi && l16 < kc) {
-                if (first && !trans && row < n) bv = sm.Y[row][l16];
-                else bv = Bin[row + (int64_t)l16 * ldbi];
-            }
-            const T b = T(bv);
+        if (!first && wide_rows_ok(Vc + lo, ldv, Bin + lo, ldbi, hi - lo)) {
+            // 16-byte loads of 4 consecutive rows per lane (as in the first pass)
+#pragma unroll 1
+            for (int64_t r16 = lo; r16 < hi; r16 += 16) {
+                const int64_t rb = r16 + 4 * l4;
+                T b4[4];
+                load4<T>(Bin + rb + (int64_t)l16 * ldbi, l16 < kc, b4);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                if (mt >= mtn) break;
-                const T a = (row < hi) ? v_elem<T>(Vc, ldv, row, 16 * mt + l16, valid, n, first) : T(0);
-                acc[mt] = Tile::mfma(a, b, acc[mt]);
+                for (int mt = 0; mt < 4; ++mt) {
+                    if (mt >= mtn) break;
+                    T a4[4];
+                    load4<T>(Vc + rb + (int64_t)(16 * mt + l16) * ldv, 16 * mt + l16 < n, a4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[mt] = Tile::mfma(a4[q], b4[q], acc[mt]);
+                }
+            }
+        } else {
+            for (int64_t r4 = lo; r4 < hi; r4 += 4) {
+                const int64_t row = r4 + l4;
+                double bv = 0.0;
+                if (row < hi && l16 < kc) {
+                    if (first && !trans && row < n) bv = sm.Y[row][l16];
+                    else bv = Bin[row + (int64_t)l16 * ldbi];
+                }
+                const T b = T(bv);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    if (mt >= mtn) break;
+                    const T a = (row < hi) ? v_elem<T>(Vc, ldv, row, 16 * mt + l16, valid, n, first) : T(0);
+                    acc[mt] = Tile::mfma(a, b, acc[mt]);
+                }
             }
         }
 #pragma unroll
@@ -275,14 +321,33 @@ __device__ __forceinline__ void chunk_vtb(VtbSmem<Tile> &sm, const typename Tile
     const int64_t span = valid - rlo;
     const int64_t per = ((span + 15) / 16 + 3) / 4 * 16;
     const int64_t lo = rlo + w * per, hi = (lo + per < valid) ? lo + per : valid;
-    for (int64_t r4 = lo; r4 < hi; r4 += 4) {
-        const int64_t row = r4 + l4;
-        const T b = T((row < hi && l16 < kc) ? Bc[row + (int64_t)l16 * ldb] : 0.0);
+    if (wide_rows_ok(Vc + lo, ldv, Bc + lo, ldb, hi - lo)) {
+        // each lane reads 4 consecutive rows of its column with 16-byte
+        // loads (16 rows x 16 columns per instruction); MFMA q takes row
+        // 4 l4 + q of the 16-row block as its k = l4 element
+        for (int64_t r16 = lo; r16 < hi; r16 += 16) {
+            const int64_t rb = r16 + 4 * l4;
+            T b4[4];
+            load4<T>(Bc + rb + (int64_t)l16 * ldb, l16 < kc, b4);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            if (mt >= mtn) break;
-            const T a = (row < hi) ? v_elem<T>(Vc, ldv, row, 16 * mt + l16, valid, n, first) : T(0);
-            acc[mt] = Tile::mfma(a, b, acc[mt]);
+            for (int mt = 0; mt < 4; ++mt) {
+                if (mt >= mtn) break;
+                T a4[4];
+                load4<T>(Vc + rb + (int64_t)(16 * mt + l16) * ldv, 16 * mt + l16 < n, a4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[mt] = Tile::mfma(a4[q], b4[q], acc[mt]);
+            }
+        }
+    } else {
+        for (int64_t r4 = lo; r4 < hi; r4 += 4) {
+            const int64_t row = r4 + l4;
+            const T b = T((row < hi && l16 < kc) ? Bc[row + (int64_t)l16 * ldb] : 0.0);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                if (mt >= mtn) break;
+                const T a = (row < hi) ? v_elem<T>(Vc, ldv, row, 16 * mt + l16, valid, n, first) : T(0);
+                acc[mt] = Tile::mfma(a, b, acc[mt]);
+            }
         }
     }
 #pragma unroll

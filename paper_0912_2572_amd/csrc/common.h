@@ -17,6 +17,15 @@ constexpr int kLdsStride = 65;
 __host__ __device__ constexpr int rows_per_thread(int ns) { return ns >= 2 ? 16 : 32; }
 __host__ __device__ constexpr int chunk_rows(int ns) { return 16 * rows_per_thread(ns); }
 
+// The thread index, hidden from the optimizer: values derived from it are
+// then computed where they are used instead of being hoisted out of outer
+// loops, which under full register files only spills them.
+__device__ __forceinline__ int local_tid() {
+    int v = (int)threadIdx.x;
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // 64-bit lane permutations built from 32-bit DPP / swizzle primitives.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
