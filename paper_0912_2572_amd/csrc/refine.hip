@@ -99,6 +99,140 @@ __device__ __forceinline__ void resid_block(const double *__restrict__ A, int64_
     }
 }
 
+// Sum over the 16 lanes of a row (lane bits 0..3), the same bits in all 16.
+__device__ __forceinline__ double row16_sum(double v) {
+    v = sum_quad(v);
+    v += __shfl_xor(v, 4);
+    v += dpp_f64<kDppRowRor8>(v);
+    return v;
+}
+
+// Rows p[0 .. nv) of one column (zeros elsewhere, all zeros if !ok): two
+// 16-byte loads when all four rows are there and p is 16-byte aligned.
+__device__ __forceinline__ void load_rows4(const double *__restrict__ p, bool ok, int nv, bool al,
+                                           double (&v)[4]) {
+    if (ok && nv == 4 && al) {
+        const double2 x0 = reinterpret_cast<const double2 *>(p)[0];
+        const double2 x1 = reinterpret_cast<const double2 *>(p)[1];
+        v[0] = x0.x; v[1] = x0.y; v[2] = x1.x; v[3] = x1.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (ok && q < nv) ? p[q] : 0.0;
+    }
+}
+
+// The same pass as resid_block for n <= 16 MAXJT columns and k <= K
+// right-hand sides, laid out for HBM: lane = 16 rg + cg takes column
+// 16 jt + cg of the 16-column tile jt and the 4 consecutive rows 4 rg .. 4 rg + 3
+// of a 16-row block (16-byte loads), so an instruction reads whole lines.
+// A^T Rr accumulates per lane (one column, many rows) and is summed over
+// the lanes once at the end; A X is summed over the 16 column lanes of a
+// row per block.  Blocks of rows are multiples of 16; block blk covers
+// rows [blk per, (blk + 1) per) (possibly empty).
+template <int MAXJT, int K>
+__device__ __forceinline__ void resid_fast(const double *__restrict__ A, int64_t lda, int64_t m, int n,
+                                           const double *__restrict__ B, int64_t ldb,
+                                           const double *__restrict__ X, int64_t ldx,
+                                           const double *__restrict__ Rr, double *__restrict__ F, int k,
+                                           double *__restrict__ gpart, double *__restrict__ rpart,
+                                           int64_t blk, int64_t nblk) {
+    __shared__ double gsh[4][MAXJT * 16 * K];
+    __shared__ double ssh[4][K];
+    const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    const int njt = (n + 15) >> 4;
+    const int64_t per = ((m + nblk - 1) / nblk + 15) / 16 * 16;
+    const int64_t lo = blk * per;
+    const int64_t hi = (lo + per < m) ? lo + per : m;
+    const bool al = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 1) == 0;
+    double xr[MAXJT][K], g[MAXJT][K];
+#pragma unroll
+    for (int jt = 0; jt < MAXJT; ++jt)
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const int col = 16 * jt + l16;
+            xr[jt][c] = (jt < njt && col < n && c < k) ? X[col + (int64_t)c * ldx] : 0.0;
+            g[jt][c] = 0.0;
+        }
+    double ss = 0.0;   // squared (B - A X) of column l16 (lanes l16 < k)
+    for (int64_t rb0 = lo + 16 * w; rb0 < hi; rb0 += 64) {
+        const int64_t rb = rb0 + 4 * l4;
+        const int nv = (int)((hi - rb >= 4) ? 4 : (hi - rb > 0 ? hi - rb : 0));
+        double rr[4][K], sx[4][K];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                rr[q][c] = (q < nv && c < k) ? Rr[rb + q + (int64_t)c * m] : 0.0;
+                sx[q][c] = 0.0;
+            }
+#pragma unroll
+        for (int jt = 0; jt < MAXJT; ++jt) {
+            if (jt < njt) {   // a guard, not a break: the loop must unroll fully
+                const int col = 16 * jt + l16;
+                double a4[4];
+                load_rows4(A + rb + (int64_t)col * lda, col < n, nv, al, a4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        sx[q][c] = fma(a4[q], xr[jt][c], sx[q][c]);
+                        g[jt][c] = fma(a4[q], rr[q][c], g[jt][c]);
+                    }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < K; ++c) sx[q][c] = row16_sum(sx[q][c]);
+        if (l16 < k) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= nv) continue;
+                double ax = sx[q][0], rc = rr[q][0];
+#pragma unroll
+                for (int c = 1; c < K; ++c) {
+                    ax = (l16 == c) ? sx[q][c] : ax;
+                    rc = (l16 == c) ? rr[q][c] : rc;
+                }
+                const int64_t row = rb + q;
+                const double sres = B[row + (int64_t)l16 * ldb] - ax;
+                ss = fma(sres, sres, ss);
+                F[row + (int64_t)l16 * m] = sres - rc;
+            }
+        }
+    }
+    // totals over the 4 row groups of a wave, then over the waves in order
+#pragma unroll
+    for (int jt = 0; jt < MAXJT; ++jt)
+#pragma unroll
+        for (int c = 0; c < K; ++c) g[jt][c] = pair_sum32(pair_sum16(g[jt][c]));
+    ss = pair_sum32(pair_sum16(ss));
+    if (l4 == 0) {
+#pragma unroll
+        for (int jt = 0; jt < MAXJT; ++jt)
+#pragma unroll
+            for (int c = 0; c < K; ++c) gsh[w][(16 * jt + l16) * K + c] = g[jt][c];
+        if (l16 < K) ssh[w][l16] = ss;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * k; e += 256) {
+        const int j = e % n, c = e / n, idx = j * K + c;
+        gpart[blk * n * k + e] = ((gsh[0][idx] + gsh[1][idx]) + gsh[2][idx]) + gsh[3][idx];
+    }
+    if (tid < k) rpart[blk * k + tid] = ((ssh[0][tid] + ssh[1][tid]) + ssh[2][tid]) + ssh[3][tid];
+}
+
+template <int MAXJT, int K>
+__global__ __launch_bounds__(256) void k_lsq_resid_fast(const double *__restrict__ A, int64_t lda, int64_t m,
+                                                        int n, const double *__restrict__ B, int64_t ldb,
+                                                        const double *__restrict__ X, int64_t ldx,
+                                                        const double *__restrict__ Rr, double *__restrict__ F,
+                                                        int k, double *__restrict__ gpart,
+                                                        double *__restrict__ rpart) {
+    resid_fast<MAXJT, K>(A, lda, m, n, B, ldb, X, ldx, Rr, F, k, gpart, rpart, blockIdx.x, gridDim.x);
+}
+
 __global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A, int64_t lda, int64_t m,
                                                    int n, const double *__restrict__ B, int64_t ldb,
                                                    const double *__restrict__ X, int64_t ldx,
@@ -271,8 +405,12 @@ __global__ __launch_bounds__(256) void k_resid_b(const BMat *__restrict__ mats, 
     const BMat &M = mats[list[blockIdx.y]];
     if ((int)blockIdx.x >= M.nb) return;
     if (sweep > 0 && M.status[1]) return;
-    resid_block(M.A, M.lda, M.pa.m, M.pa.n, M.b, M.pa.m, M.Xw, M.pa.n, M.Rr, M.F, 1, M.gpart, M.rpart,
-                blockIdx.x, M.nb, sh);
+    if (M.pa.n <= 64)
+        resid_fast<4, 1>(M.A, M.lda, M.pa.m, M.pa.n, M.b, M.pa.m, M.Xw, M.pa.n, M.Rr, M.F, 1, M.gpart, M.rpart,
+                         blockIdx.x, M.nb);
+    else
+        resid_block(M.A, M.lda, M.pa.m, M.pa.n, M.b, M.pa.m, M.Xw, M.pa.n, M.Rr, M.F, 1, M.gpart, M.rpart,
+                    blockIdx.x, M.nb, sh);
 }
 
 // One workgroup per matrix.  Sweep 0 is the plain solve (g = 0); an FP64
@@ -390,6 +528,24 @@ int resid_blocks(int64_t m) {
 hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, const double *B, int64_t ldb,
                             const double *X, int64_t ldx, const double *Rr, double *F, int k,
                             double *gpart, double *rpart, int nblocks, hipStream_t st) {
+    // the line-wide pass for up to 16 MAXJT columns x K right-hand sides
+    // (MAXJT K <= 32 accumulators per lane), the tiled pass otherwise
+    const int njt = (n + 15) / 16;
+    const int jt = njt <= 4 ? 4 : (njt <= 8 ? 8 : (njt <= 16 ? 16 : 0));
+    const int kk = k <= 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : (k <= 8 ? 8 : 0)));
+    if (jt > 0 && kk > 0 && jt * kk <= 32) {
+        ProfScope ps("lsq_resid", st);
+#define TSQR_RESID_FAST(J, KK)                                                                              \
+    if (jt == J && kk == KK) {                                                                          \
+        hipLaunchKernelGGL((k_lsq_resid_fast<J, KK>), dim3(nblocks), dim3(256), 0, st, A, lda, m, n, B, ldb, \
+                           X, ldx, Rr, F, k, gpart, rpart);                                             \
+        return hipGetLastError();                                                                       \
+    }
+        TSQR_RESID_FAST(4, 1) TSQR_RESID_FAST(4, 2) TSQR_RESID_FAST(4, 4) TSQR_RESID_FAST(4, 8)
+        TSQR_RESID_FAST(8, 1) TSQR_RESID_FAST(8, 2) TSQR_RESID_FAST(8, 4)
+        TSQR_RESID_FAST(16, 1) TSQR_RESID_FAST(16, 2)
+#undef TSQR_RESID_FAST
+    }
     const size_t sh =
         sizeof(double) * ((size_t)kResRows * n + (size_t)n * k + 2 * (size_t)kResRows * k);
     hipError_t e = hipFuncSetAttribute((const void *)k_lsq_resid,
