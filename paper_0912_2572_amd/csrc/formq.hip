@@ -32,17 +32,43 @@ struct FormSmem {
 
 // Loads an n x n column-major matrix into a zero-padded 64 x 64 row-major
 // LDS matrix (optionally as a unit-lower-trapezoidal block: diagonal 1,
-// zeros above).
+// zeros above).  256 threads; each issues its 16 loads before the first
+// LDS store, so the block costs one memory round trip.
 __device__ __forceinline__ void load_nn(double *dst, const double *__restrict__ src, int64_t lds,
                                         int n, bool unit_lower) {
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-        const int r = e & 63, c = e >> 6;
-        double v = 0.0;
-        if (r < n && c < n) {
-            v = src[r + (int64_t)c * lds];
-            if (unit_lower) v = (r == c) ? 1.0 : (r > c ? v : 0.0);
-        }
-        dst[r * LD + c] = v;
+    constexpr int kPer = 64 * 64 / 256;
+    const int tid = local_tid();
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + 256 * u, r = e & 63, c = e >> 6;
+        v[u] = (r < n && c < n) ? src[r + (int64_t)c * lds] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + 256 * u, r = e & 63, c = e >> 6;
+        double x = v[u];
+        if (unit_lower && r < n && c < n) x = (r == c) ? 1.0 : (r > c ? x : 0.0);
+        dst[r * LD + c] = x;
+    }
+}
+
+// The same block in registers (thread's 16 entries, loads in flight) and
+// its later store into the LDS matrix.
+__device__ __forceinline__ void fetch_nn(double (&v)[16], const double *__restrict__ src, int64_t lds, int n) {
+    const int tid = local_tid();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, r = e & 63, c = e >> 6;
+        v[u] = (r < n && c < n) ? src[r + (int64_t)c * lds] : 0.0;
+    }
+}
+__device__ __forceinline__ void put_nn(double *dst, const double (&v)[16]) {
+    const int tid = local_tid();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, r = e & 63, c = e >> 6;
+        dst[r * LD + c] = v[u];
     }
 }
 
@@ -97,7 +123,7 @@ __global__ void k_seed_root(double *S, int n, const double *d) {
 __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__restrict__ Vc, int64_t ldv,
                                           double *__restrict__ Qc, int64_t ldq, int64_t valid, int n,
                                           bool first) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     const int kbn = (n + 3) >> 2;
     double za[16][4];
@@ -164,13 +190,16 @@ __global__ __launch_bounds__(256) void k_form_leaf(const double *__restrict__ V,
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     load_nn(sm.X, S + dom * nn, n, n, false);
+    // T of the chunk processed next, fetched one chunk ahead
+    double tn[16];
+    fetch_nn(tn, Tc + (dom * pa.cpd + nch - 1) * nn, n, n);
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
         const int64_t r0 = row0 + ch * pa.chunk;
         const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
-        const double *Tk = Tc + (dom * pa.cpd + ch) * nn;
         __syncthreads();
         if (ch > 0) {
-            load_nn(sm.T, Tk, n, n, false);
+            put_nn(sm.T, tn);
+            fetch_nn(tn, Tc + (dom * pa.cpd + ch - 1) * nn, n, n);
             __syncthreads();
             lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);    // Z = T_k X
             __syncthreads();
@@ -182,7 +211,7 @@ __global__ __launch_bounds__(256) void k_form_leaf(const double *__restrict__ V,
             __syncthreads();
             lds_gemm64(sm.T, sm.X, sm.W, LD, true, true, 1.0);     // W = V_0top^T X
             __syncthreads();
-            load_nn(sm.T, Tk, n, n, false);
+            put_nn(sm.T, tn);
             __syncthreads();
             lds_gemm64(sm.T, sm.W, sm.Z, LD, true, false, 1.0);    // Z = T_0 W
             __syncthreads();

@@ -9,6 +9,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.h"
+
 namespace tsqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -54,7 +56,7 @@ __device__ __forceinline__ int d_col(int lane) { return lane & 15; }
 // triangular A.  If transA, op(A) = A^T.  C may not alias A or B.
 __device__ __forceinline__ void lds_gemm64(const double *A, const double *B, double *C, int ld,
                                            bool a_upper, bool transA, double scale) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int I = w;
     d4 acc[4];
 #pragma unroll
