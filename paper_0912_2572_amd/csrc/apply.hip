@@ -225,11 +225,23 @@ __device__ __forceinline__ void tree_apply_chain(ApplySmem &sm, const double *__
         const double *U = Rdom + right * nn;
         const double *T = Tnode + right * nn;
         double *Yr = B0 + right * pa.mb;
+        // the node's U and T: every load in flight before the LDS stores
+        double uv[16], tv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            uv[u] = (e < n * n) ? U[e] : 0.0;
+            tv[u] = (e < n * n) ? T[e] : 0.0;
+        }
         __syncthreads();
-        for (int e = tid; e < n * n; e += 256) {
-            const int r = e % n, c = e / n;
-            sm.Vs[r * kLdsStride + c] = U[e];
-            sm.Ts[r * kLdsStride + c] = T[e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            if (e < n * n) {
+                const int r = e % n, c = e / n;
+                sm.Vs[r * kLdsStride + c] = uv[u];
+                sm.Ts[r * kLdsStride + c] = tv[u];
+            }
         }
         for (int e = tid; e < 64 * KB; e += 256) {
             const int r = e & 63, c = e >> 6;

@@ -490,9 +490,20 @@ __device__ __forceinline__ void tree_chain(FactorSmem &sm, double *__restrict__ 
     zero_lds(sm.R);
     zero_lds(sm.T);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e % n, k = e / n;
-        if (r <= k) sm.R[r * kLdsStride + k] = Rdom[left * nn + e];
+    {
+        // the left triangle, every load in flight before the LDS stores
+        double rv[64 * 64 / kFactorThreads];
+#pragma unroll
+        for (int u = 0; u < 64 * 64 / kFactorThreads; ++u) {
+            const int e = threadIdx.x + kFactorThreads * u;
+            rv[u] = (e < n * n) ? Rdom[left * nn + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 64 * 64 / kFactorThreads; ++u) {
+            const int e = threadIdx.x + kFactorThreads * u;
+            const int r = e % n, k = e / n;
+            if (e < n * n && r <= k) sm.R[r * kLdsStride + k] = rv[u];
+        }
     }
     __syncthreads();
     constexpr int RPT = 64 / kRowGroups;   // the right triangle has n <= 64 rows
