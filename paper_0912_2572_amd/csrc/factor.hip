@@ -16,7 +16,7 @@
 //
 // Register tile of a chunk: 256 threads (4 waves); lane = 16 rg + cg (cg =
 // column group 0..15, rg = row group 0..3 inside the wave, 16 row groups per
-// workgroup).  A thread owns rows {16 i + 4 w + rg : i < RPT} and columns
+// workgroup).  A thread owns rows {RPT (4 w + rg) + i : i < RPT} and columns
 // {cg + 16 t : t < NS}.  Column step j of Householder QR needs one reduction: with x = column
 // j, the dots d_k = x . c_k for every column k give ||x||^2 (k = j), the
 // update coefficients (k > j) and, for k < j, the Gram entries y_k . y_j
@@ -174,8 +174,8 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     // first chunk: row j is the pivot row, reduced separately (qv) and left
     // out of the dots.  Lane-dependent choices below are selects, not
     // branches, so the wave keeps one execution mask.
-    const bool own_j = FIRST && (rgw == (j % kRowGroups));
-    const int ij = j / kRowGroups;
+    const bool own_j = FIRST && (rgw == j / RPT);
+    const int ij = j % RPT;
     double qv[NS];
     if (FIRST) {
 #pragma unroll
@@ -372,9 +372,19 @@ __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
     }
 }
 
+// Thread rows: row group rgw owns the RPT consecutive rows RPT rgw .. RPT rgw
+// + RPT - 1 of a chunk, so a lane moves whole 16-byte pieces (and, over its
+// loop, whole cache lines) of each column.  Vector accesses need a 16-byte
+// aligned column start; otherwise the same rows go element by element.
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ bool rows_aligned(const T *p, int64_t ld) {
+    return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && (ld * (int64_t)sizeof(T)) % 16 == 0;
+}
+
 // Loads rows [0, valid) x columns [0, n) of a chunk at src (ld) into c
-// (zeros elsewhere).  A full chunk takes one base address per column slot
-// plus immediate row offsets, so no per-element address stays live.
+// (zeros elsewhere).
 template <int NS, int RPT>
 __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
                                            const double *__restrict__ src, int64_t ld, int64_t valid,
@@ -382,17 +392,22 @@ __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
+    const bool vec = full && (RPT % 2 == 0) && rows_aligned(src, ld);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
-        const double *p = src + rgw + (int64_t)k * ld;
-        if (k < n && full) {
+        const double *p = src + (int64_t)rgw * RPT + (int64_t)k * ld;
+        if (k < n && vec) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) c[i][t] = __builtin_nontemporal_load(p + i * kRowGroups);
+            for (int i = 0; i < RPT; i += 2) {
+                const dv2 v = __builtin_nontemporal_load(reinterpret_cast<const dv2 *>(p + i));
+                c[i][t] = v.x;
+                c[i + 1][t] = v.y;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
-                c[i][t] = (k < n && i * kRowGroups + rgw < valid) ? p[i * kRowGroups] : 0.0;
+                c[i][t] = (k < n && (int64_t)rgw * RPT + i < valid) ? p[i] : 0.0;
         }
     }
 }
@@ -403,17 +418,36 @@ __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
+    constexpr int VW = 16 / sizeof(OT);   // elements per 16-byte store
+    const bool vec = full && (RPT % VW == 0) && rows_aligned(dst, ld);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
-        OT *p = dst + rgw + (int64_t)k * ld;
-        if (k < n && full) {
+        OT *p = dst + (int64_t)rgw * RPT + (int64_t)k * ld;
+        if (k < n && vec) {
+            if constexpr (VW == 2) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) p[i * kRowGroups] = OT(c[i][t]);
+                for (int i = 0; i < RPT; i += 2) {
+                    double2 v;
+                    v.x = c[i][t];
+                    v.y = c[i + 1][t];
+                    *reinterpret_cast<double2 *>(p + i) = v;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < RPT; i += 4) {
+                    float4 v;
+                    v.x = float(c[i][t]);
+                    v.y = float(c[i + 1][t]);
+                    v.z = float(c[i + 2][t]);
+                    v.w = float(c[i + 3][t]);
+                    *reinterpret_cast<float4 *>(p + i) = v;
+                }
+            }
         } else if (k < n) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
-                if (i * kRowGroups + rgw < valid) p[i * kRowGroups] = OT(c[i][t]);
+                if ((int64_t)rgw * RPT + i < valid) p[i] = OT(c[i][t]);
         }
     }
 }
