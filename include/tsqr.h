@@ -122,7 +122,13 @@ TSQR_API int tsqr_apply_qt(tsqr_factors f, int64_t k, double *B, int64_t ldb, vo
 TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream);
 
 /* Thin Q (m x n, device, ldq >= m), sign-normalised so that A = Q R with
-   diag(R) >= 0 and Q^T Q = I. */
+   diag(R) >= 0 and Q^T Q = I.
+   Concurrency: calls on one factor are ordered by the caller (one stream,
+   or events).  One exception: for an FP64 factor with n <= 64 this call only
+   reads the factor and writes Q and its own workspace blocks (the top-down
+   tree blocks), so once tsqr_factor has completed it may run on another
+   stream at the same time as tsqr_lsq_solve, tsqr_apply_qt or tsqr_apply_q
+   on the same factor. */
 TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream);
 
 /* Least squares min ||A x_j - b_j||_2 for k <= opts.lsq_max_rhs right-hand

@@ -146,6 +146,35 @@ def test_zero_column_info(tl):
     assert torch.all(X0 == 7.0)
 
 
+def test_form_q_concurrent_with_solve(tl):
+    """The documented exception to call ordering: for an FP64 factor with
+    n <= 64 the thin Q may be formed on another stream while the same factor
+    solves a least-squares problem; both results equal (bitwise) those of
+    the two calls made one after the other."""
+    A = synth.gaussian(60000, 64, seed=21)
+    b = np.random.default_rng(22).standard_normal((60000, 1))
+    Ad, bd = dev(A), dev(b)
+    print("case form_q || lsq, 60000 x 64", flush=True)
+    f = tl.factor(Ad, row_block=4096, lsq_max_rhs=1)
+    Q1 = f.form_q()
+    X1, r1, _ = f.lsq(bd)
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        Q2 = torch.empty_like(Q1)
+        X2 = torch.full_like(X1, -1.0)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            f.form_q(Q2)
+        _, r2, info = f.lsq(bd, X=X2)
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert torch.equal(Q2, Q1), f"rep {rep}"
+        assert torch.equal(X2, X1) and torch.equal(r2, r1), f"rep {rep}"
+
+
 def test_deterministic_and_r_only(tl):
     A = synth.gaussian(50000, 48, seed=9)
     Ad = dev(A)
