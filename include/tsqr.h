@@ -168,8 +168,12 @@ TSQR_API int64_t tsqr_tree_schedule(int64_t P, int tree, int64_t *left, int64_t 
    synchronises on the recorded events and returns, for the i-th distinct
    tag (i = 0, 1, ...), its name, launch count and summed milliseconds; it
    returns 0, or -1 once i is past the last tag.  tsqr_prof_enable(0)
-   disables and clears.  Not thread-safe; process-wide. */
+   disables and clears.  tsqr_prof_only(tag) restricts the timing to the
+   kernels of one tag (a copy of the string is kept; NULL or "" times all),
+   so that a timed loop carries two events per launch of that kernel only.
+   Not thread-safe; process-wide. */
 TSQR_API int tsqr_prof_enable(int on);
+TSQR_API int tsqr_prof_only(const char *tag);
 TSQR_API int tsqr_prof_query(int i, const char **name, int64_t *launches, double *ms);
 
 /* ------------------------------------------------------------------------

@@ -139,6 +139,8 @@ def lib():
         L.tsqr_tree_schedule.restype = i64
         L.tsqr_prof_enable.argtypes = [ctypes.c_int]
         L.tsqr_prof_enable.restype = ctypes.c_int
+        L.tsqr_prof_only.argtypes = [ctypes.c_char_p]
+        L.tsqr_prof_only.restype = ctypes.c_int
         L.tsqr_prof_query.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         L.tsqr_prof_query.restype = ctypes.c_int
@@ -233,6 +235,11 @@ def tree_schedule(P: int, tree: int):
 def prof_enable(on: bool = True) -> None:
     """Bracket every library kernel launch with HIP events (see tsqr.h)."""
     lib().tsqr_prof_enable(1 if on else 0)
+
+
+def prof_only(tag: str | None) -> None:
+    """Time only the kernels tagged `tag` (None: all), see tsqr.h."""
+    lib().tsqr_prof_only(tag.encode() if tag else None)
 
 
 def prof_query() -> dict:

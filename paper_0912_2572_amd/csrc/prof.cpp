@@ -17,6 +17,7 @@ struct Rec {
 
 bool g_on = false;
 int g_suspend = 0;    // > 0 while a stream is being captured into a graph
+std::string g_only;   // when not empty, only this tag is timed
 std::vector<Rec> g_recs;       // events recorded since the last query
 std::vector<hipEvent_t> g_pool;
 struct Agg {
@@ -64,6 +65,7 @@ void prof_suspend(bool on) { g_suspend += on ? 1 : -1; }
 
 int prof_begin(const char *tag, hipStream_t st) {
     if (!g_on || g_suspend > 0) return -1;
+    if (!g_only.empty() && g_only != tag) return -1;
     if (g_recs.size() > 20000) drain();
     Rec r{tag, get_event(), get_event()};
     if (r.a) hipEventRecord(r.a, st);
@@ -84,6 +86,11 @@ TSQR_API int tsqr_prof_enable(int on) {
     tsqr::drain();
     tsqr::g_agg.clear();
     tsqr::g_on = on != 0;
+    return 0;
+}
+
+TSQR_API int tsqr_prof_only(const char *tag) {
+    tsqr::g_only = tag ? tag : "";
     return 0;
 }
 
