@@ -58,6 +58,34 @@ __device__ __forceinline__ double pair_sum32(double v) {
     return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
 
+// Two pair sums for the price of one exchange: a lane with bit 4 clear ends
+// with a[l] + a[l ^ 16], a lane with bit 4 set with b[l] + b[l ^ 16] (the
+// swap trades the odd 16-lane rows of its first operand for the even rows of
+// its second).  Each total is bitwise the one pair_sum16 gives.
+__device__ __forceinline__ double split_sum16(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+// Across lane bit 5: lanes 0..31 end with a[l] + a[l ^ 32], lanes 32..63
+// with b[l] + b[l ^ 32].
+__device__ __forceinline__ double split_sum32(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Wave total of per-slot partials p[t] (t < NS, NS in {1, 2, 4}) over the 4
+// 16-lane rows, returned in row r for slot r (r < NS): one exchange tree for
+// all slots instead of one per slot.
+template <int NS>
+__device__ __forceinline__ double row_slot_total(const double (&p)[NS]) {
+    static_assert(NS == 1 || NS == 2 || NS == 4, "slot count");
+    if constexpr (NS == 4) return split_sum32(split_sum16(p[0], p[1]), split_sum16(p[2], p[3]));
+    else if constexpr (NS == 2) return pair_sum32(split_sum16(p[0], p[1]));
+    else return pair_sum32(pair_sum16(p[0]));
+}
+
 // Sum over the 8 lanes that share a column group (lane = rg * 8 + cg), i.e.
 // across lane bits 3..5, entirely in the VALU (DPP and permlane swaps).
 // Every participating lane ends with the bitwise-identical sum.

@@ -35,6 +35,13 @@ constexpr int kWaves = 4;                  // waves per leaf/tree workgroup
 constexpr int kFactorThreads = 64 * kWaves;
 constexpr int kRowGroups = 4 * kWaves;     // row groups per workgroup
 
+// Thread index as the step code uses it: for narrow panels (NS <= 2, two
+// workgroups per CU, 256 registers) hidden from the optimizer so that
+// loop-invariant addresses are not hoisted into spills; the wide kernel has
+// the AGPRs to keep them.
+template <int NS>
+__device__ __forceinline__ int step_tid() { return NS == 2 ? local_tid() : (int)threadIdx.x; }
+
 // LDS of the leaf and tree kernels (about 75 KiB).
 struct FactorSmem {
     double R[64 * kLdsStride];   // running triangle, row-major
@@ -47,10 +54,22 @@ struct FactorSmem {
         double P[64 * 16];                // scratch of the blocked T build
     } u;
     double tau[64];
+    double scl[64];   // reflector scale s_j of a later chunk's column j
 };
 
 // Gram entry G[k][j] = y_k . y_j (k < j), kept in the lower triangle of T.
 __device__ __forceinline__ double &gram(FactorSmem &sm, int k, int j) { return sm.T[j * kLdsStride + k]; }
+
+// G[k][j] (k < j) at step j from d = x . c_k, with s = s_j.  First chunk:
+// c_k is the scaled reflector y_k below the pivot rows and e its pivot-row
+// entry, so G = e + s d.  Later chunk: the reflector column c_k is still
+// unscaled (y_k = [e_k; s_k c_k]) and y_k, y_j share no R-part entry, so
+// G = s_k (s d).
+template <bool FIRST>
+__device__ __forceinline__ double gram_entry(const FactorSmem &sm, int k, double s, double d, double e) {
+    if constexpr (FIRST) return fma(s, d, e);
+    else return sm.scl[k] * (s * d);
+}
 
 // Compact-WY factor T of the chunk (Sec. 2.2: H_1...H_n = I - V T V^T),
 // built once per chunk from tau and the Gram matrix G = Y^T Y by the
@@ -158,6 +177,8 @@ __device__ __forceinline__ double read_lane(double v, int src) {
 //     k > j:  w = e_k + s d_k,  c_k -= tau w s x,  R[j][k] = e_k - tau w
 //     k = j:  v_j = s x,  R[j][j] = beta
 //     k < j:  G[k][j] = y_k . y_j = (pivot-row value) + s d_k.
+// In a later chunk the reflector column keeps x and s is applied once at
+// the end of the chunk, so there G[k][j] = s_k s d_k.
 // The next column's pre-update values are fetched into xn from their owner
 // lanes before the barrier, and every thread applies step j's update to
 // them itself (the same fma as the owner), so the next step needs no
@@ -167,7 +188,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
                                          const int n, FactorSmem &sm, const bool want_t,
                                          double (&x)[RPT], double (&xn)[RPT], double (&rnew)[NS],
                                          int &jprev) {
-    const int tid = threadIdx.x;
+    const int tid = step_tid<NS>();
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const int par = j & 1;
@@ -219,22 +240,10 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
             }
         }
 #pragma unroll
-        for (int t = 0; t < NS; ++t) p[t] = pair_sum16(s0[t] + s1[t]);
-#pragma unroll
-        for (int t = 0; t < NS; ++t) p[t] = pair_sum32(p[t]);
-        double pub = p[0], pubq = 0.0;
-#pragma unroll
-        for (int t = 1; t < NS; ++t) pub = (rg == t) ? p[t] : pub;
-        if (FIRST) {
-            double pq[NS];
-#pragma unroll
-            for (int t = 0; t < NS; ++t) pq[t] = pair_sum16(qv[t]);
-#pragma unroll
-            for (int t = 0; t < NS; ++t) pq[t] = pair_sum32(pq[t]);
-            pubq = pq[0];
-#pragma unroll
-            for (int t = 1; t < NS; ++t) pubq = (rg == t) ? pq[t] : pubq;
-        }
+        for (int t = 0; t < NS; ++t) p[t] = s0[t] + s1[t];
+        const double pub = row_slot_total<NS>(p);
+        double pubq = 0.0;
+        if constexpr (FIRST) pubq = row_slot_total<NS>(qv);
         if (rg < NS) {
             sm.u.s.red[par][cg + 16 * rg][w] = pub;
             if (FIRST) sm.u.s.redq[par][cg + 16 * rg][w] = pubq;
@@ -296,7 +305,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         const double d = dv[t];
         const double e = ev[t];
         if (t < TJ) {
-            if (want_t && rgw == 0) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
+            if (want_t && rgw == 0) gram(sm, k, j) = gram_entry<FIRST>(sm, k, s, d, e);
             continue;
         }
         const double wv = fma(s, d, e);
@@ -311,17 +320,27 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         } else {
             const bool upd = cg > q, refl = cg == q;
             const double f = upd ? (tau * wv) * s : 0.0;
+            if constexpr (FIRST) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const double u = fma(-f, x[i], c[i][t]);
-                const double r = refl ? s * x[i] : u;
-                c[i][t] = (FIRST && own_j && upd && i == ij) ? 0.0 : r;
+                for (int i = 0; i < RPT; ++i) {
+                    const double u = fma(-f, x[i], c[i][t]);
+                    const double r = refl ? s * x[i] : u;
+                    c[i][t] = (own_j && upd && i == ij) ? 0.0 : r;
+                }
+            } else {
+                // the reflector column keeps x (bitwise its owner's column);
+                // its scale s waits in sm.scl for the end of the chunk
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
             }
             rnew[t] = upd ? e - tau * wv : beta;
-            if (want_t && rgw == 0 && cg < q) gram(sm, k, j) = fma(s, d, FIRST ? e : 0.0);
+            if (want_t && rgw == 0 && cg < q) gram(sm, k, j) = gram_entry<FIRST>(sm, k, s, d, e);
         }
     }
-    if (tid == 0) sm.tau[j] = tau;
+    if (tid == 0) {
+        sm.tau[j] = tau;
+        if (!FIRST) sm.scl[j] = s;
+    }
     jprev = j;
 }
 
@@ -355,7 +374,7 @@ __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
 template <int NS, int RPT, bool FIRST>
 __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
                                          FactorSmem &sm, const bool want_t) {
-    const int tid = threadIdx.x;
+    const int tid = step_tid<NS>();
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     StepState<NS, RPT> ss;
@@ -368,6 +387,16 @@ __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
         for (int t = 0; t < NS; ++t) {
             const int k = cg + 16 * t;
             if (k >= ss.jprev) sm.R[ss.jprev * kLdsStride + k] = ss.rnew[t];
+        }
+    }
+    if constexpr (!FIRST) {
+        // reflector tails v_k = s_k x_k (the steps left them unscaled)
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int k = cg + 16 * t;
+            const double sk = (k < n) ? sm.scl[k] : 1.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) c[i][t] = sk * c[i][t];
         }
     }
 }
@@ -389,7 +418,7 @@ template <int NS, int RPT>
 __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
                                            const double *__restrict__ src, int64_t ld, int64_t valid,
                                            int n) {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
     const bool vec = full && (RPT % 2 == 0) && rows_aligned(src, ld);
@@ -417,7 +446,7 @@ __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
 template <int NS, int RPT, typename OT = double>
 __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
                                             OT *__restrict__ dst, int64_t ld, int64_t valid, int n) {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
     constexpr int VW = 16 / sizeof(OT);   // elements per 16-byte store
@@ -503,8 +532,13 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
     store_tri(sm.R, Rdom + dom * (int64_t)n * n, n);
 }
 
+// Narrow panels (NS <= 2) fit two workgroups per CU (registers and LDS), which
+// hides step latency whenever there are more domains than CUs.
+template <int NS>
+constexpr int leaf_min_blocks() { return NS == 2 ? 2 : 1; }
+
 template <int NS, typename VT>
-__global__ __launch_bounds__(kFactorThreads) void k_leaf(const double *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf(const double *__restrict__ A, int64_t lda,
                                                  VT *__restrict__ V, int64_t ldv,
                                                  double *__restrict__ Tc, double *__restrict__ Rdom,
                                                  PanelArgs pa, int keep_q) {
@@ -584,7 +618,7 @@ size_t factor_smem_bytes() { return sizeof(FactorSmem); }
 // ---- batched forms: grid.y walks the matrix list, grid.x the domains /
 // chains of the listed matrix (a workgroup past its matrix's count returns).
 template <int NS>
-__global__ __launch_bounds__(kFactorThreads) void k_leaf_b(const BMat *__restrict__ mats,
+__global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf_b(const BMat *__restrict__ mats,
                                                    const int *__restrict__ list) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
