@@ -80,7 +80,7 @@ __device__ __forceinline__ double gram_entry(const FactorSmem &sm, int k, double
 //     T[0:16J, J] = -T[0:16J, 0:16J] (G[0:16J, J] T_JJ),
 // as FP64 MFMA tiles.
 __device__ __forceinline__ void build_t(FactorSmem &sm, const int n) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int j0 = 16 * w;
     double trow[16];
     const int i = lane & 15;
@@ -443,6 +443,46 @@ __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
     }
 }
 
+// Loads of a full chunk (all RPT * 16 rows valid) with no branch around
+// them, so that they can stay in flight across other work: the compiler
+// keeps a load's result where the chunk lives only if no join follows it.
+// A column past n reads column 0 instead; clear_pad_cols zeroes it once the
+// data is there.  VEC: 16-byte pieces (rows_aligned(src, ld) must hold).
+template <int NS, int RPT, bool VEC>
+__device__ __forceinline__ void issue_full_chunk(double (&c)[RPT][NS], const double *__restrict__ src,
+                                                 int64_t ld, int n) {
+    const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int rgw = w * 4 + rg;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int k = cg + 16 * t;
+        const double *p = src + (int64_t)rgw * RPT + (int64_t)(k < n ? k : 0) * ld;
+        if constexpr (VEC) {
+#pragma unroll
+            for (int i = 0; i < RPT; i += 2) {
+                const dv2 v = *reinterpret_cast<const dv2 *>(p + i);
+                c[i][t] = v.x;
+                c[i + 1][t] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) c[i][t] = p[i];
+        }
+    }
+}
+
+template <int NS, int RPT>
+__device__ __forceinline__ void clear_pad_cols(double (&c)[RPT][NS], int n) {
+    if (n >= 16 * NS) return;
+    const int cg = step_tid<NS>() & 15;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const bool pad = cg + 16 * t >= n;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) c[i][t] = pad ? 0.0 : c[i][t];
+    }
+}
+
 template <int NS, int RPT, typename OT = double>
 __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
                                             OT *__restrict__ dst, int64_t ld, int64_t valid, int n) {
@@ -486,7 +526,7 @@ __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
 // Upper triangle of an LDS matrix (row-major) -> column-major n x n with
 // zeros below the diagonal.
 __device__ __forceinline__ void store_tri(const double *lds, double *__restrict__ dst, int n) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    for (int e = local_tid(); e < n * n; e += kFactorThreads) {
         const int r = e % n, k = e / n;
         dst[e] = (r <= k) ? lds[r * kLdsStride + k] : 0.0;
     }
@@ -499,37 +539,62 @@ __device__ __forceinline__ void zero_lds(double *lds) {
 // Leaf QR of domain `dom` (step 2): the chunks of the domain in order, a
 // geqrt of the first and a tpqrt of [R; chunk] for each later one.
 // VT: element type of the stored reflectors (double, or float in the mixed
-// mode, where they only feed the FP32 matrix-core applies).
-template <int NS, typename VT>
+// mode, where they only feed the FP32 matrix-core applies).  VEC: the
+// columns of A allow 16-byte loads (rows_aligned).
+//
+// The loads of chunk c + 1 are issued as soon as chunk c's reflectors are
+// stored and stay in flight while chunk c's T is built and stored, so the
+// HBM time of both hides behind that work.  Only the last domain can end in
+// a partial chunk; it is loaded with masking at the top of its own
+// iteration (the prefetch before it re-reads the last full chunk, unused).
+template <int NS, typename VT, bool VEC>
 __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__restrict__ A, int64_t lda,
                                             VT *__restrict__ V, int64_t ldv, double *__restrict__ Tc,
                                             double *__restrict__ Rdom, const PanelArgs &pa, int keep_q,
                                             int64_t dom) {
     constexpr int ROWS = chunk_rows(NS);
+    constexpr int RPT = rows_per_thread(NS);
     const int64_t row0 = dom * pa.mb;
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
-    const int64_t nch = (nrows + ROWS - 1) / ROWS;
+    const int64_t nfull = nrows / ROWS;          // full chunks
+    const int64_t tail = nrows - nfull * ROWS;   // rows of a partial last chunk
     const int n = pa.n;
+    const int64_t nn = (int64_t)n * n;
     const bool want_t = keep_q != 0;
     zero_lds(sm.R);
     zero_lds(sm.T);
     __syncthreads();
-    constexpr int RPT = rows_per_thread(NS);
     double c[RPT][NS];
-    for (int64_t ch = 0; ch < nch; ++ch) {
-        const int64_t r0 = row0 + ch * ROWS;
-        const int64_t valid = (nrows - ch * ROWS < ROWS) ? nrows - ch * ROWS : ROWS;
-        load_chunk<NS, RPT>(c, A + r0, lda, valid, n);
-        if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t);
-        else chunk_qr<NS, RPT, false>(c, n, sm, want_t);
+    if (nfull == 0) {
+        // a domain shorter than one chunk
+        load_chunk<NS, RPT>(c, A + row0, lda, tail, n);
+        chunk_qr<NS, RPT, true>(c, n, sm, want_t);
         if (want_t) {
-            store_chunk<NS, RPT, VT>(c, V + r0, ldv, valid, n);
+            store_chunk<NS, RPT, VT>(c, V + row0, ldv, tail, n);
             build_t(sm, n);
-            store_tri(sm.T, Tc + (dom * pa.cpd + ch) * (int64_t)n * n, n);
+            store_tri(sm.T, Tc + dom * pa.cpd * nn, n);
         }
         __syncthreads();
+    } else {
+        const int64_t nch = nfull + (tail > 0 ? 1 : 0);
+        issue_full_chunk<NS, RPT, VEC>(c, A + row0, lda, n);
+        for (int64_t ch = 0; ch < nch; ++ch) {
+            const int64_t r0 = row0 + ch * ROWS;
+            if (ch == nfull) load_chunk<NS, RPT>(c, A + r0, lda, tail, n);
+            else clear_pad_cols<NS, RPT>(c, n);
+            if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t);
+            else chunk_qr<NS, RPT, false>(c, n, sm, want_t);
+            if (want_t) store_chunk<NS, RPT, VT>(c, V + r0, ldv, ch < nfull ? (int64_t)ROWS : tail, n);
+            const int64_t nx = (ch + 1 < nfull) ? ch + 1 : nfull - 1;
+            issue_full_chunk<NS, RPT, VEC>(c, A + row0 + nx * ROWS, lda, n);
+            if (want_t) {
+                build_t(sm, n);
+                store_tri(sm.T, Tc + (dom * pa.cpd + ch) * nn, n);
+            }
+            __syncthreads();
+        }
     }
-    store_tri(sm.R, Rdom + dom * (int64_t)n * n, n);
+    store_tri(sm.R, Rdom + dom * nn, n);
 }
 
 // Narrow panels (NS <= 2) fit two workgroups per CU (registers and LDS), which
@@ -537,14 +602,14 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
 template <int NS>
 constexpr int leaf_min_blocks() { return NS == 2 ? 2 : 1; }
 
-template <int NS, typename VT>
+template <int NS, typename VT, bool VEC>
 __global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf(const double *__restrict__ A, int64_t lda,
                                                  VT *__restrict__ V, int64_t ldv,
                                                  double *__restrict__ Tc, double *__restrict__ Rdom,
                                                  PanelArgs pa, int keep_q) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
-    leaf_domain<NS, VT>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x);
+    leaf_domain<NS, VT, VEC>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x);
 }
 
 // One chain of combines (step 3): left <- qr([R_left; R_right]) for every
@@ -625,10 +690,14 @@ __global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf_
     const BMat &M = mats[list[blockIdx.y]];
     const int64_t dom = blockIdx.x;
     if (dom >= M.pa.P) return;
-    if (M.prec)
-        leaf_domain<NS, float>(sm, M.A, M.lda, M.V32, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
-    else
-        leaf_domain<NS, double>(sm, M.A, M.lda, M.V, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+    const bool vec = rows_aligned(M.A, M.lda);
+    if (M.prec) {
+        if (vec) leaf_domain<NS, float, true>(sm, M.A, M.lda, M.V32, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+        else leaf_domain<NS, float, false>(sm, M.A, M.lda, M.V32, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+    } else {
+        if (vec) leaf_domain<NS, double, true>(sm, M.A, M.lda, M.V, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+        else leaf_domain<NS, double, false>(sm, M.A, M.lda, M.V, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
+    }
 }
 
 template <int NS>
@@ -705,18 +774,27 @@ hipError_t launch_sign_b(const BMat *mats, const int *list, int cnt, hipStream_t
     return hipGetLastError();
 }
 
+template <int NS, typename VT, bool VEC>
+static hipError_t launch_leaf_nsv(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,
+                                  double *Rdom, const PanelArgs &pa, int keep_q, const char *tag,
+                                  hipStream_t st) {
+    const size_t sh = sizeof(FactorSmem);
+    hipError_t e = hipFuncSetAttribute((const void *)k_leaf<NS, VT, VEC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps(tag, st);
+    hipLaunchKernelGGL((k_leaf<NS, VT, VEC>), dim3((unsigned)pa.P), dim3(kFactorThreads), sh, st, A, lda, V,
+                       ldv, Tc, Rdom, pa, keep_q);
+    return hipGetLastError();
+}
+
 template <int NS, typename VT>
 static hipError_t launch_leaf_ns(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,
                                  double *Rdom, const PanelArgs &pa, int keep_q, const char *tag,
                                  hipStream_t st) {
-    const size_t sh = sizeof(FactorSmem);
-    hipError_t e = hipFuncSetAttribute((const void *)k_leaf<NS, VT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    if (e != hipSuccess) return e;
-    ProfScope ps(tag, st);
-    hipLaunchKernelGGL((k_leaf<NS, VT>), dim3((unsigned)pa.P), dim3(kFactorThreads), sh, st, A, lda, V, ldv,
-                       Tc, Rdom, pa, keep_q);
-    return hipGetLastError();
+    const bool vec = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda * (int64_t)sizeof(double)) % 16 == 0;
+    return vec ? launch_leaf_nsv<NS, VT, true>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st)
+               : launch_leaf_nsv<NS, VT, false>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
 }
 
 template <typename VT>
