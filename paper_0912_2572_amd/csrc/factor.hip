@@ -145,12 +145,10 @@ struct StepState {
     int jprev = -1;
 };
 
-// Total of column `lane` over the waves' partials, in a fixed order (every
-// wave computes the same bits).  Lane k of each wave then holds column k's
-// total; a thread takes the totals of its own columns from those lanes.
-__device__ __forceinline__ double col_total(const double (&a)[2][64][kWaves], int par) {
-    const int lane = threadIdx.x & 63;
-    const double2 *p = reinterpret_cast<const double2 *>(&a[par][lane][0]);
+// Total of column k over the waves' partials, in a fixed order, so every
+// thread that needs column k's total computes the same bits.
+__device__ __forceinline__ double col_total(const double (&a)[2][64][kWaves], int par, int k) {
+    const double2 *p = reinterpret_cast<const double2 *>(&a[par][k][0]);
     double2 v[kWaves / 2];
 #pragma unroll
     for (int h = 0; h < kWaves / 2; ++h) v[h] = p[h];
@@ -269,21 +267,46 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
             if (k >= jprev) sm.R[jprev * kLdsStride + k] = rnew[t];
         }
     }
-    const double tot = col_total(sm.u.s.red, par);
-    const double totq = FIRST ? col_total(sm.u.s.redq, par) : 0.0;
-    // this thread's columns: dots d and (first chunk) the pivot-row entries e
+    // this thread's columns: dots d and (first chunk) the pivot-row entries
+    // e.  Narrow kernels: each thread sums its own columns straight from LDS
+    // (one LDS round trip on the critical path), and column j's values sit
+    // in slot TJ of lane q, column j + 1's in lane q + 1 or, past the slot,
+    // lane 0 of slot TJ + 1.  Wide kernel (no registers for that): lane k
+    // sums column k and the threads fetch their columns from those lanes.
     double dv[NS];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        dv[t] = __shfl(tot, cg + 16 * t);
-        if (FIRST) ev[t] = __shfl(totq, cg + 16 * t);
-    }
-    const double sig2 = read_lane(tot, j);
     const bool has_next = j + 1 < n;
-    const double dn = has_next ? read_lane(tot, j + 1) : 0.0;
+    double tot = 0.0, totq = 0.0;
+    if constexpr (NS <= 2) {
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            dv[t] = col_total(sm.u.s.red, par, cg + 16 * t);
+            if (FIRST) ev[t] = col_total(sm.u.s.redq, par, cg + 16 * t);
+        }
+    } else {
+        tot = col_total(sm.u.s.red, par, threadIdx.x & 63);
+        totq = FIRST ? col_total(sm.u.s.redq, par, threadIdx.x & 63) : 0.0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            dv[t] = __shfl(tot, cg + 16 * t);
+            if (FIRST) ev[t] = __shfl(totq, cg + 16 * t);
+        }
+    }
+    // column j's and j + 1's values: lanes j and j + 1 of tot (wide), or
+    // slot TJ of lanes q and q + 1, past the slot lane 0 of slot TJ + 1
+    auto at_j = [&](const double (&v)[NS], double whole) -> double {
+        if constexpr (NS <= 2) return read_lane(v[TJ], q);
+        else return read_lane(whole, j);
+    };
+    auto at_next = [&](const double (&v)[NS], double whole) -> double {
+        if constexpr (NS > 2) return read_lane(whole, j + 1);
+        else if constexpr (TJ + 1 < NS) return q < 15 ? read_lane(v[TJ], q + 1) : read_lane(v[TJ + 1], 0);
+        else return read_lane(v[TJ], q < 15 ? q + 1 : q);
+    };
+    const double sig2 = at_j(dv, tot);
+    const double dn = has_next ? at_next(dv, tot) : 0.0;
     if (FIRST) {
-        alpha = read_lane(totq, j);
-        if (has_next) en = read_lane(totq, j + 1);
+        alpha = at_j(ev, totq);
+        if (has_next) en = at_next(ev, totq);
     }
     double beta, tau, s;
     householder_scalars(alpha, sig2, beta, tau, s);
