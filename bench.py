@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--row-block", type=int, default=4096)
     ap.add_argument("--cpu-passes", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="single workload: tsqr_factor, tsqr_form_q and tsqr_lsq_solve as three calls "
+                         "(the thin Q and the solve on two streams) instead of one tsqr_factor_solve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU; multi-GPU sharding of TSQR is a design "
@@ -127,14 +130,20 @@ def run_single(args):
     Bcol = b.reshape(-1, 1)
     P, chunk, _ = tl.plan_info(m, n, o)
 
-    # the thin Q and the solve only read the factor and use disjoint
-    # workspace blocks (FP64, n <= 64): after the factor they run on two
-    # streams, joined before the next step's factor overwrites the workspace
+    # one tsqr_factor_solve call per step: the solve's leaf pass of Q^T b
+    # runs on the library's second stream beside the tree factorization, its
+    # tree pass beside the thin Q.  --separate-calls: the three calls, the
+    # thin Q and the solve on two streams after the factor (FP64, n <= 64:
+    # they only read the factor and use disjoint workspace blocks), joined
+    # before the next step's factor overwrites the workspace
     side = torch.cuda.Stream()
 
     overlap = n <= 64
 
     def step():
+        if not args.separate_calls:
+            f, _, _, _ = tl.factor_solve(A, Bcol, o, work=work, X=X, resid=res, info=info, Q=Q)
+            return f
         main = torch.cuda.current_stream()
         f = tl.Factors(A, o, work=work)
         if overlap:
@@ -215,11 +224,13 @@ def run_single(args):
         "config": {"workload": f"tsqr_factor_formq_lsq {m}x{n}", "m": m, "n": n, "row_block": mb,
                    "domains": P, "chunk_rows": chunk, "tree": "binary", "rhs": 1,
                    "parallelism": "single GPU",
-                   "streams": "thin Q and the solve overlap on two streams after the factor" if overlap
+                   "streams": ("one tsqr_factor_solve call: the solve's leaf pass beside the tree, its tree "
+                               "pass beside the thin Q" if not args.separate_calls else
+                               "thin Q and the solve overlap on two streams after the factor") if overlap
                    else "one stream"},
         "kernels_ms_per_step": {k: round(v[1] / prof_steps, 4) for k, v in kern_all.items()},
-        "kernels_ms_note": "per-kernel times from an untimed pass with every launch timed; the thin Q "
-                           "and the solve overlap, so they do not add up to ms_per_step",
+        "kernels_ms_note": "per-kernel times from an untimed pass with every launch timed; kernels on "
+                           "the two streams overlap, so they do not add up to ms_per_step",
         "roofline": roof,
     }
     if not args.no_cpu:

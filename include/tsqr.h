@@ -146,6 +146,29 @@ TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_
                             const double *B, int64_t ldb, double *X, int64_t ldx,
                             double *resid, int32_t *dinfo, void *stream);
 
+/* tsqr_factor, tsqr_lsq_solve and (Q != NULL) tsqr_form_q in one call, with
+   the arguments and results of those three (*out: the factor handle, as
+   from tsqr_factor; opts.keep_q must be set: TSQR_ERR_STATE otherwise).
+   Least squares through TSQR applies Q^T to B leaf by leaf and then up the
+   tree, the same traversal as the factorization (Sec. 2.3): the leaf pass of
+   Q^T B needs only the leaf factors, so for an FP64 factor of one panel
+   (n <= 64) it runs on a second stream, owned by the library, while the
+   tree is factored, and the solve's tree pass then runs beside the thin Q.
+   `stream` waits for that stream before the call's work ends, so the call is
+   ordered on `stream` like any other.  The second stream and its events are
+   created on the current device at the first call and kept until the
+   process ends; concurrent calls from several host threads are serialised
+   while they enqueue.  Other factors run the three calls in order on
+   `stream`.  Results are bitwise those of the three separate calls.
+   Errors: those of tsqr_factor (-1 .. -5, TSQR_ERR_WORKSPACE), then -8 k,
+   -9 B NULL, -10 ldb, -11 X NULL, -12 ldx, -16 ldq, -18 out NULL, and the
+   errors of the solve and the thin Q. */
+TSQR_API int tsqr_factor_solve(int64_t m, int64_t n, const double *A, int64_t lda,
+                               const tsqr_opts *o, void *dwork, size_t work_bytes,
+                               int64_t k, const double *B, int64_t ldb, double *X, int64_t ldx,
+                               double *resid, int32_t *dinfo, double *Q, int64_t ldq,
+                               void *stream, tsqr_factors *out);
+
 /* Number of sweeps (the first solve included) the last mixed-precision
    tsqr_lsq_solve on this handle ran, the largest over its groups of 8
    right-hand sides; 0 for FP64 factors.  Host only; `stream` is unused. */

@@ -132,6 +132,8 @@ def lib():
         L.tsqr_apply_q.argtypes = [vp, i64, vp, i64, vp]
         L.tsqr_form_q.argtypes = [vp, vp, i64, vp]
         L.tsqr_lsq_solve.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, vp, vp]
+        L.tsqr_factor_solve.argtypes = [i64, i64, vp, i64, op, vp, sz, i64, vp, i64, vp, i64, vp, vp, vp,
+                                        i64, vp, ctypes.POINTER(vp)]
         L.tsqr_last_refine_iters.argtypes = [vp, vp]
         L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(i64)]
@@ -364,6 +366,42 @@ class Factors:
 
     def last_refine_iters(self, stream=None) -> int:
         return int(lib().tsqr_last_refine_iters(self._h, _stream(stream)))
+
+
+def factor_solve(A: torch.Tensor, B: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = None,
+                 X: torch.Tensor | None = None, resid: torch.Tensor | None = None,
+                 info: torch.Tensor | None = None, Q: torch.Tensor | None = None, stream=None):
+    """Factor A, solve min ||A x - b|| for the columns of B and, if Q is
+    given, write the thin Q, in one call (tsqr_factor_solve).  Returns
+    (Factors, X, resid, info)."""
+    m, n = A.shape
+    k = 1 if B.dim() == 1 else B.shape[1]
+    o = o if o is not None else opts()
+    dev = A.device
+    need = workspace_bytes(m, n, o)
+    if need == 0:
+        raise ValueError(f"invalid problem {m} x {n} for the given options")
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    if X is None:
+        X = empty_colmajor(n, k, device=dev)
+    if resid is None:
+        resid = torch.empty(k, dtype=torch.float64, device=dev)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+    pa, lda = _col_major(A, m, "A")
+    pb, ldb = _col_major(B, m, "B")
+    px, ldx = _col_major(X, n, "X")
+    pq, ldq = (0, m) if Q is None else _col_major(Q, m, "Q")
+    h = ctypes.c_void_p()
+    _check(lib().tsqr_factor_solve(m, n, ctypes.c_void_p(pa), lda, ctypes.byref(o),
+                                   ctypes.c_void_p(work.data_ptr()), work.numel(), k, ctypes.c_void_p(pb), ldb,
+                                   ctypes.c_void_p(px), ldx, ctypes.c_void_p(resid.data_ptr()),
+                                   ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(pq), ldq, _stream(stream),
+                                   ctypes.byref(h)), "tsqr_factor_solve")
+    F = Factors.__new__(Factors)
+    F.m, F.n, F.opts, F.work, F._h = m, n, o, work, h
+    return F, X, resid, info
 
 
 def factor(A: torch.Tensor, **kw) -> Factors:

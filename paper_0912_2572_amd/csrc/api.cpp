@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "kernels.h"
@@ -387,6 +388,145 @@ TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_
                                 at<double>(f, P.off_small), st);
     f->last_refine = 0;
     return e == hipSuccess ? 0 : hip_code(e);
+}
+
+}  // extern "C"
+
+namespace {
+
+// tsqr_factor_solve's second stream and its three events, per device,
+// created on first use and kept until the process ends.  g_fork_mu is held
+// while a call enqueues its work, so the events' record/wait pairs of two
+// concurrent calls do not interleave.
+struct ForkJoin {
+    hipStream_t aux = nullptr;
+    hipEvent_t leaf = nullptr, tree = nullptr, done = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_fork_mu;
+ForkJoin g_fork[kMaxDevices];
+
+int fork_join_for_current_device(ForkJoin **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_code(e);
+    if (dev < 0 || dev >= kMaxDevices) return TSQR_ERR_UNSUPPORTED;
+    ForkJoin &fj = g_fork[dev];
+    if (!fj.aux) {
+        ForkJoin n;
+        e = hipStreamCreateWithFlags(&n.aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.leaf, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.tree, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_code(e);
+        fj = n;
+    }
+    *out = &fj;
+    return 0;
+}
+
+// The fork/join schedule of tsqr_factor_solve for a single-panel FP64
+// factor (caller holds g_fork_mu).  main: leaf, tree, signs, thin Q.  aux:
+// after the leaf, the solve's copy and leaf pass of Q^T B; after the tree,
+// its tree pass and the triangular solve.  main finally waits for aux.
+int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t k, const double *B,
+                        int64_t ldb, double *X, int64_t ldx, double *resid, int32_t *dinfo, double *Q,
+                        int64_t ldq, hipStream_t st, const ForkJoin &fj) {
+    const Plan &P = f->plan;
+    const Panel &p = P.panels[0];
+    const PanelArgs pa = panel_args(p);
+    double *W = at<double>(f, P.off_w);
+    double *Rdom = at<double>(f, p.off_rdom);
+    double *Tnode = at<double>(f, p.off_tnode);
+    double *C = at<double>(f, P.off_lsq);
+    const auto levels = tsqr::tree_levels(p.P, p.tree);
+    TRY(tsqr::launch_leaf(A, lda, W, P.m, at<double>(f, p.off_tc), Rdom, pa, 1, st));
+    TRY(hipEventRecord(fj.leaf, st));
+    TRY(hipStreamWaitEvent(fj.aux, fj.leaf, 0));
+    TRY(tsqr::launch_copy(B, ldb, C, P.m, P.m, k, fj.aux));
+    TRY(leaf_apply(f, p, C, P.m, C, P.m, k, 1, fj.aux));
+    for (const auto &L : levels) {
+        TreeArgs ta{L.stride, L.span, L.chains};
+        TRY(tsqr::launch_tree_level(Rdom, Tnode, pa, ta, 1, st));
+    }
+    TRY(tsqr::launch_sign_normalise(Rdom, p.n, at<double>(f, P.off_r), P.n, p.row_off, p.col_off,
+                                    at<double>(f, P.off_d), st));
+    TRY(hipEventRecord(fj.tree, st));
+    TRY(hipStreamWaitEvent(fj.aux, fj.tree, 0));
+    for (const auto &L : levels) {
+        TreeArgs ta{L.stride, L.span, L.chains};
+        TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, C, P.m, k, 1, fj.aux));
+    }
+    // rows 0..n-1 of Q^T B for the sign-normalised Q (as tsqr_apply_qt)
+    TRY(tsqr::launch_scale_rows(C + p.row_off, P.m, p.n, k, at<double>(f, P.off_d) + p.row_off, fj.aux));
+    TRY(tsqr::launch_lsq_finish(at<double>(f, P.off_r), (int)P.n, C, P.m, P.m, k, X, ldx, resid, dinfo,
+                                at<double>(f, P.off_small), fj.aux));
+    TRY(hipEventRecord(fj.done, fj.aux));
+    int rc = Q ? tsqr_form_q(f, Q, ldq, st) : 0;
+    const hipError_t e = hipStreamWaitEvent(st, fj.done, 0);
+    if (rc) return rc;
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+TSQR_API int tsqr_factor_solve(int64_t m, int64_t n, const double *A, int64_t lda, const tsqr_opts *o,
+                               void *dwork, size_t work_bytes, int64_t k, const double *B, int64_t ldb,
+                               double *X, int64_t ldx, double *resid, int32_t *dinfo, double *Q,
+                               int64_t ldq, void *stream, tsqr_factors *out) {
+    if (!out) return -18;
+    *out = nullptr;
+    tsqr_opts defaults;
+    tsqr_default_opts(&defaults);
+    if (!o) o = &defaults;
+    Plan plan;
+    int rc = tsqr::make_plan(m, n, o, &plan);
+    if (rc) return rc;
+    if (!A) return -3;
+    if (lda < m) return -4;
+    if (!o->keep_q) return TSQR_ERR_STATE;
+    if (!dwork || work_bytes < plan.total || (reinterpret_cast<uintptr_t>(dwork) % tsqr::kAlign))
+        return TSQR_ERR_WORKSPACE;
+    if (k < 1 || k > o->lsq_max_rhs) return -8;
+    if (!B) return -9;
+    if (ldb < m) return -10;
+    if (!X) return -11;
+    if (ldx < n) return -12;
+    if (Q && ldq < m) return -16;
+    if (o->prec != TSQR_F64 || plan.panels.size() != 1) {
+        // the three calls in order on `stream`
+        rc = tsqr_factor(m, n, A, lda, o, dwork, work_bytes, stream, out);
+        if (rc) return rc;
+        rc = tsqr_lsq_solve(*out, A, lda, k, B, ldb, X, ldx, resid, dinfo, stream);
+        if (!rc && Q) rc = tsqr_form_q(*out, Q, ldq, stream);
+        if (rc) {
+            tsqr_free(*out);
+            *out = nullptr;
+        }
+        return rc;
+    }
+    tsqr_factors_s *f = new (std::nothrow) tsqr_factors_s;
+    if (!f) return TSQR_ERR_WORKSPACE;
+    f->plan = plan;
+    f->ws = static_cast<char *>(dwork);
+    f->ws_bytes = work_bytes;
+    f->keep_q = 1;
+    f->last_refine = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_fork_mu);
+        ForkJoin *fj = nullptr;
+        rc = fork_join_for_current_device(&fj);
+        if (!rc) rc = factor_solve_forked(f, A, lda, k, B, ldb, X, ldx, resid, dinfo, Q, ldq,
+                                          static_cast<hipStream_t>(stream), *fj);
+    }
+    if (rc) {
+        delete f;
+        return rc;
+    }
+    *out = f;
+    return 0;
 }
 
 TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream) {

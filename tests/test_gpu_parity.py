@@ -175,6 +175,54 @@ def test_form_q_concurrent_with_solve(tl):
         assert torch.equal(X2, X1) and torch.equal(r2, r1), f"rep {rep}"
 
 
+@pytest.mark.parametrize("m,n,mb,prec,k,with_q", [
+    (60000, 64, 4096, "f64", 1, True),     # forked: leaf pass of Q^T b beside the tree
+    (70001, 33, 2048, "f64", 2, False),    # forked, ragged last domain, no thin Q
+    (20000, 100, 4096, "f64", 1, True),    # two panels: the three calls in order
+    (40000, 48, 4096, "mixed", 1, True),   # mixed precision: the three calls in order
+])
+def test_factor_solve_matches_separate_calls(tl, m, n, mb, prec, k, with_q):
+    """tsqr_factor_solve gives bitwise the results of tsqr_factor,
+    tsqr_lsq_solve and tsqr_form_q called one after the other, also for two
+    calls enqueued back to back (the second reuses the fork's events)."""
+    print(f"case factor_solve m={m} n={n} mb={mb} {prec} k={k} q={with_q}", flush=True)
+    A = synth.gaussian(m, n, seed=31)
+    b = np.random.default_rng(32).standard_normal((m, k))
+    Ad, bd = dev(A), dev(b)
+    o = tl.opts(row_block=mb, lsq_max_rhs=k, prec=tl.MIXED if prec == "mixed" else tl.F64)
+    f = tl.Factors(Ad, o)
+    X1, r1, i1 = f.lsq(bd, A=Ad)
+    Q1 = f.form_q() if with_q else None
+    R1 = f.R()
+    torch.cuda.synchronize()
+    outs = []
+    for rep in range(2):
+        Q2 = tl.empty_colmajor(m, n, device=Ad.device) if with_q else None
+        F, X2, r2, i2 = tl.factor_solve(Ad, bd, o, Q=Q2)
+        outs.append((F, X2, r2, i2, Q2))
+    torch.cuda.synchronize()
+    for rep, (F, X2, r2, i2, Q2) in enumerate(outs):
+        assert int(i2.item()) == int(i1.item()) == 0, f"rep {rep}"
+        assert torch.equal(X2, X1) and torch.equal(r2, r1), f"rep {rep}"
+        assert torch.equal(F.R(), R1), f"rep {rep}"
+        if with_q:
+            assert torch.equal(Q2, Q1), f"rep {rep}"
+    # the handle serves later calls like one from tsqr_factor
+    B3 = bd.clone()
+    assert torch.equal(outs[0][0].apply_qt_(B3), f.apply_qt_(bd.clone()))
+
+
+def test_factor_solve_argument_errors(tl):
+    A = dev(synth.gaussian(1000, 8, seed=1))
+    b = dev(np.ones((1000, 1)))
+    with pytest.raises(tl.TSQRError) as ei:
+        tl.factor_solve(A, b, tl.opts(keep_q=False))
+    assert ei.value.code == tl.ERR_STATE
+    with pytest.raises(tl.TSQRError) as ei:
+        tl.factor_solve(A, dev(np.ones((1000, 3))), tl.opts(lsq_max_rhs=2))
+    assert ei.value.code == -8
+
+
 def test_deterministic_and_r_only(tl):
     A = synth.gaussian(50000, 48, seed=9)
     Ad = dev(A)
