@@ -470,16 +470,19 @@ __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
 // them, so that they can stay in flight across other work: the compiler
 // keeps a load's result where the chunk lives only if no join follows it.
 // A column past n reads column 0 instead; clear_pad_cols zeroes it once the
-// data is there.  VEC: 16-byte pieces (rows_aligned(src, ld) must hold).
+// data is there.  live == false: a placeholder whose values are never used
+// (every lane reads the 16 bytes at src), keeping the loop free of a branch
+// around the loads.  VEC: 16-byte pieces (rows_aligned(src, ld) must hold).
 template <int NS, int RPT, bool VEC>
 __device__ __forceinline__ void issue_full_chunk(double (&c)[RPT][NS], const double *__restrict__ src,
-                                                 int64_t ld, int n) {
+                                                 int64_t ld, int n, bool live = true) {
     const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
-        const double *p = src + (int64_t)rgw * RPT + (int64_t)(k < n ? k : 0) * ld;
+        const int64_t off = (int64_t)rgw * RPT + (int64_t)(k < n ? k : 0) * ld;
+        const double *p = src + (live ? off : 0);
         if constexpr (VEC) {
 #pragma unroll
             for (int i = 0; i < RPT; i += 2) {
@@ -569,7 +572,8 @@ __device__ __forceinline__ void zero_lds(double *lds) {
 // stored and stay in flight while chunk c's T is built and stored, so the
 // HBM time of both hides behind that work.  Only the last domain can end in
 // a partial chunk; it is loaded with masking at the top of its own
-// iteration (the prefetch before it re-reads the last full chunk, unused).
+// iteration (the prefetch before it, like the one after the last chunk, is
+// a placeholder that reads 16 bytes).
 template <int NS, typename VT, bool VEC>
 __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__restrict__ A, int64_t lda,
                                             VT *__restrict__ V, int64_t ldv, double *__restrict__ Tc,
@@ -608,8 +612,8 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
             if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t);
             else chunk_qr<NS, RPT, false>(c, n, sm, want_t);
             if (want_t) store_chunk<NS, RPT, VT>(c, V + r0, ldv, ch < nfull ? (int64_t)ROWS : tail, n);
-            const int64_t nx = (ch + 1 < nfull) ? ch + 1 : nfull - 1;
-            issue_full_chunk<NS, RPT, VEC>(c, A + row0 + nx * ROWS, lda, n);
+            const bool more = ch + 1 < nfull;
+            issue_full_chunk<NS, RPT, VEC>(c, A + row0 + (more ? ch + 1 : 0) * ROWS, lda, n, more);
             if (want_t) {
                 build_t(sm, n);
                 store_tri(sm.T, Tc + (dom * pa.cpd + ch) * nn, n);
