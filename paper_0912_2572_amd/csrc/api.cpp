@@ -335,15 +335,14 @@ TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, voi
     return apply_q_impl(f, k, B, ldb, true, false, static_cast<hipStream_t>(stream));
 }
 
-TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
-    int rc = validate_handle(f, true);
-    if (rc) return rc;
-    if (!Q) return -2;
-    if (ldq < f->plan.m) return -3;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+// Thin Q of a single-panel FP64 factor: the top-down tree on n x n blocks,
+// then the MFMA leaf; `before_leaf`, if set, is an event the leaf waits for.
+static int form_q_single_panel(tsqr_factors_s *f, double *Q, int64_t ldq, hipStream_t st,
+                               hipEvent_t before_leaf) {
     const double *dsign = at<double>(f, f->plan.off_d);
-    if (f->plan.panels.size() == 1 && !is_mixed(f)) {
-        // single panel: top-down tree on n x n blocks, then the MFMA leaf
+    {
         const Panel &p = f->plan.panels[0];
         const PanelArgs pa = panel_args(p);
         double *S = at<double>(f, p.off_s);
@@ -354,10 +353,23 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
             TRY(tsqr::launch_tree_down(at<double>(f, p.off_rdom), at<double>(f, p.off_tnode), S, pa, ta,
                                        st));
         }
+        if (before_leaf) TRY(hipStreamWaitEvent(st, before_leaf, 0));
         TRY(tsqr::launch_form_leaf(at<double>(f, f->plan.off_w), f->plan.m, at<double>(f, p.off_tc), S,
                                    pa, Q, ldq, st));
-        return 0;
     }
+    return 0;
+}
+
+extern "C" {
+
+TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
+    int rc = validate_handle(f, true);
+    if (rc) return rc;
+    if (!Q) return -2;
+    if (ldq < f->plan.m) return -3;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (f->plan.panels.size() == 1 && !is_mixed(f)) return form_q_single_panel(f, Q, ldq, st, nullptr);
+    const double *dsign = at<double>(f, f->plan.off_d);
     hipError_t e = tsqr::launch_fill_identity_signs(Q, ldq, f->plan.m, (int)f->plan.n, dsign, st);
     if (e != hipSuccess) return hip_code(e);
     return apply_q_impl(f, f->plan.n, Q, ldq, false, true, st);
@@ -462,9 +474,17 @@ int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t
     TRY(tsqr::launch_lsq_finish(at<double>(f, P.off_r), (int)P.n, C, P.m, P.m, k, X, ldx, resid, dinfo,
                                 at<double>(f, P.off_small), fj.aux));
     TRY(hipEventRecord(fj.done, fj.aux));
-    int rc = Q ? tsqr_form_q(f, Q, ldq, st) : 0;
+    // the thin Q's top-down tree runs beside the solve's tree pass; its leaf
+    // kernel (which fills the GPU) starts once the solve is done
+    if (Q) {
+        const int rc = form_q_single_panel(f, Q, ldq, st, fj.done);
+        if (rc) {
+            (void)hipStreamWaitEvent(st, fj.done, 0);
+            return rc;
+        }
+        return 0;
+    }
     const hipError_t e = hipStreamWaitEvent(st, fj.done, 0);
-    if (rc) return rc;
     return e == hipSuccess ? 0 : hip_code(e);
 }
 
