@@ -119,7 +119,7 @@ __global__ void k_seed_root(double *S, int n, const double *d) {
 // Q = -V Z (+ [X; 0] on a first chunk) for the rows of one chunk; wave w
 // takes the 16-row tiles 4 w .. 4 w + 3 of every 256-row block.  The wave
 // keeps its Z operands in registers for the whole chunk and fetches the next
-// tile's V while the current tile's products run.
+// two tiles' V while the current tile's products run.
 __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__restrict__ Vc, int64_t ldv,
                                           double *__restrict__ Qc, int64_t ldq, int64_t valid, int n,
                                           bool first) {
@@ -134,23 +134,41 @@ __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__re
             za[kb][CT] = (kb < kbn) ? sm.Z[(4 * kb + l4) * LD + 16 * CT + l16] : 0.0;
     auto load_v = [&](int64_t tile, double (&vb)[16]) {
         const int64_t row = 16 * tile + l16;
+        if (first) {
 #pragma unroll
-        for (int kb = 0; kb < 16; ++kb) {
-            const int col = 4 * kb + l4;
-            double v = 0.0;
-            if (kb < kbn && row < valid && col < n) {
-                v = Vc[row + (int64_t)col * ldv];
-                if (first && row <= col) v = (row == col) ? 1.0 : 0.0;
+            for (int kb = 0; kb < 16; ++kb) {
+                const int col = 4 * kb + l4;
+                double v = 0.0;
+                if (kb < kbn && row < valid && col < n) {
+                    v = Vc[row + (int64_t)col * ldv];
+                    if (row <= col) v = (row == col) ? 1.0 : 0.0;
+                }
+                vb[kb] = v;
             }
-            vb[kb] = v;
+        } else {
+            // no branch around the loads (so the compiler can keep them in
+            // flight): a row past the chunk reads its last row (that output
+            // row is not stored) and a column past n reads column n - 1 (it
+            // meets a zero row of the padded Z)
+            const int64_t rr = row < valid ? row : valid - 1;
+#pragma unroll
+            for (int kb = 0; kb < 16; ++kb) {
+                const int col = 4 * kb + l4;
+                vb[kb] = Vc[rr + (int64_t)(col < n ? col : n - 1) * ldv];
+            }
         }
     };
+    // tiles t, t + 1 (+ 13 past a 4-tile group): two tiles in flight while
+    // one computes, in three buffers whose roles rotate through a 3-way
+    // unrolled loop (no copies of registers whose loads are still in flight)
+    auto next_of = [](int64_t t) { return t + ((t % 4 == 3) ? 13 : 1); };
     int64_t tile = 4 * w;
-    double vb[16], vn[16];
-    if (16 * tile < valid) load_v(tile, vb);
-    while (16 * tile < valid) {
-        const int64_t next = tile + ((tile % 4 == 3) ? 13 : 1);
-        if (16 * next < valid) load_v(next, vn);
+    double ba[16], bb[16], bc[16];
+    if (16 * tile < valid) load_v(tile, ba);
+    if (16 * next_of(tile) < valid) load_v(next_of(tile), bb);
+    auto step = [&](double (&cur)[16], double (&ahead)[16]) {
+        const int64_t t2 = next_of(next_of(tile));
+        if (16 * t2 < valid) load_v(t2, ahead);
         const int64_t row = 16 * tile + l16;
         d4 acc[4];
 #pragma unroll
@@ -159,7 +177,7 @@ __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__re
         for (int kb = 0; kb < 16; ++kb)
 #pragma unroll
             for (int CT = 0; CT < 4; ++CT)
-                if (kb < kbn) acc[CT] = mfma_f64(za[kb][CT], vb[kb], acc[CT]);
+                if (kb < kbn) acc[CT] = mfma_f64(za[kb][CT], cur[kb], acc[CT]);
 #pragma unroll
         for (int CT = 0; CT < 4; ++CT)
 #pragma unroll
@@ -171,9 +189,14 @@ __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__re
                     Qc[row + (int64_t)col * ldq] = val;
                 }
             }
-#pragma unroll
-        for (int kb = 0; kb < 16; ++kb) vb[kb] = vn[kb];
-        tile = next;
+        tile = next_of(tile);
+    };
+    while (16 * tile < valid) {
+        step(ba, bc);
+        if (16 * tile >= valid) break;
+        step(bb, ba);
+        if (16 * tile >= valid) break;
+        step(bc, bb);
     }
 }
 
