@@ -173,22 +173,32 @@ __device__ __forceinline__ void chunk_out(const FormSmem &sm, const double *__re
         d4 acc[4];
 #pragma unroll
         for (int CT = 0; CT < 4; ++CT) acc[CT] = d4_zero();
+        // all 16 k-steps, with no branch: past n the Z operand is zero and the
+        // V operand finite, so those products add exact zeros
 #pragma unroll
         for (int kb = 0; kb < 16; ++kb)
 #pragma unroll
+            for (int CT = 0; CT < 4; ++CT) acc[CT] = mfma_f64(za[kb][CT], cur[kb], acc[CT]);
+        if (!first && n == 64 && 16 * tile + 16 <= valid) {
+            // a whole tile of a later chunk: no guard around the stores
+#pragma unroll
             for (int CT = 0; CT < 4; ++CT)
-                if (kb < kbn) acc[CT] = mfma_f64(za[kb][CT], cur[kb], acc[CT]);
 #pragma unroll
-        for (int CT = 0; CT < 4; ++CT)
+                for (int r = 0; r < 4; ++r)
+                    Qc[row + (int64_t)(16 * CT + 4 * r + l4) * ldq] = -acc[CT][r];
+        } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int col = 16 * CT + 4 * r + l4;
-                if (row < valid && col < n) {
-                    double val = -acc[CT][r];
-                    if (first && row < n) val += sm.X[row * LD + col];
-                    Qc[row + (int64_t)col * ldq] = val;
+            for (int CT = 0; CT < 4; ++CT)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = 16 * CT + 4 * r + l4;
+                    if (row < valid && col < n) {
+                        double val = -acc[CT][r];
+                        if (first && row < n) val += sm.X[row * LD + col];
+                        Qc[row + (int64_t)col * ldq] = val;
+                    }
                 }
-            }
+        }
         tile = next_of(tile);
     };
     while (16 * tile < valid) {
