@@ -90,13 +90,28 @@ __global__ __launch_bounds__(256) void k_tree_down(const double *__restrict__ Rd
     const int64_t left = (int64_t)blockIdx.x * ta.span;
     int64_t nr = 0;
     for (int64_t q = 1; q * ta.stride < ta.span && left + q * ta.stride < pa.P; ++q) ++nr;
-    load_nn(sm.X, S + left * nn, n, n, false);
+    {
+        // S_l and the first node's T and U: all loads in flight at once
+        double xv[16], tv[16], uv[16];
+        fetch_nn(xv, S + left * nn, n, n);
+        if (nr >= 1) {
+            fetch_nn(tv, Tnode + (left + nr * ta.stride) * nn, n, n);
+            fetch_nn(uv, Rdom + (left + nr * ta.stride) * nn, n, n);
+        }
+        put_nn(sm.X, xv);
+        if (nr >= 1) {
+            put_nn(sm.T, tv);
+            put_nn(sm.W, uv);
+        }
+    }
     for (int64_t q = nr; q >= 1; --q) {
         const int64_t right = left + q * ta.stride;
         __syncthreads();
-        load_nn(sm.T, Tnode + right * nn, n, n, false);
-        load_nn(sm.W, Rdom + right * nn, n, n, false);   // U (upper triangular)
-        __syncthreads();
+        if (q < nr) {
+            load_nn(sm.T, Tnode + right * nn, n, n, false);
+            load_nn(sm.W, Rdom + right * nn, n, n, false);   // U (upper triangular)
+            __syncthreads();
+        }
         lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);       // Z = T S_l
         __syncthreads();
         for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) sm.X[e] -= sm.Z[e];
