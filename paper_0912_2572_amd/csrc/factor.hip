@@ -22,6 +22,7 @@
 // update coefficients (k > j) and, for k < j, the Gram entries y_k . y_j
 // that build T.  The reduction over the 4 row groups of a wave runs in the
 // VALU (lane permutes); the 4 waves meet at one barrier per step.
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -133,6 +134,56 @@ __device__ __forceinline__ void build_t(FactorSmem &sm, const int n) {
                 sm.T[(16 * w + d_row(r, lane)) * kLdsStride + 16 * J + d_col(lane)] = -acc[r];
         }
         __syncthreads();
+    }
+}
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+// Half of a full chunk's reflectors (slots 2 and 3: columns 32..63) of the
+// wide FP64 kernel, parked in LDS at the end of the chunk and copied out in
+// four parts at the starts of the next chunk's four column slots: the V
+// stores then drain while the column steps run (they issue no other memory
+// traffic) instead of all 256 CUs storing 32 MB at once at the chunk's end.
+// Passed by value (dst == nullptr: nothing staged), so that its uniform
+// fields stay in scalar registers.
+constexpr int kStageLd = 256 + 2;   // doubles per staged column (padded against bank conflicts)
+constexpr size_t kStageBytes = sizeof(double) * 32 * kStageLd;
+
+struct Drain {
+    const double *stage;   // LDS, column cl (0..31) at stage + cl * kStageLd
+    double *dst;           // row 0 of the staged chunk's V, or nullptr
+    int64_t ld;
+    int n;
+};
+
+// Slots 2 and 3 of a 256-row chunk (RPT = 16) into the stage.
+__device__ __forceinline__ void stage_slots(double *stage, const double (&c)[16][4]) {
+    const int tid = local_tid(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
+    const int rgw = w * 4 + rg;
+#pragma unroll
+    for (int t = 2; t < 4; ++t) {
+        double *base = stage + (cg + 16 * (t - 2)) * kStageLd + 16 * rgw;
+#pragma unroll
+        for (int i = 0; i < 16; i += 2) {
+            dv2 v;
+            v.x = c[i][t];
+            v.y = c[i + 1][t];
+            *reinterpret_cast<dv2 *>(base + i) = v;
+        }
+    }
+}
+
+// Part p (0..3) of the staged columns: 32 + 8p .. 32 + 8p + 7; per store a
+// thread moves rows 2 (tid % 128), +1 of one column (16 bytes).
+__device__ __forceinline__ void drain_part(const Drain d, int p) {
+    const int tid = local_tid(), half = tid >> 7, rp = 2 * (tid & 127);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int cl = 8 * p + 2 * i + half;
+        if (32 + cl < d.n) {
+            const dv2 v = *reinterpret_cast<const dv2 *>(d.stage + cl * kStageLd + rp);
+            *reinterpret_cast<dv2 *>(d.dst + rp + (int64_t)(32 + cl) * d.ld) = v;
+        }
     }
 }
 
@@ -382,11 +433,22 @@ __device__ __forceinline__ void qr_steps(double (&c)[RPT][NS], const int n, Fact
     }
 }
 
+// Slot TJ's steps, after part TJ of the previous chunk's staged reflectors
+// (if any) has been sent to memory.
+template <int NS, int RPT, int TJ, bool FIRST>
+__device__ __forceinline__ void qr_slot(double (&c)[RPT][NS], const int n, FactorSmem &sm,
+                                        const bool want_t, StepState<NS, RPT> &ss, const Drain dr) {
+    if constexpr (NS == 4) {
+        if (dr.dst != nullptr) drain_part(dr, TJ);
+    }
+    qr_steps<NS, RPT, TJ, FIRST>(c, n, sm, want_t, ss);
+}
+
 template <int NS, int RPT, bool FIRST, int... TJ>
 __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
                                              double (&c)[RPT][NS], const int n, FactorSmem &sm,
-                                             const bool want_t, StepState<NS, RPT> &ss) {
-    (qr_steps<NS, RPT, TJ, FIRST>(c, n, sm, want_t, ss), ...);
+                                             const bool want_t, StepState<NS, RPT> &ss, const Drain dr) {
+    (qr_slot<NS, RPT, TJ, FIRST>(c, n, sm, want_t, ss, dr), ...);
 }
 
 // Householder QR of [R; C] (FIRST == false) or of C alone (FIRST == true,
@@ -396,14 +458,15 @@ __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
 // of sm.T the chunk's T.
 template <int NS, int RPT, bool FIRST>
 __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
-                                         FactorSmem &sm, const bool want_t) {
+                                         FactorSmem &sm, const bool want_t,
+                                         const Drain dr = Drain{nullptr, nullptr, 0, 0}) {
     const int tid = step_tid<NS>();
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     StepState<NS, RPT> ss;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
-    qr_all_steps<NS, RPT, FIRST>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss);
+    qr_all_steps<NS, RPT, FIRST>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss, dr);
     __syncthreads();
     if (ss.jprev >= 0 && rgw == 0) {
 #pragma unroll
@@ -428,7 +491,6 @@ __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
 // + RPT - 1 of a chunk, so a lane moves whole 16-byte pieces (and, over its
 // loop, whole cache lines) of each column.  Vector accesses need a 16-byte
 // aligned column start; otherwise the same rows go element by element.
-typedef double dv2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
 __device__ __forceinline__ bool rows_aligned(const T *p, int64_t ld) {
@@ -511,7 +573,8 @@ __device__ __forceinline__ void clear_pad_cols(double (&c)[RPT][NS], int n) {
 
 template <int NS, int RPT, typename OT = double>
 __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
-                                            OT *__restrict__ dst, int64_t ld, int64_t valid, int n) {
+                                            OT *__restrict__ dst, int64_t ld, int64_t valid, int n,
+                                            int t_end = NS) {
     const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     const bool full = valid >= (int64_t)RPT * kRowGroups;
@@ -521,7 +584,7 @@ __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
     for (int t = 0; t < NS; ++t) {
         const int k = cg + 16 * t;
         OT *p = dst + (int64_t)rgw * RPT + (int64_t)k * ld;
-        if (k < n && vec) {
+        if (t < t_end && k < n && vec) {
             if constexpr (VW == 2) {
 #pragma unroll
                 for (int i = 0; i < RPT; i += 2) {
@@ -541,7 +604,7 @@ __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
                     *reinterpret_cast<float4 *>(p + i) = v;
                 }
             }
-        } else if (k < n) {
+        } else if (t < t_end && k < n) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
                 if ((int64_t)rgw * RPT + i < valid) p[i] = OT(c[i][t]);
@@ -573,12 +636,14 @@ __device__ __forceinline__ void zero_lds(double *lds) {
 // HBM time of both hides behind that work.  Only the last domain can end in
 // a partial chunk; it is loaded with masking at the top of its own
 // iteration (the prefetch before it, like the one after the last chunk, is
-// a placeholder that reads 16 bytes).
-template <int NS, typename VT, bool VEC>
+// a placeholder that reads 16 bytes).  STAGE (wide FP64 kernel, `stage` =
+// kStageBytes of LDS): half of each full chunk's reflectors are sent to
+// memory during the next chunk's column steps (see Drain).
+template <int NS, typename VT, bool VEC, bool STAGE = false>
 __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__restrict__ A, int64_t lda,
                                             VT *__restrict__ V, int64_t ldv, double *__restrict__ Tc,
                                             double *__restrict__ Rdom, const PanelArgs &pa, int keep_q,
-                                            int64_t dom) {
+                                            int64_t dom, double *stage = nullptr) {
     constexpr int ROWS = chunk_rows(NS);
     constexpr int RPT = rows_per_thread(NS);
     const int64_t row0 = dom * pa.mb;
@@ -604,14 +669,32 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
         __syncthreads();
     } else {
         const int64_t nch = nfull + (tail > 0 ? 1 : 0);
+        bool staging = false;
+        if constexpr (STAGE) staging = want_t && rows_aligned(V + row0, ldv);
+        double *pend = nullptr;   // V of the chunk whose slots 2 and 3 sit in the stage
         issue_full_chunk<NS, RPT, VEC>(c, A + row0, lda, n);
         for (int64_t ch = 0; ch < nch; ++ch) {
             const int64_t r0 = row0 + ch * ROWS;
             if (ch == nfull) load_chunk<NS, RPT>(c, A + r0, lda, tail, n);
             else clear_pad_cols<NS, RPT>(c, n);
-            if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t);
-            else chunk_qr<NS, RPT, false>(c, n, sm, want_t);
-            if (want_t) store_chunk<NS, RPT, VT>(c, V + r0, ldv, ch < nfull ? (int64_t)ROWS : tail, n);
+            Drain dr{stage, nullptr, ldv, n};
+            if constexpr (STAGE) dr.dst = pend;
+            if (ch == 0) chunk_qr<NS, RPT, true>(c, n, sm, want_t, dr);
+            else chunk_qr<NS, RPT, false>(c, n, sm, want_t, dr);
+            if (want_t) {
+                bool staged = false;
+                if constexpr (STAGE) {
+                    if (staging && ch < nfull) {
+                        store_chunk<NS, RPT, VT>(c, V + r0, ldv, ROWS, n, 2);   // slots 0 and 1
+                        stage_slots(stage, c);
+                        pend = V + r0;
+                        staged = true;
+                    } else {
+                        pend = nullptr;
+                    }
+                }
+                if (!staged) store_chunk<NS, RPT, VT>(c, V + r0, ldv, ch < nfull ? (int64_t)ROWS : tail, n);
+            }
             const bool more = ch + 1 < nfull;
             issue_full_chunk<NS, RPT, VEC>(c, A + row0 + (more ? ch + 1 : 0) * ROWS, lda, n, more);
             if (want_t) {
@@ -619,6 +702,10 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
                 store_tri(sm.T, Tc + (dom * pa.cpd + ch) * nn, n);
             }
             __syncthreads();
+        }
+        if constexpr (STAGE) {
+            if (pend != nullptr)
+                for (int part = 0; part < 4; ++part) drain_part(Drain{stage, pend, ldv, n}, part);
         }
     }
     store_tri(sm.R, Rdom + dom * nn, n);
@@ -629,6 +716,10 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
 template <int NS>
 constexpr int leaf_min_blocks() { return NS == 2 ? 2 : 1; }
 
+// The wide FP64 leaf stages half of each chunk's reflectors in LDS.
+template <int NS, typename VT>
+constexpr bool leaf_stages() { return NS == 4 && std::is_same<VT, double>::value; }
+
 template <int NS, typename VT, bool VEC>
 __global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf(const double *__restrict__ A, int64_t lda,
                                                  VT *__restrict__ V, int64_t ldv,
@@ -636,7 +727,9 @@ __global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf(
                                                  PanelArgs pa, int keep_q) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
-    leaf_domain<NS, VT, VEC>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x);
+    constexpr bool S = leaf_stages<NS, VT>();
+    leaf_domain<NS, VT, VEC, S>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x,
+                                S ? smem_raw + sizeof(FactorSmem) / sizeof(double) : nullptr);
 }
 
 // One chain of combines (step 3): left <- qr([R_left; R_right]) for every
@@ -805,7 +898,7 @@ template <int NS, typename VT, bool VEC>
 static hipError_t launch_leaf_nsv(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,
                                   double *Rdom, const PanelArgs &pa, int keep_q, const char *tag,
                                   hipStream_t st) {
-    const size_t sh = sizeof(FactorSmem);
+    const size_t sh = sizeof(FactorSmem) + (leaf_stages<NS, VT>() ? kStageBytes : 0);
     hipError_t e = hipFuncSetAttribute((const void *)k_leaf<NS, VT, VEC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
