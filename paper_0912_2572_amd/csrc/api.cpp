@@ -346,10 +346,32 @@ static int form_q_single_panel(tsqr_factors_s *f, double *Q, int64_t ldq, hipStr
         const Panel &p = f->plan.panels[0];
         const PanelArgs pa = panel_args(p);
         double *S = at<double>(f, p.off_s);
-        TRY(tsqr::launch_seed_root(S, p.n, dsign, st));
-        auto levels = tsqr::tree_levels(p.P, p.tree);
-        for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
-            TreeArgs ta{it->stride, it->span, it->chains};
+        const auto levels = tsqr::tree_levels(p.P, p.tree);
+        const int nlev = (int)levels.size();
+        // the top levels in one launch, one workgroup per path to a left of
+        // level lstop - 1 (at most kTopPaths of them); the rest level by level
+        constexpr int64_t kTopPaths = 32;
+        int lstop = nlev;
+        for (int L = 0; L < nlev; ++L)
+            if ((p.P + levels[L].stride - 1) / levels[L].stride <= kTopPaths) {
+                lstop = L;
+                break;
+            }
+        if (lstop < nlev && nlev <= tsqr::kMaxTreeLevels) {
+            tsqr::TreePath tp{};
+            tp.nlev = nlev;
+            for (int L = 0; L < nlev; ++L) {
+                tp.stride[L] = levels[L].stride;
+                tp.span[L] = levels[L].span;
+            }
+            TRY(tsqr::launch_tree_down_top(at<double>(f, p.off_rdom), at<double>(f, p.off_tnode), dsign, S, pa,
+                                           tp, lstop, levels[lstop].stride, st));
+        } else {
+            lstop = nlev;
+            TRY(tsqr::launch_seed_root(S, p.n, dsign, st));
+        }
+        for (int L = lstop - 1; L >= 0; --L) {
+            TreeArgs ta{levels[L].stride, levels[L].span, levels[L].chains};
             TRY(tsqr::launch_tree_down(at<double>(f, p.off_rdom), at<double>(f, p.off_tnode), S, pa, ta,
                                        st));
         }

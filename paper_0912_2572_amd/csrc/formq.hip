@@ -123,6 +123,57 @@ __global__ __launch_bounds__(256) void k_tree_down(const double *__restrict__ Rd
     store_nn(S + left * nn, sm.X, n);
 }
 
+// The top levels of the top-down tree in one launch: workgroup g takes the
+// domain d = g * dstride (a left of a chain at level lstop - 1), starts from
+// the root block D and applies the maps of the nodes on its path down to
+// level lstop (the left's S_l <- S_l - T S_l for each later right of its
+// chain, then S_r = -U (T S_l) on entering a right) -- the products and
+// order of k_tree_down, so the blocks are bitwise the same.  The few upper
+// nodes are recomputed by each path through them; in exchange the top
+// levels cost one launch and occupy only P / dstride CUs.
+__global__ __launch_bounds__(256) void k_tree_down_top(const double *__restrict__ Rdom,
+                                                       const double *__restrict__ Tnode,
+                                                       const double *__restrict__ dsign,
+                                                       double *__restrict__ S, PanelArgs pa, TreePath tp,
+                                                       int lstop, int64_t dstride) {
+    extern __shared__ double smem_raw[];
+    FormSmem &sm = *reinterpret_cast<FormSmem *>(smem_raw);
+    const int n = pa.n;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t d = (int64_t)blockIdx.x * dstride;
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int r = e / LD, c = e % LD;
+        sm.X[e] = (r == c && r < n) ? dsign[r] : 0.0;
+    }
+    for (int L = tp.nlev - 1; L >= lstop; --L) {
+        const int64_t stride = tp.stride[L], span = tp.span[L];
+        const int64_t left = d / span * span;
+        const int64_t qd = (d - left) / stride;
+        int64_t nr = 0;
+        for (int64_t q = 1; q * stride < span && left + q * stride < pa.P; ++q) ++nr;
+        for (int64_t q = nr; q > qd; --q) {
+            __syncthreads();
+            load_nn(sm.T, Tnode + (left + q * stride) * nn, n, n, false);
+            __syncthreads();
+            lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);   // Z = T S_l
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) sm.X[e] -= sm.Z[e];
+        }
+        if (qd >= 1) {
+            const int64_t right = left + qd * stride;
+            __syncthreads();
+            load_nn(sm.T, Tnode + right * nn, n, n, false);
+            load_nn(sm.W, Rdom + right * nn, n, n, false);   // U (upper triangular)
+            __syncthreads();
+            lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);   // Z = T S_l
+            __syncthreads();
+            lds_gemm64(sm.W, sm.Z, sm.X, LD, true, false, -1.0);  // S_r = -U Z
+        }
+    }
+    __syncthreads();
+    store_nn(S + d * nn, sm.X, n);
+}
+
 // S_0 = D (n x n, column-major).
 __global__ void k_seed_root(double *S, int n, const double *d) {
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -275,6 +326,18 @@ static hipError_t set_smem(const void *k) {
 hipError_t launch_seed_root(double *S, int n, const double *dsign, hipStream_t st) {
     ProfScope ps("seed_root", st);
     hipLaunchKernelGGL(k_seed_root, dim3(1), dim3(256), 0, st, S, n, dsign);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_down_top(const double *Rdom, const double *Tnode, const double *dsign, double *S,
+                                const PanelArgs &pa, const TreePath &tp, int lstop, int64_t dstride,
+                                hipStream_t st) {
+    hipError_t e = set_smem((const void *)k_tree_down_top);
+    if (e != hipSuccess) return e;
+    ProfScope ps("tree_down", st);
+    const int64_t groups = (pa.P + dstride - 1) / dstride;
+    hipLaunchKernelGGL(k_tree_down_top, dim3((unsigned)groups), dim3(256), sizeof(FormSmem), st, Rdom, Tnode,
+                       dsign, S, pa, tp, lstop, dstride);
     return hipGetLastError();
 }
 

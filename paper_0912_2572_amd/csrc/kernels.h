@@ -33,6 +33,14 @@ struct TreeArgs {
     int64_t chains;
 };
 
+// All levels of a reduction tree (bottom first), passed by value.
+constexpr int kMaxTreeLevels = 64;
+struct TreePath {
+    int nlev;
+    int64_t stride[kMaxTreeLevels];
+    int64_t span[kMaxTreeLevels];
+};
+
 size_t factor_smem_bytes();
 
 // ---------------------------------------------------------------------------
@@ -116,6 +124,9 @@ hipError_t launch_scale_rows(double *B, int64_t ldb, int n, int64_t k, const dou
 
 // formq.hip: thin Q of a single-panel factorization (n <= 64).
 hipError_t launch_seed_root(double *S, int n, const double *dsign, hipStream_t st);
+hipError_t launch_tree_down_top(const double *Rdom, const double *Tnode, const double *dsign, double *S,
+                                const PanelArgs &pa, const TreePath &tp, int lstop, int64_t dstride,
+                                hipStream_t st);
 hipError_t launch_tree_down(const double *Rdom, const double *Tnode, double *S, const PanelArgs &pa,
                             const TreeArgs &ta, hipStream_t st);
 hipError_t launch_form_leaf(const double *V, int64_t ldv, const double *Tc, const double *S,
