@@ -115,6 +115,11 @@ SHAPES = [
     (20000, 64, 3000, 4),
     (9000, 40, 700, 0),
     (3000, 33, 300, 2),
+    # even m (16-byte aligned reflector columns: half of each full chunk's
+    # reflectors leave through LDS during the next chunk), n < 64, long runs
+    # of full chunks, the drain after a domain's last chunk and into a tail
+    (40000, 48, 4096, 2),
+    (50002, 40, 2048, 4),
 ]
 
 
