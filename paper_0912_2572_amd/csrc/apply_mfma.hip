@@ -240,15 +240,24 @@ __device__ __forceinline__ void leaf_apply_domain(ApplyMSmem<Tile> &sm, const ty
     }
 }
 
+// Workgroup order: groups of 8 domains x ncb column blocks, the column
+// blocks of one domain 8 workgroups apart.  Workgroups go to the 8 XCDs
+// round-robin by index, so a domain's column blocks share one XCD (one L2)
+// and run side by side: its V comes from HBM about once instead of ncb times.
 template <typename Tile>
 __global__ __launch_bounds__(256) void k_leaf_apply_m(const typename Tile::T *__restrict__ V, int64_t ldv,
                                                       const double *__restrict__ Tc, PanelArgs pa,
                                                       const double *__restrict__ Bsrc, int64_t ldbs,
                                                       double *__restrict__ B, int64_t ldb, int64_t k,
-                                                      int trans) {
+                                                      int trans, int ncb) {
     extern __shared__ double smem_raw[];
     ApplyMSmem<Tile> &sm = *reinterpret_cast<ApplyMSmem<Tile> *>(smem_raw);
-    leaf_apply_domain<Tile>(sm, V, ldv, Tc, pa, Bsrc, ldbs, B, ldb, k, trans, blockIdx.x, blockIdx.y);
+    const int64_t b = blockIdx.x, per = 8 * (int64_t)ncb;
+    const int64_t within = b % per;
+    const int64_t dom = (b / per) * 8 + within % 8;
+    const int64_t cblk = within / 8;
+    if (dom >= pa.P) return;
+    leaf_apply_domain<Tile>(sm, V, ldv, Tc, pa, Bsrc, ldbs, B, ldb, k, trans, dom, cblk);
 }
 
 template <typename Tile>
@@ -260,10 +269,11 @@ static hipError_t launch_apply_m(const typename Tile::T *V, int64_t ldv, const d
     hipError_t e = hipFuncSetAttribute((const void *)k_leaf_apply_m<Tile>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)pa.P, (unsigned)((k + KBM - 1) / KBM));
+    const int ncb = (int)((k + KBM - 1) / KBM);
+    const int64_t groups = (pa.P + 7) / 8;
     ProfScope ps(tag, st);
-    hipLaunchKernelGGL(k_leaf_apply_m<Tile>, grid, dim3(256), sh, st, V, ldv, Tc, pa, Bsrc, ldbs, B, ldb,
-                       k, trans);
+    hipLaunchKernelGGL(k_leaf_apply_m<Tile>, dim3((unsigned)(groups * 8 * ncb)), dim3(256), sh, st, V, ldv, Tc,
+                       pa, Bsrc, ldbs, B, ldb, k, trans, ncb);
     return hipGetLastError();
 }
 
