@@ -257,17 +257,32 @@ __device__ __forceinline__ void refine_step(const double *__restrict__ R, int n,
     const int tid = threadIdx.x, lane = tid & 63;
     bool all_ok = true;
     for (int c = 0; c < k; ++c) {
-        // g = -sum_b gpart[b] (every thread), in a fixed order per entry
+        // g = -sum_b gpart[b] (every thread), in a fixed order per entry:
+        // even blocks into s0, odd blocks into s1, in block order.  The loads
+        // go out 16 at a time ahead of the adds (the sum waits on memory
+        // latency, not on the adds); the order of the adds is unchanged.
         __syncthreads();
         for (int j = tid; j < n; j += blockDim.x) {
             double s0 = 0.0, s1 = 0.0;
             if (gpart) {
+                const double *__restrict__ p = gpart + j + (int64_t)n * c;
+                const int64_t bs = (int64_t)n * k;
                 int b = 0;
-                for (; b + 1 < nblocks; b += 2) {
-                    s0 += gpart[(int64_t)b * n * k + j + n * c];
-                    s1 += gpart[(int64_t)(b + 1) * n * k + j + n * c];
+                for (; b + 15 < nblocks; b += 16) {
+                    double v[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) v[u] = p[(int64_t)(b + u) * bs];
+#pragma unroll
+                    for (int u = 0; u < 16; u += 2) {
+                        s0 += v[u];
+                        s1 += v[u + 1];
+                    }
                 }
-                if (b < nblocks) s0 += gpart[(int64_t)b * n * k + j + n * c];
+                for (; b + 1 < nblocks; b += 2) {
+                    s0 += p[(int64_t)b * bs];
+                    s1 += p[(int64_t)(b + 1) * bs];
+                }
+                if (b < nblocks) s0 += p[(int64_t)b * bs];
             }
             g[j] = -(s0 + s1);
         }
