@@ -784,6 +784,9 @@ __global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rd
                                                  PanelArgs pa, TreeArgs ta, int keep_q) {
     extern __shared__ double smem_raw[];
     FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    // The levels are the critical path while a solve's leaf passes share the
+    // CUs: the chain's waves take the issue slots first.
+    __builtin_amdgcn_s_setprio(3);
     tree_chain<NS>(sm, Rdom, Tnode, pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, keep_q);
 }
 
