@@ -133,8 +133,14 @@ __device__ __forceinline__ void householder_scalars(double alpha, double sig2, d
 
 // ---- one-wave triangular solves for n <= 256 (column-major R, ld n) ----
 // Lane l holds entries l + 64 q in xr[q], q < 4.  No barrier: the wave
-// broadcasts each solved entry with a lane read, and the next column (or
-// row) of R is fetched one step ahead.
+// broadcasts each solved entry with a lane read.  The columns (or rows) of R
+// and their diagonal entries are fetched kSolveAhead steps ahead into a ring
+// of registers, so a step waits on a load issued several steps earlier
+// instead of a full memory latency.  Every load address is clamped into R
+// (out-of-range entries are loaded from R[0..] and replaced by zero), so the
+// loads are unconditional.
+
+constexpr int kSolveAhead = 4;
 
 __device__ __forceinline__ double wave_bcast(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -148,54 +154,86 @@ __device__ __forceinline__ double pick4(const double (&xr)[4], int q) {
 
 // Back substitution R x = b (b in xr on entry, x on exit).
 __device__ __forceinline__ void wave_backsub(const double *__restrict__ R, int n, double (&xr)[4]) {
+    if (n <= 0) return;
     const int lane = threadIdx.x & 63;
-    double col[4], nxt[4];
-    auto fetch = [&](int j, double (&cc)[4]) {
+    constexpr int D = kSolveAhead;
+    double col[D][4], dg[D];
+    // column j above the diagonal and R[j][j]; j < 0 loads column 0 (unused)
+    auto fetch = [&](int j, double (&cc)[4], double &d) {
+        const int jj = j < 0 ? 0 : j;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = lane + 64 * q;
-            cc[q] = (i < j) ? R[i + (int64_t)j * n] : 0.0;
+            const double v = R[(i < jj ? i : 0) + (int64_t)jj * n];
+            cc[q] = (i < jj) ? v : 0.0;
         }
+        d = R[jj + (int64_t)jj * n];
     };
-    if (n > 0) fetch(n - 1, col);
-    for (int j = n - 1; j >= 0; --j) {
-        if (j > 0) fetch(j - 1, nxt);
+    auto step = [&](int j, const double (&cc)[4], double d) {
         const int qj = j >> 6, lj = j & 63;
-        const double xj = wave_bcast(pick4(xr, qj), lj) / R[j + (int64_t)j * n];
+        const double xj = wave_bcast(pick4(xr, qj), lj) / d;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            xr[q] = fma(-col[q], xj, xr[q]);
+            xr[q] = fma(-cc[q], xj, xr[q]);
             if (q == qj && lane == lj) xr[q] = xj;
         }
+    };
 #pragma unroll
-        for (int q = 0; q < 4; ++q) col[q] = nxt[q];
+    for (int u = 0; u < D; ++u) fetch(n - 1 - u, col[u], dg[u]);
+    int j0 = n - 1;
+    for (; j0 - (D - 1) >= 0; j0 -= D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            step(j0 - u, col[u], dg[u]);
+            fetch(j0 - u - D, col[u], dg[u]);
+        }
     }
+#pragma unroll
+    for (int u = 0; u < D - 1; ++u)
+        if (j0 - u >= 0) step(j0 - u, col[u], dg[u]);
 }
 
 // Forward substitution R^T h = g (g in xr on entry, h on exit).
 __device__ __forceinline__ void wave_fwdsub_t(const double *__restrict__ R, int n, double (&xr)[4]) {
+    if (n <= 0) return;
     const int lane = threadIdx.x & 63;
-    double row[4], nxt[4];
-    auto fetch = [&](int i, double (&rr)[4]) {   // R[i][q] for q > i
+    constexpr int D = kSolveAhead;
+    double row[D][4], dg[D];
+    // row i right of the diagonal (R[i][c], i < c < n) and R[i][i];
+    // i >= n loads row 0 (unused)
+    auto fetch = [&](int i, double (&rr)[4], double &d) {
+        const int ii = i < n ? i : 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = lane + 64 * q;
-            rr[q] = (c > i && c < n) ? R[i + (int64_t)c * n] : 0.0;
+            const bool in = c > ii && c < n;
+            const double v = R[ii + (int64_t)(in ? c : ii) * n];
+            rr[q] = in ? v : 0.0;
         }
+        d = R[ii + (int64_t)ii * n];
     };
-    if (n > 0) fetch(0, row);
-    for (int i = 0; i < n; ++i) {
-        if (i + 1 < n) fetch(i + 1, nxt);
+    auto step = [&](int i, const double (&rr)[4], double d) {
         const int qi = i >> 6, li = i & 63;
-        const double hi = wave_bcast(pick4(xr, qi), li) / R[i + (int64_t)i * n];
+        const double hi = wave_bcast(pick4(xr, qi), li) / d;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            xr[q] = fma(-row[q], hi, xr[q]);
+            xr[q] = fma(-rr[q], hi, xr[q]);
             if (q == qi && lane == li) xr[q] = hi;
         }
+    };
 #pragma unroll
-        for (int q = 0; q < 4; ++q) row[q] = nxt[q];
+    for (int u = 0; u < D; ++u) fetch(u, row[u], dg[u]);
+    int i0 = 0;
+    for (; i0 + (D - 1) < n; i0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            step(i0 + u, row[u], dg[u]);
+            fetch(i0 + u + D, row[u], dg[u]);
+        }
     }
+#pragma unroll
+    for (int u = 0; u < D - 1; ++u)
+        if (i0 + u < n) step(i0 + u, row[u], dg[u]);
 }
 
 // Sum over the 64 lanes, identical in every lane.
