@@ -306,6 +306,9 @@ __global__ __launch_bounds__(256) void k_tree_apply(const double *__restrict__ R
                                                     int64_t k, int trans) {
     extern __shared__ double smem_raw[];
     ApplySmem &sm = *reinterpret_cast<ApplySmem *>(smem_raw);
+    // A latency-bound chain that may share CUs with a thin Q's top-down tree:
+    // its waves take the issue slots first.
+    __builtin_amdgcn_s_setprio(3);
     tree_apply_chain(sm, Rdom, Tnode, pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, B, ldb, k,
                      trans, blockIdx.y);
 }
