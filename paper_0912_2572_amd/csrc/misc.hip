@@ -39,8 +39,10 @@ constexpr int kResidBlocks = 512;
 // partial[b][c] = sum of C[r][c]^2 over the rows n..m-1 owned by block b
 // (contiguous row ranges, fixed summation order).
 __global__ __launch_bounds__(256) void k_resid_partial(const double *C, int64_t ldc, int64_t m, int n,
-                                                       int64_t k, double *partial) {
+                                                       int64_t k, double *partial, int32_t *dinfo) {
     __shared__ double red[256];
+    // the info word the final kernel raises with atomics starts at zero
+    if (dinfo && blockIdx.x == 0 && threadIdx.x == 0) *dinfo = 0;
     const int64_t rows = m - n;
     const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
     const int64_t lo = n + (int64_t)blockIdx.x * per;
@@ -69,6 +71,16 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
                                                   int32_t *dinfo, const double *partial, int nparts) {
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
+    // the right-hand side and the residual partials are loaded before the
+    // diagonal test, so the three load rounds overlap
+    double xr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        xr[q] = (i < n) ? C[i + c * ldc] : 0.0;
+    }
+    double s = 0.0;
+    for (int b = lane; b < nparts; b += 64) s += partial[(int64_t)b * k + c];
     int info = 0;
     for (int j0 = 0; j0 < n && !info; j0 += 64) {
         const int j = j0 + lane;
@@ -76,8 +88,6 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
         const unsigned long long mask = __ballot(zero);
         if (mask) info = j0 + __ffsll((long long)mask);
     }
-    double s = 0.0;
-    for (int b = lane; b < nparts; b += 64) s += partial[(int64_t)b * k + c];
     const double rn = sqrt(wave_sum(s));
     if (lane == 0) {
         if (resid) resid[c] = rn;
@@ -89,12 +99,6 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
         }
     }
     if (info) return;
-    double xr[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = lane + 64 * q;
-        xr[q] = (i < n) ? C[i + c * ldc] : 0.0;
-    }
     wave_backsub(R, n, xr);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -138,11 +142,11 @@ hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ld
     if (blocks < 1) blocks = 1;
     ProfScope ps("lsq_finish", st);
     if (m > n) {
-        hipLaunchKernelGGL(k_resid_partial, dim3(blocks), dim3(256), 0, st, C, ldc, m, n, k, partial);
+        hipLaunchKernelGGL(k_resid_partial, dim3(blocks), dim3(256), 0, st, C, ldc, m, n, k, partial, dinfo);
     } else {
         blocks = 0;
+        if (dinfo) hipLaunchKernelGGL(k_info_clear, dim3(1), dim3(64), 0, st, dinfo);
     }
-    if (dinfo) hipLaunchKernelGGL(k_info_clear, dim3(1), dim3(64), 0, st, dinfo);
     hipLaunchKernelGGL(k_lsq_final, dim3((unsigned)k), dim3(64), 0, st, R, n, C, ldc, k, X, ldx, resid, dinfo,
                        partial, blocks);
     return hipGetLastError();
