@@ -437,11 +437,13 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
         sm.V0[r * kLdsStride + q] = v;
     }
     // Only the n x kc live entries are computed (e < n kc: i = e % n, j = e / n).
-    // The next chunk's T is fetched into registers while the current chunk
-    // is processed.
+    // The next chunk's T and P_c are fetched into registers while the current
+    // chunk is processed (loads retire in order, so a P_c loaded inside the
+    // step would also wait for the T fetched ahead).
     const int live = n * kc;
-    constexpr int kTPer = 64 * 64 / 256;   // T entries per thread
-    double tnext[kTPer];
+    constexpr int kTPer = 64 * 64 / 256;    // T entries per thread
+    constexpr int kPPer = 64 * KBM / 256;   // P_c entries per thread (live <= 64 KBM)
+    double tnext[kTPer], pnext[kPPer];
     auto fetch_t = [&](int64_t ch) {
         const double *Tk = Tc + (dom * pa.cpd + ch) * nn;
 #pragma unroll
@@ -449,18 +451,30 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
             const int e = tid + 256 * u, r = e & 63, q = e >> 6;
             tnext[u] = (r < n && q < n) ? Tk[r + (int64_t)q * n] : 0.0;
         }
+        // P_c is n x kc, column-major with ld n: entry (e % n, e / n) at e
+        const double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
+#pragma unroll
+        for (int u = 0; u < kPPer; ++u) {
+            const int e = tid + 256 * u;
+            pnext[u] = (e < live) ? P[e] : 0.0;
+        }
     };
     auto chunk_step = [&](int64_t ch, int64_t ch_next) {
-        const double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTPer; ++u) {
             const int e = tid + 256 * u, r = e & 63, q = e >> 6;
             sm.Tm[r * kLdsStride + q] = tnext[u];
         }
+        double pcur[kPPer];
+#pragma unroll
+        for (int u = 0; u < kPPer; ++u) pcur[u] = pnext[u];
         if (ch_next >= 0) fetch_t(ch_next);
         // W = (V_0top^T Y on a first chunk, else Y) + P_c
-        for (int e = tid; e < live; e += 256) {
+#pragma unroll
+        for (int u = 0; u < kPPer; ++u) {
+            const int e = tid + 256 * u;
+            if (e >= live) continue;
             const int m = e % n, j = e / n;
             double wv = 0.0;
             if (ch == 0) {
@@ -468,7 +482,7 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
             } else {
                 wv = sm.Y[m][j];
             }
-            sm.W[m][j] = wv + P[m + (int64_t)j * n];
+            sm.W[m][j] = wv + pcur[u];
         }
         __syncthreads();
         for (int e = tid; e < live; e += 256) {
