@@ -403,11 +403,16 @@ __global__ __launch_bounds__(256) void k_apply_p1(const typename Tile::T *__rest
 
 struct ChainSmem {
     double Tm[64 * kLdsStride];
-    double V0[64 * kLdsStride];   // unit lower V_0top of the first chunk
+    // unit lower V_0top of the first chunk, its lower triangle (diagonal of
+    // ones included) packed by rows: entry (r, c), c <= r, at r (r + 1) / 2 + c.
+    // Packed, the struct fits two workgroups in a CU's LDS.
+    double V0[64 * 65 / 2];
     double Y[64][KBM];
     double W[64][KBM];
     double Z[64][KBM];
 };
+static_assert(2 * sizeof(ChainSmem) <= 160 * 1024, "two chain workgroups per CU");
+__device__ __forceinline__ int v0_at(int r, int c) { return r * (r + 1) / 2 + c; }
 
 // Pass 2 for one domain (FP64).
 __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, const float *__restrict__ V32,
@@ -429,12 +434,13 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
     // V_0top, unit lower triangular (the reflector storage precision)
     for (int e = tid; e < 64 * 64; e += 256) {
         const int r = e & 63, q = e >> 6;
+        if (q > r) continue;
         double v = 0.0;
         if (r < n && q < n) {
             if (r == q) v = 1.0;
-            else if (r > q) v = V32 ? (double)V32[row0 + r + (int64_t)q * ldv] : V64[row0 + r + (int64_t)q * ldv];
+            else v = V32 ? (double)V32[row0 + r + (int64_t)q * ldv] : V64[row0 + r + (int64_t)q * ldv];
         }
-        sm.V0[r * kLdsStride + q] = v;
+        sm.V0[v0_at(r, q)] = v;
     }
     // Only the n x kc live entries are computed (e < n kc: i = e % n, j = e / n).
     // The next chunk's T and P_c are fetched into registers while the current
@@ -478,7 +484,7 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
             const int m = e % n, j = e / n;
             double wv = 0.0;
             if (ch == 0) {
-                for (int r = m; r < n; ++r) wv = fma(sm.V0[r * kLdsStride + m], sm.Y[r][j], wv);
+                for (int r = m; r < n; ++r) wv = fma(sm.V0[v0_at(r, m)], sm.Y[r][j], wv);
             } else {
                 wv = sm.Y[m][j];
             }
@@ -502,7 +508,7 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
             const int i = e % n, j = e / n;
             if (ch == 0) {
                 double u = 0.0;
-                for (int q = 0; q <= i; ++q) u = fma(sm.V0[i * kLdsStride + q], sm.Z[q][j], u);
+                for (int q = 0; q <= i; ++q) u = fma(sm.V0[v0_at(i, q)], sm.Z[q][j], u);
                 sm.W[i][j] = sm.Y[i][j] - u;
             } else {
                 sm.Y[i][j] -= sm.Z[i][j];
