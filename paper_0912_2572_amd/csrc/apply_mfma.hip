@@ -307,14 +307,19 @@ hipError_t launch_leaf_apply_m32(const float *V, int64_t ldv, const double *Tc, 
 // chunk; the chain touches only T and n x k blocks.  P_c and Z_c are n x k
 // column-major blocks, one per chunk.
 
-// Rows [rlo, valid) of chunk c: W(n x kc) = V_c^T B_c, reduced over the
-// waves into sm.W (tile precision).
+// Rows [rlo, valid) of chunk c: W(n x kc) = V_c^T B_c, one partial per wave
+// in sm.Wp (tile precision); the caller adds the four in wave order.
 template <typename Tile>
 struct VtbSmem {
     using T = typename Tile::T;
-    T Wp[4][64][KBM];
-    T W[64][KBM];
+    // per-wave partials of V^T B, entry (wave w, row m, column j < kc) at
+    // (64 w + m) kc + j: a launch sizes the LDS by its own kc (vtb_lds_bytes)
+    T Wp[4 * 64 * KBM];
 };
+template <typename Tile>
+constexpr size_t vtb_lds_bytes(int64_t kc) {
+    return (size_t)4 * 64 * (size_t)kc * sizeof(typename Tile::T);
+}
 
 template <typename Tile>
 __device__ __forceinline__ void chunk_vtb(VtbSmem<Tile> &sm, const typename Tile::T *__restrict__ Vc,
@@ -360,14 +365,11 @@ __device__ __forceinline__ void chunk_vtb(VtbSmem<Tile> &sm, const typename Tile
             }
         }
     }
+    if (l16 < kc) {
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sm.Wp[w][16 * mt + Tile::drow(r, lane)][l16] = acc[mt][r];
-    __syncthreads();
-    for (int e = tid; e < 64 * KBM; e += 256) {
-        const int m = e >> 4, j = e & 15;
-        sm.W[m][j] = ((sm.Wp[0][m][j] + sm.Wp[1][m][j]) + sm.Wp[2][m][j]) + sm.Wp[3][m][j];
+            for (int r = 0; r < 4; ++r) sm.Wp[(64 * w + 16 * mt + Tile::drow(r, lane)) * kc + l16] = acc[mt][r];
     }
     __syncthreads();
 }
@@ -387,10 +389,14 @@ __device__ __forceinline__ void apply_p1_body(const typename Tile::T *__restrict
     const int64_t r0 = row0 + ch * pa.chunk;
     const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
     chunk_vtb<Tile>(sm, V + r0, ldv, B + r0, ldb, ch == 0 ? n : 0, valid, n, kc, ch == 0);
+    // P_c = the four waves' partials added in wave order
+    using T = typename Tile::T;
     double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
+    const int ws = 64 * kc;
     for (int e = threadIdx.x; e < n * kc; e += 256) {
-        const int m = e % n, j = e / n;
-        P[e] = (double)sm.W[m][j];
+        const int m = e % n, j = e / n, o = m * kc + j;
+        const T sum = ((sm.Wp[o] + sm.Wp[ws + o]) + sm.Wp[2 * ws + o]) + sm.Wp[3 * ws + o];
+        P[e] = (double)sum;
     }
 }
 
@@ -643,7 +649,7 @@ __global__ __launch_bounds__(256) void k_apply_p3_b(const BMat *__restrict__ mat
 hipError_t launch_apply3_b(const BMat *mats, const int *list, int cnt, int64_t max_chunks, int64_t max_p,
                            int trans, int sweep, hipStream_t st) {
     if (cnt <= 0 || max_chunks <= 0) return hipSuccess;
-    const size_t sh = sizeof(VtbSmem<TileF64>);
+    const size_t sh = vtb_lds_bytes<TileF64>(1);   // k = 1
     hipError_t e = hipFuncSetAttribute((const void *)k_apply_p1_b, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)sh);
     if (e == hipSuccess)
@@ -673,7 +679,7 @@ static hipError_t launch_apply3(const typename Tile::T *V, const double *V64, co
                                 const double *Tc, const PanelArgs &pa, double *B, int64_t ldb, int64_t k,
                                 int trans, double *Pc, double *Zc, hipStream_t st) {
     if (k <= 0) return hipSuccess;
-    const size_t sh = sizeof(VtbSmem<Tile>);
+    const size_t sh = vtb_lds_bytes<Tile>(k);
     hipError_t e = hipFuncSetAttribute((const void *)k_apply_p1<Tile>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e == hipSuccess)
