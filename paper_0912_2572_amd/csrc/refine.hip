@@ -535,9 +535,15 @@ hipError_t launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd
     return hipGetLastError();
 }
 
+// At most 768 workgroups: the widest line-wide residual pass (16 accumulator
+// pairs per lane, 152 VGPRs) keeps three 256-thread workgroups on each of the
+// 256 CUs, so a tall matrix's pass is resident in one round instead of
+// leaving a partly filled second one.
 int resid_blocks(int64_t m) {
+    constexpr int64_t kResident = 3 * 256;
+    static_assert(kResident <= kRefineBlocks, "partials buffer");
     int64_t b = (m + 2047) / 2048;
-    return (int)(b < 1 ? 1 : (b > kRefineBlocks ? kRefineBlocks : b));
+    return (int)(b < 1 ? 1 : (b > kResident ? kResident : b));
 }
 
 hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, const double *B, int64_t ldb,
