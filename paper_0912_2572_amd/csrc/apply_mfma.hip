@@ -32,10 +32,10 @@ template <typename Tile>
 struct ApplyMSmem {
     using T = typename Tile::T;
     T Tm[64 * kLdsStride];
-    T Wp[4][64][KBM];   // per-wave partials of W; Wp[0] later holds Z
-    T W[64][KBM];
+    T Wp[4][64][KBM];   // per-wave partials of W; then W in Wp[1] and Z in Wp[0]
     double Y[64][KBM];  // the domain's top n rows of B (columns of this block)
 };
+static_assert(2 * sizeof(ApplyMSmem<TileF64>) <= 160 * 1024, "two workgroups per CU");
 
 // V element of a chunk with the implicit unit diagonal of a first chunk.
 template <typename VT>
@@ -138,18 +138,18 @@ __device__ __forceinline__ void chunk_apply_m(ApplyMSmem<Tile> &sm, const typena
         const int m = e >> 4, j = e & 15;
         T s = ((sm.Wp[0][m][j] + sm.Wp[1][m][j]) + sm.Wp[2][m][j]) + sm.Wp[3][m][j];
         if (!first) s += T(sm.Y[m][j]);
-        sm.W[m][j] = s;
+        sm.Wp[1][m][j] = s;   // W: each entry read and written by one thread
     }
     __syncthreads();
-    // Z = op(T) W, written over the partial buffer of wave 0
+    // Z = op(T) W (W in Wp[1]), written over the partial buffer of wave 0
     for (int e = tid; e < 64 * KBM; e += 256) {
         const int i = e >> 4, j = e & 15;
         T z = 0;
         if (i < n) {
             if (trans) {
-                for (int q = 0; q <= i; ++q) z = fma(sm.Tm[q * kLdsStride + i], sm.W[q][j], z);
+                for (int q = 0; q <= i; ++q) z = fma(sm.Tm[q * kLdsStride + i], sm.Wp[1][q][j], z);
             } else {
-                for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.W[q][j], z);
+                for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.Wp[1][q][j], z);
             }
         }
         sm.Wp[0][i][j] = z;
