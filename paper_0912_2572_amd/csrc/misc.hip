@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
     // the right-hand side and the residual partials are loaded before the
-    // diagonal test, so the three load rounds overlap
+    // diagonal test, so the three groups of loads overlap
     double xr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

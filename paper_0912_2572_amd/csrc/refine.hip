@@ -537,8 +537,8 @@ hipError_t launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd
 
 // At most 768 workgroups: the widest line-wide residual pass (16 accumulator
 // pairs per lane, 152 VGPRs) keeps three 256-thread workgroups on each of the
-// 256 CUs, so a tall matrix's pass is resident in one round instead of
-// leaving a partly filled second one.
+// 256 CUs, so a tall matrix's whole pass is resident at once instead of
+// leaving a partly filled second dispatch wave.
 int resid_blocks(int64_t m) {
     constexpr int64_t kResident = 3 * 256;
     static_assert(kResident <= kRefineBlocks, "partials buffer");
