@@ -47,33 +47,53 @@ def flops_step(m: int, n: int, k: int) -> float:
     return 2.0 * f_r + 4.0 * m * n * k + n * n * k
 
 
-def cpu_baseline(m: int, n: int, mb: int, passes: int):
-    """The FP64 CPU oracle on the same workload (a bounded number of full
-    passes), on the host cores; test infrastructure only."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(m: int, n: int, mb: int, passes: int, samples: int = 3):
+    """The FP64 CPU oracle on the same workload, on the host cores; test
+    infrastructure only.  `samples` timed samples of `passes` full passes
+    each (factor + thin Q + 1-RHS solve); the median sample is the value."""
     import numpy as np
     import oracle
     import synth
     A = synth.config_large(m, n, seed=0)
-    b = np.random.default_rng(1).standard_normal(m)
-    t0 = time.perf_counter()
-    for _ in range(passes):
-        f = oracle.TSQR(A, mb=mb)
-        f.form_q()
-        f.lsq(b)
-    dt = time.perf_counter() - t0
+    b = synth.config_large_rhs(m, seed=1)
+    rates, walls = [], []
+    for _ in range(samples):
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            f = oracle.TSQR(A, mb=mb)
+            f.form_q()
+            f.lsq(b)
+        dt = time.perf_counter() - t0
+        walls.append(dt)
+        rates.append(flops_step(m, n, 1) * passes / dt / 1e9)
     return {
-        "value": round(flops_step(m, n, 1) * passes / dt / 1e9, 3),
+        "value": round(float(np.median(rates)), 3),
         "unit": "Gflop/s",
         "cores": oracle.max_threads(),
         "kind": "oracle",
-        "sample": f"{passes} full passes (factor + thin Q + 1-RHS solve) of the {m}x{n} matrix, "
-                  f"{dt:.1f} s wall",
+        "cpu_model": host_cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "samples_gflops": [round(r, 3) for r in rates],
+        "sample": f"median of {samples} samples, each {passes} full passes (factor + thin Q + 1-RHS "
+                  f"solve) of the {m}x{n} matrix ({', '.join(f'{w:.1f}' for w in walls)} s wall)",
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single", choices=["single", "mixed", "batch", "serve", "copy"])
+    ap.add_argument("--workload", default="single",
+                    choices=["single", "mixed", "batch", "serve", "sweep", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -81,7 +101,9 @@ def main():
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--row-block", type=int, default=4096)
-    ap.add_argument("--cpu-passes", type=int, default=20)
+    ap.add_argument("--cpu-passes", type=int, default=7)
+    ap.add_argument("--no-sub", action="store_true",
+                    help="single workload: leave out the compact mixed / batch / serve / n-sweep records")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--separate-calls", action="store_true",
                     help="single workload: tsqr_factor, tsqr_form_q and tsqr_lsq_solve as three calls "
@@ -92,7 +114,7 @@ def main():
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
-     "copy": run_copy}[args.workload](args)
+     "sweep": run_sweep, "copy": run_copy}[args.workload](args)
 
 
 def counted_traffic(kernel: str, m: int, n: int, mb: int):
@@ -113,14 +135,24 @@ def counted_traffic(kernel: str, m: int, n: int, mb: int):
 
 
 def run_single(args):
+    line = measure_single(args, args.m, args.n, args.row_block, args.steps, args.warmup)
+    if not args.no_sub:
+        line["sub_records"] = sub_records(args)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.m, args.n, args.row_block, args.cpu_passes)
+    print(json.dumps(line), flush=True)
+
+
+def measure_single(args, m, n, mb, steps, warmup):
+    """One tsqr_factor_solve (factor + thin Q + 1-RHS solve) per step on an
+    m x n N(0,1) matrix; returns the record of the timed loop."""
     import torch
     import paper_0912_2572_amd as tl
     import synth
 
-    m, n, mb = args.m, args.n, args.row_block
     dev = torch.device("cuda:0")
     A = torch.as_tensor(synth.config_large(m, n, seed=0)).t().contiguous().t().to(dev)
-    b = torch.as_tensor(__import__("numpy").random.default_rng(1).standard_normal(m)).to(dev)
+    b = torch.as_tensor(synth.config_large_rhs(m, seed=1)).to(dev)
     o = tl.opts(row_block=mb, tree=tl.TREE_BINARY, keep_q=True, lsq_max_rhs=1)
     work = torch.empty(tl.workspace_bytes(m, n, o), dtype=torch.uint8, device=dev)
     Q = tl.empty_colmajor(m, n, device=dev)
@@ -157,13 +189,13 @@ def run_single(args):
             main.wait_stream(side)
         return f
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     # per-kernel breakdown from an untimed pass with every launch bracketed
     # by events; the timed loop then carries events around the dominant
     # kernel only (an event pair per launch of ~35 kernels costs ~0.2 ms)
-    prof_steps = min(args.steps, 3)
+    prof_steps = min(steps, 3)
     tl.prof_enable(True)
     for _ in range(prof_steps):
         step()
@@ -176,11 +208,11 @@ def run_single(args):
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     stop.record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    ms = start.elapsed_time(stop) / steps
     kern = tl.prof_query()
     tl.prof_only(None)
     tl.prof_enable(False)
@@ -213,8 +245,8 @@ def run_single(args):
         "value": round(value, 2),
         "unit": "Gflop/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -233,9 +265,63 @@ def run_single(args):
                            "the two streams overlap, so they do not add up to ms_per_step",
         "roofline": roof,
     }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(m, n, mb, args.cpu_passes)
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def run_sweep(args):
+    print(json.dumps(sweep_n(args, steps=args.steps, warmup=args.warmup)), flush=True)
+
+
+def sweep_n(args, steps, warmup):
+    """The single-matrix path at m = 2^20 for n in {8, 16, 32, 64} (the
+    HBM-bound range of the factorization, n <= 64)."""
+    out = {}
+    for n in (8, 16, 32, 64):
+        r = measure_single(args, 1 << 20, n, 4096, steps, warmup)
+        rf = r["roofline"] or {}
+        out[str(n)] = {"ms_per_step": r["ms_per_step"], "gflops": r["value"],
+                       "dominant_kernel": rf.get("kernel"), "dominant_frac_hbm": rf.get("frac"),
+                       "dominant_avg_us": rf.get("avg_launch_us"),
+                       "leaf_ms": r["kernels_ms_per_step"].get("leaf_factor")}
+    return {"metric": "TSQR Gflop/s (factor + thin Q + LSQ), FP64, n sweep at m = 2^20", "unit": "Gflop/s",
+            "steps": steps, "warmup": warmup, "by_n": out}
+
+
+def sub_records(args):
+    """Compact records of the rest of the headline metric (mixed vs FP64 at
+    kappa 1e6, the batch, the server) and the n sweep, so that one default
+    run carries all of it."""
+    t0 = time.perf_counter()
+    mx = measure_mixed(args, steps=3, warmup=1)
+    t1 = time.perf_counter()
+    bt = measure_batch(args, steps=3, warmup=1)
+    t2 = time.perf_counter()
+    sv = measure_serve(args, requests=200, loads=(0.8,), mixed_pass=True)
+    t3 = time.perf_counter()
+    sw = sweep_n(args, steps=10, warmup=2)
+    t4 = time.perf_counter()
+    return {
+        "mixed_kappa1e6": {
+            "workload": mx["config"]["workload"],
+            "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
+            "speedup_mixed_over_f64": mx["speedup_mixed_over_f64"],
+            "mixed_sweeps": mx["mixed"]["sweeps"],
+            "eta_f64": mx["f64"]["eta"], "eta_mixed": mx["mixed"]["eta"],
+            "mixed_info": mx["mixed"]["info"], "wall_s": round(t1 - t0, 1)},
+        "batch_512": {
+            "ms_per_run": bt["ms_per_step"], "solves_per_s": bt["solves_per_s"], "gflops": bt["value"],
+            "roofline_frac_hbm": bt["roofline"]["frac"], "speedup_vs_sequential": bt["speedup_vs_sequential"],
+            "sampled_eta_max": bt["sampled_eta_max"], "wall_s": round(t2 - t1, 1)},
+        "serve_200": {
+            "f64_saturated_solves_per_s": round(sv["saturated"]["solves_per_s"], 2),
+            "f64_p50_ms_at_0.8": round(sv["poisson"]["0.8"]["p50_ms"], 2),
+            "f64_p99_ms_at_0.8": round(sv["poisson"]["0.8"]["p99_ms"], 2),
+            "mixed_saturated_solves_per_s": round(sv["mixed_saturated"]["solves_per_s"], 2),
+            "mixed_p50_ms_saturated": round(sv["mixed_saturated"]["p50_ms"], 2),
+            "mixed_p99_ms_saturated": round(sv["mixed_saturated"]["p99_ms"], 2),
+            "sampled_eta_max": sv["sampled_eta_max"], "wall_s": round(t3 - t2, 1)},
+        "n_sweep_m2p20": {**sw["by_n"], "wall_s": round(t4 - t3, 1)},
+    }
 
 
 def _eta(A, x, b):
@@ -247,6 +333,10 @@ def _eta(A, x, b):
 
 
 def run_mixed(args):
+    print(json.dumps(measure_mixed(args, args.steps, args.warmup)), flush=True)
+
+
+def measure_mixed(args, steps, warmup):
     """Config with kappa = 1e6: FP64 path vs mixed path, factor + 2-RHS solve."""
     import torch
     import paper_0912_2572_amd as tl
@@ -279,14 +369,14 @@ def run_mixed(args):
             f = tl.Factors(A, o, work=work)
             f.lsq(B, A=A, X=X, resid=res, info=info)
             return f
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             f = step()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms = (time.perf_counter() - t0) * 1e3 / steps
         sweeps = f.last_refine_iters()
         # per-kernel breakdown from one more, untimed step with every launch timed
         tl.prof_enable(True)
@@ -296,7 +386,7 @@ def run_mixed(args):
         tl.prof_enable(False)
         e1 = [_eta(A, X[:, c], B[:, c]) for c in range(2)]
         out[name] = {"ms": ms, "gflops": flops / (ms * 1e-3) / 1e9, "eta": e1, "sweeps": sweeps,
-                     "x": X.clone(),
+                     "info": int(info.item()), "x": X.clone(),
                      "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()}}
         del work
     xf, xm = out["f64"]["x"], out["mixed"]["x"]
@@ -306,7 +396,7 @@ def run_mixed(args):
         "metric": "TSQR least squares Gflop/s (factor + 2-RHS solve), mixed vs FP64 at kappa 1e6",
         "value": round(out["mixed"]["gflops"], 2),
         "unit": "Gflop/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(out["mixed"]["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic U diag(s) V^T, U, V from QR of torch N(0,1) draws (Philox, seed 0)",
@@ -318,10 +408,16 @@ def run_mixed(args):
         "mixed_consistent_rhs_rel_err_x_true": e_true,
         "speedup_mixed_over_f64": round(out["f64"]["ms"] / out["mixed"]["ms"], 3),
     }
-    print(json.dumps(line), flush=True)
+    del A, B, bc
+    torch.cuda.empty_cache()
+    return line
 
 
 def run_batch(args):
+    print(json.dumps(measure_batch(args, args.steps, args.warmup)), flush=True)
+
+
+def measure_batch(args, steps, warmup):
     """512 independent least-squares problems through the batched path."""
     import numpy as np
     import torch
@@ -345,16 +441,16 @@ def run_batch(args):
     B = tl.Batch(As, bs, precs, tune=table, refine_sweeps=4)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        for _ in range(max(args.warmup, 1)):
+        for _ in range(max(warmup, 1)):
             B.run(use_graph=True, stream=stream)
         stream.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(steps):
             B.run(use_graph=True, stream=stream)
         ev1.record(stream)
     stream.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms = ev0.elapsed_time(ev1) / steps
     # per-kernel breakdown of one run with plain launches (HIP events per launch)
     tl.prof_enable(True)
     B.run(use_graph=False)
@@ -395,7 +491,7 @@ def run_batch(args):
         "metric": "batched TSQR + least squares Gflop/s (512 matrices, half mixed)",
         "value": round(flops / (ms * 1e-3) / 1e9, 2),
         "unit": "Gflop/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
         "data": "synthetic iid N(0,1), torch Philox seed 1; shapes from numpy PCG64 seed 0",
         "config": {"workload": "tsqr_batch_512", "count": len(shapes),
@@ -414,17 +510,25 @@ def run_batch(args):
         "sampled_eta_max": max(eta),
         "sampled_info_nonzero": infos,
     }
-    print(json.dumps(line), flush=True)
+    del B, As, bs, work
+    torch.cuda.empty_cache()
+    return line
 
 
 def run_serve(args):
-    """Least-squares serving: closed-loop saturation, then Poisson arrivals."""
+    print(json.dumps(measure_serve(args, args.requests, loads=(0.5, 0.8, 0.95), mixed_pass=True)), flush=True)
+
+
+def measure_serve(args, requests, loads, mixed_pass):
+    """Least-squares serving: closed-loop saturation, then Poisson arrivals
+    at the given fractions of it; with mixed_pass, a saturated pass of a
+    mixed-precision server over the same stream."""
     import numpy as np
     import torch
     import paper_0912_2572_amd as tl
     import synth
     dev = torch.device("cuda:0")
-    reqs = synth.serving_stream(args.requests, seed=0)
+    reqs = synth.serving_stream(requests, seed=0)
     # host data: windows of one pinned pool of N(0,1) values (drawn on the
     # device from torch's Philox generator, seed 0, then copied); requests at
     # kappa 1e6 get their own scaled copy G diag(s) / sqrt(m)
@@ -463,8 +567,8 @@ def run_serve(args):
     flops = sum(2.0 * r["m"] * r["n"] ** 2 - 2.0 * r["n"] ** 3 / 3.0 + 4.0 * r["m"] * r["n"] * r["k"]
                 for r in reqs)
 
-    def one_pass(rate):
-        S = tl.Server(hbm_budget=budget, streams=4, max_inflight=8, cache=True)
+    def one_pass(rate, prec=tl.F64):
+        S = tl.Server(hbm_budget=budget, streams=4, max_inflight=8, cache=True, prec=prec)
         t0 = tl.server_now()
         arrive = []
         t = 0.0
@@ -504,9 +608,13 @@ def run_serve(args):
     one_pass(0.0)                       # warm-up (kernels, allocator)
     sat = one_pass(0.0)
     mu = sat["solves_per_s"]
-    loads = {}
-    for frac in (0.5, 0.8, 0.95):
-        loads[str(frac)] = one_pass(frac * mu)
+    by_load = {}
+    for frac in loads:
+        by_load[str(frac)] = one_pass(frac * mu)
+    mixed_sat = None
+    if mixed_pass:
+        one_pass(0.0, tl.MIXED)
+        mixed_sat = one_pass(0.0, tl.MIXED)
     # accuracy: backward error of a sample of results (FP64, on the device)
     worst = 0.0
     for r in reqs[:: max(1, len(reqs) // 12)]:
@@ -528,10 +636,11 @@ def run_serve(args):
                    "ill_share": float(np.mean([r["ill"] for r in reqs])),
                    "repeat_share": float(np.mean([r["matrix_id"] != r["id"] for r in reqs]))},
         "saturated": sat,
-        "poisson": loads,
+        "poisson": by_load,
+        "mixed_saturated": mixed_sat,
         "sampled_eta_max": worst,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_copy(args):

@@ -43,9 +43,15 @@ extern "C" {
 #define TSQR_API __attribute__((visibility("default")))
 
 /* Reduction-tree shapes (Sec. 2.3: binary and flat trees; the k-ary tree
-   generalises the binary one).  Results always land in the lower-index
-   child, so the root is domain 0 and its first n rows hold the top of Q^T B. */
-enum { TSQR_TREE_FLAT = 0, TSQR_TREE_BINARY = 2, TSQR_TREE_QUAD = 4 };
+   generalises the binary one).  TSQR_TREE_XCD is the hierarchical tree of
+   Sec. 2.3 (Fig. 2) and Sec. 3 with an XCD of the GPU as a cluster: domain d
+   belongs to XCD d mod 8 (the leaves are dispatched round-robin over the 8
+   XCDs); a binary tree reduces each XCD's domains first, so those
+   triangles stay in that XCD's L2, and a binary tree then reduces the 8 XCD
+   roots: 7 combines cross an XCD boundary (G - 1 for G groups).  Results
+   always land in the lower-index child, so the root is domain 0 and its
+   first n rows hold the top of Q^T B. */
+enum { TSQR_TREE_FLAT = 0, TSQR_TREE_BINARY = 2, TSQR_TREE_QUAD = 4, TSQR_TREE_XCD = 8 };
 
 /* Arithmetic of the factorization.  TSQR_F64: everything in FP64.
    TSQR_MIXED: reflector generation (norms, beta, tau), the leaf and tree
@@ -109,20 +115,31 @@ TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda,
                          void *stream, tsqr_factors *out);
 
 /* Copy the sign-normalised R (n x n upper triangular, zeros below the
-   diagonal, diag >= 0) to R (device, leading dimension ldr >= n). */
+   diagonal, diag >= 0) to R (device, leading dimension ldr >= n).
+   Defined by Sec. 2.2 (A = QR with R upper triangular; unique once the
+   diagonal is made positive).  Errors: -1 handle, -2 R NULL, -3 ldr. */
 TSQR_API int tsqr_get_r(tsqr_factors f, double *R, int64_t ldr, void *stream);
 
 /* B <- Q^T B for the factor's full m x m orthogonal Q (k columns, device,
    ldb >= m).  Rows 0..n-1 of the result equal Q_1^T B for the
    sign-normalised thin Q_1, whatever the tree or partition; rows n..m-1 are
-   a valid complement for this factor's Q and depend on its representation. */
+   a valid complement for this factor's Q and depend on its representation.
+   Defined by Sec. 2.3 (Q is kept implicitly as the leaves' and the tree
+   nodes' reflectors; Q^T is applied leaves first, then up the tree in the
+   factorization's order) and Sec. 4, Property 1 (the Q work has the
+   structure of the R work).  Errors: -1 handle, TSQR_ERR_STATE (keep_q = 0),
+   -2 k < 0, -3 B NULL, -4 ldb. */
 TSQR_API int tsqr_apply_qt(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream);
 
-/* B <- Q B, the inverse of tsqr_apply_qt (same representation). */
+/* B <- Q B, the inverse of tsqr_apply_qt (same representation): the tree
+   top-down, then the leaves (Sec. 2.3).  Errors as tsqr_apply_qt. */
 TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, void *stream);
 
 /* Thin Q (m x n, device, ldq >= m), sign-normalised so that A = Q R with
-   diag(R) >= 0 and Q^T Q = I.
+   diag(R) >= 0 and Q^T Q = I.  Defined by Sec. 1 (Q formed explicitly, at
+   twice the cost of R: Table 2) and Sec. 2.3 (Q = [I_n; 0] pushed down the
+   tree, then through each leaf).  Errors: -1 handle, TSQR_ERR_STATE, -2 Q
+   NULL, -3 ldq.
    Concurrency: calls on one factor are ordered by the caller (one stream,
    or events).  One exception: for an FP64 factor with n <= 64 this call only
    reads the factor and writes Q and its own workspace blocks (the top-down
@@ -132,7 +149,9 @@ TSQR_API int tsqr_apply_q(tsqr_factors f, int64_t k, double *B, int64_t ldb, voi
 TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream);
 
 /* Least squares min ||A x_j - b_j||_2 for k <= opts.lsq_max_rhs right-hand
-   sides: X = R^{-1} (Q^T B)[0:n], resid[j] = ||(Q^T B)[n:m, j]||_2.
+   sides: X = R^{-1} (Q^T B)[0:n], resid[j] = ||(Q^T B)[n:m, j]||_2.  The
+   paper names QR as the first step toward least squares (Sec. 1); the solve
+   is the textbook one through the factors of Sec. 2.3.
    A (m x n, lda) is the matrix that was factored; it is read only by the
    mixed-precision refinement (required there: -2 when NULL), which
    synchronises `stream` once per sweep to read its convergence flag and
@@ -141,7 +160,15 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream);
    ldx >= n) and resid (k doubles, may be NULL) are device outputs.
    dinfo (device int32, may be NULL) receives 0, or j+1 when R_jj == 0
    exactly (X is then left untouched, LAPACK dtrtrs convention), or -2 when
-   a residual is not finite.  dinfo is valid after the stream synchronises. */
+   a residual is not finite, or (mixed precision only) -3 when the
+   refinement ended -- stalled, or after refine_max_iter sweeps -- with an
+   upper bound on the backward error eta = ||A^T (b - A x)|| /
+   (||A||_F (||A||_F ||x|| + ||b - A x||)) above 1e-12 for some right-hand
+   side: X is then written but is not FP64-accurate (the bound of every
+   right-hand side is available from tsqr_lsq_backward_error).  dinfo is
+   valid after the stream synchronises.
+   Errors: -1 handle, TSQR_ERR_STATE, -2 A (mixed: NULL), -3 lda, -4 k,
+   -5 B NULL, -6 ldb, -7 X NULL, -8 ldx. */
 TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_t k,
                             const double *B, int64_t ldb, double *X, int64_t ldx,
                             double *resid, int32_t *dinfo, void *stream);
@@ -169,13 +196,24 @@ TSQR_API int tsqr_factor_solve(int64_t m, int64_t n, const double *A, int64_t ld
                                double *resid, int32_t *dinfo, double *Q, int64_t ldq,
                                void *stream, tsqr_factors *out);
 
+/* Backward-error bounds of the last mixed-precision tsqr_lsq_solve on this
+   handle, one per right-hand side (k <= that solve's k), copied to eta
+   (device, k doubles) on `stream`: eta_j bounds ||A^T s_j|| / (||A||_F
+   (||A||_F ||x_j|| + ||s_j||)) with s_j = b_j - A x_j, from the last
+   refinement sweep's FP64 residuals (||A^T s|| <= ||A^T r|| + ||A|| ||b - r
+   - A x||, ||A||_F = ||R||_F).  A right-hand side with eta_j > 1e-12 made
+   that solve's dinfo -3.  Errors: -1 handle, TSQR_ERR_STATE (FP64 factor,
+   or no mixed solve yet), -2 k, -3 eta NULL. */
+TSQR_API int tsqr_lsq_backward_error(tsqr_factors f, int64_t k, double *eta, void *stream);
+
 /* Number of sweeps (the first solve included) the last mixed-precision
    tsqr_lsq_solve on this handle ran, the largest over its groups of 8
    right-hand sides; 0 for FP64 factors.  Host only; `stream` is unused. */
 TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream);
 
-/* Plan introspection (host only, no device work): number of domains, rows
-   per chunk of the leaf kernel and number of 64-column panels. */
+/* Plan introspection (host only, no device work): number of domains
+   (Sec. 2.3's partition into P domains), rows per chunk of the leaf kernel
+   and number of 64-column panels. */
 TSQR_API int tsqr_plan_info(int64_t m, int64_t n, const tsqr_opts *o,
                             int64_t *num_domains, int64_t *chunk_rows, int64_t *num_panels);
 
@@ -194,7 +232,8 @@ TSQR_API int64_t tsqr_tree_schedule(int64_t P, int tree, int64_t *left, int64_t 
    disables and clears.  tsqr_prof_only(tag) restricts the timing to the
    kernels of one tag (a copy of the string is kept; NULL or "" times all),
    so that a timed loop carries two events per launch of that kernel only.
-   Not thread-safe; process-wide. */
+   Process-wide; the calls may come from several host threads (the
+   recorded events are kept under a lock). */
 TSQR_API int tsqr_prof_enable(int on);
 TSQR_API int tsqr_prof_only(const char *tag);
 TSQR_API int tsqr_prof_query(int i, const char **name, int64_t *launches, double *ms);
@@ -235,7 +274,9 @@ typedef struct {
     double *resid;       /* 1 output: ||b - A x||_2 (FP64 matrices: the    */
                          /* norm of (Q^T b)[n:m])                           */
     int32_t *info;       /* 1 output: 0, j+1 for R_jj == 0 (x untouched),  */
-                         /* -2 for a non-finite residual                    */
+                         /* -2 for a non-finite residual, -3 (mixed) when   */
+                         /* the refined x's backward-error bound is above   */
+                         /* 1e-12 (see tsqr_lsq_solve)                      */
 } tsqr_batch_item;
 
 typedef struct tsqr_batch_s *tsqr_batch;
@@ -315,7 +356,10 @@ typedef struct {
     int32_t cache;          /* 1: keep factors of finished requests          */
     int32_t prec;           /* TSQR_F64 or TSQR_MIXED for every request      */
     int32_t tree;           /* TSQR_TREE_*                                   */
-    int32_t reserved;
+    int32_t bypass_ms;      /* a queued request whose memory does not fit   */
+                            /* yet lets younger requests that fit be         */
+                            /* admitted past it until it has waited this     */
+                            /* long (ms); 0 = 100 ms, < 0 = strict FIFO       */
 } tsqr_server_opts;
 
 typedef struct {
@@ -344,10 +388,15 @@ TSQR_API int tsqr_server_create(const tsqr_server_opts *o, tsqr_server *out);
    -2 shape out of scope, -3 NULL buffer, -4 matrix_id reused with another
    shape, TSQR_ERR_WORKSPACE when it can never fit the budget. */
 TSQR_API int64_t tsqr_server_submit(tsqr_server s, const tsqr_request *r);
-/* Retires finished requests and admits queued ones (FIFO; a request that
-   does not fit waits, after evicting idle cached factors, until memory
-   frees up).  wait = 1 blocks until at least one request finishes when
-   any is running.  Returns the number of requests queued or running. */
+/* Retires finished requests and admits queued ones in arrival order while
+   slots are free.  A request that does not fit even after evicting idle
+   cached factors waits; younger requests that fit are admitted past it
+   until it has waited bypass_ms, after which nothing passes it.  A
+   mixed-precision solve (which reads its convergence flag back after every
+   refinement sweep) is enqueued by a worker thread of the server, so this
+   call never waits for a refinement.  wait = 1 blocks until at least one
+   request finishes when any is running.  Returns the number of requests
+   queued or running. */
 TSQR_API int tsqr_server_progress(tsqr_server s, int wait);
 /* 1 when the request's outputs are written, 0 while pending, < 0 on error. */
 TSQR_API int tsqr_server_status(tsqr_server s, int64_t ticket);

@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 TREE_FLAT = 0
 TREE_BINARY = 2
 TREE_QUAD = 4
+XCDS = 8          # clusters of the hierarchical GPU tree: domain d on XCD d mod 8
 
 
 def build(force: bool = False) -> str:
@@ -145,6 +146,27 @@ def schedule(P: int, tree: int):
     sr = np.zeros(max(P - 1, 1), dtype=np.int64)
     cnt = int(lib().or_schedule(P, tree, _ip(sl), _ip(sr)))
     return list(zip(sl[:cnt].tolist(), sr[:cnt].tolist()))
+
+
+def hierarchical_schedule(group):
+    """Grid-tuned reduction tree (Sec. 2.3, Fig. 2; Sec. 3): domain d
+    belongs to cluster group[d]; the domains of each cluster are reduced by a
+    binary tree over its members in increasing order (the result in the
+    smallest), then the cluster roots by a binary tree in increasing order
+    of their indices.  Returns the (left, right) combines, cluster by
+    cluster, then across clusters; only one combine per cluster boundary
+    of that last tree, G - 1 in all, joins two clusters."""
+    members = {}
+    for d, g in enumerate(group):
+        members.setdefault(g, []).append(d)
+    sched = []
+    roots = []
+    for g in sorted(members, key=lambda g: members[g][0]):
+        mem = members[g]
+        sched += [(mem[l], mem[r]) for l, r in schedule(len(mem), TREE_BINARY)]
+        roots.append(mem[0])
+    sched += [(roots[l], roots[r]) for l, r in schedule(len(roots), TREE_BINARY)]
+    return sched
 
 
 class TSQR:

@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(_HERE, "libtsqr.so")
 TREE_FLAT = 0
 TREE_BINARY = 2
 TREE_QUAD = 4
+TREE_XCD = 8
 F64 = 0
 MIXED = 1
 
@@ -77,7 +78,7 @@ class ServerOpts(ctypes.Structure):
         ("cache", ctypes.c_int32),
         ("prec", ctypes.c_int32),
         ("tree", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("bypass_ms", ctypes.c_int32),
     ]
 
 
@@ -135,6 +136,7 @@ def lib():
         L.tsqr_factor_solve.argtypes = [i64, i64, vp, i64, op, vp, sz, i64, vp, i64, vp, i64, vp, vp, vp,
                                         i64, vp, ctypes.POINTER(vp)]
         L.tsqr_last_refine_iters.argtypes = [vp, vp]
+        L.tsqr_lsq_backward_error.argtypes = [vp, i64, vp, vp]
         L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(i64)]
         L.tsqr_tree_schedule.argtypes = [i64, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
@@ -179,7 +181,7 @@ def lib():
                      "tsqr_server_times", "tsqr_server_get_stats", "tsqr_server_free"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("tsqr_factor", "tsqr_get_r", "tsqr_apply_qt", "tsqr_apply_q", "tsqr_form_q",
-                     "tsqr_lsq_solve", "tsqr_last_refine_iters", "tsqr_plan_info", "tsqr_free",
+                     "tsqr_lsq_solve", "tsqr_last_refine_iters", "tsqr_lsq_backward_error", "tsqr_plan_info", "tsqr_free",
                      "tsqr_batch_create", "tsqr_batch_bad_item", "tsqr_batch_run", "tsqr_batch_plan",
                      "tsqr_batch_launches", "tsqr_batch_free", "tsqr_autotune"):
             getattr(L, name).restype = ctypes.c_int
@@ -363,6 +365,14 @@ class Factors:
                                     ctypes.c_void_p(info.data_ptr()), _stream(stream)),
                "tsqr_lsq_solve")
         return X, resid, info
+
+    def backward_error(self, k: int, stream=None) -> torch.Tensor:
+        """Backward-error bounds (device, k doubles) of the last mixed-precision
+        least-squares solve on this factor."""
+        eta = torch.empty(k, dtype=torch.float64, device=self.work.device)
+        _check(lib().tsqr_lsq_backward_error(self._h, k, ctypes.c_void_p(eta.data_ptr()), _stream(stream)),
+               "tsqr_lsq_backward_error")
+        return eta
 
     def last_refine_iters(self, stream=None) -> int:
         return int(lib().tsqr_last_refine_iters(self._h, _stream(stream)))
@@ -560,11 +570,11 @@ class Server:
     the server keeps references to them."""
 
     def __init__(self, hbm_budget: int = 8 << 30, streams: int = 4, max_inflight: int = 16,
-                 cache: bool = True, prec: int = F64, tree: int = TREE_BINARY):
+                 cache: bool = True, prec: int = F64, tree: int = TREE_BINARY, bypass_ms: int = 0):
         o = ServerOpts()
         lib().tsqr_server_default_opts(ctypes.byref(o))
         o.hbm_budget, o.streams, o.max_inflight = hbm_budget, streams, max_inflight
-        o.cache, o.prec, o.tree = 1 if cache else 0, prec, tree
+        o.cache, o.prec, o.tree, o.bypass_ms = 1 if cache else 0, prec, tree, bypass_ms
         h = ctypes.c_void_p()
         _check(lib().tsqr_server_create(ctypes.byref(o), ctypes.byref(h)), "tsqr_server_create")
         self._h = h

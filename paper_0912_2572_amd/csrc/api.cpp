@@ -9,16 +9,9 @@
 #include <mutex>
 #include <new>
 
+#include "handle.h"
 #include "kernels.h"
 #include "plan.h"
-
-struct tsqr_factors_s {
-    tsqr::Plan plan;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    int keep_q = 1;
-    int last_refine = 0;
-};
 
 namespace {
 
@@ -89,13 +82,13 @@ int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int
     if (trans) {
         TRY(leaf_apply(f, p, Bsrc, ldbs, B, ldb, k, 1, st));
         for (const auto &L : levels) {
-            TreeArgs ta{L.stride, L.span, L.chains};
+            TreeArgs ta{L.stride, L.span, L.chains, L.width};
             TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 1, st));
         }
     } else {
         if (Bsrc != B) TRY(tsqr::launch_copy(Bsrc, ldbs, B, ldb, p.m, k, st));
         for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
-            TreeArgs ta{it->stride, it->span, it->chains};
+            TreeArgs ta{it->stride, it->span, it->chains, it->width};
             TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, B, ldb, k, 0, st));
         }
         TRY(leaf_apply(f, p, B, ldb, B, ldb, k, 0, st));
@@ -142,10 +135,14 @@ TSQR_API int tsqr_plan_info(int64_t m, int64_t n, const tsqr_opts *o, int64_t *n
     return 0;
 }
 
-TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, const tsqr_opts *o,
-                         void *dwork, size_t work_bytes, void *stream, tsqr_factors *out) {
-    if (!out) return -9;
-    *out = nullptr;
+}  // extern "C"
+
+static int factor_enqueue(tsqr_factors_s *f, const double *A, int64_t lda, hipStream_t st);
+
+// tsqr_factor into a caller-provided handle (which this call fills in);
+// the handle's owner frees nothing here.
+int tsqr::factor_into(tsqr_factors_s *f, int64_t m, int64_t n, const double *A, int64_t lda,
+                      const tsqr_opts *o, void *dwork, size_t work_bytes, hipStream_t st) {
     tsqr_opts defaults;
     tsqr_default_opts(&defaults);
     if (!o) o = &defaults;
@@ -156,13 +153,38 @@ TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, con
     if (lda < m) return -4;
     if (!dwork || work_bytes < plan.total || (reinterpret_cast<uintptr_t>(dwork) % tsqr::kAlign))
         return TSQR_ERR_WORKSPACE;
-    tsqr_factors_s *f = new (std::nothrow) tsqr_factors_s;
-    if (!f) return TSQR_ERR_WORKSPACE;
     f->plan = plan;
     f->ws = static_cast<char *>(dwork);
     f->ws_bytes = work_bytes;
     f->keep_q = o->keep_q ? 1 : 0;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    f->last_refine = 0;
+    f->last_k = 0;
+    return factor_enqueue(f, A, lda, st);
+}
+
+extern "C" {
+
+TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, const tsqr_opts *o,
+                         void *dwork, size_t work_bytes, void *stream, tsqr_factors *out) {
+    if (!out) return -9;
+    *out = nullptr;
+    tsqr_factors_s *f = new (std::nothrow) tsqr_factors_s;
+    if (!f) return TSQR_ERR_WORKSPACE;
+    const int rc = tsqr::factor_into(f, m, n, A, lda, o, dwork, work_bytes, static_cast<hipStream_t>(stream));
+    if (rc) {
+        delete f;
+        return rc;
+    }
+    *out = f;
+    return 0;
+}
+
+}  // extern "C"
+
+// The kernels of a factorization whose handle is filled in (plan, workspace).
+static int factor_enqueue(tsqr_factors_s *f, const double *A, int64_t lda, hipStream_t st) {
+    const Plan &plan = f->plan;
+    const int64_t m = plan.m, n = plan.n;
     double *W = at<double>(f, plan.off_w);
     double *R = at<double>(f, plan.off_r);
     double *dsign = at<double>(f, plan.off_d);
@@ -184,13 +206,13 @@ TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, con
         double *Rdom = at<double>(f, p.off_rdom);
         double *Tnode = at<double>(f, p.off_tnode);
         hipError_t e =
-            (o->prec == TSQR_MIXED)
+            (plan.opts.prec == TSQR_MIXED)
                 ? tsqr::launch_leaf32(src_p, lds, at<float>(f, plan.off_w32) + (V - W), m,
                                       at<double>(f, p.off_tc), Rdom, pa, keep, st)
                 : tsqr::launch_leaf(src_p, lds, V, m, at<double>(f, p.off_tc), Rdom, pa, keep, st);
         for (const auto &L : tsqr::tree_levels(p.P, p.tree)) {
             if (e != hipSuccess) break;
-            TreeArgs ta{L.stride, L.span, L.chains};
+            TreeArgs ta{L.stride, L.span, L.chains, L.width};
             e = tsqr::launch_tree_level(Rdom, Tnode, pa, ta, keep, st);
         }
         if (e == hipSuccess)
@@ -214,13 +236,10 @@ TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda, con
             if (e != hipSuccess) err = hip_code(e);
         }
     }
-    if (err) {
-        delete f;
-        return err;
-    }
-    *out = f;
-    return 0;
+    return err;
 }
+
+extern "C" {
 
 TSQR_API int tsqr_get_r(tsqr_factors f, double *R, int64_t ldr, void *stream) {
     int rc = validate_handle(f, false);
@@ -269,6 +288,16 @@ static int apply_q_impl(tsqr_factors_s *f, int64_t k, double *B, int64_t ldb, bo
     return 0;
 }
 
+// Backward-error bounds of the last mixed solve (lsq_max_rhs doubles in the
+// refinement scratch, after the partial sums and the sweep history).
+static double *mixed_eta(const tsqr_factors_s *f) {
+    const Plan &P = f->plan;
+    const int kmax = P.opts.lsq_max_rhs < 8 ? P.opts.lsq_max_rhs : 8;
+    double *Xw = at<double>(f, P.off_ref);
+    return Xw + (size_t)P.n * kmax + (size_t)tsqr::kRefineBlocks * P.n * kmax +
+           (size_t)tsqr::kRefineBlocks * 2 * kmax + 2 * (size_t)kmax;
+}
+
 // Mixed-precision least squares: Bjorck refinement of the augmented system
 // [I A; A^T 0][r; x] = [b; 0] from r = 0, x = 0, so the first sweep is the
 // plain solve through the mixed factor.  Per sweep (groups of at most 8
@@ -291,8 +320,9 @@ static int lsq_solve_mixed(tsqr_factors_s *f, const double *A, int64_t lda, int6
     double *Xw = at<double>(f, P.off_ref);
     double *gpart = Xw + (size_t)n * kmax;
     double *rpart = gpart + (size_t)tsqr::kRefineBlocks * n * kmax;
-    double *hist = rpart + (size_t)tsqr::kRefineBlocks * kmax;
-    int32_t *status = reinterpret_cast<int32_t *>(hist + kmax);
+    double *hist = rpart + (size_t)tsqr::kRefineBlocks * 2 * kmax;   // rel (kmax), ||g|| (kmax)
+    double *eta = mixed_eta(f);
+    int32_t *status = reinterpret_cast<int32_t *>(eta + P.opts.lsq_max_rhs);
     const double *Rf = at<double>(f, P.off_r);
     int sweeps_max = 0;
     for (int64_t c0 = 0; c0 < k; c0 += kmax) {
@@ -307,7 +337,7 @@ static int lsq_solve_mixed(tsqr_factors_s *f, const double *A, int64_t lda, int6
             int rc = tsqr_apply_qt(f, kg, F, m, st);
             if (rc) return rc;
             TRY(tsqr::launch_lsq_refine(Rf, n, F, m, kg, gpart, nb, Xw, n, P.opts.refine_tol, status, hist,
-                                        st));
+                                        hist + kmax, st));
             int32_t hs[2] = {0, 0};
             TRY(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
             TRY(hipStreamSynchronize(st));
@@ -319,9 +349,10 @@ static int lsq_solve_mixed(tsqr_factors_s *f, const double *A, int64_t lda, int6
         }
         if (sweeps > sweeps_max) sweeps_max = sweeps;
         TRY(tsqr::launch_mixed_final(Rf, n, kg, Xw, X + c0 * ldx, ldx, resid ? resid + c0 : nullptr, dinfo,
-                                     c0 > 0 ? 1 : 0, rpart, nb, st));
+                                     c0 > 0 ? 1 : 0, rpart, nb, hist + kmax, eta + c0, st));
     }
     f->last_refine = sweeps_max;
+    f->last_k = k;
     return 0;
 }
 
@@ -351,8 +382,9 @@ static int form_q_single_panel(tsqr_factors_s *f, double *Q, int64_t ldq, hipStr
         // the top levels in one launch, one workgroup per path to a left of
         // level lstop - 1 (at most kTopPaths of them); the rest level by level
         constexpr int64_t kTopPaths = 32;
+        // (the path walk assumes one left per span: not for the XCD tree)
         int lstop = nlev;
-        for (int L = 0; L < nlev; ++L)
+        for (int L = 0; L < nlev && p.tree != TSQR_TREE_XCD; ++L)
             if ((p.P + levels[L].stride - 1) / levels[L].stride <= kTopPaths) {
                 lstop = L;
                 break;
@@ -371,7 +403,7 @@ static int form_q_single_panel(tsqr_factors_s *f, double *Q, int64_t ldq, hipStr
             TRY(tsqr::launch_seed_root(S, p.n, dsign, st));
         }
         for (int L = lstop - 1; L >= 0; --L) {
-            TreeArgs ta{levels[L].stride, levels[L].span, levels[L].chains};
+            TreeArgs ta{levels[L].stride, levels[L].span, levels[L].chains, levels[L].width};
             TRY(tsqr::launch_tree_down(at<double>(f, p.off_rdom), at<double>(f, p.off_tnode), S, pa, ta,
                                        st));
         }
@@ -480,7 +512,7 @@ int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t
     TRY(tsqr::launch_copy(B, ldb, C, P.m, P.m, k, fj.aux));
     TRY(leaf_apply(f, p, C, P.m, C, P.m, k, 1, fj.aux));
     for (const auto &L : levels) {
-        TreeArgs ta{L.stride, L.span, L.chains};
+        TreeArgs ta{L.stride, L.span, L.chains, L.width};
         TRY(tsqr::launch_tree_level(Rdom, Tnode, pa, ta, 1, st));
     }
     TRY(tsqr::launch_sign_normalise(Rdom, p.n, at<double>(f, P.off_r), P.n, p.row_off, p.col_off,
@@ -488,7 +520,7 @@ int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t
     TRY(hipEventRecord(fj.tree, st));
     TRY(hipStreamWaitEvent(fj.aux, fj.tree, 0));
     for (const auto &L : levels) {
-        TreeArgs ta{L.stride, L.span, L.chains};
+        TreeArgs ta{L.stride, L.span, L.chains, L.width};
         TRY(tsqr::launch_tree_apply(Rdom, Tnode, pa, ta, C, P.m, k, 1, fj.aux));
     }
     // rows 0..n-1 of Q^T B for the sign-normalised Q (as tsqr_apply_qt)
@@ -571,6 +603,17 @@ TSQR_API int tsqr_factor_solve(int64_t m, int64_t n, const double *A, int64_t ld
     return 0;
 }
 
+TSQR_API int tsqr_lsq_backward_error(tsqr_factors f, int64_t k, double *eta, void *stream) {
+    int rc = validate_handle(f, true);
+    if (rc) return rc;
+    if (!is_mixed(f) || !f->last_k) return TSQR_ERR_STATE;
+    if (k < 1 || k > f->last_k) return -2;
+    if (!eta) return -3;
+    const hipError_t e = hipMemcpyAsync(eta, mixed_eta(f), sizeof(double) * (size_t)k, hipMemcpyDeviceToDevice,
+                                        static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
 TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream) {
     (void)stream;
     return f ? f->last_refine : -1;
@@ -578,7 +621,8 @@ TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream) {
 
 TSQR_API int64_t tsqr_tree_schedule(int64_t P, int tree, int64_t *left, int64_t *right, int64_t cap) {
     if (P < 1) return -1;
-    if (tree != TSQR_TREE_FLAT && tree != TSQR_TREE_BINARY && tree != TSQR_TREE_QUAD) return -2;
+    if (tree != TSQR_TREE_FLAT && tree != TSQR_TREE_BINARY && tree != TSQR_TREE_QUAD && tree != TSQR_TREE_XCD)
+        return -2;
     auto s = tsqr::tree_schedule(P, tree);
     for (int64_t i = 0; i < (int64_t)s.size() && i < cap; ++i) {
         if (left) left[i] = s[i].first;

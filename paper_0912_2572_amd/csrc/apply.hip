@@ -309,7 +309,9 @@ __global__ __launch_bounds__(256) void k_tree_apply(const double *__restrict__ R
     // A latency-bound chain that may share CUs with a thin Q's top-down tree:
     // its waves take the issue slots first.
     __builtin_amdgcn_s_setprio(3);
-    tree_apply_chain(sm, Rdom, Tnode, pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, B, ldb, k,
+    const int64_t left = tree_left(ta, blockIdx.x);
+    if (left >= pa.P) return;
+    tree_apply_chain(sm, Rdom, Tnode, pa, left, ta.stride, ta.span, B, ldb, k,
                      trans, blockIdx.y);
 }
 
@@ -325,7 +327,9 @@ __global__ __launch_bounds__(256) void k_tree_apply_b(const BMat *__restrict__ m
     if (sweep > 0 && M.status[1]) return;
     const TreeArgs ta = M.lev[trans ? step : M.nlev - 1 - step];
     if ((int64_t)blockIdx.x >= ta.chains) return;
-    tree_apply_chain(sm, M.Rdom, M.Tnode, M.pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, M.F,
+    const int64_t left = tree_left(ta, blockIdx.x);
+    if (left >= M.pa.P) return;
+    tree_apply_chain(sm, M.Rdom, M.Tnode, M.pa, left, ta.stride, ta.span, M.F,
                      M.pa.m, 1, trans, 0);
 }
 

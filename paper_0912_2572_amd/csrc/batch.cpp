@@ -87,8 +87,8 @@ int plan_matrix(const tsqr_batch_item &it, int64_t mb, int tree, MatPlan *mp) {
     if (it.prec) b += align_up(sizeof(double) * m);                          // Rr
     b += align_up(sizeof(double) * n);                                       // Xw
     if (it.prec) b += align_up(sizeof(double) * nb * n);                     // gpart
-    b += align_up(sizeof(double) * nb);                                      // rpart
-    b += align_up(sizeof(double) * 2 + sizeof(int32_t) * 2);                 // hist, status
+    b += align_up(sizeof(double) * 2 * nb);                                  // rpart
+    b += align_up(sizeof(double) * 3 + sizeof(int32_t) * 2);                 // hist, status
     b += 2 * align_up(sizeof(double) * n * (size_t)p.total_chunks);         // Pc, Zc
     mp->bytes = b;
     return 0;
@@ -331,10 +331,10 @@ TSQR_API int tsqr_batch_create(int count, const tsqr_batch_item *items, const ts
         if (it.prec) M.Rr = reinterpret_cast<double *>(take(sizeof(double) * m));
         M.Xw = reinterpret_cast<double *>(take(sizeof(double) * n));
         if (it.prec) M.gpart = reinterpret_cast<double *>(take(sizeof(double) * (size_t)nb * n));
-        M.rpart = reinterpret_cast<double *>(take(sizeof(double) * (size_t)nb));
-        char *hs = take(sizeof(double) * 2 + sizeof(int32_t) * 2);
+        M.rpart = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)nb));
+        char *hs = take(sizeof(double) * 3 + sizeof(int32_t) * 2);
         M.hist = reinterpret_cast<double *>(hs);
-        M.status = reinterpret_cast<int32_t *>(hs + 2 * sizeof(double));
+        M.status = reinterpret_cast<int32_t *>(hs + 3 * sizeof(double));
         M.Pc = reinterpret_cast<double *>(take(sizeof(double) * n * (size_t)p.total_chunks));
         M.Zc = reinterpret_cast<double *>(take(sizeof(double) * n * (size_t)p.total_chunks));
         M.tchunks = p.total_chunks;
@@ -355,7 +355,7 @@ TSQR_API int tsqr_batch_create(int count, const tsqr_batch_item *items, const ts
             return -2;
         }
         M.nlev = (int)lv.size();
-        for (int l = 0; l < M.nlev; ++l) M.lev[l] = tsqr::TreeArgs{lv[l].stride, lv[l].span, lv[l].chains};
+        for (int l = 0; l < M.nlev; ++l) M.lev[l] = tsqr::TreeArgs{lv[l].stride, lv[l].span, lv[l].chains, lv[l].width};
         B->mb[i] = p.mb;
         B->tree[i] = p.tree;
         B->P[i] = p.P;

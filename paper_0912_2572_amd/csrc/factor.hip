@@ -32,42 +32,49 @@
 
 namespace tsqr {
 
-constexpr int kWaves = 4;                  // waves per leaf/tree workgroup
+constexpr int kWaves = 4;                  // waves per tree workgroup (and narrow leaves)
 constexpr int kFactorThreads = 64 * kWaves;
-constexpr int kRowGroups = 4 * kWaves;     // row groups per workgroup
+constexpr int kRowGroups = 4 * kWaves;     // row groups per 4-wave workgroup
 
-// Thread index as the step code uses it: for narrow panels (NS <= 2, two
-// workgroups per CU, 256 registers) hidden from the optimizer so that
-// loop-invariant addresses are not hoisted into spills; the wide kernel has
-// the AGPRs to keep them.
+// Thread index as the step code uses it: for kernels that run two waves per
+// SIMD (NS = 2: two workgroups per CU; an 8-wave leaf: two waves of one
+// workgroup), 256 registers each, hidden from the optimizer so that
+// loop-invariant addresses and masks are not hoisted into spills; a 4-wave
+// wide kernel has the AGPRs to keep them.
 template <int NS>
-__device__ __forceinline__ int step_tid() { return NS == 2 ? local_tid() : (int)threadIdx.x; }
+__device__ __forceinline__ int step_tid() {
+    return (NS == 2 || leaf_waves(NS) > kWaves) ? local_tid() : (int)threadIdx.x;
+}
 
-// LDS of the leaf and tree kernels (about 75 KiB).
-struct FactorSmem {
+// LDS of the leaf and tree kernels with W waves per workgroup (about 75 KiB
+// for 4 waves, 83 KiB for 8).
+template <int W>
+struct FactorSmemT {
     double R[64 * kLdsStride];   // running triangle, row-major
     double T[64 * kLdsStride];   // upper: T of the chunk; strictly lower: Gram G^T
     union {
         struct {
-            double red[2][64][kWaves];    // per-wave partial dots, double-buffered
-            double redq[2][64][kWaves];   // per-wave pivot-row values (first chunk only)
+            double red[2][64][W];    // per-wave partial dots, double-buffered
+            double redq[2][64][W];   // per-wave pivot-row values (first chunk only)
         } s;
-        double P[64 * 16];                // scratch of the blocked T build
+        double P[64 * 16];           // scratch of the blocked T build
     } u;
     double tau[64];
     double scl[64];   // reflector scale s_j of a later chunk's column j
 };
+using FactorSmem = FactorSmemT<kWaves>;
 
 // Gram entry G[k][j] = y_k . y_j (k < j), kept in the lower triangle of T.
-__device__ __forceinline__ double &gram(FactorSmem &sm, int k, int j) { return sm.T[j * kLdsStride + k]; }
+template <int W>
+__device__ __forceinline__ double &gram(FactorSmemT<W> &sm, int k, int j) { return sm.T[j * kLdsStride + k]; }
 
 // G[k][j] (k < j) at step j from d = x . c_k, with s = s_j.  First chunk:
 // c_k is the scaled reflector y_k below the pivot rows and e its pivot-row
 // entry, so G = e + s d.  Later chunk: the reflector column c_k is still
 // unscaled (y_k = [e_k; s_k c_k]) and y_k, y_j share no R-part entry, so
 // G = s_k (s d).
-template <bool FIRST>
-__device__ __forceinline__ double gram_entry(const FactorSmem &sm, int k, double s, double d, double e) {
+template <bool FIRST, int W>
+__device__ __forceinline__ double gram_entry(const FactorSmemT<W> &sm, int k, double s, double d, double e) {
     if constexpr (FIRST) return fma(s, d, e);
     else return sm.scl[k] * (s * d);
 }
@@ -80,7 +87,9 @@ __device__ __forceinline__ double gram_entry(const FactorSmem &sm, int k, double
 // from the block form of the same recurrence,
 //     T[0:16J, J] = -T[0:16J, 0:16J] (G[0:16J, J] T_JJ),
 // as FP64 MFMA tiles.
-__device__ __forceinline__ void build_t(FactorSmem &sm, const int n) {
+// Waves past the fourth (8-wave leaves) take part in the barriers only.
+template <int W>
+__device__ __forceinline__ void build_t(FactorSmemT<W> &sm, const int n) {
     const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int j0 = 16 * w;
     double trow[16];
@@ -198,14 +207,15 @@ struct StepState {
 
 // Total of column k over the waves' partials, in a fixed order, so every
 // thread that needs column k's total computes the same bits.
-__device__ __forceinline__ double col_total(const double (&a)[2][64][kWaves], int par, int k) {
+template <int W>
+__device__ __forceinline__ double col_total(const double (&a)[2][64][W], int par, int k) {
     const double2 *p = reinterpret_cast<const double2 *>(&a[par][k][0]);
-    double2 v[kWaves / 2];
+    double2 v[W / 2];
 #pragma unroll
-    for (int h = 0; h < kWaves / 2; ++h) v[h] = p[h];
+    for (int h = 0; h < W / 2; ++h) v[h] = p[h];
     double s = v[0].x + v[0].y;
 #pragma unroll
-    for (int h = 1; h < kWaves / 2; ++h) s = (s + v[h].x) + v[h].y;
+    for (int h = 1; h < W / 2; ++h) s = (s + v[h].x) + v[h].y;
     return s;
 }
 
@@ -231,10 +241,15 @@ __device__ __forceinline__ double read_lane(double v, int src) {
 // The next column's pre-update values are fetched into xn from their owner
 // lanes before the barrier, and every thread applies step j's update to
 // them itself (the same fma as the owner), so the next step needs no
-// shuffle on its critical path.
-template <int NS, int RPT, int TJ, bool FIRST>
+// shuffle on its critical path.  The 8-wave leaf (lean steps) has no
+// registers for xn: it fetches column j from its owner lanes at the start
+// of step j, and the other wave on its SIMD covers that latency.
+template <int NS, int W>
+constexpr bool lean_steps() { return W > kWaves; }
+
+template <int NS, int RPT, int TJ, bool FIRST, int W>
 __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[RPT][NS],
-                                         const int n, FactorSmem &sm, const bool want_t,
+                                         const int n, FactorSmemT<W> &sm, const bool want_t,
                                          double (&x)[RPT], double (&xn)[RPT], double (&rnew)[NS],
                                          int &jprev) {
     const int tid = step_tid<NS>();
@@ -246,6 +261,13 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     // branches, so the wave keeps one execution mask.
     const bool own_j = FIRST && (rgw == j / RPT);
     const int ij = j % RPT;
+    constexpr bool LEAN = lean_steps<NS, W>();
+    if constexpr (LEAN) {
+        // column j (after step j - 1's update) from its owner lanes
+        const int src = (rg << 4) | q;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) x[i] = __shfl(c[i][TJ], src);
+    }
     double qv[NS];
     if (FIRST) {
 #pragma unroll
@@ -259,7 +281,8 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         }
     }
     // prefetch column j + 1 (pre-update) from its owner lane
-    if (q < 15) {
+    if constexpr (LEAN) {
+    } else if (q < 15) {
         const int src = (rg << 4) | (q + 1);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) xn[i] = __shfl(c[i][TJ], src);
@@ -304,7 +327,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     double alpha = 0.0, en = 0.0, ev[NS];
     if (!FIRST) {
         alpha = sm.R[j * kLdsStride + j];
-        en = (j + 1 < n) ? sm.R[j * kLdsStride + j + 1] : 0.0;
+        if constexpr (!LEAN) en = (j + 1 < n) ? sm.R[j * kLdsStride + j + 1] : 0.0;
 #pragma unroll
         for (int t = 0; t < NS; ++t) ev[t] = sm.R[j * kLdsStride + cg + 16 * t];
     }
@@ -354,15 +377,15 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         else return read_lane(v[TJ], q < 15 ? q + 1 : q);
     };
     const double sig2 = at_j(dv, tot);
-    const double dn = has_next ? at_next(dv, tot) : 0.0;
+    const double dn = (has_next && !LEAN) ? at_next(dv, tot) : 0.0;
     if (FIRST) {
         alpha = at_j(ev, totq);
-        if (has_next) en = at_next(ev, totq);
+        if (has_next && !LEAN) en = at_next(ev, totq);
     }
     double beta, tau, s;
     householder_scalars(alpha, sig2, beta, tau, s);
     // the next column after this step's update (same fma as its owner)
-    {
+    if constexpr (!LEAN) {
         const double fn = (tau * fma(s, dn, en)) * s;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -379,7 +402,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         const double d = dv[t];
         const double e = ev[t];
         if (t < TJ) {
-            if (want_t && rgw == 0) gram(sm, k, j) = gram_entry<FIRST>(sm, k, s, d, e);
+            if (want_t && rgw == 0) gram(sm, k, j) = gram_entry<FIRST, W>(sm, k, s, d, e);
             continue;
         }
         const double wv = fma(s, d, e);
@@ -408,7 +431,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
                 for (int i = 0; i < RPT; ++i) c[i][t] = fma(-f, x[i], c[i][t]);
             }
             rnew[t] = upd ? e - tau * wv : beta;
-            if (want_t && rgw == 0 && cg < q) gram(sm, k, j) = gram_entry<FIRST>(sm, k, s, d, e);
+            if (want_t && rgw == 0 && cg < q) gram(sm, k, j) = gram_entry<FIRST, W>(sm, k, s, d, e);
         }
     }
     if (tid == 0) {
@@ -420,33 +443,39 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
 
 // Column steps j = 16 TJ .. 16 TJ + 15 (< n), two at a time so that the
 // current and next column buffers swap roles without copies.
-template <int NS, int RPT, int TJ, bool FIRST>
-__device__ __forceinline__ void qr_steps(double (&c)[RPT][NS], const int n, FactorSmem &sm,
+template <int NS, int RPT, int TJ, bool FIRST, int W>
+__device__ __forceinline__ void qr_steps(double (&c)[RPT][NS], const int n, FactorSmemT<W> &sm,
                                          const bool want_t, StepState<NS, RPT> &ss) {
 #pragma unroll 1
     for (int q = 0; q < 16; q += 2) {
         const int j = TJ * 16 + q;
         if (j >= n) return;
-        one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
-        if (j + 1 >= n) return;
-        one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
+        if constexpr (lean_steps<NS, W>()) {
+            one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xa, ss.rnew, ss.jprev);
+            if (j + 1 >= n) return;
+            one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xa, ss.xa, ss.rnew, ss.jprev);
+        } else {
+            one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
+            if (j + 1 >= n) return;
+            one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
+        }
     }
 }
 
 // Slot TJ's steps, after part TJ of the previous chunk's staged reflectors
 // (if any) has been sent to memory.
-template <int NS, int RPT, int TJ, bool FIRST>
-__device__ __forceinline__ void qr_slot(double (&c)[RPT][NS], const int n, FactorSmem &sm,
+template <int NS, int RPT, int TJ, bool FIRST, int W>
+__device__ __forceinline__ void qr_slot(double (&c)[RPT][NS], const int n, FactorSmemT<W> &sm,
                                         const bool want_t, StepState<NS, RPT> &ss, const Drain dr) {
-    if constexpr (NS == 4) {
+    if constexpr (NS == 4 && W == kWaves) {
         if (dr.dst != nullptr) drain_part(dr, TJ);
     }
     qr_steps<NS, RPT, TJ, FIRST>(c, n, sm, want_t, ss);
 }
 
-template <int NS, int RPT, bool FIRST, int... TJ>
+template <int NS, int RPT, bool FIRST, int W, int... TJ>
 __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
-                                             double (&c)[RPT][NS], const int n, FactorSmem &sm,
+                                             double (&c)[RPT][NS], const int n, FactorSmemT<W> &sm,
                                              const bool want_t, StepState<NS, RPT> &ss, const Drain dr) {
     (qr_slot<NS, RPT, TJ, FIRST>(c, n, sm, want_t, ss, dr), ...);
 }
@@ -456,17 +485,19 @@ __device__ __forceinline__ void qr_all_steps(std::integer_sequence<int, TJ...>,
 // on and above the diagonal of a first chunk, whose unit diagonal is
 // implicit), sm.R the updated triangle and, if want_t, the upper triangle
 // of sm.T the chunk's T.
-template <int NS, int RPT, bool FIRST>
+template <int NS, int RPT, bool FIRST, int W>
 __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
-                                         FactorSmem &sm, const bool want_t,
+                                         FactorSmemT<W> &sm, const bool want_t,
                                          const Drain dr = Drain{nullptr, nullptr, 0, 0}) {
     const int tid = step_tid<NS>();
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     StepState<NS, RPT> ss;
+    if constexpr (!lean_steps<NS, W>()) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
-    qr_all_steps<NS, RPT, FIRST>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss, dr);
+        for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
+    }
+    qr_all_steps<NS, RPT, FIRST, W>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss, dr);
     __syncthreads();
     if (ss.jprev >= 0 && rgw == 0) {
 #pragma unroll
@@ -499,13 +530,13 @@ __device__ __forceinline__ bool rows_aligned(const T *p, int64_t ld) {
 
 // Loads rows [0, valid) x columns [0, n) of a chunk at src (ld) into c
 // (zeros elsewhere).
-template <int NS, int RPT>
+template <int NS, int RPT, int W = kWaves>
 __device__ __forceinline__ void load_chunk(double (&c)[RPT][NS],
                                            const double *__restrict__ src, int64_t ld, int64_t valid,
                                            int n) {
     const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
-    const bool full = valid >= (int64_t)RPT * kRowGroups;
+    const bool full = valid >= (int64_t)RPT * 4 * W;
     const bool vec = full && (RPT % 2 == 0) && rows_aligned(src, ld);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -571,13 +602,13 @@ __device__ __forceinline__ void clear_pad_cols(double (&c)[RPT][NS], int n) {
     }
 }
 
-template <int NS, int RPT, typename OT = double>
+template <int NS, int RPT, typename OT = double, int W = kWaves>
 __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
                                             OT *__restrict__ dst, int64_t ld, int64_t valid, int n,
                                             int t_end = NS) {
     const int tid = step_tid<NS>(), w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
-    const bool full = valid >= (int64_t)RPT * kRowGroups;
+    const bool full = valid >= (int64_t)RPT * 4 * W;
     constexpr int VW = 16 / sizeof(OT);   // elements per 16-byte store
     const bool vec = full && (RPT % VW == 0) && rows_aligned(dst, ld);
 #pragma unroll
@@ -615,7 +646,7 @@ __device__ __forceinline__ void store_chunk(const double (&c)[RPT][NS],
 // Upper triangle of an LDS matrix (row-major) -> column-major n x n with
 // zeros below the diagonal.
 __device__ __forceinline__ void store_tri(const double *lds, double *__restrict__ dst, int n) {
-    for (int e = local_tid(); e < n * n; e += kFactorThreads) {
+    for (int e = local_tid(); e < n * n; e += (int)blockDim.x) {
         const int r = e % n, k = e / n;
         dst[e] = (r <= k) ? lds[r * kLdsStride + k] : 0.0;
     }
@@ -639,13 +670,14 @@ __device__ __forceinline__ void zero_lds(double *lds) {
 // a placeholder that reads 16 bytes).  STAGE (wide FP64 kernel, `stage` =
 // kStageBytes of LDS): half of each full chunk's reflectors are sent to
 // memory during the next chunk's column steps (see Drain).
-template <int NS, typename VT, bool VEC, bool STAGE = false>
-__device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__restrict__ A, int64_t lda,
+template <int NS, typename VT, bool VEC, bool STAGE = false, int W>
+__device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__restrict__ A, int64_t lda,
                                             VT *__restrict__ V, int64_t ldv, double *__restrict__ Tc,
                                             double *__restrict__ Rdom, const PanelArgs &pa, int keep_q,
                                             int64_t dom, double *stage = nullptr) {
     constexpr int ROWS = chunk_rows(NS);
     constexpr int RPT = rows_per_thread(NS);
+    static_assert(ROWS == 4 * W * RPT, "workgroup shape");
     const int64_t row0 = dom * pa.mb;
     const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
     const int64_t nfull = nrows / ROWS;          // full chunks
@@ -659,10 +691,10 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
     double c[RPT][NS];
     if (nfull == 0) {
         // a domain shorter than one chunk
-        load_chunk<NS, RPT>(c, A + row0, lda, tail, n);
+        load_chunk<NS, RPT, W>(c, A + row0, lda, tail, n);
         chunk_qr<NS, RPT, true>(c, n, sm, want_t);
         if (want_t) {
-            store_chunk<NS, RPT, VT>(c, V + row0, ldv, tail, n);
+            store_chunk<NS, RPT, VT, W>(c, V + row0, ldv, tail, n);
             build_t(sm, n);
             store_tri(sm.T, Tc + dom * pa.cpd * nn, n);
         }
@@ -675,7 +707,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
         issue_full_chunk<NS, RPT, VEC>(c, A + row0, lda, n);
         for (int64_t ch = 0; ch < nch; ++ch) {
             const int64_t r0 = row0 + ch * ROWS;
-            if (ch == nfull) load_chunk<NS, RPT>(c, A + r0, lda, tail, n);
+            if (ch == nfull) load_chunk<NS, RPT, W>(c, A + r0, lda, tail, n);
             else clear_pad_cols<NS, RPT>(c, n);
             Drain dr{stage, nullptr, ldv, n};
             if constexpr (STAGE) dr.dst = pend;
@@ -685,7 +717,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
                 bool staged = false;
                 if constexpr (STAGE) {
                     if (staging && ch < nfull) {
-                        store_chunk<NS, RPT, VT>(c, V + r0, ldv, ROWS, n, 2);   // slots 0 and 1
+                        store_chunk<NS, RPT, VT, W>(c, V + r0, ldv, ROWS, n, 2);   // slots 0 and 1
                         stage_slots(stage, c);
                         pend = V + r0;
                         staged = true;
@@ -693,7 +725,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
                         pend = nullptr;
                     }
                 }
-                if (!staged) store_chunk<NS, RPT, VT>(c, V + r0, ldv, ch < nfull ? (int64_t)ROWS : tail, n);
+                if (!staged) store_chunk<NS, RPT, VT, W>(c, V + r0, ldv, ch < nfull ? (int64_t)ROWS : tail, n);
             }
             const bool more = ch + 1 < nfull;
             issue_full_chunk<NS, RPT, VEC>(c, A + row0 + (more ? ch + 1 : 0) * ROWS, lda, n, more);
@@ -712,24 +744,31 @@ __device__ __forceinline__ void leaf_domain(FactorSmem &sm, const double *__rest
 }
 
 // Narrow panels (NS <= 2) fit two workgroups per CU (registers and LDS), which
-// hides step latency whenever there are more domains than CUs.
+// hides step latency whenever there are more domains than CUs; the widest
+// (NS = 4) run 8 waves, two per SIMD, in one workgroup per CU.
 template <int NS>
 constexpr int leaf_min_blocks() { return NS == 2 ? 2 : 1; }
+template <int NS>
+constexpr int leaf_threads() { return 64 * leaf_waves(NS); }
 
-// The wide FP64 leaf stages half of each chunk's reflectors in LDS.
+// A 4-wave wide FP64 leaf could stage half of each chunk's reflectors in
+// LDS; the 8-wave leaf has no LDS to spare for it.
 template <int NS, typename VT>
-constexpr bool leaf_stages() { return NS == 4 && std::is_same<VT, double>::value; }
+constexpr bool leaf_stages() { return NS == 4 && leaf_waves(NS) == kWaves && std::is_same<VT, double>::value; }
+
+template <int NS>
+using LeafSmem = FactorSmemT<leaf_waves(NS)>;
 
 template <int NS, typename VT, bool VEC>
-__global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf(const double *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(leaf_threads<NS>(), leaf_min_blocks<NS>()) void k_leaf(const double *__restrict__ A, int64_t lda,
                                                  VT *__restrict__ V, int64_t ldv,
                                                  double *__restrict__ Tc, double *__restrict__ Rdom,
                                                  PanelArgs pa, int keep_q) {
     extern __shared__ double smem_raw[];
-    FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    LeafSmem<NS> &sm = *reinterpret_cast<LeafSmem<NS> *>(smem_raw);
     constexpr bool S = leaf_stages<NS, VT>();
     leaf_domain<NS, VT, VEC, S>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x,
-                                S ? smem_raw + sizeof(FactorSmem) / sizeof(double) : nullptr);
+                                S ? smem_raw + sizeof(LeafSmem<NS>) / sizeof(double) : nullptr);
 }
 
 // One chain of combines (step 3): left <- qr([R_left; R_right]) for every
@@ -787,7 +826,9 @@ __global__ __launch_bounds__(kFactorThreads) void k_tree(double *__restrict__ Rd
     // The levels are the critical path while a solve's leaf passes share the
     // CUs: the chain's waves take the issue slots first.
     __builtin_amdgcn_s_setprio(3);
-    tree_chain<NS>(sm, Rdom, Tnode, pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, keep_q);
+    const int64_t left = tree_left(ta, blockIdx.x);
+    if (left >= pa.P) return;
+    tree_chain<NS>(sm, Rdom, Tnode, pa, left, ta.stride, ta.span, keep_q);
 }
 
 // R_out = D R_root with D = diag(sgn R_jj), sgn(0) = +1; d_out = diag(D).
@@ -806,14 +847,14 @@ size_t factor_smem_bytes() { return sizeof(FactorSmem); }
 // ---- batched forms: grid.y walks the matrix list, grid.x the domains /
 // chains of the listed matrix (a workgroup past its matrix's count returns).
 template <int NS>
-__global__ __launch_bounds__(kFactorThreads, leaf_min_blocks<NS>()) void k_leaf_b(const BMat *__restrict__ mats,
+__global__ __launch_bounds__(leaf_threads<NS>(), leaf_min_blocks<NS>()) void k_leaf_b(const BMat *__restrict__ mats,
                                                    const int *__restrict__ list) {
     extern __shared__ double smem_raw[];
-    FactorSmem &sm = *reinterpret_cast<FactorSmem *>(smem_raw);
+    LeafSmem<NS> &sm = *reinterpret_cast<LeafSmem<NS> *>(smem_raw);
     const BMat &M = mats[list[blockIdx.y]];
     const int64_t dom = blockIdx.x;
     if (dom >= M.pa.P) return;
-    const bool vec = rows_aligned(M.A, M.lda);
+    const bool vec = rows_aligned(M.A, M.lda) && (M.pa.mb % 2) == 0;
     if (M.prec) {
         if (vec) leaf_domain<NS, float, true>(sm, M.A, M.lda, M.V32, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
         else leaf_domain<NS, float, false>(sm, M.A, M.lda, M.V32, M.pa.m, M.Tc, M.Rdom, M.pa, 1, dom);
@@ -832,7 +873,9 @@ __global__ __launch_bounds__(kFactorThreads) void k_tree_b(const BMat *__restric
     if (level >= M.nlev) return;
     const TreeArgs ta = M.lev[level];
     if ((int64_t)blockIdx.x >= ta.chains) return;
-    tree_chain<NS>(sm, M.Rdom, M.Tnode, M.pa, (int64_t)blockIdx.x * ta.span, ta.stride, ta.span, 1);
+    const int64_t left = tree_left(ta, blockIdx.x);
+    if (left >= M.pa.P) return;
+    tree_chain<NS>(sm, M.Rdom, M.Tnode, M.pa, left, ta.stride, ta.span, 1);
 }
 
 __global__ void k_sign_b(const BMat *__restrict__ mats, const int *__restrict__ list) {
@@ -848,12 +891,12 @@ __global__ void k_sign_b(const BMat *__restrict__ mats, const int *__restrict__ 
 
 template <int NS>
 static hipError_t launch_leaf_b_ns(const BMat *mats, const int *list, int cnt, int64_t gx, hipStream_t st) {
-    const size_t sh = sizeof(FactorSmem);
+    const size_t sh = sizeof(LeafSmem<NS>);
     hipError_t e = hipFuncSetAttribute((const void *)k_leaf_b<NS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     ProfScope ps("batch_leaf_factor", st);
-    hipLaunchKernelGGL(k_leaf_b<NS>, dim3((unsigned)gx, (unsigned)cnt), dim3(kFactorThreads), sh, st, mats,
+    hipLaunchKernelGGL(k_leaf_b<NS>, dim3((unsigned)gx, (unsigned)cnt), dim3(leaf_threads<NS>()), sh, st, mats,
                        list);
     return hipGetLastError();
 }
@@ -901,12 +944,12 @@ template <int NS, typename VT, bool VEC>
 static hipError_t launch_leaf_nsv(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,
                                   double *Rdom, const PanelArgs &pa, int keep_q, const char *tag,
                                   hipStream_t st) {
-    const size_t sh = sizeof(FactorSmem) + (leaf_stages<NS, VT>() ? kStageBytes : 0);
+    const size_t sh = sizeof(LeafSmem<NS>) + (leaf_stages<NS, VT>() ? kStageBytes : 0);
     hipError_t e = hipFuncSetAttribute((const void *)k_leaf<NS, VT, VEC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     ProfScope ps(tag, st);
-    hipLaunchKernelGGL((k_leaf<NS, VT, VEC>), dim3((unsigned)pa.P), dim3(kFactorThreads), sh, st, A, lda, V,
+    hipLaunchKernelGGL((k_leaf<NS, VT, VEC>), dim3((unsigned)pa.P), dim3(leaf_threads<NS>()), sh, st, A, lda, V,
                        ldv, Tc, Rdom, pa, keep_q);
     return hipGetLastError();
 }
@@ -915,7 +958,10 @@ template <int NS, typename VT>
 static hipError_t launch_leaf_ns(const double *A, int64_t lda, VT *V, int64_t ldv, double *Tc,
                                  double *Rdom, const PanelArgs &pa, int keep_q, const char *tag,
                                  hipStream_t st) {
-    const bool vec = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda * (int64_t)sizeof(double)) % 16 == 0;
+    // 16-byte loads need every chunk's first row 16-byte aligned: A itself,
+    // every column start (lda) and every domain start (mb) must be even
+    const bool vec = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda * (int64_t)sizeof(double)) % 16 == 0 &&
+                     (pa.mb % 2) == 0;
     return vec ? launch_leaf_nsv<NS, VT, true>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st)
                : launch_leaf_nsv<NS, VT, false>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
 }

@@ -87,7 +87,8 @@ __global__ __launch_bounds__(256) void k_tree_down(const double *__restrict__ Rd
     FormSmem &sm = *reinterpret_cast<FormSmem *>(smem_raw);
     const int n = pa.n;
     const int64_t nn = (int64_t)n * n;
-    const int64_t left = (int64_t)blockIdx.x * ta.span;
+    const int64_t left = tree_left(ta, blockIdx.x);
+    if (left >= pa.P) return;
     int64_t nr = 0;
     for (int64_t q = 1; q * ta.stride < ta.span && left + q * ta.stride < pa.P; ++q) ++nr;
     {

@@ -25,13 +25,23 @@ inline int64_t max_domain_chunks(const PanelArgs &pa) {
     return last > pa.cpd ? last : pa.cpd;
 }
 
-// One tree level: chains g = 0..chains-1 start at left = g * span and take
-// rights left + q * stride for q = 1.. while q * stride < span and < P.
+// One tree level: chain c = 0..chains-1 starts at
+//     left = (c / width) * span + c % width
+// and takes rights left + q * stride for q = 1.. while q * stride < span and
+// the right is < P (width = 1: left = c * span; the XCD-local levels of the
+// hierarchical tree have width = the XCD count, so that consecutive chains
+// -- dispatched round-robin over the XCDs -- reduce the domains of their own
+// XCD).  A chain whose left is >= P does nothing.
 struct TreeArgs {
     int64_t stride;
     int64_t span;
     int64_t chains;
+    int64_t width = 1;
 };
+
+__host__ __device__ inline int64_t tree_left(const TreeArgs &ta, int64_t c) {
+    return (c / ta.width) * ta.span + c % ta.width;
+}
 
 // All levels of a reduction tree (bottom first), passed by value.
 constexpr int kMaxTreeLevels = 64;
@@ -68,8 +78,8 @@ struct BMat {
     double *Rr;           // m: refined residual (mixed)
     double *Xw;           // n: running solution
     double *gpart;        // nb x n partial A^T r
-    double *rpart;        // nb partial ||b - A x||^2
-    double *hist;         // [0] last relative correction, [1] residual norm (FP64)
+    double *rpart;        // nb x 2 partial ||b - A x||^2 and ||b - r - A x||^2
+    double *hist;         // [0] last relative correction, [1] residual norm (FP64), [2] ||A^T r|| (mixed)
     int32_t *status;      // [0] sweeps done, [1] converged
     PanelArgs pa;
     double *Pc, *Zc;      // per chunk n x 1 blocks of the few-column apply
@@ -150,12 +160,12 @@ hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, cons
                             double *gpart, double *rpart, int nblocks, hipStream_t st);
 hipError_t launch_lsq_refine(const double *R, int n, double *F, int64_t m, int k, const double *gpart,
                              int nblocks, double *X, int64_t ldx, double tol, int32_t *status,
-                             double *hist, hipStream_t st);
+                             double *hist, double *gnorm, hipStream_t st);
 hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st);
 hipError_t launch_status_init(int32_t *status, double *hist, int k, hipStream_t st);
 hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, double *X, int64_t ldx,
                               double *resid, int32_t *dinfo, int merge, const double *rpart, int nblocks,
-                              hipStream_t st);
+                              const double *gnorm, double *eta_out, hipStream_t st);
 
 // batched launches (device descriptor array `mats`, index list `list` of
 // `cnt` entries, `gx` = grid.x as described above)

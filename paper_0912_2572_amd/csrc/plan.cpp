@@ -5,7 +5,9 @@
 // than n rows is merged into the one before it so that every domain's QR has
 // n reflectors.  Trees (Sec. 2.3): binary (adjacent pairs per level), k-ary
 // (groups of k consecutive live nodes reduced left to right) and flat
-// (R <- comb(R, R_i) for i = 1..P-1); results stay in the lower index.
+// (R <- comb(R, R_i) for i = 1..P-1), and the hierarchical tree (each XCD's
+// domains first, then across the XCDs; plan.h); results stay in the lower
+// index.
 // Matrices wider than 64 columns are factored in 64-column panels, each a
 // TSQR of the rows that remain below the previous panels, with the panel's
 // Q^T applied to the columns to its right in between: the factor-panel /
@@ -23,7 +25,32 @@ std::vector<TreeLevel> tree_levels(int64_t P, int tree) {
     std::vector<TreeLevel> lv;
     if (P <= 1) return lv;
     if (tree == TSQR_TREE_FLAT) {
-        lv.push_back(TreeLevel{1, P, 1, P - 1});
+        lv.push_back(TreeLevel{1, P, 1, P - 1, 1});
+        return lv;
+    }
+    if (tree == TSQR_TREE_XCD) {
+        // inside each XCD: members x, x + G, x + 2G, ... paired as a binary
+        // tree (chain g: left = (g / G) 2s + g % G, right = left + s)
+        for (int64_t s = kXcds; s < P; s *= 2) {
+            TreeLevel L;
+            L.stride = s;
+            L.span = 2 * s;
+            L.width = kXcds;
+            L.chains = ((P - s + L.span - 1) / L.span) * kXcds;
+            L.max_rights = 1;
+            lv.push_back(L);
+        }
+        // across the XCDs: the roots 0 .. min(P, G) - 1
+        const int64_t roots = P < kXcds ? P : kXcds;
+        for (int64_t s = 1; s < roots; s *= 2) {
+            TreeLevel L;
+            L.stride = s;
+            L.span = 2 * s;
+            L.width = 1;
+            L.chains = (roots - s + L.span - 1) / L.span;
+            L.max_rights = 1;
+            lv.push_back(L);
+        }
         return lv;
     }
     int64_t k = (tree == TSQR_TREE_QUAD) ? 4 : 2;
@@ -42,7 +69,7 @@ std::vector<std::pair<int64_t, int64_t>> tree_schedule(int64_t P, int tree) {
     std::vector<std::pair<int64_t, int64_t>> s;
     for (const TreeLevel &L : tree_levels(P, tree))
         for (int64_t g = 0; g < L.chains; ++g) {
-            int64_t left = g * L.span;
+            const int64_t left = (g / L.width) * L.span + g % L.width;
             for (int64_t q = 1; q * L.stride < L.span && left + q * L.stride < P; ++q)
                 s.emplace_back(left, left + q * L.stride);
         }
@@ -67,7 +94,8 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     if (n < 1) return -2;
     if (m < n || m > 2147483647LL) return -1;
     if (n > kMaxN) return TSQR_ERR_UNSUPPORTED;
-    if (o->tree != TSQR_TREE_FLAT && o->tree != TSQR_TREE_BINARY && o->tree != TSQR_TREE_QUAD)
+    if (o->tree != TSQR_TREE_FLAT && o->tree != TSQR_TREE_BINARY && o->tree != TSQR_TREE_QUAD &&
+        o->tree != TSQR_TREE_XCD)
         return -5;
     if (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) return -5;
     if (o->row_block != 0 && o->row_block < n) return -5;
@@ -115,9 +143,10 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     if (o->prec == TSQR_MIXED) {
         P.off_lsq2 = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);
         // x (n x k), per-block A^T r partials (blocks x n x k), per-block
-        // residual norms (blocks x k), last relative corrections (k), flags
+        // squared residual norms (blocks x 2k), last relative corrections
+        // and ||A^T r|| (2k), backward-error bounds (k), flags
         const size_t k = (size_t)o->lsq_max_rhs;
-        P.off_ref = take(sizeof(double) * (n * k + (size_t)kRefineBlocks * (n + 1) * k + k) + 64);
+        P.off_ref = take(sizeof(double) * (n * k + (size_t)kRefineBlocks * (n + 2) * k + 3 * k) + 64);
     }
     // small scratch: per-block partial sums (4096 blocks x rhs), a few
     // n x rhs vectors, info words and counters

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/tsqr.h"
+#include "common.h"
 
 namespace tsqr {
 
@@ -19,19 +20,15 @@ constexpr size_t kAlign = 256;
 constexpr int kRefineBlocks = 1024;   // workgroups of the refinement's residual pass
 
 // Column slots per thread of the leaf kernel for a panel of width w: 16
-// column groups x ns slots must cover w (ns = 1, 2 or 4).  Rows per thread
-// are 32 for ns = 1 and 16 otherwise; a chunk holds 16 row groups x rows
-// per thread (the same constants as the device tile in common.h).
+// column groups x ns slots must cover w (ns = 1, 2 or 4).  Rows per chunk
+// are the device tile's (common.h: 512 for ns = 1 and 4, 256 for ns = 2).
 inline int slots_for(int w) {
     int need = (w + 15) / 16;
     int ns = 1;
     while (ns < need) ns <<= 1;
     return ns;
 }
-inline int chunk_rows_for(int w) {
-    int ns = slots_for(w);
-    return 16 * (ns >= 2 ? 16 : 32);
-}
+inline int chunk_rows_for(int w) { return chunk_rows(slots_for(w)); }
 
 // One TSQR over rows [row_off, row_off + m) and columns [col_off, col_off+n)
 // of the working matrix (n <= 64).
@@ -60,12 +57,22 @@ struct Panel {
 // Tree levels: one kernel launch per level, one workgroup per chain.  A chain
 // is (left, right_1, ..., right_c): the rights are combined into left one
 // after the other (binary: c = 1, k-ary: c = k - 1, flat: one chain of P - 1).
+// Chain g of a level starts at left = (g / width) span + g % width.
 struct TreeLevel {
     int64_t stride = 0;    // distance between consecutive rights of a chain
-    int64_t span = 0;      // distance between the lefts of consecutive chains
+    int64_t span = 0;      // distance between consecutive groups of lefts
     int64_t chains = 0;
     int64_t max_rights = 0;
+    int64_t width = 1;     // lefts per group (consecutive indices)
 };
+
+// The hierarchical tree (TSQR_TREE_XCD) groups domain d with the domains of
+// its XCD: leaves are dispatched round-robin over the XCDs, so domain d runs
+// on XCD d mod kXcds.  A binary tree reduces each XCD's domains first (their
+// triangles stay in that XCD's L2), then a binary tree reduces the kXcds
+// roots 0 .. kXcds - 1: kXcds - 1 combines cross an XCD boundary, the
+// grid-tuned tree of the paper's Sec. 2.3 (Fig. 2) with an XCD as a cluster.
+constexpr int64_t kXcds = 8;
 std::vector<TreeLevel> tree_levels(int64_t P, int tree);
 // The flat list of (left, right) combines in execution order, for tests.
 std::vector<std::pair<int64_t, int64_t>> tree_schedule(int64_t P, int tree);

@@ -1,7 +1,9 @@
 // prof.cpp -- HIP-event timing of kernel launches (tsqr_prof_* in tsqr.h).
 #include "prof.h"
 
+#include <atomic>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,7 +17,11 @@ struct Rec {
     hipEvent_t a, b;
 };
 
-bool g_on = false;
+// The state below is shared by every host thread that launches library
+// kernels (the request server enqueues mixed-precision solves from worker
+// threads): g_mu guards it; g_on is read without the lock on the fast path.
+std::mutex g_mu;
+std::atomic<bool> g_on{false};
 int g_suspend = 0;    // > 0 while a stream is being captured into a graph
 std::string g_only;   // when not empty, only this tag is timed
 std::vector<Rec> g_recs;       // events recorded since the last query
@@ -61,10 +67,15 @@ void drain() {
 
 }  // namespace
 
-void prof_suspend(bool on) { g_suspend += on ? 1 : -1; }
+void prof_suspend(bool on) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_suspend += on ? 1 : -1;
+}
 
 int prof_begin(const char *tag, hipStream_t st) {
-    if (!g_on || g_suspend > 0) return -1;
+    if (!g_on.load(std::memory_order_relaxed)) return -1;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (g_suspend > 0) return -1;
     if (!g_only.empty() && g_only != tag) return -1;
     if (g_recs.size() > 20000) drain();
     Rec r{tag, get_event(), get_event()};
@@ -74,7 +85,9 @@ int prof_begin(const char *tag, hipStream_t st) {
 }
 
 void prof_end(int slot, hipStream_t st) {
-    if (slot < 0 || slot >= (int)g_recs.size()) return;
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (slot >= (int)g_recs.size()) return;
     if (g_recs[slot].b) hipEventRecord(g_recs[slot].b, st);
 }
 
@@ -83,6 +96,7 @@ void prof_end(int slot, hipStream_t st) {
 extern "C" {
 
 TSQR_API int tsqr_prof_enable(int on) {
+    std::lock_guard<std::mutex> lock(tsqr::g_mu);
     tsqr::drain();
     tsqr::g_agg.clear();
     tsqr::g_on = on != 0;
@@ -90,11 +104,13 @@ TSQR_API int tsqr_prof_enable(int on) {
 }
 
 TSQR_API int tsqr_prof_only(const char *tag) {
+    std::lock_guard<std::mutex> lock(tsqr::g_mu);
     tsqr::g_only = tag ? tag : "";
     return 0;
 }
 
 TSQR_API int tsqr_prof_query(int i, const char **name, int64_t *launches, double *ms) {
+    std::lock_guard<std::mutex> lock(tsqr::g_mu);
     tsqr::drain();
     if (i < 0 || i >= (int)tsqr::g_agg.size()) return -1;
     if (name) *name = tsqr::g_agg[i].tag.c_str();

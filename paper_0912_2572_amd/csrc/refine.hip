@@ -32,8 +32,9 @@ __global__ void k_to_f32(const double *__restrict__ src, int64_t lds, float *__r
 constexpr int kResRows = 32;   // rows per LDS tile of the residual pass
 
 // One pass over A (FP64): F = B - Rr - A X (rows of this block),
-// gpart[block] = A_block^T Rr_block (n x k) and rpart[block] = the squared
-// norms of the columns of (B - A X)_block, all in a fixed summation order.
+// gpart[block] = A_block^T Rr_block (n x k), and rpart[block] = the squared
+// column norms of (B - A X)_block (entries 0..k-1) and of F_block (entries
+// k..2k-1), all in a fixed summation order.
 __device__ __forceinline__ void resid_block(const double *__restrict__ A, int64_t lda, int64_t m, int n,
                                             const double *__restrict__ B, int64_t ldb,
                                             const double *__restrict__ X, int64_t ldx,
@@ -44,12 +45,16 @@ __device__ __forceinline__ void resid_block(const double *__restrict__ A, int64_
     double *Xs = At + kResRows * n;         // n x k
     double *Rt = Xs + n * k;                // kResRows x k
     double *Ss = Rt + kResRows * k;         // kResRows x k: (B - A X)^2
+    double *Fs = Ss + kResRows * k;         // kResRows x k: F^2
     const int tid = threadIdx.x;
     const int64_t per = (m + nblk - 1) / nblk;
     const int64_t lo = blk * per;
     const int64_t hi = (lo + per < m) ? lo + per : m;
     for (int e = tid; e < n * k; e += 256) Xs[e] = X[(e % n) + (int64_t)(e / n) * ldx];
-    for (int e = tid; e < kResRows * k; e += 256) Ss[e] = 0.0;
+    for (int e = tid; e < kResRows * k; e += 256) {
+        Ss[e] = 0.0;
+        Fs[e] = 0.0;
+    }
     // accumulators of A^T Rr: thread owns (j, c) pairs e = tid + 256 q
     constexpr int kMaxOwn = 8;              // n * k <= 2048
     double acc[kMaxOwn];
@@ -73,7 +78,9 @@ __device__ __forceinline__ void resid_block(const double *__restrict__ A, int64_
             double s = B[r0 + r + (int64_t)c * ldb];
             for (int j = 0; j < n; ++j) s = fma(-At[r * n + j], Xs[j + n * c], s);
             Ss[r * k + c] = fma(s, s, Ss[r * k + c]);
-            F[r0 + r + (int64_t)c * m] = s - Rt[r * k + c];
+            const double fv = s - Rt[r * k + c];
+            Fs[r * k + c] = fma(fv, fv, Fs[r * k + c]);
+            F[r0 + r + (int64_t)c * m] = fv;
         }
 #pragma unroll
         for (int q = 0; q < kMaxOwn; ++q) {
@@ -93,9 +100,13 @@ __device__ __forceinline__ void resid_block(const double *__restrict__ A, int64_
     }
     __syncthreads();
     if (tid < k) {
-        double s = 0.0;
-        for (int r = 0; r < kResRows; ++r) s += Ss[r * k + tid];
-        rpart[blk * k + tid] = s;
+        double s = 0.0, f = 0.0;
+        for (int r = 0; r < kResRows; ++r) {
+            s += Ss[r * k + tid];
+            f += Fs[r * k + tid];
+        }
+        rpart[blk * 2 * k + tid] = s;
+        rpart[blk * 2 * k + k + tid] = f;
     }
 }
 
@@ -138,6 +149,7 @@ __device__ __forceinline__ void resid_fast(const double *__restrict__ A, int64_t
                                            int64_t blk, int64_t nblk) {
     __shared__ double gsh[4][MAXJT * 16 * K];
     __shared__ double ssh[4][K];
+    __shared__ double fsh[4][K];
     const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     const int njt = (n + 15) >> 4;
@@ -155,6 +167,7 @@ __device__ __forceinline__ void resid_fast(const double *__restrict__ A, int64_t
             g[jt][c] = 0.0;
         }
     double ss = 0.0;   // squared (B - A X) of column l16 (lanes l16 < k)
+    double ff = 0.0;   // squared F of column l16
     for (int64_t rb0 = lo + 16 * w; rb0 < hi; rb0 += 64) {
         const int64_t rb = rb0 + 4 * l4;
         const int nv = (int)((hi - rb >= 4) ? 4 : (hi - rb > 0 ? hi - rb : 0));
@@ -198,7 +211,9 @@ __device__ __forceinline__ void resid_fast(const double *__restrict__ A, int64_t
                 const int64_t row = rb + q;
                 const double sres = B[row + (int64_t)l16 * ldb] - ax;
                 ss = fma(sres, sres, ss);
-                F[row + (int64_t)l16 * m] = sres - rc;
+                const double fv = sres - rc;
+                ff = fma(fv, fv, ff);
+                F[row + (int64_t)l16 * m] = fv;
             }
         }
     }
@@ -208,19 +223,26 @@ __device__ __forceinline__ void resid_fast(const double *__restrict__ A, int64_t
 #pragma unroll
         for (int c = 0; c < K; ++c) g[jt][c] = pair_sum32(pair_sum16(g[jt][c]));
     ss = pair_sum32(pair_sum16(ss));
+    ff = pair_sum32(pair_sum16(ff));
     if (l4 == 0) {
 #pragma unroll
         for (int jt = 0; jt < MAXJT; ++jt)
 #pragma unroll
             for (int c = 0; c < K; ++c) gsh[w][(16 * jt + l16) * K + c] = g[jt][c];
-        if (l16 < K) ssh[w][l16] = ss;
+        if (l16 < K) {
+            ssh[w][l16] = ss;
+            fsh[w][l16] = ff;
+        }
     }
     __syncthreads();
     for (int e = tid; e < n * k; e += 256) {
         const int j = e % n, c = e / n, idx = j * K + c;
         gpart[blk * n * k + e] = ((gsh[0][idx] + gsh[1][idx]) + gsh[2][idx]) + gsh[3][idx];
     }
-    if (tid < k) rpart[blk * k + tid] = ((ssh[0][tid] + ssh[1][tid]) + ssh[2][tid]) + ssh[3][tid];
+    if (tid < k) {
+        rpart[blk * 2 * k + tid] = ((ssh[0][tid] + ssh[1][tid]) + ssh[2][tid]) + ssh[3][tid];
+        rpart[blk * 2 * k + k + tid] = ((fsh[0][tid] + fsh[1][tid]) + fsh[2][tid]) + fsh[3][tid];
+    }
 }
 
 template <int MAXJT, int K>
@@ -246,13 +268,15 @@ __global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A,
 // One workgroup: g = -sum_b gpart[b];  R^T h = g;  dx = R^{-1} (d_1 - h)
 // with d_1 = F[0:n] (= (Q^T f)[0:n] on entry);  X += dx;  F[0:n] = h.
 // status[0] = sweeps done, status[1] = 1 when converged or stalled,
-// hist[c] = ||dx_c|| / ||x_c|| of the last sweep.  A sweep counts as
+// hist[c] = ||dx_c|| / ||x_c|| of the last sweep and, if gnorm is set,
+// gnorm[c] = ||g_c||.  A sweep counts as
 // final when every column either met the tolerance or stalled (its
 // correction shrank by less than 10 %).
 __device__ __forceinline__ void refine_step(const double *__restrict__ R, int n, double *__restrict__ F,
                                             int64_t m, int k, const double *__restrict__ gpart, int nblocks,
                                             double *__restrict__ X, int64_t ldx, double tol,
-                                            int32_t *__restrict__ status, double *__restrict__ hist) {
+                                            int32_t *__restrict__ status, double *__restrict__ hist,
+                                            double *__restrict__ gnorm) {
     __shared__ double g[256];
     const int tid = threadIdx.x, lane = tid & 63;
     bool all_ok = true;
@@ -294,6 +318,13 @@ __device__ __forceinline__ void refine_step(const double *__restrict__ R, int n,
                 const int i = lane + 64 * q;
                 h[q] = (i < n) ? g[i] : 0.0;
             }
+            if (gnorm) {
+                double gg = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gg = fma(h[q], h[q], gg);
+                gg = wave_sum(gg);
+                if (lane == 0) gnorm[c] = sqrt(gg);
+            }
             wave_fwdsub_t(R, n, h);                       // R^T h = g
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -333,8 +364,8 @@ __global__ __launch_bounds__(256) void k_lsq_refine(const double *__restrict__ R
                                                     const double *__restrict__ gpart, int nblocks,
                                                     double *__restrict__ X, int64_t ldx, double tol,
                                                     int32_t *__restrict__ status,
-                                                    double *__restrict__ hist) {
-    refine_step(R, n, F, m, k, gpart, nblocks, X, ldx, tol, status, hist);
+                                                    double *__restrict__ hist, double *__restrict__ gnorm) {
+    refine_step(R, n, F, m, k, gpart, nblocks, X, ldx, tol, status, hist, gnorm);
 }
 
 __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, int64_t count) {
@@ -351,13 +382,48 @@ __global__ void k_status_init(int32_t *status, double *hist, int k) {
     if ((int)threadIdx.x < k) hist[threadIdx.x] = 1.0;
 }
 
+// Upper bound on the least-squares backward error of x (Sec. 1 of the
+// paper only names least squares; the bound is the normwise one used to
+// judge refinement):  with the last residual pass's s = b - A x,
+// f = b - r - A x and g = -A^T r,
+//     ||A^T s|| <= ||g|| + ||A|| ||f||,
+//     eta = ||A^T s|| / (||A|| (||A|| ||x|| + ||s||)),
+// and ||A||_F = ||R||_F (A = QR, Q orthogonal).
+__device__ __forceinline__ double eta_bound(double gn, double fn, double sn, double xn, double an) {
+    const double den = an * fma(an, xn, sn);
+    return den > 0.0 ? fma(an, fn, gn) / den : 0.0;
+}
+
+constexpr double kEtaMax = 1e-12;   // a refined x above this bound is flagged (dinfo = -3)
+
+// ||R||_F of the n x n triangle, by one workgroup (every thread returns it).
+__device__ __forceinline__ double tri_fnorm(const double *__restrict__ R, int n, double *red) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e % n, c = e / n;
+        if (r <= c) s = fma(R[e], R[e], s);
+    }
+    s = wave_sum(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return sqrt(t);
+}
+
 // Last step of a refined solve: info from the diagonal of R (LAPACK dtrtrs
 // convention: X untouched when R_jj == 0), X = Xw otherwise, residual norms
-// ||b_c - A x_c|| from the last residual pass.
+// ||b_c - A x_c|| and the backward-error bound eta_c (eta_out) from the last
+// residual pass; info = -2 for a non-finite residual, -3 when some eta_c
+// exceeds kEtaMax (the refinement stalled or ran out of sweeps before x was
+// FP64-accurate).
 __global__ __launch_bounds__(256) void k_mixed_final(const double *R, int n, int k, const double *Xw,
                                                      double *X, int64_t ldx, double *resid, int32_t *dinfo,
-                                                     int merge, const double *rpart, int nblocks) {
+                                                     int merge, const double *rpart, int nblocks,
+                                                     const double *gnorm, double *eta_out) {
     __shared__ int info;
+    __shared__ double red[4];
     const int tid = threadIdx.x;
     if (tid == 0) {
         info = 0;
@@ -367,28 +433,38 @@ __global__ __launch_bounds__(256) void k_mixed_final(const double *R, int n, int
                 break;
             }
     }
+    const double an = tri_fnorm(R, n, red);
     __syncthreads();
-    bool bad = false;
+    bool bad = false, loose = false;
     if (tid < k) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += rpart[(int64_t)b * k + tid];
+        double s = 0.0, f = 0.0, xx = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            s += rpart[(int64_t)b * 2 * k + tid];
+            f += rpart[(int64_t)b * 2 * k + k + tid];
+        }
+        for (int j = 0; j < n; ++j) xx = fma(Xw[j + n * tid], Xw[j + n * tid], xx);
         const double rn = sqrt(s);
+        const double eta = eta_bound(gnorm[tid], sqrt(f), rn, sqrt(xx), an);
         if (resid) resid[tid] = rn;
+        if (eta_out) eta_out[tid] = eta;
         bad = !(rn - rn == 0.0);
+        loose = !(eta <= kEtaMax);
     }
     const int anybad = __syncthreads_or(bad);
+    const int anyloose = __syncthreads_or(loose);
     // merge: a later group of right-hand sides keeps an earlier nonzero code
-    if (tid == 0 && dinfo && !(merge && *dinfo != 0)) *dinfo = info ? info : (anybad ? -2 : 0);
+    if (tid == 0 && dinfo && !(merge && *dinfo != 0))
+        *dinfo = info ? info : (anybad ? -2 : (anyloose ? -3 : 0));
     if (info) return;
     for (int e = tid; e < n * k; e += 256) X[(e % n) + (int64_t)(e / n) * ldx] = Xw[e];
 }
 
 hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, double *X, int64_t ldx,
                               double *resid, int32_t *dinfo, int merge, const double *rpart, int nblocks,
-                              hipStream_t st) {
+                              const double *gnorm, double *eta_out, hipStream_t st) {
     ProfScope ps("lsq_final", st);
     hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(256), 0, st, R, n, k, Xw, X, ldx, resid, dinfo, merge,
-                       rpart, nblocks);
+                       rpart, nblocks, gnorm, eta_out);
     return hipGetLastError();
 }
 
@@ -410,6 +486,7 @@ __global__ void k_lsq_init_b(const BMat *__restrict__ mats, const int *__restric
             M.status[1] = 0;
             M.hist[0] = 1.0;
             M.hist[1] = 0.0;
+            M.hist[2] = 0.0;
         }
     }
 }
@@ -449,7 +526,8 @@ __global__ __launch_bounds__(256) void k_refine_b(const BMat *__restrict__ mats,
         if (threadIdx.x == 0) M.hist[1] = sqrt(red[0]);
         __syncthreads();
     }
-    refine_step(M.R, n, M.F, m, 1, sweep > 0 ? M.gpart : nullptr, M.nb, M.Xw, n, tol, M.status, M.hist);
+    refine_step(M.R, n, M.F, m, 1, sweep > 0 ? M.gpart : nullptr, M.nb, M.Xw, n, tol, M.status, M.hist,
+                M.prec ? M.hist + 2 : nullptr);
     if (!M.prec && threadIdx.x == 0) M.status[1] = 1;
 }
 
@@ -461,8 +539,11 @@ __global__ void k_axpy_b(const BMat *__restrict__ mats, const int *__restrict__ 
         M.Rr[r] += M.F[r];
 }
 
+// Per matrix: info, residual norm and x; a mixed matrix also gets the
+// backward-error bound of k_mixed_final (info = -3 above kEtaMax).
 __global__ void k_final_b(const BMat *__restrict__ mats, const int *__restrict__ list) {
     __shared__ int info;
+    __shared__ double red[4];
     const BMat &M = mats[list[blockIdx.x]];
     const int n = M.pa.n;
     if (threadIdx.x == 0) {
@@ -472,16 +553,26 @@ __global__ void k_final_b(const BMat *__restrict__ mats, const int *__restrict__
                 info = j + 1;
                 break;
             }
+    }
+    const double an = M.prec ? tri_fnorm(M.R, n, red) : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
         double rn;
+        bool loose = false;
         if (M.prec) {
-            double s = 0.0;
-            for (int b = 0; b < M.nb; ++b) s += M.rpart[b];
+            double s = 0.0, f = 0.0, xx = 0.0;
+            for (int b = 0; b < M.nb; ++b) {
+                s += M.rpart[2 * b];
+                f += M.rpart[2 * b + 1];
+            }
+            for (int j = 0; j < n; ++j) xx = fma(M.Xw[j], M.Xw[j], xx);
             rn = sqrt(s);
+            loose = !(eta_bound(M.hist[2], sqrt(f), rn, sqrt(xx), an) <= kEtaMax);
         } else {
             rn = M.hist[1];
         }
         *M.resid = rn;
-        *M.info = info ? info : (!(rn - rn == 0.0) ? -2 : 0);
+        *M.info = info ? info : (!(rn - rn == 0.0) ? -2 : (loose ? -3 : 0));
     }
     __syncthreads();
     if (info) return;
@@ -500,7 +591,7 @@ hipError_t launch_lsq_init_b(const BMat *mats, const int *list, int cnt, int64_t
 hipError_t launch_resid_b(const BMat *mats, const int *list, int cnt, int64_t gx, int sweep, hipStream_t st) {
     if (cnt <= 0 || gx <= 0) return hipSuccess;
     // n <= 64, k = 1
-    const size_t sh = sizeof(double) * ((size_t)kResRows * 64 + 64 + 2 * (size_t)kResRows);
+    const size_t sh = sizeof(double) * ((size_t)kResRows * 64 + 64 + 3 * (size_t)kResRows);
     ProfScope ps("batch_lsq_resid", st);
     hipLaunchKernelGGL(k_resid_b, dim3((unsigned)gx, (unsigned)cnt), dim3(256), sh, st, mats, list, sweep);
     return hipGetLastError();
@@ -523,7 +614,7 @@ hipError_t launch_axpy_b(const BMat *mats, const int *list, int cnt, int64_t gx,
 hipError_t launch_final_b(const BMat *mats, const int *list, int cnt, hipStream_t st) {
     if (cnt <= 0) return hipSuccess;
     ProfScope ps("batch_lsq_final", st);
-    hipLaunchKernelGGL(k_final_b, dim3((unsigned)cnt), dim3(64), 0, st, mats, list);
+    hipLaunchKernelGGL(k_final_b, dim3((unsigned)cnt), dim3(256), 0, st, mats, list);
     return hipGetLastError();
 }
 
@@ -568,7 +659,7 @@ hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, cons
 #undef TSQR_RESID_FAST
     }
     const size_t sh =
-        sizeof(double) * ((size_t)kResRows * n + (size_t)n * k + 2 * (size_t)kResRows * k);
+        sizeof(double) * ((size_t)kResRows * n + (size_t)n * k + 3 * (size_t)kResRows * k);
     hipError_t e = hipFuncSetAttribute((const void *)k_lsq_resid,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
@@ -580,10 +671,10 @@ hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, cons
 
 hipError_t launch_lsq_refine(const double *R, int n, double *F, int64_t m, int k, const double *gpart,
                              int nblocks, double *X, int64_t ldx, double tol, int32_t *status,
-                             double *hist, hipStream_t st) {
+                             double *hist, double *gnorm, hipStream_t st) {
     ProfScope ps("lsq_refine", st);
     hipLaunchKernelGGL(k_lsq_refine, dim3(1), dim3(256), 0, st, R, n, F, m, k, gpart, nblocks, X, ldx, tol,
-                       status, hist);
+                       status, hist, gnorm);
     return hipGetLastError();
 }
 

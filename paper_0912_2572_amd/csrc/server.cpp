@@ -10,15 +10,28 @@
 // Each admitted request runs on one of several HIP streams, so copies and
 // kernels of different requests overlap on the device.  Device memory comes
 // from one arena (first-fit free list with coalescing); when a request does
-// not fit, idle cached factors are evicted least recently used first.
+// not fit, idle cached factors are evicted least recently used first, and
+// younger requests that do fit may be admitted past it while it has waited
+// less than the bypass window.
+//
+// A mixed-precision solve reads a convergence flag back after every
+// refinement sweep, so it blocks the thread that enqueues it.  Its solve is
+// therefore enqueued by a worker thread of its own (one per admitted mixed
+// request); the driving thread keeps retiring and admitting meanwhile.  The
+// solves of one cached factor share its workspace and are serialised by the
+// entry's lock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <atomic>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -91,6 +104,16 @@ struct Entry {
     int stream = 0;
     int refs = 0;
     uint64_t last_use = 0;
+    std::shared_ptr<std::mutex> solve_mu;   // serialises solves on this factor's workspace
+};
+
+// A mixed-precision solve enqueued by a worker thread.  state: 0 while the
+// worker runs, 1 once the solve, the copies back and the completion event
+// are enqueued, -1 when one of them failed (rc).
+struct Job {
+    std::thread th;
+    std::atomic<int> state{0};
+    int rc = 0;
 };
 
 struct Req {
@@ -101,6 +124,7 @@ struct Req {
     int64_t entry = -1;             // matrix id of its cache entry
     int stream = 0;
     hipEvent_t ev = nullptr;
+    std::unique_ptr<Job> job;       // mixed precision: the worker enqueueing the solve
 };
 
 }  // namespace
@@ -112,7 +136,8 @@ struct tsqr_server_s {
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<Req> reqs;
+    std::deque<Req> reqs;           // a deque: references stay valid while requests are appended
+    int device = 0;
     std::deque<int64_t> queue;
     std::vector<int64_t> running;
     std::unordered_map<int64_t, Entry> cache;
@@ -153,11 +178,14 @@ void drop_entry(tsqr_server_s *S, int64_t id) {
     S->cache.erase(it);
 }
 
-bool evict_one(tsqr_server_s *S) {
+// Drops the least recently used idle cached factor other than `keep` (the
+// matrix the admitting request is about to use, whose entry must survive the
+// admission); false when there is none.
+bool evict_one(tsqr_server_s *S, int64_t keep) {
     int64_t victim = -1;
     uint64_t oldest = ~0ull;
     for (auto &kv : S->cache)
-        if (kv.second.refs == 0 && kv.second.last_use < oldest) {
+        if (kv.first != keep && kv.second.refs == 0 && kv.second.last_use < oldest) {
             oldest = kv.second.last_use;
             victim = kv.first;
         }
@@ -189,26 +217,57 @@ void fail(tsqr_server_s *S, Req &q, int code) {
     S->st.failed += 1;
 }
 
+// The solve of an admitted request and the copies of its results back to
+// the host, then its completion event, all on `st`.
+int enqueue_solve(tsqr_factors f, const double *Adev, const tsqr_request &r, double *B, double *X,
+                  double *res, int32_t *info, hipEvent_t ev, hipStream_t st) {
+    int rc = tsqr_lsq_solve(f, Adev, r.m, r.k, B, r.m, X, r.n, res, info, st);
+    if (!rc && (hipMemcpyAsync(r.X, X, sizeof(double) * r.n * r.k, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(r.resid, res, sizeof(double) * r.k, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(r.info, info, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess))
+        rc = -1000;
+    if (!rc && hipEventRecord(ev, st) != hipSuccess) rc = -1000;
+    return rc;
+}
+
 // Tries to admit request q; returns 1 admitted, 0 must wait, -1 failed.
 int admit(tsqr_server_s *S, int64_t ticket) {
     Req &q = S->reqs[ticket];
     const tsqr_request &r = q.r;
     const bool mixed = S->o.prec == TSQR_MIXED;
     auto hit = S->cache.find(r.matrix_id);
-    const bool have = hit != S->cache.end();
-    const bool a_in_io = !have && !mixed;   // FP64 factors do not keep A
-    size_t ws = 0;
-    const size_t eb = have ? 0 : entry_bytes(S, r, &ws);
-    const size_t ib = io_bytes(S, r, a_in_io);
-    if (!have && ws == 0) return -1;
+    bool have = hit != S->cache.end();
+    size_t ws = 0, eb = 0, ib = 0;
     size_t io_off = 0, e_off = 0;
     for (;;) {
-        bool ok_io = S->arena.alloc(ib, &io_off);
-        bool ok_e = ok_io && (have || S->arena.alloc(eb, &e_off));
-        if (ok_io && ok_e) break;
-        if (ok_io) S->arena.release(io_off, ib);
-        if (!evict_one(S)) return S->running.empty() ? -1 : 0;
+        const bool a_in_io = !have && !mixed;   // FP64 factors do not keep A
+        eb = have ? 0 : entry_bytes(S, r, &ws);
+        ib = io_bytes(S, r, a_in_io);
+        if (!have && ws == 0) return -1;
+        bool placed = false;
+        for (;;) {
+            bool ok_io = S->arena.alloc(ib, &io_off);
+            bool ok_e = ok_io && (have || S->arena.alloc(eb, &e_off));
+            if (ok_io && ok_e) {
+                placed = true;
+                break;
+            }
+            if (ok_io) S->arena.release(io_off, ib);
+            if (!evict_one(S, r.matrix_id)) break;
+        }
+        if (placed) break;
+        // the cached factor of this very matrix can be what is in the way
+        // (it may split the free space): when it is idle, drop it and admit
+        // the request as a new matrix
+        if (have && hit->second.refs == 0) {
+            drop_entry(S, r.matrix_id);
+            S->st.evictions += 1;
+            have = false;
+            continue;
+        }
+        return S->running.empty() ? -1 : 0;
     }
+    const bool a_in_io = !have && !mixed;
     hipStream_t st;
     int si;
     if (have) {
@@ -235,6 +294,7 @@ int admit(tsqr_server_s *S, int64_t ticket) {
         e.ws_off = e_off;
         e.ws_bytes = ws;
         e.stream = si;
+        e.solve_mu = std::make_shared<std::mutex>();
         double *Ad = a_in_io ? Aio : reinterpret_cast<double *>(S->base + e_off + up(ws));
         e.a_off = (size_t)(reinterpret_cast<char *>(Ad) - S->base);
         if (hipMemcpyAsync(Ad, r.A, sizeof(double) * r.m * r.n, hipMemcpyHostToDevice, st) != hipSuccess)
@@ -242,6 +302,7 @@ int admit(tsqr_server_s *S, int64_t ticket) {
         tsqr_opts o = factor_opts(S);
         if (!rc) rc = tsqr_factor(r.m, r.n, Ad, r.m, &o, S->base + e.ws_off, ws, st, &e.f);
         if (rc) {
+            hipStreamSynchronize(st);
             S->arena.release(io_off, ib);
             S->arena.release(e_off, eb);
             fail(S, q, rc);
@@ -256,11 +317,6 @@ int admit(tsqr_server_s *S, int64_t ticket) {
     }
     Entry &E = hit->second;
     if (hipMemcpyAsync(B, r.B, sizeof(double) * r.m * r.k, hipMemcpyHostToDevice, st) != hipSuccess) rc = -1000;
-    if (!rc) rc = tsqr_lsq_solve(E.f, Adev, r.m, r.k, B, r.m, X, r.n, res, info, st);
-    if (!rc && (hipMemcpyAsync(r.X, X, sizeof(double) * r.n * r.k, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(r.resid, res, sizeof(double) * r.k, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(r.info, info, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess))
-        rc = -1000;
     if (!rc) {
         if (!S->ev_pool.empty()) {
             q.ev = S->ev_pool.back();
@@ -270,7 +326,32 @@ int admit(tsqr_server_s *S, int64_t ticket) {
             rc = -1000;
         }
     }
-    if (!rc && hipEventRecord(q.ev, st) != hipSuccess) rc = -1000;
+    if (!rc && mixed) {
+        // the worker enqueues the blocking solve; this thread goes on
+        auto job = std::make_unique<Job>();
+        Job *jp = job.get();
+        const tsqr_request rr = r;
+        const tsqr_factors f = E.f;
+        const std::shared_ptr<std::mutex> mu = E.solve_mu;
+        const hipEvent_t ev = q.ev;
+        const int dev = S->device;
+        try {
+            jp->th = std::thread([jp, rr, f, mu, Adev, B, X, res, info, ev, st, dev]() {
+                int wrc = hipSetDevice(dev) == hipSuccess ? 0 : -1000;
+                if (!wrc) {
+                    std::lock_guard<std::mutex> lock(*mu);
+                    wrc = enqueue_solve(f, Adev, rr, B, X, res, info, ev, st);
+                }
+                jp->rc = wrc;
+                jp->state.store(wrc ? -1 : 1, std::memory_order_release);
+            });
+            q.job = std::move(job);
+        } catch (...) {
+            rc = -1000;
+        }
+    } else if (!rc) {
+        rc = enqueue_solve(E.f, Adev, r, B, X, res, info, q.ev, st);
+    }
     if (rc) {
         // the stream may still read the buffers: wait before releasing them
         hipStreamSynchronize(st);
@@ -298,14 +379,33 @@ int retire(tsqr_server_s *S, bool block_one) {
     int done = 0;
     for (size_t i = 0; i < S->running.size();) {
         Req &q = S->reqs[S->running[i]];
-        hipError_t e = (block_one && done == 0 && i == 0) ? hipEventSynchronize(q.ev) : hipEventQuery(q.ev);
+        const bool block = block_one && done == 0 && i == 0;
+        int job_rc = 0;
+        if (q.job) {
+            // a mixed solve: its event means something only once the worker
+            // has enqueued everything
+            if (block && q.job->state.load(std::memory_order_acquire) == 0) q.job->th.join();
+            const int js = q.job->state.load(std::memory_order_acquire);
+            if (js == 0) {
+                ++i;
+                continue;
+            }
+            if (q.job->th.joinable()) q.job->th.join();
+            if (js < 0) {
+                job_rc = q.job->rc ? q.job->rc : -1000;
+                hipStreamSynchronize(S->streams[q.stream]);   // nothing may still read its buffers
+            }
+        }
+        hipError_t e = hipSuccess;
+        if (!job_rc) e = block ? hipEventSynchronize(q.ev) : hipEventQuery(q.ev);
         if (e == hipErrorNotReady) {
             ++i;
             continue;
         }
+        q.job.reset();
         q.t_done = now_s();
-        q.state = (e == hipSuccess) ? 2 : -1000 - (int)e;
-        if (e == hipSuccess) S->st.completed += 1;
+        q.state = job_rc ? job_rc : ((e == hipSuccess) ? 2 : -1000 - (int)e);
+        if (q.state == 2) S->st.completed += 1;
         else S->st.failed += 1;
         S->ev_pool.push_back(q.ev);
         q.ev = nullptr;
@@ -320,6 +420,25 @@ int retire(tsqr_server_s *S, bool block_one) {
         ++done;
     }
     return done;
+}
+
+// Admits queued requests in arrival order while slots are free.  A request
+// whose memory does not fit yet stays queued, and younger ones that fit are
+// admitted past it until it has waited the bypass window; from then on
+// nothing is admitted past it, so the memory that frees up goes to it.
+void admit_queued(tsqr_server_s *S) {
+    const double window = S->o.bypass_ms < 0 ? 0.0 : (S->o.bypass_ms == 0 ? 100.0 : S->o.bypass_ms) * 1e-3;
+    for (auto it = S->queue.begin(); it != S->queue.end() && (int)S->running.size() < S->o.max_inflight;) {
+        const int64_t t = *it;
+        const int a = admit(S, t);
+        if (a == 0) {
+            if (now_s() - S->reqs[t].t_submit >= window) break;
+            ++it;
+            continue;
+        }
+        if (a < 0 && S->reqs[t].state == 0) fail(S, S->reqs[t], TSQR_ERR_WORKSPACE);
+        it = S->queue.erase(it);
+    }
 }
 
 }  // namespace
@@ -347,7 +466,8 @@ TSQR_API int tsqr_server_create(const tsqr_server_opts *o, tsqr_server *out) {
     if (!o) o = &d;
     if (o->hbm_budget < ((size_t)1 << 20) || o->streams < 1 || o->streams > 64 || o->max_inflight < 1 ||
         (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) ||
-        (o->tree != TSQR_TREE_FLAT && o->tree != TSQR_TREE_BINARY && o->tree != TSQR_TREE_QUAD))
+        (o->tree != TSQR_TREE_FLAT && o->tree != TSQR_TREE_BINARY && o->tree != TSQR_TREE_QUAD &&
+         o->tree != TSQR_TREE_XCD))
         return -1;
     tsqr_server_s *S = new (std::nothrow) tsqr_server_s;
     if (!S) return TSQR_ERR_WORKSPACE;
@@ -360,6 +480,7 @@ TSQR_API int tsqr_server_create(const tsqr_server_opts *o, tsqr_server *out) {
     }
     S->base = static_cast<char *>(p);
     S->arena.init(o->hbm_budget);
+    if (hipGetDevice(&S->device) != hipSuccess) S->device = 0;
     for (int i = 0; i < o->streams; ++i) {
         hipStream_t st = nullptr;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -387,10 +508,10 @@ TSQR_API int64_t tsqr_server_submit(tsqr_server S, const tsqr_request *r) {
     if (ws == 0) return -2;
     if (need > S->arena.size()) return TSQR_ERR_WORKSPACE;
     S->shapes[r->matrix_id] = {r->m, r->n};
-    Req q;
+    S->reqs.emplace_back();
+    Req &q = S->reqs.back();
     q.r = *r;
     q.t_submit = now_s();
-    S->reqs.push_back(q);
     const int64_t t = (int64_t)S->reqs.size() - 1;
     S->queue.push_back(t);
     S->st.submitted += 1;
@@ -401,23 +522,11 @@ TSQR_API int tsqr_server_progress(tsqr_server S, int wait) {
     if (!S) return -1;
     account(S);
     int done = retire(S, false);
-    while (!S->queue.empty() && (int)S->running.size() < S->o.max_inflight) {
-        const int64_t t = S->queue.front();
-        int a = admit(S, t);
-        if (a == 0) break;
-        if (a < 0 && S->reqs[t].state == 0) fail(S, S->reqs[t], TSQR_ERR_WORKSPACE);
-        S->queue.pop_front();
-    }
+    admit_queued(S);
     if (wait && done == 0 && !S->running.empty()) {
         account(S);
         retire(S, true);
-        while (!S->queue.empty() && (int)S->running.size() < S->o.max_inflight) {
-            const int64_t t = S->queue.front();
-            int a = admit(S, t);
-            if (a == 0) break;
-            if (a < 0 && S->reqs[t].state == 0) fail(S, S->reqs[t], TSQR_ERR_WORKSPACE);
-            S->queue.pop_front();
-        }
+        admit_queued(S);
     }
     account(S);
     return (int)(S->queue.size() + S->running.size());

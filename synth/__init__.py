@@ -34,6 +34,11 @@ def config_large(m: int = 1 << 20, n: int = 64, seed: int = 0) -> np.ndarray:
     return gaussian(m, n, seed)
 
 
+def config_large_rhs(m: int = 1 << 20, seed: int = 1) -> np.ndarray:
+    """The single-matrix workload's right-hand side: b ~ N(0,1), seed 1."""
+    return np.random.default_rng(seed).standard_normal(m)
+
+
 def log_spaced_spectrum(n: int, lo_exp: float = -6.0) -> np.ndarray:
     """s_i = 10^(lo_exp * i / (n-1)), i = 0..n-1 (1 down to 10^lo_exp)."""
     if n == 1:

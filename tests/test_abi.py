@@ -61,6 +61,24 @@ def test_tree_schedule_matches_oracle(tl, tree, P):
     assert tl.tree_schedule(P, tree) == oracle.schedule(P, tree)
 
 
+@pytest.mark.parametrize("P", [1, 2, 5, 8, 9, 17, 64, 255, 256, 1024])
+def test_xcd_tree_schedule(tl, P):
+    """The hierarchical tree (TSQR_TREE_XCD): the same combines as the
+    oracle's grid-tuned tree with domain d in cluster d mod 8, executed in
+    an order the dependencies allow (a right is never used again, a left is
+    used only after everything combined into it below), and XCD count - 1
+    combines across an XCD boundary."""
+    s = tl.tree_schedule(P, tl.TREE_XCD)
+    want = oracle.hierarchical_schedule([d % 8 for d in range(P)])
+    assert sorted(s) == sorted(want)
+    done = set()
+    for l, r in s:
+        assert l < r and l not in done and r not in done
+        done.add(r)
+    assert sum(1 for l, r in s if l % 8 != r % 8) == min(P, 8) - 1
+    assert len(tl.tree_schedule(P, tl.TREE_BINARY)) == len(s) == P - 1
+
+
 def test_workspace_bytes(tl):
     o = tl.opts(row_block=4096)
     w = tl.workspace_bytes(1 << 20, 64, o)

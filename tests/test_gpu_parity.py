@@ -48,10 +48,38 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def colwise(a, b, tol, scale=None):
+    """Column by column: ||a_j - b_j|| <= tol * (scale_j or ||b_j||), so a
+    wrong small column cannot hide under a large one in a Frobenius norm."""
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    for j in range(b.shape[1]):
+        ref = np.linalg.norm(b[:, j]) if scale is None else scale[j]
+        err = np.linalg.norm(a[:, j] - b[:, j])
+        assert err <= tol * max(ref, 1e-300), f"column {j}: {err:.3e} > {tol:.1e} * {ref:.3e}"
+
+
+def r_entrywise(R, Ro, tol=1e-12):
+    """Every entry of R within tol of its column's norm (R_ij is a dot of
+    column j of A with a unit vector, so |error| scales with ||a_j||)."""
+    cn = np.linalg.norm(Ro, axis=0)
+    assert np.all(np.abs(R - Ro) <= tol * np.maximum(cn, 1e-300)[None, :]), \
+        float(np.max(np.abs(R - Ro) / np.maximum(cn, 1e-300)[None, :]))
+
+
 def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True):
     m, n = A.shape
     print(f"case m={m} n={n} mb={mb} tree={tree}", flush=True)
-    orc = oracle.TSQR(A, mb=mb, tree=tree)
+    if tree == tl.TREE_XCD:
+        # the oracle runs the hierarchical schedule over its own domains (for
+        # n > 64 the GPU's first panel merges a short last domain by its own
+        # width, so the counts can differ; R, Q and x do not depend on it)
+        P = len(oracle.partition(m, n, mb))
+        sched = tl.tree_schedule(P, tree)
+        assert sorted(sched) == sorted(oracle.hierarchical_schedule([d % 8 for d in range(P)]))
+        orc = oracle.TSQR(A, mb=mb, sched=sched)
+    else:
+        orc = oracle.TSQR(A, mb=mb, tree=tree)
     Ad = dev(A)
     f = tl.factor(Ad, row_block=mb, tree=tree)
     R = host(f.R())
@@ -59,11 +87,14 @@ def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True):
     assert np.all(np.tril(R, -1) == 0.0)
     assert np.all(np.diag(R) >= 0.0)
     assert rel(R, Ro) <= 1e-12
+    r_entrywise(R, Ro)
     if full_q:
         Q = host(f.form_q())
         assert rel(Q @ R, A) <= 1e-13
         assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-13
-        assert rel(Q, orc.form_q()) <= 1e-12
+        Qo = orc.form_q()
+        assert rel(Q, Qo) <= 1e-12
+        colwise(Q, Qo, 1e-12)
     rng = np.random.default_rng(seed)
     B = rng.standard_normal((m, nrhs))
     Bd = dev(B)
@@ -71,6 +102,7 @@ def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True):
     C = host(Bd)
     Co = orc.apply_qt(B)
     assert rel(C[:n], Co[:n]) <= 1e-12
+    colwise(C[:n], Co[:n], 1e-12, scale=np.linalg.norm(B, axis=0))
     assert np.allclose(np.linalg.norm(C[n:], axis=0), np.linalg.norm(Co[n:], axis=0), rtol=1e-11,
                        atol=1e-13 * np.linalg.norm(B))
     f.apply_q_(Bd)
@@ -84,6 +116,9 @@ def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True):
         tan = reso[c] / max(np.linalg.norm(A @ Xo[:, c]), 1e-300)
         tol = max(1e-12, 10 * (kappa + kappa ** 2 * tan) * U)
         assert rel(host(X)[:, c], Xo[:, c]) <= tol
+        # entry by entry: x_i = e_i^T R^{-1} c, so each entry's error is
+        # bounded by the same relative tolerance times ||x||
+        assert np.max(np.abs(host(X)[:, c] - Xo[:, c])) <= tol * np.linalg.norm(Xo[:, c])
     assert np.allclose(host(res), reso, rtol=1e-11)
     return f
 
@@ -120,6 +155,11 @@ SHAPES = [
     # of full chunks, the drain after a domain's last chunk and into a tail
     (40000, 48, 4096, 2),
     (50002, 40, 2048, 4),
+    # the hierarchical (XCD) tree: P below, at and above the 8 XCDs, ragged
+    (5000, 16, 1024, 8),
+    (65536, 64, 4096, 8),
+    (100003, 33, 1024, 8),
+    (300000, 8, 2048, 8),
 ]
 
 
@@ -129,11 +169,72 @@ def test_shapes(tl, m, n, mb, tree):
     check_all(tl, A, mb, tree)
 
 
-@pytest.mark.parametrize("m,n,mb", [(5000, 65, 1024), (3000, 128, 512), (4096, 200, 1024),
-                                    (2048, 256, 512)])
-def test_wide_panels(tl, m, n, mb):
+def strided_view(A, row_off, extra_rows):
+    """A as a view into a taller column-major device matrix: leading
+    dimension m + extra_rows, first row at row_off (row_off odd: the view's
+    columns start off 16-byte boundaries)."""
+    m, n = A.shape
+    big = np.zeros((m + extra_rows, n))
+    big[row_off:row_off + m] = A
+    Bd = dev(big)
+    return Bd[row_off:row_off + m]
+
+
+@pytest.mark.parametrize("m,n,mb,row_off,extra", [
+    (10001, 24, 1001, 0, 0),     # odd row block: 8-byte loads for every chunk
+    (9000, 64, 2049, 0, 0),      # odd row block, wide kernel
+    (20000, 40, 2048, 0, 6),     # lda = m + 6 (even: 16-byte loads still allowed)
+    (20000, 40, 2048, 3, 8),     # row offset 3: columns start off 16-byte boundaries
+    (8193, 16, 1024, 1, 1),      # odd lda and odd offset, narrow kernel
+])
+def test_layouts(tl, m, n, mb, row_off, extra):
+    """Odd row blocks, a leading dimension larger than m and a view of A
+    that starts at an odd row (the leaf's 16-byte loads must fall back to
+    8-byte loads wherever a chunk would not start on a 16-byte boundary)."""
+    A = synth.gaussian(m, n, seed=m + n + row_off)
+    print(f"case layout m={m} n={n} mb={mb} row_off={row_off} lda={m + extra}", flush=True)
+    Ad = strided_view(A, row_off, extra)
+    assert Ad.stride(1) == m + extra
+    orc = oracle.TSQR(A, mb=mb)
+    f = tl.factor(Ad, row_block=mb)
+    R, Ro = host(f.R()), orc.R()
+    assert rel(R, Ro) <= 1e-12
+    r_entrywise(R, Ro)
+    Q = host(f.form_q())
+    Qo = orc.form_q()
+    colwise(Q, Qo, 1e-12)
+    b = np.random.default_rng(m).standard_normal((m, 1))
+    X, res, info = f.lsq(dev(b))
+    torch.cuda.synchronize()
+    Xo, reso, _ = orc.lsq(b)
+    assert int(info.item()) == 0
+    assert rel(host(X), Xo) <= 1e-12
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_nonfinite_input_info(tl, bad, prec):
+    """A NaN or an infinity in A: the factor completes (no pivoting, no
+    data-dependent loop), and the least-squares solve reports the documented
+    dinfo = -2 (non-finite residual)."""
+    m, n = 6000, 20
+    A = synth.gaussian(m, n, seed=77)
+    A[4321, 5] = bad
+    print(f"case non-finite A ({bad}, {prec})", flush=True)
+    Ad = dev(A)
+    f = tl.factor(Ad, row_block=1024, prec=tl.MIXED if prec == "mixed" else tl.F64)
+    b = dev(np.ones((m, 1)))
+    _, res, info = f.lsq(b, A=Ad)
+    torch.cuda.synchronize()
+    assert int(info.item()) == -2
+    assert not np.isfinite(host(res)[0])
+
+
+@pytest.mark.parametrize("m,n,mb,tree", [(5000, 65, 1024, 2), (3000, 128, 512, 2), (4096, 200, 1024, 2),
+                                         (2048, 256, 512, 2), (40000, 100, 1024, 8)])
+def test_wide_panels(tl, m, n, mb, tree):
     A = synth.gaussian(m, n, seed=m * 3 + n)
-    check_all(tl, A, mb, 2)
+    check_all(tl, A, mb, tree)
 
 
 def test_zero_column_info(tl):
@@ -258,8 +359,28 @@ def test_large_config_sampled(tl):
                                      [0, 63, 64, 4095, 4096, A.shape[0] - 1]]))
     Qo = orc.form_q()
     assert rel(host(Q[torch.as_tensor(rows, device="cuda")]), Qo[rows]) <= 1e-12
+    colwise(host(Q[torch.as_tensor(rows, device="cuda")]), Qo[rows], 1e-12,
+            scale=np.linalg.norm(Qo[rows], axis=0))
+    r_entrywise(host(R), Ro)
     # global identities in FP64 on the device (torch matmul only checks)
     G = Q.t() @ Q
     assert float(torch.linalg.norm(G - torch.eye(64, dtype=torch.float64, device="cuda"))) <= 1e-13
     E = Ad - Q @ R
     assert float(torch.linalg.norm(E) / torch.linalg.norm(Ad)) <= 1e-13
+    # the benchmark's right-hand side (seed 1): x against the oracle's x,
+    # through the separate solve and through the fused factor-solve call
+    b = synth.config_large_rhs()
+    Xo, reso, _ = orc.lsq(b)
+    X, res, info = f.lsq(dev(b.reshape(-1, 1)))
+    o = tl.opts(row_block=4096, lsq_max_rhs=1)
+    _, X2, res2, info2 = tl.factor_solve(Ad, dev(b.reshape(-1, 1)), o)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0 and int(info2.item()) == 0
+    kappa = np.linalg.cond(Ro)
+    tan = reso[0] / np.linalg.norm(A @ Xo[:, 0])
+    tol = max(1e-12, 10 * (kappa + kappa ** 2 * tan) * U)
+    for Xg in (host(X), host(X2)):
+        assert rel(Xg[:, 0], Xo[:, 0]) <= tol
+        assert np.max(np.abs(Xg[:, 0] - Xo[:, 0])) <= tol * np.linalg.norm(Xo[:, 0])
+    assert abs(host(res)[0] - reso[0]) <= 1e-11 * reso[0]
+    assert torch.equal(X, X2)

@@ -172,6 +172,35 @@ def test_paper_message_counts():
         assert _depth(oracle.schedule(P, 2), P) == case["critical_path_messages"]
 
 
+def test_hierarchical_schedule_inter_cluster_counts():
+    """The grid-tuned tree builder: G - 1 combines join two clusters (the
+    paper's inter-cluster message counts, Fig. 2 caption and Sec. 5), for
+    contiguous clusters and for clusters interleaved the way domains fall
+    on XCDs (domain d on cluster d mod G); every domain is combined into
+    another exactly once, the root is domain 0, and the tree applied by the
+    oracle gives the same R as the binary tree."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_counts.json")))
+    for case in g["tuned_tree_inter_cluster"]:
+        sizes = case["domains_per_cluster"]
+        contiguous = np.repeat(np.arange(len(sizes)), sizes).tolist()
+        P = len(contiguous)
+        rng = np.random.default_rng(P)
+        shuffled = rng.permutation(contiguous).tolist()
+        for group in (contiguous, shuffled):
+            sched = oracle.hierarchical_schedule(group)
+            assert sum(1 for l, r in sched if group[l] != group[r]) == case["inter_cluster_messages"]
+            assert sorted(r for _, r in sched) == [d for d in range(P) if d != 0]
+    for P in (1, 3, 8, 9, 64, 256):
+        group = [d % oracle.XCDS for d in range(P)]
+        sched = oracle.hierarchical_schedule(group)
+        assert sum(1 for l, r in sched if group[l] != group[r]) == min(P, oracle.XCDS) - 1
+    A = np.random.default_rng(3).standard_normal((9000, 12))
+    P = len(oracle.partition(9000, 12, 500))
+    R1 = oracle.TSQR(A, mb=500, sched=oracle.hierarchical_schedule([d % 8 for d in range(P)])).R()
+    R2 = oracle.TSQR(A, mb=500).R()
+    assert rel(R1, R2) <= 1e-13
+
+
 # ------------------------------------------------------------- whole TSQR
 
 def test_single_domain_is_unpartitioned_householder():
@@ -231,11 +260,40 @@ def test_shuffled_order_with_root_zero():
     assert rel(R1, R2) <= 1e-13
 
 
-@pytest.mark.parametrize("m,n,mb", [(4096, 16, 1024), (5003, 13, 700), (300, 30, 60)])
-def test_form_q_and_apply_qt(m, n, mb):
+def _shuffled_binary_schedule(P, rng):
+    """A binary tree over a random leaf order whose root is domain 0."""
+    order = [0] + (1 + rng.permutation(P - 1)).tolist()
+    sched, live = [], order[:]
+    while len(live) > 1:
+        nxt = []
+        for i in range(0, len(live) - 1, 2):
+            sched.append((live[i], live[i + 1]))
+            nxt.append(live[i])
+        if len(live) % 2:
+            nxt.append(live[-1])
+        live = nxt
+    return sched
+
+
+# (m, n, mb, tree): the binary, flat and 4-ary trees of Sec. 2.3, plus an
+# explicit schedule (a binary tree over a shuffled leaf order, "shuffled");
+# each with a ragged last domain in some cases.  Q and Q^T B follow the
+# factorization's tree, so every traversal is pinned to NumPy's QR.
+QSHAPES = [(4096, 16, 1024, 2), (5003, 13, 700, 2), (300, 30, 60, 2),
+           (5003, 13, 700, 0), (4096, 16, 512, 0), (300, 30, 60, 0),
+           (5003, 13, 700, 4), (9000, 20, 500, 4), (300, 30, 60, 4),
+           (7001, 11, 600, "shuffled"), (3000, 25, 100, "shuffled")]
+
+
+@pytest.mark.parametrize("m,n,mb,tree", QSHAPES)
+def test_form_q_and_apply_qt(m, n, mb, tree):
     rng = np.random.default_rng(7 * m + n)
     A = rng.standard_normal((m, n))
-    f = oracle.TSQR(A, mb=mb)
+    if tree == "shuffled":
+        P = len(oracle.partition(m, n, mb))
+        f = oracle.TSQR(A, mb=mb, sched=_shuffled_binary_schedule(P, rng))
+    else:
+        f = oracle.TSQR(A, mb=mb, tree=tree)
     Q, R = f.form_q(), f.R()
     assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-13
     assert rel(Q @ R, A) <= 1e-13
@@ -249,6 +307,12 @@ def test_form_q_and_apply_qt(m, n, mb):
     assert np.allclose(np.linalg.norm(C[n:], axis=0), tail_expected, rtol=1e-12)
     # Q^T is orthogonal: column norms are preserved
     assert np.allclose(np.linalg.norm(C, axis=0), np.linalg.norm(B, axis=0), rtol=1e-13)
+    # column by column: no small column of Q or Q^T B hides under a large one
+    for j in range(n):
+        assert np.linalg.norm(Q[:, j] - Qn[:, j] * d[j]) <= 1e-12
+    QtB = Q.T @ B
+    for c in range(3):
+        assert np.linalg.norm(C[:n, c] - QtB[:, c]) <= 1e-13 * np.linalg.norm(B[:, c])
 
 
 def test_lsq_against_lapack_and_consistent_rhs():
