@@ -196,6 +196,31 @@ TSQR_API int tsqr_factor_solve(int64_t m, int64_t n, const double *A, int64_t ld
                                double *resid, int32_t *dinfo, double *Q, int64_t ldq,
                                void *stream, tsqr_factors *out);
 
+/* Bytes of the device scratch array behind tsqr_factor_solve_noalloc (one
+   per GPU, held from the library's load until the process ends). */
+#define TSQR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+   factorization, least squares and, when Q / R are not NULL, the thin Q and
+   R of one matrix, with no allocation and no handle.  The arguments and
+   results are those of tsqr_factor_solve followed by tsqr_get_r (R: n x n,
+   ldr >= n); the three calls run in order on `stream`, so the results are
+   bitwise those of tsqr_factor_solve with the same options.  The workspace
+   is the library's own static device array of TSQR_NOALLOC_SCRATCH_BYTES on
+   the current GPU (its address is looked up at the first call on each
+   device): problems whose tsqr_workspace_bytes(m, n, o) exceeds that size
+   return TSQR_ERR_WORKSPACE.  Every call on one GPU shares that array, so
+   calls that overlap on one GPU race: order them (one stream, or events).
+   Errors: -1 m, -2 n, -3 A NULL, -4 lda, -5 opts, TSQR_ERR_UNSUPPORTED for
+   a precision other than TSQR_F64, TSQR_ERR_STATE for keep_q = 0,
+   TSQR_ERR_WORKSPACE (too large), -6 k, -7 B NULL, -8 ldb, -9 X NULL,
+   -10 ldx, -14 ldq, -16 ldr, -1000-e on a HIP error. */
+TSQR_API int tsqr_factor_solve_noalloc(int64_t m, int64_t n, const double *A, int64_t lda,
+                                       const tsqr_opts *o, int64_t k, const double *B, int64_t ldb,
+                                       double *X, int64_t ldx, double *resid, int32_t *dinfo,
+                                       double *Q, int64_t ldq, double *R, int64_t ldr, void *stream);
+
 /* Backward-error bounds of the last mixed-precision tsqr_lsq_solve on this
    handle, one per right-hand side (k <= that solve's k), copied to eta
    (device, k doubles) on `stream`: eta_j bounds ||A^T s_j|| / (||A||_F

@@ -137,6 +137,9 @@ def lib():
                                         i64, vp, ctypes.POINTER(vp)]
         L.tsqr_last_refine_iters.argtypes = [vp, vp]
         L.tsqr_lsq_backward_error.argtypes = [vp, i64, vp, vp]
+        L.tsqr_factor_solve_noalloc.argtypes = [i64, i64, vp, i64, op, i64, vp, i64, vp, i64, vp, vp, vp, i64,
+                                                vp, i64, vp]
+        L.tsqr_factor_solve_noalloc.restype = ctypes.c_int
         L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(i64)]
         L.tsqr_tree_schedule.argtypes = [i64, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
@@ -412,6 +415,39 @@ def factor_solve(A: torch.Tensor, B: torch.Tensor, o: Opts | None = None, work: 
     F = Factors.__new__(Factors)
     F.m, F.n, F.opts, F.work, F._h = m, n, o, work, h
     return F, X, resid, info
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def factor_solve_noalloc(A: torch.Tensor, B: torch.Tensor, o: Opts | None = None, X: torch.Tensor | None = None,
+                         resid: torch.Tensor | None = None, info: torch.Tensor | None = None,
+                         Q: torch.Tensor | None = None, R: torch.Tensor | None = None, stream=None):
+    """tsqr_factor_solve_noalloc: factor, least squares and (if given) the
+    thin Q and R with the library's static device scratch as the workspace
+    (no device allocation inside the call; the outputs are the caller's).
+    Returns (X, resid, info)."""
+    m, n = A.shape
+    k = 1 if B.dim() == 1 else B.shape[1]
+    o = o if o is not None else opts()
+    dev = A.device
+    if X is None:
+        X = empty_colmajor(n, k, device=dev)
+    if resid is None:
+        resid = torch.empty(k, dtype=torch.float64, device=dev)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+    pa, lda = _col_major(A, m, "A")
+    pb, ldb = _col_major(B, m, "B")
+    px, ldx = _col_major(X, n, "X")
+    pq, ldq = (0, m) if Q is None else _col_major(Q, m, "Q")
+    pr, ldr = (0, n) if R is None else _col_major(R, n, "R")
+    _check(lib().tsqr_factor_solve_noalloc(m, n, ctypes.c_void_p(pa), lda, ctypes.byref(o), k, ctypes.c_void_p(pb),
+                                           ldb, ctypes.c_void_p(px), ldx, ctypes.c_void_p(resid.data_ptr()),
+                                           ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(pq), ldq,
+                                           ctypes.c_void_p(pr), ldr, _stream(stream)),
+           "tsqr_factor_solve_noalloc")
+    return X, resid, info
 
 
 def factor(A: torch.Tensor, **kw) -> Factors:
