@@ -12,11 +12,10 @@ constexpr int kLdsStride = 65;
 
 // Leaf register tile: 16 column groups x 4 row groups per wave (lane =
 // 16 rg + cg), `ns` column slots per thread (16 ns columns) and
-// rows_per_thread(ns) rows per thread; 4 row groups per wave, so a chunk
-// has 4 * leaf_waves(ns) * rows_per_thread(ns) rows.
+// rows_per_thread(ns) rows per thread; 16 row groups per 256-thread
+// workgroup, so a chunk has 16 * rows_per_thread(ns) rows.
 __host__ __device__ constexpr int rows_per_thread(int ns) { return ns >= 2 ? 16 : 32; }
-__host__ __device__ constexpr int leaf_waves(int ns) { return ns > 0 ? 4 : 4; }
-__host__ __device__ constexpr int chunk_rows(int ns) { return 4 * leaf_waves(ns) * rows_per_thread(ns); }
+__host__ __device__ constexpr int chunk_rows(int ns) { return 16 * rows_per_thread(ns); }
 
 // The thread index, hidden from the optimizer: values derived from it are
 // then computed where they are used instead of being hoisted out of outer

@@ -36,15 +36,12 @@ constexpr int kWaves = 4;                  // waves per tree workgroup (and narr
 constexpr int kFactorThreads = 64 * kWaves;
 constexpr int kRowGroups = 4 * kWaves;     // row groups per 4-wave workgroup
 
-// Thread index as the step code uses it: for kernels that run two waves per
-// SIMD (NS = 2: two workgroups per CU; an 8-wave leaf: two waves of one
-// workgroup), 256 registers each, hidden from the optimizer so that
-// loop-invariant addresses and masks are not hoisted into spills; a 4-wave
-// wide kernel has the AGPRs to keep them.
+// Thread index as the step code uses it: for narrow panels (NS <= 2, two
+// workgroups per CU, 256 registers) hidden from the optimizer so that
+// loop-invariant addresses are not hoisted into spills; the wide kernel has
+// the AGPRs to keep them.
 template <int NS>
-__device__ __forceinline__ int step_tid() {
-    return (NS == 2 || leaf_waves(NS) > kWaves) ? local_tid() : (int)threadIdx.x;
-}
+__device__ __forceinline__ int step_tid() { return NS == 2 ? local_tid() : (int)threadIdx.x; }
 
 // LDS of the leaf and tree kernels with W waves per workgroup (about 75 KiB
 // for 4 waves, 83 KiB for 8).
@@ -241,12 +238,7 @@ __device__ __forceinline__ double read_lane(double v, int src) {
 // The next column's pre-update values are fetched into xn from their owner
 // lanes before the barrier, and every thread applies step j's update to
 // them itself (the same fma as the owner), so the next step needs no
-// shuffle on its critical path.  The 8-wave leaf (lean steps) has no
-// registers for xn: it fetches column j from its owner lanes at the start
-// of step j, and the other wave on its SIMD covers that latency.
-template <int NS, int W>
-constexpr bool lean_steps() { return W > kWaves; }
-
+// shuffle on its critical path.
 template <int NS, int RPT, int TJ, bool FIRST, int W>
 __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[RPT][NS],
                                          const int n, FactorSmemT<W> &sm, const bool want_t,
@@ -261,13 +253,6 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     // branches, so the wave keeps one execution mask.
     const bool own_j = FIRST && (rgw == j / RPT);
     const int ij = j % RPT;
-    constexpr bool LEAN = lean_steps<NS, W>();
-    if constexpr (LEAN) {
-        // column j (after step j - 1's update) from its owner lanes
-        const int src = (rg << 4) | q;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) x[i] = __shfl(c[i][TJ], src);
-    }
     double qv[NS];
     if (FIRST) {
 #pragma unroll
@@ -281,8 +266,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         }
     }
     // prefetch column j + 1 (pre-update) from its owner lane
-    if constexpr (LEAN) {
-    } else if (q < 15) {
+    if (q < 15) {
         const int src = (rg << 4) | (q + 1);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) xn[i] = __shfl(c[i][TJ], src);
@@ -327,7 +311,7 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
     double alpha = 0.0, en = 0.0, ev[NS];
     if (!FIRST) {
         alpha = sm.R[j * kLdsStride + j];
-        if constexpr (!LEAN) en = (j + 1 < n) ? sm.R[j * kLdsStride + j + 1] : 0.0;
+        en = (j + 1 < n) ? sm.R[j * kLdsStride + j + 1] : 0.0;
 #pragma unroll
         for (int t = 0; t < NS; ++t) ev[t] = sm.R[j * kLdsStride + cg + 16 * t];
     }
@@ -377,15 +361,15 @@ __device__ __forceinline__ void one_step(const int j, const int q, double (&c)[R
         else return read_lane(v[TJ], q < 15 ? q + 1 : q);
     };
     const double sig2 = at_j(dv, tot);
-    const double dn = (has_next && !LEAN) ? at_next(dv, tot) : 0.0;
+    const double dn = has_next ? at_next(dv, tot) : 0.0;
     if (FIRST) {
         alpha = at_j(ev, totq);
-        if (has_next && !LEAN) en = at_next(ev, totq);
+        if (has_next) en = at_next(ev, totq);
     }
     double beta, tau, s;
     householder_scalars(alpha, sig2, beta, tau, s);
     // the next column after this step's update (same fma as its owner)
-    if constexpr (!LEAN) {
+    {
         const double fn = (tau * fma(s, dn, en)) * s;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -450,15 +434,9 @@ __device__ __forceinline__ void qr_steps(double (&c)[RPT][NS], const int n, Fact
     for (int q = 0; q < 16; q += 2) {
         const int j = TJ * 16 + q;
         if (j >= n) return;
-        if constexpr (lean_steps<NS, W>()) {
-            one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xa, ss.rnew, ss.jprev);
-            if (j + 1 >= n) return;
-            one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xa, ss.xa, ss.rnew, ss.jprev);
-        } else {
-            one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
-            if (j + 1 >= n) return;
-            one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
-        }
+        one_step<NS, RPT, TJ, FIRST>(j, q, c, n, sm, want_t, ss.xa, ss.xb, ss.rnew, ss.jprev);
+        if (j + 1 >= n) return;
+        one_step<NS, RPT, TJ, FIRST>(j + 1, q + 1, c, n, sm, want_t, ss.xb, ss.xa, ss.rnew, ss.jprev);
     }
 }
 
@@ -493,10 +471,8 @@ __device__ __forceinline__ void chunk_qr(double (&c)[RPT][NS], const int n,
     const int w = tid >> 6, lane = tid & 63, cg = lane & 15, rg = lane >> 4;
     const int rgw = w * 4 + rg;
     StepState<NS, RPT> ss;
-    if constexpr (!lean_steps<NS, W>()) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
-    }
+    for (int i = 0; i < RPT; ++i) ss.xa[i] = __shfl(c[i][0], rg << 4);
     qr_all_steps<NS, RPT, FIRST, W>(std::make_integer_sequence<int, NS>{}, c, n, sm, want_t, ss, dr);
     __syncthreads();
     if (ss.jprev >= 0 && rgw == 0) {
@@ -744,20 +720,18 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
 }
 
 // Narrow panels (NS <= 2) fit two workgroups per CU (registers and LDS), which
-// hides step latency whenever there are more domains than CUs; the widest
-// (NS = 4) run 8 waves, two per SIMD, in one workgroup per CU.
+// hides step latency whenever there are more domains than CUs.
 template <int NS>
 constexpr int leaf_min_blocks() { return NS == 2 ? 2 : 1; }
 template <int NS>
-constexpr int leaf_threads() { return 64 * leaf_waves(NS); }
+constexpr int leaf_threads() { return kFactorThreads; }
 
-// A 4-wave wide FP64 leaf could stage half of each chunk's reflectors in
-// LDS; the 8-wave leaf has no LDS to spare for it.
+// The wide FP64 leaf stages half of each chunk's reflectors in LDS.
 template <int NS, typename VT>
-constexpr bool leaf_stages() { return NS == 4 && leaf_waves(NS) == kWaves && std::is_same<VT, double>::value; }
+constexpr bool leaf_stages() { return NS == 4 && std::is_same<VT, double>::value; }
 
 template <int NS>
-using LeafSmem = FactorSmemT<leaf_waves(NS)>;
+using LeafSmem = FactorSmem;
 
 template <int NS, typename VT, bool VEC>
 __global__ __launch_bounds__(leaf_threads<NS>(), leaf_min_blocks<NS>()) void k_leaf(const double *__restrict__ A, int64_t lda,
