@@ -93,7 +93,7 @@ def cpu_baseline(m: int, n: int, mb: int, passes: int, samples: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="single",
-                    choices=["single", "mixed", "batch", "serve", "sweep", "copy"])
+                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -114,7 +114,7 @@ def main():
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
-     "sweep": run_sweep, "copy": run_copy}[args.workload](args)
+     "sweep": run_sweep, "orth": run_orth, "copy": run_copy}[args.workload](args)
 
 
 def counted_traffic(kernel: str, m: int, n: int, mb: int):
@@ -300,6 +300,8 @@ def sub_records(args):
     t3 = time.perf_counter()
     sw = sweep_n(args, steps=10, warmup=2)
     t4 = time.perf_counter()
+    ob = measure_orth(args, steps=3, warmup=1)
+    t5 = time.perf_counter()
     return {
         "mixed_kappa1e6": {
             "workload": mx["config"]["workload"],
@@ -321,6 +323,10 @@ def sub_records(args):
             "mixed_p99_ms_saturated": round(sv["mixed_saturated"]["p99_ms"], 2),
             "sampled_eta_max": sv["sampled_eta_max"], "wall_s": round(t3 - t2, 1)},
         "n_sweep_m2p20": {**sw["by_n"], "wall_s": round(t4 - t3, 1)},
+        "block_krylov_orth": {
+            "workload": ob["config"]["workload"], "ms_per_loop": ob["ms_per_step"], "gflops": ob["value"],
+            "roofline_frac_hbm": ob["roofline"]["frac"], "proj_update_gbs": ob["proj_update_gbs"],
+            "basis_orthogonality_fro": ob["basis_orthogonality_fro"], "wall_s": round(t5 - t4, 1)},
     }
 
 
@@ -641,6 +647,86 @@ def measure_serve(args, requests, loads, mixed_pass):
         "sampled_eta_max": worst,
     }
     return line
+
+
+def run_orth(args):
+    print(json.dumps(measure_orth(args, steps=args.steps, warmup=args.warmup)), flush=True)
+
+
+def measure_orth(args, steps, warmup, m=1 << 20, b=16, nblocks=16):
+    """Block orthogonalisation inside a block Krylov loop: a basis of
+    `nblocks` blocks of b columns for a diagonal operator D, each new block
+    D Q_j orthogonalised against all previous ones (two block Gram-Schmidt
+    passes, then TSQR and the thin Q).  One step is the whole loop."""
+    import torch
+    import paper_0912_2572_amd as tl
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    W0 = torch.randn((b, m), generator=g, device=dev, dtype=torch.float64).t()
+    d = torch.linspace(1.0, 2.0, m, device=dev, dtype=torch.float64)
+    Vg = tl.empty_colmajor(m, nblocks * b, device=dev)
+    o = tl.opts(row_block=4096)
+    work = torch.empty(tl.lib().tsqr_block_orth_workspace_bytes(m, (nblocks - 1) * b, b, ctypes_ref(o)),
+                       dtype=torch.uint8, device=dev)
+    Hs = [tl.empty_colmajor(max(j * b, 1), b, device=dev) for j in range(nblocks)]
+    Rs = [tl.empty_colmajor(b, b, device=dev) for _ in range(nblocks)]
+
+    def step():
+        for j in range(nblocks):
+            Wj = Vg[:, j * b:(j + 1) * b]
+            if j == 0:
+                Wj.copy_(W0)
+                tl.block_orth(None, Wj, o, R=Rs[j], work=work)
+            else:
+                torch.mul(Vg[:, (j - 1) * b:j * b], d[:, None], out=Wj)
+                tl.block_orth(Vg[:, :j * b], Wj, o, H=Hs[j], R=Rs[j], work=work)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tl.prof_enable(True)
+    step()
+    torch.cuda.synchronize()
+    kern = tl.prof_query()
+    tl.prof_enable(False)
+    G = Vg.t() @ Vg
+    orth_err = float(torch.linalg.norm(G - torch.eye(nblocks * b, device=dev, dtype=torch.float64)))
+    # useful flops: four block products per block (2 m nv b each) and TSQR +
+    # thin Q of the m x b block (2 (2 m b^2 - 2 b^3 / 3))
+    flops = sum(4 * 2.0 * m * (j * b) * b + 2 * (2.0 * m * b * b - 2.0 * b ** 3 / 3.0) for j in range(nblocks))
+    # algorithmic HBM bytes: V read four times, W read/written by the
+    # projections, the block read by TSQR, V and Q written by TSQR
+    alg = sum(4 * 8.0 * m * j * b + 6 * 8.0 * m * b + 3 * 8.0 * m * b for j in range(nblocks))
+    upd_cnt, upd_ms = kern.get("orth_proj_update", (0, 0.0))
+    upd_bytes = sum(2 * (8.0 * m * j * b + 16.0 * m * b) for j in range(1, nblocks))
+    line = {
+        "metric": "block orthogonalisation (block Gram-Schmidt x2 + TSQR) Gflop/s in a block Krylov loop",
+        "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "Gflop/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic: first block N(0,1) (torch Philox seed 2), operator diag(linspace(1, 2, m))",
+        "config": {"workload": f"tsqr_block_krylov {m}x({nblocks}x{b})", "m": m, "b": b, "blocks": nblocks},
+        "roofline": {"kernel": "whole loop", "bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_step": alg},
+        "proj_update_gbs": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1) if upd_ms else None,
+        "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()},
+        "basis_orthogonality_fro": orth_err,
+    }
+    del Vg, work
+    torch.cuda.empty_cache()
+    return line
+
+
+def ctypes_ref(o):
+    import ctypes
+    return ctypes.byref(o)
 
 
 def run_copy(args):

@@ -231,6 +231,33 @@ TSQR_API int tsqr_factor_solve_noalloc(int64_t m, int64_t n, const double *A, in
    or no mixed solve yet), -2 k, -3 eta NULL. */
 TSQR_API int tsqr_lsq_backward_error(tsqr_factors f, int64_t k, double *eta, void *stream);
 
+/* ------------------------------------------------------------------------
+   Block orthogonalisation: the step block-iterative methods (block Krylov
+   solvers, block eigensolvers) repeat to grow an orthonormal basis, with
+   TSQR as the stable orthogonalisation of each new block (Scope section and
+   Sec. 6 of the paper).  For an orthonormal V (m x nv) and a new block W
+   (m x b): two passes of block classical Gram-Schmidt
+       H1 = V^T W,  W -= V H1,  H2 = V^T W,  W -= V H2,
+   then TSQR of the projected W (opts: row block and tree; FP64, keep_q
+   forced) and its sign-normalised thin Q written over W, so that on return
+       W_in = V H + Q R  with H = H1 + H2,  [V Q]^T [V Q] = I,  diag(R) >= 0.
+   ------------------------------------------------------------------------ */
+
+/* Device workspace for tsqr_block_orth (0 for arguments out of scope:
+   b < 1, b > 64, nv < 0, nv + b > m). */
+TSQR_API size_t tsqr_block_orth_workspace_bytes(int64_t m, int64_t nv, int64_t b, const tsqr_opts *o);
+
+/* V: m x nv (ldv >= m, orthonormal columns, read only; NULL when nv = 0),
+   W: m x b (ldw >= m; in: the new block, out: Q), H: nv x b (ldh >= nv;
+   unused when nv = 0), R: b x b (ldr >= b), all device, column-major.
+   dwork: >= tsqr_block_orth_workspace_bytes, 256-byte aligned.  Runs on
+   `stream`; allocates nothing.  Errors: -1 m, -2 nv (nv < 0 or nv + b > m),
+   -3 V NULL, -4 ldv, -5 b (1..64), -6 W NULL, -7 ldw, -8 H NULL, -9 ldh,
+   -10 R NULL, -11 ldr, -12 opts, TSQR_ERR_WORKSPACE, -1000-e. */
+TSQR_API int tsqr_block_orth(int64_t m, int64_t nv, const double *V, int64_t ldv, int64_t b, double *W,
+                             int64_t ldw, double *H, int64_t ldh, double *R, int64_t ldr, const tsqr_opts *o,
+                             void *dwork, size_t work_bytes, void *stream);
+
 /* Number of sweeps (the first solve included) the last mixed-precision
    tsqr_lsq_solve on this handle ran, the largest over its groups of 8
    right-hand sides; 0 for FP64 factors.  Host only; `stream` is unused. */

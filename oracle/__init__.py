@@ -246,3 +246,25 @@ class TSQR:
         if it < 0:
             raise np.linalg.LinAlgError("singular R")
         return x, it
+
+
+def block_orth(V, W, mb: int, tree: int = TREE_BINARY):
+    """One step of block orthogonalisation as block-iterative methods use
+    TSQR (Scope section and Sec. 6 of the paper: TSQR generates an
+    orthogonal basis stably): two passes of block classical Gram-Schmidt
+    against the orthonormal V (NumPy products in FP64), then TSQR of the
+    projected block.  Returns (Q, H, R) with W = V H + Q R."""
+    W = np.array(W, dtype=np.float64, copy=True)
+    m, b = W.shape
+    if V is None or V.shape[1] == 0:
+        H = np.zeros((0, b))
+    else:
+        V = np.asarray(V, dtype=np.float64)
+        H1 = V.T @ W
+        W = W - V @ H1
+        H2 = V.T @ W
+        W = W - V @ H2
+        H = H1 + H2
+    f = TSQR(W, mb=mb, tree=tree)
+    return f.form_q(), H, f.R()
+

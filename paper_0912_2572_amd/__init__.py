@@ -137,6 +137,10 @@ def lib():
                                         i64, vp, ctypes.POINTER(vp)]
         L.tsqr_last_refine_iters.argtypes = [vp, vp]
         L.tsqr_lsq_backward_error.argtypes = [vp, i64, vp, vp]
+        L.tsqr_block_orth_workspace_bytes.argtypes = [i64, i64, i64, op]
+        L.tsqr_block_orth_workspace_bytes.restype = sz
+        L.tsqr_block_orth.argtypes = [i64, i64, vp, i64, i64, vp, i64, vp, i64, vp, i64, op, vp, sz, vp]
+        L.tsqr_block_orth.restype = ctypes.c_int
         L.tsqr_factor_solve_noalloc.argtypes = [i64, i64, vp, i64, op, i64, vp, i64, vp, i64, vp, vp, vp, i64,
                                                 vp, i64, vp]
         L.tsqr_factor_solve_noalloc.restype = ctypes.c_int
@@ -448,6 +452,33 @@ def factor_solve_noalloc(A: torch.Tensor, B: torch.Tensor, o: Opts | None = None
                                            ctypes.c_void_p(pr), ldr, _stream(stream)),
            "tsqr_factor_solve_noalloc")
     return X, resid, info
+
+
+def block_orth(V: torch.Tensor | None, W: torch.Tensor, o: Opts | None = None, H: torch.Tensor | None = None,
+               R: torch.Tensor | None = None, work: torch.Tensor | None = None, stream=None):
+    """tsqr_block_orth: W <- Q with W_in = V H + Q R, [V Q] orthonormal (V may
+    be None for the first block).  W is overwritten; returns (W, H, R)."""
+    m, b = W.shape
+    nv = 0 if V is None else V.shape[1]
+    o = o if o is not None else opts()
+    dev = W.device
+    need = int(lib().tsqr_block_orth_workspace_bytes(m, nv, b, ctypes.byref(o)))
+    if need == 0:
+        raise ValueError(f"block_orth out of scope: m={m} nv={nv} b={b}")
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    if H is None and nv > 0:
+        H = empty_colmajor(nv, b, device=dev)
+    if R is None:
+        R = empty_colmajor(b, b, device=dev)
+    pv, ldv = (0, m) if V is None else _col_major(V, m, "V")
+    pw, ldw = _col_major(W, m, "W")
+    ph, ldh = (0, max(nv, 1)) if H is None else _col_major(H, nv, "H")
+    pr, ldr = _col_major(R, b, "R")
+    _check(lib().tsqr_block_orth(m, nv, ctypes.c_void_p(pv), ldv, b, ctypes.c_void_p(pw), ldw, ctypes.c_void_p(ph),
+                                 ldh, ctypes.c_void_p(pr), ldr, ctypes.byref(o), ctypes.c_void_p(work.data_ptr()),
+                                 work.numel(), _stream(stream)), "tsqr_block_orth")
+    return W, H, R
 
 
 def factor(A: torch.Tensor, **kw) -> Factors:

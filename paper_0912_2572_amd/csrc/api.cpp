@@ -614,6 +614,70 @@ TSQR_API int tsqr_lsq_backward_error(tsqr_factors f, int64_t k, double *eta, voi
     return e == hipSuccess ? 0 : hip_code(e);
 }
 
+static size_t orth_align(size_t x) { return (x + tsqr::kAlign - 1) / tsqr::kAlign * tsqr::kAlign; }
+
+static tsqr_opts orth_opts(const tsqr_opts *o) {
+    tsqr_opts q;
+    if (o) q = *o;
+    else tsqr_default_opts(&q);
+    q.keep_q = 1;
+    q.prec = TSQR_F64;
+    return q;
+}
+
+TSQR_API size_t tsqr_block_orth_workspace_bytes(int64_t m, int64_t nv, int64_t b, const tsqr_opts *o) {
+    if (nv < 0 || b < 1 || b > tsqr::kMaxPanel || nv + b > m) return 0;
+    const tsqr_opts q = orth_opts(o);
+    const size_t ws = tsqr_workspace_bytes(m, b, &q);
+    if (!ws) return 0;
+    const size_t part = sizeof(double) * (size_t)tsqr::proj_blocks(m) * (size_t)nv * (size_t)b;
+    return orth_align(ws) + orth_align(part) + orth_align(sizeof(double) * (size_t)nv * (size_t)b);
+}
+
+TSQR_API int tsqr_block_orth(int64_t m, int64_t nv, const double *V, int64_t ldv, int64_t b, double *W,
+                             int64_t ldw, double *H, int64_t ldh, double *R, int64_t ldr, const tsqr_opts *o,
+                             void *dwork, size_t work_bytes, void *stream) {
+    if (m < 1) return -1;
+    if (nv < 0 || nv + b > m) return -2;
+    if (nv > 0 && !V) return -3;
+    if (nv > 0 && ldv < m) return -4;
+    if (b < 1 || b > tsqr::kMaxPanel) return -5;
+    if (!W) return -6;
+    if (ldw < m) return -7;
+    if (nv > 0 && !H) return -8;
+    if (nv > 0 && ldh < nv) return -9;
+    if (!R) return -10;
+    if (ldr < b) return -11;
+    const tsqr_opts q = orth_opts(o);
+    Plan plan;
+    int rc = tsqr::make_plan(m, b, &q, &plan);
+    if (rc) return -12;
+    const size_t need = tsqr_block_orth_workspace_bytes(m, nv, b, &q);
+    if (!dwork || need == 0 || work_bytes < need || (reinterpret_cast<uintptr_t>(dwork) % tsqr::kAlign))
+        return TSQR_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(dwork);
+    const size_t ws = orth_align(plan.total);
+    double *Hpart = reinterpret_cast<double *>(base + ws);
+    double *H2 = reinterpret_cast<double *>(
+        base + ws + orth_align(sizeof(double) * (size_t)tsqr::proj_blocks(m) * (size_t)nv * (size_t)b));
+    if (nv > 0) {
+        const int iv = (int)nv, ib = (int)b;
+        // two passes of block classical Gram-Schmidt
+        TRY(tsqr::launch_proj(V, ldv, iv, W, ldw, ib, m, Hpart, H, ldh, nullptr, 0, st));
+        TRY(tsqr::launch_proj_update(V, ldv, iv, H, ldh, W, ldw, ib, m, st));
+        TRY(tsqr::launch_proj(V, ldv, iv, W, ldw, ib, m, Hpart, H2, nv, H, ldh, st));
+        TRY(tsqr::launch_proj_update(V, ldv, iv, H2, nv, W, ldw, ib, m, st));
+    }
+    // TSQR of the projected block; its thin Q replaces it
+    tsqr_factors_s f;
+    rc = tsqr::factor_into(&f, m, b, W, ldw, &q, dwork, ws, st);
+    if (rc) return rc;
+    rc = tsqr_form_q(&f, W, ldw, stream);
+    if (!rc) rc = tsqr_get_r(&f, R, ldr, stream);
+    return rc;
+}
+
 TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream) {
     (void)stream;
     return f ? f->last_refine : -1;

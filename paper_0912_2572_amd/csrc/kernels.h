@@ -153,6 +153,17 @@ hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ld
                              double *X, int64_t ldx, double *resid, int32_t *dinfo, double *partial,
                              hipStream_t st);
 
+// orth.hip: block Gram-Schmidt projections against an orthonormal basis.
+constexpr int kProjMaxBlocks = 512;   // row blocks of the partial products
+int proj_blocks(int64_t m);
+// H = V^T W (nv x b, ld ldh) through per-block partials (Hpart: proj_blocks(m)
+// x nv x b doubles); if Hacc, also Hacc += H.
+hipError_t launch_proj(const double *V, int64_t ldv, int nv, const double *W, int64_t ldw, int b, int64_t m,
+                       double *Hpart, double *H, int64_t ldh, double *Hacc, int64_t ldacc, hipStream_t st);
+// W -= V H.
+hipError_t launch_proj_update(const double *V, int64_t ldv, int nv, const double *H, int64_t ldh, double *W,
+                              int64_t ldw, int b, int64_t m, hipStream_t st);
+
 // refine.hip: FP64 pieces of the mixed-precision least-squares refinement.
 int resid_blocks(int64_t m);
 hipError_t launch_lsq_resid(const double *A, int64_t lda, int64_t m, int n, const double *B, int64_t ldb,

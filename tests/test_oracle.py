@@ -484,3 +484,46 @@ def test_refined_reference_converges_on_ill_conditioned_lsq():
     r = b - A @ x
     eta = np.linalg.norm(A.T @ r) / (np.linalg.norm(A) * (np.linalg.norm(A) * np.linalg.norm(x) + np.linalg.norm(b)))
     assert eta <= 1e-15
+
+
+# ------------------------------------------------- block orthogonalisation
+
+@pytest.mark.parametrize("m,nv,b,mb", [(5000, 0, 8, 1000), (5000, 24, 8, 1000), (3001, 40, 13, 700),
+                                       (2000, 100, 32, 512)])
+def test_block_orth_invariants(m, nv, b, mb):
+    """The oracle's block orthogonalisation step against what the
+    mathematics fixes: [V Q] orthonormal, W = V H + Q R, R upper triangular
+    with diag >= 0, H = V^T W (exactly in exact arithmetic, since V^T (W - V H1)
+    = 0 for orthonormal V), and with no basis it is plain TSQR."""
+    rng = np.random.default_rng(m + nv + b)
+    V = np.linalg.qr(rng.standard_normal((m, nv)))[0] if nv else None
+    W = rng.standard_normal((m, b))
+    Q, H, R = oracle.block_orth(V, W, mb)
+    B = Q if V is None else np.hstack([V, Q])
+    assert np.linalg.norm(B.T @ B - np.eye(B.shape[1])) <= 1e-13
+    recon = Q @ R if V is None else V @ H + Q @ R
+    assert rel(recon, W) <= 1e-14
+    assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) >= 0.0)
+    if V is not None:
+        assert rel(H, V.T @ W) <= 1e-14
+    else:
+        assert rel(R, oracle.TSQR(W, mb=mb).R()) == 0.0
+
+
+def test_block_orth_of_a_block_in_the_complement():
+    """A block already orthogonal to V has H = 0 and Q R = W; a block inside
+    span(V) plus a small complement keeps orthogonality to V (the second
+    pass), the case a single Gram-Schmidt pass gets wrong."""
+    rng = np.random.default_rng(5)
+    m, nv, b = 4000, 30, 6
+    V = np.linalg.qr(rng.standard_normal((m, nv)))[0]
+    G = rng.standard_normal((m, b))
+    W = G - V @ (V.T @ G)
+    Q, H, R = oracle.block_orth(V, W, 800)
+    assert np.linalg.norm(H) <= 1e-14 * np.linalg.norm(W)
+    assert rel(Q @ R, W) <= 1e-14
+    W2 = V @ rng.standard_normal((nv, b)) + 1e-8 * G
+    Q2, H2, R2 = oracle.block_orth(V, W2, 800)
+    assert np.linalg.norm(V.T @ Q2) <= 1e-13
+    assert rel(V @ H2 + Q2 @ R2, W2) <= 1e-14
+
