@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--row-block", type=int, default=4096)
+    ap.add_argument("--tree", default="binary", choices=["binary", "quad", "flat", "xcd"],
+                    help="single workload: reduction tree (xcd: each XCD's domains first)")
     ap.add_argument("--cpu-passes", type=int, default=7)
     ap.add_argument("--no-sub", action="store_true",
                     help="single workload: leave out the compact mixed / batch / serve / n-sweep records")
@@ -117,13 +119,13 @@ def main():
      "sweep": run_sweep, "orth": run_orth, "copy": run_copy}[args.workload](args)
 
 
-def counted_traffic(kernel: str, m: int, n: int, mb: int):
-    """HBM bytes per launch from the committed counter record of this kernel
-    and workload (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None
-    when there is none or the kernel's sources changed since it was taken."""
+def counter_record(kernel: str, m: int, n: int, mb: int, tree: str, kind: str):
+    """The committed counter record profiles/<kernel>_<m>x<n>_<kind>.json of
+    this kernel and workload (row block 4096, binary tree), or None when there
+    is none or the kernel's sources changed since its counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{m}x{n}_hbm.json")
-    if not os.path.exists(path) or mb != 4096:
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{m}x{n}_{kind}.json")
+    if not os.path.exists(path) or mb != 4096 or tree != "binary":
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
@@ -131,7 +133,14 @@ def counted_traffic(kernel: str, m: int, n: int, mb: int):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest() != rec["sources_sha256"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
+
+
+def counted_traffic(kernel: str, m: int, n: int, mb: int, tree: str):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by a plain
+    copy) from the kernel's counter record, or None."""
+    rec = counter_record(kernel, m, n, mb, tree, "hbm")
+    return rec["traffic_bytes_per_launch"] if rec else None
 
 
 def run_single(args):
@@ -153,7 +162,10 @@ def measure_single(args, m, n, mb, steps, warmup):
     dev = torch.device("cuda:0")
     A = torch.as_tensor(synth.config_large(m, n, seed=0)).t().contiguous().t().to(dev)
     b = torch.as_tensor(synth.config_large_rhs(m, seed=1)).to(dev)
-    o = tl.opts(row_block=mb, tree=tl.TREE_BINARY, keep_q=True, lsq_max_rhs=1)
+    tree_name = getattr(args, "tree", "binary")
+    tree = {"binary": tl.TREE_BINARY, "quad": tl.TREE_QUAD, "flat": tl.TREE_FLAT,
+            "xcd": tl.TREE_XCD}[tree_name]
+    o = tl.opts(row_block=mb, tree=tree, keep_q=True, lsq_max_rhs=1)
     work = torch.empty(tl.workspace_bytes(m, n, o), dtype=torch.uint8, device=dev)
     Q = tl.empty_colmajor(m, n, device=dev)
     X = tl.empty_colmajor(n, 1, device=dev)
@@ -238,8 +250,13 @@ def measure_single(args, m, n, mb, steps, warmup):
         gbs = ab / avg_s / 1e9
         roof = {"kernel": dom_name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": counted_traffic(dom_name, m, n, mb),
+                "traffic": counted_traffic(dom_name, m, n, mb, tree_name),
                 "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": ab}
+        util = counter_record(dom_name, m, n, mb, tree_name, "util")
+        if util:
+            # matrix-core and vector-ALU use of the same kernel from its
+            # committed SQ counter record (fractions of the FP64 peak)
+            roof.update({k: util[k] for k in ("mfma_util", "valu_fp64_frac", "valu_issue_busy")})
     line = {
         "metric": "TSQR Gflop/s (factor + thin Q + LSQ), FP64",
         "value": round(value, 2),
@@ -254,7 +271,7 @@ def measure_single(args, m, n, mb, steps, warmup):
         "dtype": "f64",
         "data": "synthetic iid N(0,1), seed 0",
         "config": {"workload": f"tsqr_factor_formq_lsq {m}x{n}", "m": m, "n": n, "row_block": mb,
-                   "domains": P, "chunk_rows": chunk, "tree": "binary", "rhs": 1,
+                   "domains": P, "chunk_rows": chunk, "tree": tree_name, "rhs": 1,
                    "parallelism": "single GPU",
                    "streams": ("one tsqr_factor_solve call: the solve's leaf pass beside the tree, its tree "
                                "pass beside the thin Q" if not args.separate_calls else
