@@ -215,6 +215,7 @@ static int factor_enqueue(tsqr_factors_s *f, const double *A, int64_t lda, hipSt
             TreeArgs ta{L.stride, L.span, L.chains, L.width};
             e = tsqr::launch_tree_level(Rdom, Tnode, pa, ta, keep, st);
         }
+        if (e == hipSuccess && keep) e = tsqr::launch_tree_t(Tnode, pa, st);
         if (e == hipSuccess)
             e = tsqr::launch_sign_normalise(Rdom, p.n, R, n, p.row_off, p.col_off, dsign, st);
         if (e != hipSuccess) {
@@ -515,6 +516,7 @@ int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t
         TreeArgs ta{L.stride, L.span, L.chains, L.width};
         TRY(tsqr::launch_tree_level(Rdom, Tnode, pa, ta, 1, st));
     }
+    TRY(tsqr::launch_tree_t(Tnode, pa, st));
     TRY(tsqr::launch_sign_normalise(Rdom, p.n, at<double>(f, P.off_r), P.n, p.row_off, p.col_off,
                                     at<double>(f, P.off_d), st));
     TRY(hipEventRecord(fj.tree, st));

@@ -166,11 +166,14 @@ int enqueue(tsqr_batch_s *B, hipStream_t st, int *launches) {
         TRYB(tsqr::launch_leaf_b(D, L(g), g.cnt, g.maxP, g.ns, st));
         ++nl;
     }
-    for (const Group &g : B->cls)
+    for (const Group &g : B->cls) {
         for (int lv = 0; lv < g.maxLev; ++lv) {
             TRYB(tsqr::launch_tree_b(D, L(g), g.cnt, g.up[lv], g.ns, lv, st));
             ++nl;
         }
+        TRYB(tsqr::launch_tree_t_b(D, L(g), g.cnt, g.maxP, st));
+        ++nl;
+    }
     const Group &A = B->all;
     TRYB(tsqr::launch_sign_b(D, L(A), A.cnt, st));
     TRYB(tsqr::launch_lsq_init_b(D, L(A), A.cnt, (A.maxM + 2047) / 2048, st));

@@ -96,6 +96,9 @@ hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, dou
                        const PanelArgs &pa, int keep_q, hipStream_t st);
 hipError_t launch_tree_level(double *Rdom, double *Tnode, const PanelArgs &pa, const TreeArgs &ta,
                              int keep_q, hipStream_t st);
+// T of every tree node (nodes 1 .. P - 1) from the Gram entries and tau the
+// levels stored; launched once after the last level when Q is kept.
+hipError_t launch_tree_t(double *Tnode, const PanelArgs &pa, hipStream_t st);
 // The same leaf with the reflectors stored in FP32 (mixed precision).
 hipError_t launch_leaf32(const double *A, int64_t lda, float *V, int64_t ldv, double *Tc, double *Rdom,
                          const PanelArgs &pa, int keep_q, hipStream_t st);
@@ -183,6 +186,7 @@ hipError_t launch_mixed_final(const double *R, int n, int k, const double *Xw, d
 hipError_t launch_leaf_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, hipStream_t st);
 hipError_t launch_tree_b(const BMat *mats, const int *list, int cnt, int64_t gx, int ns, int level,
                          hipStream_t st);
+hipError_t launch_tree_t_b(const BMat *mats, const int *list, int cnt, int64_t maxP, hipStream_t st);
 hipError_t launch_sign_b(const BMat *mats, const int *list, int cnt, hipStream_t st);
 // Q^T (trans = 1) or Q (trans = 0) on F, leaves, in three chunk-parallel
 // passes (grid.x: max_chunks for passes 1 and 3, max_p for pass 2); sweep > 0
