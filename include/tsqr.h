@@ -87,7 +87,9 @@ typedef struct {
     int32_t refine_max_iter; /* mixed: refinement sweeps after the first   */
                              /* solve (cap)                                */
     int32_t reserved;
-    double refine_tol;       /* stop when ||dx|| <= tol ||x||               */
+    double refine_tol;       /* stop when the error left, estimated as
+                                ||dx|| times the sweep-to-sweep contraction
+                                ||dx|| / ||dx_prev||, is <= tol ||x||       */
 } tsqr_opts;
 
 /* Opaque host handle describing one factorization.  It points into the
@@ -345,7 +347,8 @@ TSQR_API size_t tsqr_batch_workspace_bytes(int count, const tsqr_batch_item *ite
 /* Plans the batch (host), writes its device descriptors into dwork (256-byte
    aligned, >= tsqr_batch_workspace_bytes) on `stream`, and returns a host
    handle.  refine_sweeps: refinement sweeps after the first solve for the
-   mixed matrices (each stops early on its own once ||dx|| <= refine_tol ||x||
+   mixed matrices (each stops early on its own once its estimated remaining
+   error (||dx|| times the observed contraction) is <= refine_tol ||x||
    or it stalls; the sweeps are part of the captured graph, so no host
    synchronisation happens inside a run).  Errors: -1 count, -2 items (an
    item out of scope: its index is reported by tsqr_batch_bad_item), -3 tune,

@@ -269,9 +269,13 @@ __global__ __launch_bounds__(256) void k_lsq_resid(const double *__restrict__ A,
 // with d_1 = F[0:n] (= (Q^T f)[0:n] on entry);  X += dx;  F[0:n] = h.
 // status[0] = sweeps done, status[1] = 1 when converged or stalled,
 // hist[c] = ||dx_c|| / ||x_c|| of the last sweep and, if gnorm is set,
-// gnorm[c] = ||g_c||.  A sweep counts as
-// final when every column either met the tolerance or stalled (its
-// correction shrank by less than 10 %).
+// gnorm[c] = ||g_c||.  A sweep counts as final when every column either
+// converged or stalled (its correction shrank by less than 10 %).  A column
+// has converged when the error left after this sweep's correction,
+// estimated as rho ||dx|| with rho = ||dx|| / ||dx_prev|| the observed
+// contraction of the iteration (at most 1), is below tol ||x|| -- so a
+// sweep whose correction is already far below the tolerance is not needed
+// just to confirm it.
 __device__ __forceinline__ void refine_step(const double *__restrict__ R, int n, double *__restrict__ F,
                                             int64_t m, int k, const double *__restrict__ gpart, int nblocks,
                                             double *__restrict__ X, int64_t ldx, double tol,
@@ -348,7 +352,8 @@ __device__ __forceinline__ void refine_step(const double *__restrict__ R, int n,
             b = wave_sum(b);
             const double rel = sqrt(a) / fmax(sqrt(b), 1e-300);
             const double prev = hist[c];
-            const bool done = (rel <= tol) || (status[0] >= 1 && rel > 0.9 * prev) || !(rel == rel);
+            const double rho = (status[0] >= 1 && prev > 0.0) ? fmin(rel / prev, 1.0) : 1.0;
+            const bool done = (rho * rel <= tol) || (status[0] >= 1 && rel > 0.9 * prev) || !(rel == rel);
             all_ok = all_ok && done;
             if (lane == 0) hist[c] = rel;
         }
