@@ -205,11 +205,11 @@ static int factor_enqueue(tsqr_factors_s *f, const double *A, int64_t lda, hipSt
         const int keep = (f->keep_q || q < np - 1) ? 1 : 0;
         double *Rdom = at<double>(f, p.off_rdom);
         double *Tnode = at<double>(f, p.off_tnode);
+        double *Tc = at<double>(f, p.off_tc);
         hipError_t e =
             (plan.opts.prec == TSQR_MIXED)
-                ? tsqr::launch_leaf32(src_p, lds, at<float>(f, plan.off_w32) + (V - W), m,
-                                      at<double>(f, p.off_tc), Rdom, pa, keep, st)
-                : tsqr::launch_leaf(src_p, lds, V, m, at<double>(f, p.off_tc), Rdom, pa, keep, st);
+                ? tsqr::launch_leaf32(src_p, lds, at<float>(f, plan.off_w32) + (V - W), m, Tc, Rdom, pa, keep, st)
+                : tsqr::launch_leaf(src_p, lds, V, m, Tc, Rdom, pa, keep, st);
         for (const auto &L : tsqr::tree_levels(p.P, p.tree)) {
             if (e != hipSuccess) break;
             TreeArgs ta{L.stride, L.span, L.chains, L.width};
@@ -494,8 +494,9 @@ int fork_join_for_current_device(ForkJoin **out) {
 
 // The fork/join schedule of tsqr_factor_solve for a single-panel FP64
 // factor (caller holds g_fork_mu).  main: leaf, tree, signs, thin Q.  aux:
-// after the leaf, the solve's copy and leaf pass of Q^T B; after the tree,
-// its tree pass and the triangular solve.  main finally waits for aux.
+// after the leaf, the chunks' T factors and the solve's copy and leaf pass
+// of Q^T B; after the tree, its tree pass and the triangular solve.  main
+// finally waits for aux.
 int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t k, const double *B,
                         int64_t ldb, double *X, int64_t ldx, double *resid, int32_t *dinfo, double *Q,
                         int64_t ldq, hipStream_t st, const ForkJoin &fj) {
@@ -507,9 +508,14 @@ int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t
     double *Tnode = at<double>(f, p.off_tnode);
     double *C = at<double>(f, P.off_lsq);
     const auto levels = tsqr::tree_levels(p.P, p.tree);
-    TRY(tsqr::launch_leaf(A, lda, W, P.m, at<double>(f, p.off_tc), Rdom, pa, 1, st));
+    double *Tc = at<double>(f, p.off_tc);
+    TRY(tsqr::launch_leaf(A, lda, W, P.m, Tc, Rdom, pa, 2, st));
     TRY(hipEventRecord(fj.leaf, st));
     TRY(hipStreamWaitEvent(fj.aux, fj.leaf, 0));
+    // the chunks' T factors (the leaf stored their Gram entries), beside the
+    // tree: the tree does not read them; the solve's leaf pass and the thin
+    // Q's leaf kernel (after fj.done) do
+    TRY(tsqr::launch_chunk_t(Tc, pa, p.total_chunks, fj.aux));
     TRY(tsqr::launch_copy(B, ldb, C, P.m, P.m, k, fj.aux));
     TRY(leaf_apply(f, p, C, P.m, C, P.m, k, 1, fj.aux));
     for (const auto &L : levels) {

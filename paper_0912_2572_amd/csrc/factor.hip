@@ -543,6 +543,17 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
     const int n = pa.n;
     const int64_t nn = (int64_t)n * n;
     const bool want_t = keep_q != 0;
+    // keep_q == 2: each chunk's Gram entries and tau go to its T slot and
+    // k_chunk_t builds the T factors after the leaf, off the chunk loop
+    const bool defer_t = keep_q == 2;
+    auto chunk_t_out = [&](double *dst) {
+        if (defer_t) {
+            store_gram(sm, dst, n);
+        } else {
+            build_t(sm, n);
+            store_tri(sm.T, dst, n);
+        }
+    };
     zero_lds(sm.R);
     zero_lds(sm.T);
     __syncthreads();
@@ -553,8 +564,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
         chunk_qr<NS, RPT, true>(c, n, sm, want_t);
         if (want_t) {
             store_chunk<NS, RPT, VT, W>(c, V + row0, ldv, tail, n);
-            build_t(sm, n);
-            store_tri(sm.T, Tc + dom * pa.cpd * nn, n);
+            chunk_t_out(Tc + dom * pa.cpd * nn);
         }
         __syncthreads();
     } else {
@@ -587,10 +597,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
             }
             const bool more = ch + 1 < nfull;
             issue_full_chunk<NS, RPT, VEC>(c, A + row0 + (more ? ch + 1 : 0) * ROWS, lda, n, more);
-            if (want_t) {
-                build_t(sm, n);
-                store_tri(sm.T, Tc + (dom * pa.cpd + ch) * nn, n);
-            }
+            if (want_t) chunk_t_out(Tc + (dom * pa.cpd + ch) * nn);
             __syncthreads();
         }
         if constexpr (STAGE) {
@@ -625,6 +632,50 @@ __global__ __launch_bounds__(leaf_threads<NS>(), leaf_min_blocks<NS>()) void k_l
     constexpr bool S = leaf_stages<NS, VT>();
     leaf_domain<NS, VT, VEC, S>(sm, A, lda, V, ldv, Tc, Rdom, pa, keep_q, blockIdx.x,
                                 S ? smem_raw + sizeof(LeafSmem<NS>) / sizeof(double) : nullptr);
+}
+
+// T of every chunk of the panel (the leaf left each chunk's Gram entries and
+// tau in its slot: keep_q == 2), slots 0 .. total - 1.  Workgroup b takes
+// slots b, b + gridDim.x, ...; the next slot's entries are loaded into
+// registers while the current T is built, so each slot costs one memory
+// round trip less than a workgroup per slot.
+__global__ __launch_bounds__(kFactorThreads) void k_chunk_t(double *__restrict__ Tc, int64_t total, int n) {
+    extern __shared__ double smem_raw[];
+    TBuildSmem &sm = *reinterpret_cast<TBuildSmem *>(smem_raw);
+    const int64_t nn = (int64_t)n * n;
+    constexpr int kPer = 64 * 64 / kFactorThreads;
+    if (n % 16 != 0) {
+        // build_t's block products read Gram entries of the last 16-column
+        // block past n (times zero); nothing below writes them
+        for (int e = threadIdx.x; e < 64 * kLdsStride; e += kFactorThreads) sm.T[e] = 0.0;
+    }
+    double gv[kPer];
+    auto fetch = [&](int64_t g) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + kFactorThreads * u;
+            gv[u] = (e < n * n) ? Tc[g * nn + e] : 0.0;
+        }
+    };
+    int64_t g = blockIdx.x;
+    if (g < total) fetch(g);
+    for (; g < total; g += gridDim.x) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + kFactorThreads * u;
+            if (e < n * n) {
+                const int r = e % n, c = e / n;
+                if (r > c) sm.T[r * kLdsStride + c] = gv[u];
+                else if (r == c) sm.tau[r] = gv[u];
+            }
+        }
+        const int64_t next = g + gridDim.x;
+        if (next < total) fetch(next);
+        __syncthreads();
+        build_t(sm, n);
+        store_tri(sm.T, Tc + g * nn, n);
+    }
 }
 
 // ---- batched forms: grid.y walks the matrix list, grid.x the domains /
@@ -702,6 +753,18 @@ static hipError_t launch_leaf_t(const double *A, int64_t lda, VT *V, int64_t ldv
         case 2: return launch_leaf_ns<2, VT>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
         default: return launch_leaf_ns<4, VT>(A, lda, V, ldv, Tc, Rdom, pa, keep_q, tag, st);
     }
+}
+
+hipError_t launch_chunk_t(double *Tc, const PanelArgs &pa, int64_t total_chunks, hipStream_t st) {
+    if (total_chunks <= 0) return hipSuccess;
+    const size_t sh = sizeof(TBuildSmem);
+    hipError_t e = hipFuncSetAttribute((const void *)k_chunk_t, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    ProfScope ps("chunk_t", st);
+    // two workgroups per CU (the LDS fits two)
+    const int64_t grid = total_chunks < 512 ? total_chunks : 512;
+    hipLaunchKernelGGL(k_chunk_t, dim3((unsigned)grid), dim3(kFactorThreads), sh, st, Tc, total_chunks, pa.n);
+    return hipGetLastError();
 }
 
 hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, double *Tc, double *Rdom,

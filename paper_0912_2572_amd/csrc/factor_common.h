@@ -31,8 +31,19 @@ struct FactorSmemT {
 using FactorSmem = FactorSmemT<kWaves>;
 
 // Gram entry G[k][j] = y_k . y_j (k < j), kept in the lower triangle of T.
-template <int W>
-__device__ __forceinline__ double &gram(FactorSmemT<W> &sm, int k, int j) { return sm.T[j * kLdsStride + k]; }
+template <typename SM>
+__device__ __forceinline__ double &gram(SM &sm, int k, int j) { return sm.T[j * kLdsStride + k]; }
+
+// The LDS that build_t alone needs (T with the Gram entries below it, the
+// block scratch, tau): about 42 KiB, so that T builds can share a CU with
+// a tree combine's workgroup.
+struct TBuildSmem {
+    double T[64 * kLdsStride];
+    union {
+        double P[64 * 16];
+    } u;
+    double tau[64];
+};
 
 // Compact-WY factor T of the chunk (Sec. 2.2: H_1...H_n = I - V T V^T),
 // built once per chunk from tau and the Gram matrix G = Y^T Y by the
@@ -43,8 +54,8 @@ __device__ __forceinline__ double &gram(FactorSmemT<W> &sm, int k, int j) { retu
 //     T[0:16J, J] = -T[0:16J, 0:16J] (G[0:16J, J] T_JJ),
 // as FP64 MFMA tiles.
 // Waves past the fourth (8-wave leaves) take part in the barriers only.
-template <int W>
-__device__ __forceinline__ void build_t(FactorSmemT<W> &sm, const int n) {
+template <typename SM>
+__device__ __forceinline__ void build_t(SM &sm, const int n) {
     const int tid = local_tid(), lane = tid & 63, w = tid >> 6;
     const int j0 = 16 * w;
     double trow[16];
@@ -122,6 +133,37 @@ __device__ __forceinline__ void store_tri(const double *lds, double *__restrict_
 
 __device__ __forceinline__ void zero_lds(double *lds) {
     for (int e = threadIdx.x; e < 64 * kLdsStride; e += blockDim.x) lds[e] = 0.0;
+}
+
+// Gram entries and tau of a chunk's or a tree node's reflectors, for its T
+// (built later by node_t):
+// dst (n x n, column-major) gets G[c][r] = y_c . y_r at (r, c) for r > c
+// and tau_r at (r, r).
+__device__ __forceinline__ void store_gram(const FactorSmem &sm, double *__restrict__ dst, int n) {
+    for (int e = threadIdx.x; e < n * n; e += kFactorThreads) {
+        const int r = e % n, c = e / n;
+        dst[e] = (r > c) ? sm.T[r * kLdsStride + c] : ((r == c) ? sm.tau[r] : 0.0);
+    }
+}
+
+// T from the Gram entries and tau that store_gram left in Tn, by the
+// forward recurrence of build_t; T overwrites them.
+__device__ __forceinline__ void node_t(FactorSmem &sm, double *__restrict__ Tn, int n) {
+    // build_t's block products read Gram entries of the last 16-column block
+    // past n (times zero) when n is not a multiple of 16
+    if (n % 16 != 0) {
+        zero_lds(sm.T);
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n * n; e += kFactorThreads) {
+        const int r = e % n, c = e / n;
+        const double v = Tn[e];
+        if (r > c) sm.T[r * kLdsStride + c] = v;
+        else if (r == c) sm.tau[r] = v;
+    }
+    __syncthreads();
+    build_t(sm, n);
+    store_tri(sm.T, Tn, n);
 }
 
 }  // namespace tsqr

@@ -92,6 +92,10 @@ struct BMat {
 };
 
 // factor.hip
+// keep_q of the leaf launches: 0 no Q, 1 each chunk's T built in the leaf,
+// 2 each chunk's Gram entries and tau stored instead, for launch_chunk_t.
+// T of every chunk from what a keep_q == 2 leaf stored.
+hipError_t launch_chunk_t(double *Tc, const PanelArgs &pa, int64_t total_chunks, hipStream_t st);
 hipError_t launch_leaf(const double *A, int64_t lda, double *V, int64_t ldv, double *Tc, double *Rdom,
                        const PanelArgs &pa, int keep_q, hipStream_t st);
 hipError_t launch_tree_level(double *Rdom, double *Tnode, const PanelArgs &pa, const TreeArgs &ta,

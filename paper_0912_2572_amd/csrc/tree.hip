@@ -140,16 +140,6 @@ __device__ __forceinline__ void store_quarter(const double (&c)[16], double *__r
     }
 }
 
-// Gram entries and tau of a combine, for the node's T (built by k_tree_t):
-// dst (n x n, column-major) gets G[c][r] = y_c . y_r at (r, c) for r > c
-// and tau_r at (r, r).
-__device__ __forceinline__ void store_gram(const FactorSmem &sm, double *__restrict__ dst, int n) {
-    for (int e = threadIdx.x; e < n * n; e += kFactorThreads) {
-        const int r = e % n, c = e / n;
-        dst[e] = (r > c) ? sm.T[r * kLdsStride + c] : ((r == c) ? sm.tau[r] : 0.0);
-    }
-}
-
 // One chain of combines (step 3): left <- qr([R_left; R_right]) for every
 // right = left + q stride (q = 1, 2, ... while q stride < span and right < P),
 // in order.  The right triangle is overwritten by the combine's reflector
@@ -193,23 +183,6 @@ __device__ __forceinline__ void tree_chain(FactorSmem &sm, double *__restrict__ 
         __syncthreads();
     }
     store_tri(sm.R, Rdom + left * nn, n);
-}
-
-// T of tree node `node` from the Gram entries and tau its combine stored
-// (store_gram), by the forward recurrence of build_t; T overwrites them.
-__device__ __forceinline__ void node_t(FactorSmem &sm, double *__restrict__ Tn, int n) {
-    // build_t's block products read Gram entries past n (times zero)
-    zero_lds(sm.T);
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += kFactorThreads) {
-        const int r = e % n, c = e / n;
-        const double v = Tn[e];
-        if (r > c) sm.T[r * kLdsStride + c] = v;
-        else if (r == c) sm.tau[r] = v;
-    }
-    __syncthreads();
-    build_t(sm, n);
-    store_tri(sm.T, Tn, n);
 }
 
 // Every tree node's T: nodes 1 .. P - 1 (each domain but 0 is absorbed as
