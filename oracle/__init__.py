@@ -62,6 +62,10 @@ def lib():
         L.or_factor.restype = vp
         L.or_factor_sched.argtypes = [i64, i64, dp, i64, i64, i64, ip, ip, ctypes.c_int]
         L.or_factor_sched.restype = vp
+        L.or_partition_weighted.argtypes = [i64, i64, i64, i64, ip, ip, ip]
+        L.or_partition_weighted.restype = i64
+        L.or_factor_parts.argtypes = [i64, i64, dp, i64, i64, ip, ip, i64, ip, ip, ctypes.c_int]
+        L.or_factor_parts.restype = vp
         L.or_free.argtypes = [vp]
         L.or_num_domains.argtypes = [vp]
         L.or_num_domains.restype = i64
@@ -140,6 +144,22 @@ def partition(m: int, n: int, mb: int):
     return list(zip(r0.tolist(), nr.tolist()))
 
 
+def partition_weighted(m: int, n: int, P: int, granule: int, weights=None):
+    """Load-balanced partition (Sec. 3: rows per domain follow the
+    processing power given to it): list of (row0, nrows) for P domains of
+    integer powers `weights` (None = equal), in whole granules of `granule`
+    rows, apportioned by largest remainders (ties to the lower index)."""
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.int64)
+    if w is not None and w.shape != (P,):
+        raise ValueError("one weight per domain")
+    r0 = np.zeros(P, dtype=np.int64)
+    nr = np.zeros(P, dtype=np.int64)
+    got = int(lib().or_partition_weighted(m, n, P, granule, None if w is None else _ip(w), _ip(r0), _ip(nr)))
+    if got < 1:
+        raise ValueError("no such partition (a domain gets no granule or fewer than n rows)")
+    return list(zip(r0.tolist(), nr.tolist()))
+
+
 def schedule(P: int, tree: int):
     """Reduction-tree schedule (Sec. 2.3): list of (left, right) combines."""
     sl = np.zeros(max(P - 1, 1), dtype=np.int64)
@@ -172,13 +192,25 @@ def hierarchical_schedule(group):
 class TSQR:
     """TSQR factorization of an m x n matrix (Sec. 2.3) held by the oracle."""
 
-    def __init__(self, A, mb: int, tree: int = TREE_BINARY, nthreads: int = 0,
-                 sched=None):
+    def __init__(self, A, mb: int = 0, tree: int = TREE_BINARY, nthreads: int = 0,
+                 sched=None, parts=None):
+        """mb: rows per domain; parts: an explicit partition, a list of
+        (row0, nrows) (e.g. from partition_weighted), in place of mb."""
         A = _fortran(A)
         self.m, self.n = A.shape
         self.mb = mb
         nt = nthreads if nthreads > 0 else max_threads()
-        if sched is None:
+        if parts is not None:
+            P = len(parts)
+            if sched is None:
+                sched = schedule(P, tree)
+            r0 = np.array([p[0] for p in parts], dtype=np.int64)
+            nr = np.array([p[1] for p in parts], dtype=np.int64)
+            sl = np.array([s[0] for s in sched] or [0], dtype=np.int64)
+            sr = np.array([s[1] for s in sched] or [0], dtype=np.int64)
+            h = lib().or_factor_parts(self.m, self.n, _dp(A), self.m, P, _ip(r0), _ip(nr),
+                                      len(sched), _ip(sl), _ip(sr), nt)
+        elif sched is None:
             h = lib().or_factor(self.m, self.n, _dp(A), self.m, mb, tree, nt)
         else:
             sl = np.array([s[0] for s in sched], dtype=np.int64)

@@ -31,6 +31,9 @@
  *   - norms are plain sequential sums of squares, no scaling;
  *   - partition: P = ceil(m / mb) contiguous domains; a last domain with
  *     fewer than n rows is merged into the one before it;
+ *   - load-balanced partition (Sec. 3 names it as future work): rows in
+ *     whole granules, apportioned to the domains' integer powers by largest
+ *     remainders, ties to the lower index;
  *   - tree results always land in the lower-index child, so the root is
  *     domain 0 and its first n rows are global rows 0..n-1;
  *   - binary tree: adjacent pairs per level, an odd node passes up;
@@ -179,6 +182,56 @@ ORACLE_API int64_t or_partition(int64_t m, int64_t n, int64_t mb, int64_t *row0,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Load-balanced partition (Sec. 3: the rows given to each domain follow    */
+/* the processing power dedicated to it).  w[d] >= 1 is the power of domain */
+/* d in integer units (e.g. its cores; NULL = equal power).  Rows go out in */
+/* whole granules of g rows, the last granule short when g does not divide */
+/* m: C = ceil(m / g) granules, domain d first gets floor(C w_d / W) of     */
+/* them (W = sum of w), and the C - sum floor(...) granules left over go    */
+/* one each to the domains with the largest remainders C w_d mod W, ties    */
+/* to the lower index (largest-remainder apportionment, exact in integers). */
+/* Domains are contiguous in index order; the last one ends at row m.       */
+/* Returns P, or -1 if some domain would hold no granule or fewer than n    */
+/* rows.  Fills row0/nrows when they are not NULL.                          */
+/* ------------------------------------------------------------------------ */
+ORACLE_API int64_t or_partition_weighted(int64_t m, int64_t n, int64_t P, int64_t g,
+                                         const int64_t *w, int64_t *row0, int64_t *nrows)
+{
+    if (m < n || n < 1 || P < 1 || g < 1) return -1;
+    int64_t C = (m + g - 1) / g, W = 0;
+    for (int64_t d = 0; d < P; ++d) {
+        int64_t wd = w ? w[d] : 1;
+        if (wd < 1) return -1;
+        W += wd;
+    }
+    int64_t *k = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
+    int64_t *rem = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
+    int64_t given = 0;
+    for (int64_t d = 0; d < P; ++d) {
+        int64_t wd = w ? w[d] : 1;
+        k[d] = C * wd / W;
+        rem[d] = C * wd % W;
+        given += k[d];
+    }
+    for (int64_t left = C - given; left > 0; --left) {
+        int64_t best = -1;
+        for (int64_t d = 0; d < P; ++d)
+            if (rem[d] >= 0 && (best < 0 || rem[d] > rem[best])) best = d;
+        k[best] += 1;
+        rem[best] = -1;      /* one extra granule per domain at most */
+    }
+    int64_t ok = P, r = 0;
+    for (int64_t d = 0; d < P; ++d) {
+        int64_t rows = (d == P - 1) ? m - r : g * k[d];
+        if (k[d] < 1 || rows < n) ok = -1;
+        if (row0 && nrows) { row0[d] = r; nrows[d] = rows; }
+        r += g * k[d];
+    }
+    free(k); free(rem);
+    return ok;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reduction-tree schedules (Sec. 2.3: binary, flat; k-ary generalises the  */
 /* binary tree).  A schedule is an ordered list of combines (left, right);  */
 /* the result stays in the left slot.  Returns the number of combines      */
@@ -233,19 +286,23 @@ ORACLE_API void or_free(or_tsqr *f)
     free(f->R); free(f->d); free(f);
 }
 
-/* Factor with an explicit schedule (nnodes combines, result in the left). */
-ORACLE_API or_tsqr *or_factor_sched(int64_t m, int64_t n, const double *A, int64_t lda,
-                                    int64_t mb, int64_t nnodes, const int64_t *sl,
-                                    const int64_t *sr, int nthreads)
+/* Factor over an explicit partition (P contiguous domains covering rows  */
+/* 0..m-1 in order, each of at least n rows) with an explicit schedule     */
+/* (nnodes combines, result in the left).                                  */
+ORACLE_API or_tsqr *or_factor_parts(int64_t m, int64_t n, const double *A, int64_t lda,
+                                    int64_t P, const int64_t *row0, const int64_t *nrows,
+                                    int64_t nnodes, const int64_t *sl, const int64_t *sr,
+                                    int nthreads)
 {
-    int64_t P = or_partition(m, n, mb, NULL, NULL);
-    if (P < 1 || lda < m || nnodes != P - 1) return NULL;
+    if (P < 1 || n < 1 || lda < m || nnodes != P - 1) return NULL;
+    for (int64_t i = 0, r = 0; i < P; r += nrows[i], ++i)
+        if (row0[i] != r || nrows[i] < n || (i == P - 1 && r + nrows[i] != m)) return NULL;
     or_tsqr *f = (or_tsqr *)calloc(1, sizeof(or_tsqr));
     f->m = m; f->n = n; f->P = P; f->nnodes = nnodes;
     f->nthreads = nthreads > 0 ? nthreads : 1;
     f->row0 = (int64_t *)malloc(sizeof(int64_t) * P);
     f->nrows = (int64_t *)malloc(sizeof(int64_t) * P);
-    or_partition(m, n, mb, f->row0, f->nrows);
+    for (int64_t i = 0; i < P; ++i) { f->row0[i] = row0[i]; f->nrows[i] = nrows[i]; }
     f->W = (double *)malloc(sizeof(double) * (size_t)m * n);
     for (int64_t c = 0; c < n; ++c)
         memcpy(f->W + c * m, A + c * lda, sizeof(double) * (size_t)m);
@@ -285,6 +342,21 @@ ORACLE_API or_tsqr *or_factor_sched(int64_t m, int64_t n, const double *A, int64
     for (int64_t c = 0; c < n; ++c)
         for (int64_t r = 0; r <= c; ++r) f->R[r + c * n] = f->d[r] * Rs[r + c * n];
     free(Rs);
+    return f;
+}
+
+/* Factor with the mb partition and an explicit schedule. */
+ORACLE_API or_tsqr *or_factor_sched(int64_t m, int64_t n, const double *A, int64_t lda,
+                                    int64_t mb, int64_t nnodes, const int64_t *sl,
+                                    const int64_t *sr, int nthreads)
+{
+    int64_t P = or_partition(m, n, mb, NULL, NULL);
+    if (P < 1) return NULL;
+    int64_t *row0 = (int64_t *)malloc(sizeof(int64_t) * P);
+    int64_t *nrows = (int64_t *)malloc(sizeof(int64_t) * P);
+    or_partition(m, n, mb, row0, nrows);
+    or_tsqr *f = or_factor_parts(m, n, A, lda, P, row0, nrows, nnodes, sl, sr, nthreads);
+    free(row0); free(nrows);
     return f;
 }
 

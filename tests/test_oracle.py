@@ -130,6 +130,105 @@ def test_partition_rule():
     assert oracle.partition(16, 16, 16) == [(0, 16)]
 
 
+def test_weighted_partition_worked_cases():
+    # equal power: 10 granules over 3 domains, the one left over to domain 0
+    assert oracle.partition_weighted(1000, 4, 3, 100) == [(0, 400), (400, 300), (700, 300)]
+    # powers 1:2:1 of 10 granules: shares 2.5, 5, 2.5 -> 2, 5, 2 and the one
+    # left over to the lower of the two tied remainders; the last granule
+    # holds the 50 rows past 900
+    assert oracle.partition_weighted(950, 4, 3, 100, [1, 2, 1]) == [(0, 300), (300, 500), (800, 150)]
+    # half the cores of two of four machines (the paper's reservation case):
+    # powers 2:1:2:1 of 12 granules -> 4, 2, 4, 2 exactly
+    assert oracle.partition_weighted(1200, 8, 4, 100, [2, 1, 2, 1]) == [
+        (0, 400), (400, 200), (600, 400), (1000, 200)]
+    # granule 1: plain proportional rows
+    assert oracle.partition_weighted(7, 1, 2, 1, [3, 4]) == [(0, 3), (3, 4)]
+    # one domain holds everything
+    assert oracle.partition_weighted(1234, 7, 1, 256) == [(0, 1234)]
+
+
+def test_weighted_partition_rejects_empty_or_short_domains():
+    with pytest.raises(ValueError):
+        oracle.partition_weighted(1000, 4, 11, 100)          # 10 granules, 11 domains
+    with pytest.raises(ValueError):
+        oracle.partition_weighted(1000, 4, 2, 100, [1, 0])   # a domain of no power
+    with pytest.raises(ValueError):
+        oracle.partition_weighted(1010, 16, 2, 100, [10, 1])  # last domain: 10 rows < n
+    with pytest.raises(ValueError):
+        oracle.partition_weighted(1000, 4, 2, 100, [1, 2, 3])  # one weight per domain
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_partition_is_largest_remainder_apportionment(seed):
+    """Brute-force check: contiguous cover of the rows, every domain's
+    granule count is the floor or ceiling of its exact share C w_d / W, the
+    counts sum to C, and the rounding-up goes to the largest remainders."""
+    rng = np.random.default_rng(seed)
+    P = int(rng.integers(1, 40))
+    g = int(rng.integers(1, 300))
+    w = rng.integers(1, 20, size=P)
+    C = int(rng.integers(int(w.sum()), 60 * int(w.sum())))   # every share >= 1 granule
+    m = (C - 1) * g + int(rng.integers(1, g + 1))
+    parts = oracle.partition_weighted(m, 1, P, g, w)
+    assert parts[0][0] == 0 and parts[-1][0] + parts[-1][1] == m
+    for (a, na), (b, _) in zip(parts, parts[1:]):
+        assert a + na == b
+    k = [nr // g for _, nr in parts[:-1]] + [C - sum(nr // g for _, nr in parts[:-1])]
+    assert sum(k) == C
+    W = int(w.sum())
+    share = [Fraction(C * int(x), W) for x in w]
+    up = [i for i in range(P) if k[i] > share[i]]
+    for i in range(P):
+        assert math.floor(share[i]) <= k[i] <= math.ceil(share[i])
+    rem = [share[i] - math.floor(share[i]) for i in range(P)]
+    down = [i for i in range(P) if k[i] == math.floor(share[i]) and rem[i] > 0]
+    if up and down:
+        assert min(rem[i] for i in up) >= max(rem[i] for i in down)
+
+
+@pytest.mark.parametrize("m,n,P,g,w,tree", [
+    (5003, 13, 7, 256, None, oracle.TREE_BINARY),
+    (5003, 13, 5, 100, [1, 3, 2, 5, 1], oracle.TREE_BINARY),
+    (9000, 20, 6, 64, [4, 4, 2, 2, 1, 1], oracle.TREE_FLAT),
+    (3000, 25, 9, 128, None, oracle.TREE_QUAD),
+])
+def test_factor_over_a_weighted_partition(m, n, P, g, w, tree):
+    """R, Q and Q^T B do not depend on the partition (Sec. 2.2 uniqueness of
+    R with a positive diagonal): a weighted partition gives NumPy's
+    sign-normalised QR, and its leaves are Householder QRs of exactly the
+    apportioned rows."""
+    rng = np.random.default_rng(m + P)
+    A = rng.standard_normal((m, n))
+    parts = oracle.partition_weighted(m, n, P, g, w)
+    f = oracle.TSQR(A, parts=parts, tree=tree)
+    assert f.P == P
+    Qn, Rn = np.linalg.qr(A)
+    d = np.where(np.diag(Rn) < 0, -1.0, 1.0)
+    assert rel(f.R(), d[:, None] * Rn) <= 1e-13
+    Q = f.form_q()
+    for j in range(n):
+        assert np.linalg.norm(Q[:, j] - Qn[:, j] * d[j]) <= 1e-12
+    B = rng.standard_normal((m, 2))
+    C = f.apply_qt(B)
+    assert rel(C[:n], Q.T @ B) <= 1e-13
+    # each leaf is the Householder QR of its own rows
+    W, tau, _ = f.leaf()
+    for i, (r0, nr) in enumerate(parts):
+        la, ltau, _, _ = lapack.dgeqrf(np.asfortranarray(A[r0:r0 + nr].copy()))
+        assert rel(np.triu(W[r0:r0 + n]), np.triu(la[:n])) <= 1e-13
+        assert rel(tau[i], ltau) <= 1e-13
+
+
+def test_factor_over_a_partition_rejects_gaps():
+    A = np.ones((300, 2))
+    with pytest.raises(ValueError):
+        oracle.TSQR(A, parts=[(0, 100), (150, 150)])
+    with pytest.raises(ValueError):
+        oracle.TSQR(A, parts=[(0, 100), (100, 150)])      # stops short of m
+    with pytest.raises(ValueError):
+        oracle.TSQR(A, parts=[(0, 299), (299, 1)])        # a domain shorter than n
+
+
 def _depth(sched, P):
     d = [0] * P
     for l, r in sched:
