@@ -86,7 +86,22 @@ typedef struct {
     int32_t lsq_max_rhs;     /* largest k passed to tsqr_lsq_solve (>= 1)   */
     int32_t refine_max_iter; /* mixed: refinement sweeps after the first   */
                              /* solve (cap)                                */
-    int32_t reserved;
+    int32_t domains;         /* 0: the row_block partition above.  > 0:     */
+                             /* load-balanced partition (Sec. 3: rows per  */
+                             /* domain follow the processing power behind  */
+                             /* it; the compute units of one GPU are equal,*/
+                             /* so the shares are equal): this many        */
+                             /* domains of whole leaf chunks (chunk_rows   */
+                             /* of tsqr_plan_info), the first C mod P of   */
+                             /* them one chunk longer (C = ceil(m / chunk) */
+                             /* chunks), the last ending at row m.  Fewer  */
+                             /* domains are used when C < P or when the    */
+                             /* last would be shorter than n rows.  -1:    */
+                             /* one domain per leaf workgroup the GPU      */
+                             /* holds at once (256 compute units times the */
+                             /* leaf workgroups per unit for this n).      */
+                             /* Needs row_block = 0.  Each 64-column panel */
+                             /* of a wider matrix is balanced on its own.  */
     double refine_tol;       /* stop when the error left, estimated as
                                 ||dx|| times the sweep-to-sweep contraction
                                 ||dx|| / ||dx_prev||, is <= tol ||x||       */
@@ -98,7 +113,8 @@ typedef struct {
 typedef struct tsqr_factors_s *tsqr_factors;
 
 /* Fill *o with the defaults: row_block 0 (library default), binary tree,
-   FP64, keep_q 1, lsq_max_rhs 8, refine_max_iter 30, refine_tol 1e-14. */
+   FP64, keep_q 1, lsq_max_rhs 8, refine_max_iter 30, domains 0,
+   refine_tol 1e-14. */
 TSQR_API void tsqr_default_opts(tsqr_opts *o);
 
 /* Bytes of device workspace tsqr_factor needs for an m x n problem with
@@ -111,7 +127,8 @@ TSQR_API size_t tsqr_workspace_bytes(int64_t m, int64_t n, const tsqr_opts *o);
    at least tsqr_workspace_bytes() bytes, 256-byte aligned.  *out receives a
    new host handle (free it with tsqr_free).
    Errors: -1 m, -2 n, -3 A NULL, -4 lda, -5 opts (row_block < n, bad tree or
-   precision), TSQR_ERR_WORKSPACE, -1000-e on a HIP error. */
+   precision, domains < -1 or set together with row_block),
+   TSQR_ERR_WORKSPACE, -1000-e on a HIP error. */
 TSQR_API int tsqr_factor(int64_t m, int64_t n, const double *A, int64_t lda,
                          const tsqr_opts *o, void *dwork, size_t work_bytes,
                          void *stream, tsqr_factors *out);
@@ -270,6 +287,13 @@ TSQR_API int tsqr_last_refine_iters(tsqr_factors f, void *stream);
    and number of 64-column panels. */
 TSQR_API int tsqr_plan_info(int64_t m, int64_t n, const tsqr_opts *o,
                             int64_t *num_domains, int64_t *chunk_rows, int64_t *num_panels);
+
+/* The domains of the first 64-column panel (Sec. 2.3's partition, or the
+   load-balanced one of opts.domains): row0[i] and nrows[i] for i < min(P,
+   cap), host only.  Returns P, or the negative argument code of
+   tsqr_factor. */
+TSQR_API int64_t tsqr_partition(int64_t m, int64_t n, const tsqr_opts *o, int64_t *row0, int64_t *nrows,
+                                int64_t cap);
 
 /* The reduction tree as a list of combines (left, right), in execution
    order, for P domains and tree shape `tree` (host only).  Writes at most

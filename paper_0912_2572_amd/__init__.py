@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
         ("keep_q", ctypes.c_int32),
         ("lsq_max_rhs", ctypes.c_int32),
         ("refine_max_iter", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("domains", ctypes.c_int32),
         ("refine_tol", ctypes.c_double),
     ]
 
@@ -146,6 +146,8 @@ def lib():
         L.tsqr_factor_solve_noalloc.restype = ctypes.c_int
         L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(i64)]
+        L.tsqr_partition.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
+        L.tsqr_partition.restype = i64
         L.tsqr_tree_schedule.argtypes = [i64, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
         L.tsqr_tree_schedule.restype = i64
         L.tsqr_prof_enable.argtypes = [ctypes.c_int]
@@ -208,10 +210,14 @@ def _check(code: int, what: str):
 
 
 def opts(row_block: int = 0, tree: int = TREE_BINARY, prec: int = F64, keep_q: bool = True,
-         lsq_max_rhs: int = 8, refine_max_iter: int = 30, refine_tol: float = 1e-14) -> Opts:
+         lsq_max_rhs: int = 8, refine_max_iter: int = 30, refine_tol: float = 1e-14,
+         domains: int = 0) -> Opts:
+    """domains > 0 (or -1: one per resident leaf workgroup) selects the
+    load-balanced partition in place of row_block (see tsqr.h)."""
     o = Opts()
     lib().tsqr_default_opts(ctypes.byref(o))
     o.row_block = row_block
+    o.domains = domains
     o.tree = tree
     o.prec = prec
     o.keep_q = 1 if keep_q else 0
@@ -230,6 +236,18 @@ def plan_info(m: int, n: int, o: Opts | None = None):
     _check(lib().tsqr_plan_info(m, n, ctypes.byref(o) if o is not None else None,
                                 ctypes.byref(P), ctypes.byref(c), ctypes.byref(npan)), "tsqr_plan_info")
     return P.value, c.value, npan.value
+
+
+def partition(m: int, n: int, o: Opts | None = None):
+    """The library's domains of the first panel as (row0, nrows) pairs."""
+    op = ctypes.byref(o) if o is not None else None
+    P = int(lib().tsqr_partition(m, n, op, None, None, 0))
+    if P < 0:
+        raise TSQRError(P, "tsqr_partition")
+    r0 = (ctypes.c_int64 * P)()
+    nr = (ctypes.c_int64 * P)()
+    lib().tsqr_partition(m, n, op, r0, nr, P)
+    return [(r0[i], nr[i]) for i in range(P)]
 
 
 def tree_schedule(P: int, tree: int):

@@ -29,6 +29,7 @@ PanelArgs panel_args(const Panel &p) {
     a.P = p.P;
     a.cpd = p.cpd;
     a.chunk = p.chunk;
+    a.extra = p.extra;
     a.n = p.n;
     a.ns = p.ns;
     return a;
@@ -122,6 +123,19 @@ TSQR_API size_t tsqr_workspace_bytes(int64_t m, int64_t n, const tsqr_opts *o) {
     Plan p;
     if (tsqr::make_plan(m, n, o, &p) != 0) return 0;
     return p.total;
+}
+
+TSQR_API int64_t tsqr_partition(int64_t m, int64_t n, const tsqr_opts *o, int64_t *row0, int64_t *nrows,
+                                int64_t cap) {
+    Plan p;
+    int rc = tsqr::make_plan(m, n, o, &p);
+    if (rc) return rc;
+    const Panel &pa = p.panels[0];
+    for (int64_t i = 0; i < pa.P && i < cap; ++i) {
+        if (row0) row0[i] = pa.domain_row0(i);
+        if (nrows) nrows[i] = pa.domain_rows(i);
+    }
+    return pa.P;
 }
 
 TSQR_API int tsqr_plan_info(int64_t m, int64_t n, const tsqr_opts *o, int64_t *num_domains,

@@ -164,8 +164,8 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const double *__restrict__ V
     const int64_t c0 = (int64_t)blockIdx.y * KB;
     const int kc = (int)((k - c0 < KB) ? k - c0 : KB);
     const int n = pa.n;
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     const int64_t nn = (int64_t)n * n;
     const double *Bs0 = Bsrc + c0 * ldbs;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const double *__restrict__ V
         for (int64_t ch = 0; ch < nch; ++ch) {
             const int64_t r0 = row0 + ch * pa.chunk;
             const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
-            chunk_apply(sm, V + r0, ldv, Tc + (dom * pa.cpd + ch) * nn, Bs0 + r0, ldbs, B0 + r0, ldb,
+            chunk_apply(sm, V + r0, ldv, Tc + (dom_chunk0(pa, dom) + ch) * nn, Bs0 + r0, ldbs, B0 + r0, ldb,
                         valid, n, kc, ch == 0, 1);
         }
         for (int e = tid; e < n * KB; e += 256) {
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const double *__restrict__ V
         for (int64_t ch = nch - 1; ch >= 0; --ch) {
             const int64_t r0 = row0 + ch * pa.chunk;
             const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
-            chunk_apply(sm, V + r0, ldv, Tc + (dom * pa.cpd + ch) * nn, Bs0 + r0, ldbs, B0 + r0, ldb,
+            chunk_apply(sm, V + r0, ldv, Tc + (dom_chunk0(pa, dom) + ch) * nn, Bs0 + r0, ldbs, B0 + r0, ldb,
                         valid, n, kc, ch == 0, 0);
         }
     }
@@ -217,14 +217,14 @@ __device__ __forceinline__ void tree_apply_chain(ApplySmem &sm, const double *__
     for (int64_t q = 1; q * stride < span && left + q * stride < pa.P; ++q) ++nr;
     for (int e = tid; e < 64 * KB; e += 256) {
         const int r = e & 63, c = e >> 6;
-        sm.Ys[r][c] = (r < n && c < kc) ? B0[left * pa.mb + r + (int64_t)c * ldb] : 0.0;
+        sm.Ys[r][c] = (r < n && c < kc) ? B0[dom_row0(pa, left) + r + (int64_t)c * ldb] : 0.0;
     }
     for (int64_t qq = 0; qq < nr; ++qq) {
         const int64_t q = trans ? qq + 1 : nr - qq;
         const int64_t right = left + q * stride;
         const double *U = Rdom + right * nn;
         const double *T = Tnode + right * nn;
-        double *Yr = B0 + right * pa.mb;
+        double *Yr = B0 + dom_row0(pa, right);
         // the node's U and T: every load in flight before the LDS stores
         double uv[16], tv[16];
 #pragma unroll
@@ -296,7 +296,7 @@ __device__ __forceinline__ void tree_apply_chain(ApplySmem &sm, const double *__
     __syncthreads();
     for (int e = tid; e < 64 * KB; e += 256) {
         const int r = e & 63, c = e >> 6;
-        if (r < n && c < kc) B0[left * pa.mb + r + (int64_t)c * ldb] = sm.Ys[r][c];
+        if (r < n && c < kc) B0[dom_row0(pa, left) + r + (int64_t)c * ldb] = sm.Ys[r][c];
     }
 }
 

@@ -207,8 +207,8 @@ __device__ __forceinline__ void leaf_apply_domain(ApplyMSmem<Tile> &sm, const ty
     const int64_t c0 = cblk * KBM;
     const int kc = (int)((k - c0 < KBM) ? k - c0 : KBM);
     const int n = pa.n;
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     const int64_t nn = (int64_t)n * n;
     const double *Bs0 = Bsrc + c0 * ldbs;
@@ -218,7 +218,7 @@ __device__ __forceinline__ void leaf_apply_domain(ApplyMSmem<Tile> &sm, const ty
         for (int64_t ch = 0; ch < nch; ++ch) {
             const int64_t r0 = row0 + ch * pa.chunk;
             const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
-            chunk_apply_m<Tile>(sm, V + r0, ldv, Tc + (dom * pa.cpd + ch) * nn, Bs0 + r0, ldbs, B0 + r0,
+            chunk_apply_m<Tile>(sm, V + r0, ldv, Tc + (dom_chunk0(pa, dom) + ch) * nn, Bs0 + r0, ldbs, B0 + r0,
                                 ldb, valid, n, kc, ch == 0, 1);
         }
         for (int e = tid; e < 64 * KBM; e += 256) {
@@ -234,7 +234,7 @@ __device__ __forceinline__ void leaf_apply_domain(ApplyMSmem<Tile> &sm, const ty
         for (int64_t ch = nch - 1; ch >= 0; --ch) {
             const int64_t r0 = row0 + ch * pa.chunk;
             const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
-            chunk_apply_m<Tile>(sm, V + r0, ldv, Tc + (dom * pa.cpd + ch) * nn, Bs0 + r0, ldbs, B0 + r0,
+            chunk_apply_m<Tile>(sm, V + r0, ldv, Tc + (dom_chunk0(pa, dom) + ch) * nn, Bs0 + r0, ldbs, B0 + r0,
                                 ldb, valid, n, kc, ch == 0, 0);
         }
     }
@@ -381,8 +381,8 @@ __device__ __forceinline__ void apply_p1_body(const typename Tile::T *__restrict
     extern __shared__ double smem_raw[];
     VtbSmem<Tile> &sm = *reinterpret_cast<VtbSmem<Tile> *>(smem_raw);
     const int n = pa.n;
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     if (ch >= nch) return;
     const int kc = (int)k;
@@ -391,7 +391,7 @@ __device__ __forceinline__ void apply_p1_body(const typename Tile::T *__restrict
     chunk_vtb<Tile>(sm, V + r0, ldv, B + r0, ldb, ch == 0 ? n : 0, valid, n, kc, ch == 0);
     // P_c = the four waves' partials added in wave order
     using T = typename Tile::T;
-    double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
+    double *P = Pc + (dom_chunk0(pa, dom) + ch) * (int64_t)n * k;
     const int ws = 64 * kc;
     for (int e = threadIdx.x; e < n * kc; e += 256) {
         const int m = e % n, j = e / n, o = m * kc + j;
@@ -430,8 +430,8 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
     ChainSmem &sm = *reinterpret_cast<ChainSmem *>(smem_raw);
     const int n = pa.n, kc = (int)k, tid = threadIdx.x;
     const int64_t nn = (int64_t)n * n;
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     for (int e = tid; e < 64 * KBM; e += 256) {
         const int r = e >> 4, c = e & 15;
@@ -457,14 +457,14 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
     constexpr int kPPer = 64 * KBM / 256;   // P_c entries per thread (live <= 64 KBM)
     double tnext[kTPer], pnext[kPPer];
     auto fetch_t = [&](int64_t ch) {
-        const double *Tk = Tc + (dom * pa.cpd + ch) * nn;
+        const double *Tk = Tc + (dom_chunk0(pa, dom) + ch) * nn;
 #pragma unroll
         for (int u = 0; u < kTPer; ++u) {
             const int e = tid + 256 * u, r = e & 63, q = e >> 6;
             tnext[u] = (r < n && q < n) ? Tk[r + (int64_t)q * n] : 0.0;
         }
         // P_c is n x kc, column-major with ld n: entry (e % n, e / n) at e
-        const double *P = Pc + (dom * pa.cpd + ch) * (int64_t)n * k;
+        const double *P = Pc + (dom_chunk0(pa, dom) + ch) * (int64_t)n * k;
 #pragma unroll
         for (int u = 0; u < kPPer; ++u) {
             const int e = tid + 256 * u;
@@ -506,7 +506,7 @@ __device__ __forceinline__ void apply_p2_body(const double *__restrict__ V64, co
                 for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.W[q][j], z);
             }
             sm.Z[i][j] = z;
-            Zc[(dom * pa.cpd + ch) * (int64_t)n * k + i + (int64_t)j * n] = z;
+            Zc[(dom_chunk0(pa, dom) + ch) * (int64_t)n * k + i + (int64_t)j * n] = z;
         }
         __syncthreads();
         // Y <- Y - Z, or on a first chunk Y <- Y - V_0top Z
@@ -559,14 +559,14 @@ __device__ __forceinline__ void apply_p3_body(const typename Tile::T *__restrict
     using T = typename Tile::T;
     using Acc = typename Tile::Acc;
     const int n = pa.n, kc = (int)k;
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     if (ch >= nch) return;
     const int64_t r0 = row0 + ch * pa.chunk;
     const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
     const bool first = ch == 0;
-    const double *Z = Zc + (dom * pa.cpd + ch) * (int64_t)n * k;
+    const double *Z = Zc + (dom_chunk0(pa, dom) + ch) * (int64_t)n * k;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     const int kbn = (n + 3) >> 2;
@@ -612,9 +612,7 @@ __global__ __launch_bounds__(256) void k_apply_p3(const typename Tile::T *__rest
 // converged matrices.
 __device__ __forceinline__ bool chunk_of(const BMat &M, int64_t g, int64_t &dom, int64_t &ch) {
     if (g >= M.tchunks) return false;
-    dom = g / M.pa.cpd;
-    if (dom > M.pa.P - 1) dom = M.pa.P - 1;
-    ch = g - dom * M.pa.cpd;
+    dom_of_chunk(M.pa, g, dom, ch);
     return true;
 }
 

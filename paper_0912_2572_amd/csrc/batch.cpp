@@ -347,6 +347,7 @@ TSQR_API int tsqr_batch_create(int count, const tsqr_batch_item *items, const ts
         M.pa.P = p.P;
         M.pa.cpd = p.cpd;
         M.pa.chunk = p.chunk;
+        M.pa.extra = p.extra;
         M.pa.n = p.n;
         M.pa.ns = p.ns;
         M.prec = it.prec;

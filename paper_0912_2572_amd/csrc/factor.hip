@@ -536,8 +536,8 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
     constexpr int ROWS = chunk_rows(NS);
     constexpr int RPT = rows_per_thread(NS);
     static_assert(ROWS == 4 * W * RPT, "workgroup shape");
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nfull = nrows / ROWS;          // full chunks
     const int64_t tail = nrows - nfull * ROWS;   // rows of a partial last chunk
     const int n = pa.n;
@@ -564,7 +564,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
         chunk_qr<NS, RPT, true>(c, n, sm, want_t);
         if (want_t) {
             store_chunk<NS, RPT, VT, W>(c, V + row0, ldv, tail, n);
-            chunk_t_out(Tc + dom * pa.cpd * nn);
+            chunk_t_out(Tc + dom_chunk0(pa, dom) * nn);
         }
         __syncthreads();
     } else {
@@ -597,7 +597,7 @@ __device__ __forceinline__ void leaf_domain(FactorSmemT<W> &sm, const double *__
             }
             const bool more = ch + 1 < nfull;
             issue_full_chunk<NS, RPT, VEC>(c, A + row0 + (more ? ch + 1 : 0) * ROWS, lda, n, more);
-            if (want_t) chunk_t_out(Tc + (dom * pa.cpd + ch) * nn);
+            if (want_t) chunk_t_out(Tc + (dom_chunk0(pa, dom) + ch) * nn);
             __syncthreads();
         }
         if constexpr (STAGE) {

@@ -286,20 +286,20 @@ __global__ __launch_bounds__(256) void k_form_leaf(const double *__restrict__ V,
     const int n = pa.n;
     const int64_t nn = (int64_t)n * n;
     const int64_t dom = blockIdx.x;
-    const int64_t row0 = dom * pa.mb;
-    const int64_t nrows = (dom == pa.P - 1) ? pa.m - row0 : pa.mb;
+    const int64_t row0 = dom_row0(pa, dom);
+    const int64_t nrows = dom_rows(pa, dom);
     const int64_t nch = (nrows + pa.chunk - 1) / pa.chunk;
     load_nn(sm.X, S + dom * nn, n, n, false);
     // T of the chunk processed next, fetched one chunk ahead
     double tn[16];
-    fetch_nn(tn, Tc + (dom * pa.cpd + nch - 1) * nn, n, n);
+    fetch_nn(tn, Tc + (dom_chunk0(pa, dom) + nch - 1) * nn, n, n);
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
         const int64_t r0 = row0 + ch * pa.chunk;
         const int64_t valid = (nrows - ch * pa.chunk < pa.chunk) ? nrows - ch * pa.chunk : pa.chunk;
         __syncthreads();
         if (ch > 0) {
             put_nn(sm.T, tn);
-            fetch_nn(tn, Tc + (dom * pa.cpd + ch - 1) * nn, n, n);
+            fetch_nn(tn, Tc + (dom_chunk0(pa, dom) + ch - 1) * nn, n, n);
             __syncthreads();
             lds_gemm64(sm.T, sm.X, sm.Z, LD, true, false, 1.0);    // Z = T_k X
             __syncthreads();

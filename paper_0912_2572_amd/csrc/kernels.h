@@ -14,15 +14,39 @@ struct PanelArgs {
     int64_t P;      // domains
     int64_t cpd;    // chunks per full domain
     int64_t chunk;  // rows per chunk
+    int64_t extra;  // load-balanced partition: domains 0 .. extra-1 hold one
+                    // chunk more than mb (then mb = cpd chunks); 0 otherwise
     int n;          // columns (<= 64)
     int ns;         // column slots per thread of the leaf kernel
 };
 
-// Most chunks any domain has (the last domain can be longer than mb when a
-// short remainder was merged into it).
+// Domain d holds rows [dom_row0(d), dom_row0(d) + dom_rows(d)) of the panel,
+// and its chunks' T factors sit in slots dom_chunk0(d), ... of the panel's
+// chunk array.  The last domain ends at row m (it may be shorter than mb, or
+// longer when a short remainder was merged into it).
+__host__ __device__ inline int64_t dom_row0(const PanelArgs &pa, int64_t d) {
+    return d * pa.mb + (d < pa.extra ? d : pa.extra) * pa.chunk;
+}
+__host__ __device__ inline int64_t dom_rows(const PanelArgs &pa, int64_t d) {
+    return (d == pa.P - 1) ? pa.m - dom_row0(pa, d) : pa.mb + (d < pa.extra ? pa.chunk : 0);
+}
+__host__ __device__ inline int64_t dom_chunk0(const PanelArgs &pa, int64_t d) {
+    return d * pa.cpd + (d < pa.extra ? d : pa.extra);
+}
+
+// The domain holding chunk slot g of the panel and the chunk's index in it.
+__host__ __device__ inline void dom_of_chunk(const PanelArgs &pa, int64_t g, int64_t &dom, int64_t &ch) {
+    const int64_t big = pa.extra * (pa.cpd + 1);   // slots of the longer domains
+    dom = g < big ? g / (pa.cpd + 1) : pa.extra + (g - big) / pa.cpd;
+    if (dom > pa.P - 1) dom = pa.P - 1;            // a merged last domain
+    ch = g - dom_chunk0(pa, dom);
+}
+
+// Most chunks any domain has.
 inline int64_t max_domain_chunks(const PanelArgs &pa) {
-    const int64_t last = (pa.m - (pa.P - 1) * pa.mb + pa.chunk - 1) / pa.chunk;
-    return last > pa.cpd ? last : pa.cpd;
+    const int64_t last = (dom_rows(pa, pa.P - 1) + pa.chunk - 1) / pa.chunk;
+    const int64_t full = pa.cpd + (pa.extra > 0 ? 1 : 0);
+    return last > full ? last : full;
 }
 
 // One tree level: chain c = 0..chains-1 starts at

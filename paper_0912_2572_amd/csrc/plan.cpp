@@ -87,6 +87,32 @@ static int64_t default_row_block(int64_t m, int64_t n) {
     return mb;
 }
 
+// Load-balanced partition (Sec. 3: rows per domain in proportion to the
+// processing power behind it; the compute units of one GPU are equal, so
+// the shares are equal): the panel's C = ceil(m / chunk) chunks are split
+// into P domains of C / P chunks, the first C mod P of them one chunk longer;
+// the last domain ends at row m.  P is cut to C, and further while the last
+// domain would hold fewer than n rows.
+static void balance_panel(Panel &pa, int64_t want) {
+    const int64_t C = (pa.m + pa.chunk - 1) / pa.chunk;
+    int64_t P = want < C ? want : C;
+    int64_t q = 0, e = 0;
+    for (;; --P) {
+        q = C / P;
+        e = C % P;
+        const int64_t last = pa.m - pa.chunk * ((P - 1) * q + e);
+        if (P == 1 || last >= pa.n) break;
+    }
+    pa.P = P;
+    pa.mb = q * pa.chunk;
+    pa.extra = e;
+    pa.cpd = q;
+}
+
+// Leaf workgroups one compute unit holds at once: two for panels of up to 32
+// columns (their leaf fits two in registers and LDS), one for wider ones.
+static int64_t leaf_residency(int n) { return n <= 32 ? 2 : 1; }
+
 int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     tsqr_opts d;
     tsqr_default_opts(&d);
@@ -99,6 +125,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         return -5;
     if (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) return -5;
     if (o->row_block != 0 && o->row_block < n) return -5;
+    if (o->domains < -1 || (o->domains != 0 && o->row_block != 0)) return -5;
     if (o->lsq_max_rhs < 1 || o->refine_max_iter < 0) return -5;
     Plan P;
     P.m = m;
@@ -122,14 +149,18 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         pa.row_off = pa.col_off;
         pa.n = (int)std::min<int64_t>(kMaxPanel, n - pa.col_off);
         pa.m = m - pa.row_off;
-        pa.mb = P.mb;
-        if (pa.mb < pa.n) pa.mb = pa.n;
-        pa.P = (pa.m + pa.mb - 1) / pa.mb;
-        if (pa.P > 1 && pa.m - (pa.P - 1) * pa.mb < pa.n) pa.P -= 1;
         pa.ns = slots_for(pa.n);
         pa.chunk = chunk_rows_for(pa.n);
-        pa.cpd = (pa.mb + pa.chunk - 1) / pa.chunk;
-        pa.total_chunks = (pa.P - 1) * pa.cpd + pa.domain_chunks(pa.P - 1);
+        if (o->domains != 0) {
+            balance_panel(pa, o->domains > 0 ? o->domains : kComputeUnits * leaf_residency(pa.n));
+        } else {
+            pa.mb = P.mb;
+            if (pa.mb < pa.n) pa.mb = pa.n;
+            pa.P = (pa.m + pa.mb - 1) / pa.mb;
+            if (pa.P > 1 && pa.m - (pa.P - 1) * pa.mb < pa.n) pa.P -= 1;
+            pa.cpd = (pa.mb + pa.chunk - 1) / pa.chunk;
+        }
+        pa.total_chunks = pa.domain_chunk0(pa.P - 1) + pa.domain_chunks(pa.P - 1);
         pa.tree = o->tree;
         size_t nn = (size_t)pa.n * pa.n * sizeof(double);
         pa.off_tc = take(nn * (size_t)pa.total_chunks);

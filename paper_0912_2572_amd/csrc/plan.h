@@ -18,6 +18,7 @@ constexpr int kMaxN = 256;        // documented scope
 constexpr int kThreads = 256;     // threads per workgroup of the leaf kernel
 constexpr size_t kAlign = 256;
 constexpr int kRefineBlocks = 1024;   // workgroups of the refinement's residual pass
+constexpr int64_t kComputeUnits = 256;  // compute units of one gfx950 GPU (MI355X)
 
 // Column slots per thread of the leaf kernel for a panel of width w: 16
 // column groups x ns slots must cover w (ns = 1, 2 or 4).  Rows per chunk
@@ -36,6 +37,8 @@ struct Panel {
     int64_t m = 0, row_off = 0;
     int n = 0, col_off = 0;
     int64_t mb = 0, P = 0;          // domains of mb rows (the last one ragged)
+    int64_t extra = 0;              // load-balanced partition: domains 0 .. extra-1
+                                    // hold one chunk more than mb (mb whole chunks)
     int ns = 0;                     // slots per thread (1, 2, 4, 8)
     int64_t chunk = 0;              // rows per chunk of the leaf kernel
     int64_t cpd = 0;                // chunks in a full domain
@@ -48,9 +51,11 @@ struct Panel {
     size_t off_s = 0;               // P x n x n              (top-down blocks)
     size_t off_pz = 0;              // 2 x total_chunks x n x 16 (few-column apply: P_c, Z_c)
 
-    int64_t domain_row0(int64_t i) const { return i * mb; }
-    int64_t domain_rows(int64_t i) const { return (i == P - 1) ? m - i * mb : mb; }
-    int64_t domain_chunk0(int64_t i) const { return i * cpd; }
+    int64_t domain_row0(int64_t i) const { return i * mb + (i < extra ? i : extra) * chunk; }
+    int64_t domain_rows(int64_t i) const {
+        return (i == P - 1) ? m - domain_row0(i) : mb + (i < extra ? chunk : 0);
+    }
+    int64_t domain_chunk0(int64_t i) const { return i * cpd + (i < extra ? i : extra); }
     int64_t domain_chunks(int64_t i) const { return (domain_rows(i) + chunk - 1) / chunk; }
 };
 

@@ -50,6 +50,52 @@ def test_plan_matches_oracle_partition(tl):
         assert chunk >= n
 
 
+def test_partition_query_matches_oracle(tl):
+    for m, n, mb in [(4096, 16, 1024), (1 << 20, 64, 4096), (1010, 16, 500), (5003, 13, 700),
+                     (777, 1, 100), (64, 64, 64)]:
+        assert tl.partition(m, n, tl.opts(row_block=mb)) == oracle.partition(m, n, mb)
+
+
+# (m, n, requested domains): several chunks per domain, a remainder spread
+# over the first domains, more domains than chunks, a last domain that would
+# be shorter than n, and the widths of all three leaf chunk sizes
+BALANCED = [(1_200_000, 64, 256), (300_000, 64, 256), (5003, 13, 7), (100_000, 20, 100),
+            (70_000, 32, 512), (2000, 64, 16), (1034, 24, 4), (1 << 20, 64, 256), (999, 64, 1)]
+
+
+@pytest.mark.parametrize("m,n,want", BALANCED)
+def test_balanced_partition_is_the_oracle_equal_power_partition(tl, m, n, want):
+    """opts.domains: P domains of whole leaf chunks apportioned to equal
+    powers -- the oracle's load-balanced partition (Sec. 3) with one weight
+    per domain -- with P cut to the chunk count and while the last domain
+    would be shorter than n."""
+    P, chunk, _ = tl.plan_info(m, n, tl.opts(domains=want))
+    got = tl.partition(m, n, tl.opts(domains=want))
+    assert len(got) == P
+    assert got == oracle.partition_weighted(m, n, P, chunk)
+    C = -(-m // chunk)
+    expect = min(want, C)
+    while expect > 1:
+        try:
+            oracle.partition_weighted(m, n, expect, chunk)
+            break
+        except ValueError:
+            expect -= 1
+    assert P == expect
+    sizes = [nr for _, nr in got[:-1]]
+    assert not sizes or max(sizes) - min(sizes) <= chunk
+
+
+def test_balanced_partition_defaults_to_one_domain_per_resident_leaf(tl):
+    for n, per_cu in [(8, 2), (16, 2), (32, 2), (33, 1), (64, 1), (128, 1)]:
+        P, chunk, _ = tl.plan_info(1 << 22, n, tl.opts(domains=-1))
+        assert P == 256 * per_cu
+        assert tl.partition(1 << 22, n, tl.opts(domains=-1)) == oracle.partition_weighted(1 << 22, n, P, chunk)
+    # a wide matrix balances each 64-column panel over its own rows
+    assert tl.plan_info(300_000, 200, tl.opts(domains=256))[2] == 4
+    assert tl.workspace_bytes(300_000, 200, tl.opts(domains=256)) > 8 * 300_000 * 200
+
+
 def test_wide_problems_are_split_in_64_column_panels(tl):
     for n, want in [(64, 1), (65, 2), (128, 2), (200, 4), (256, 4)]:
         assert tl.plan_info(100000, n, tl.opts(row_block=4096))[2] == want
@@ -105,6 +151,9 @@ def test_invalid_arguments_rejected_on_host(tl):
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
     bad = tl.opts(tree=3)
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
+    for bad in (tl.opts(domains=-2), tl.opts(domains=4, row_block=64)):
+        assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
+        assert L.tsqr_partition(100, 4, ctypes.byref(bad), None, None, 0) == -5
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(o), None, 1 << 30, None,
                          ctypes.byref(h)) == tl.ERR_WORKSPACE
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(o), dummy, 16, None,

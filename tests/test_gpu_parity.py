@@ -67,10 +67,18 @@ def r_entrywise(R, Ro, tol=1e-12):
         float(np.max(np.abs(R - Ro) / np.maximum(cn, 1e-300)[None, :]))
 
 
-def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True):
+def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True, domains=0):
     m, n = A.shape
-    print(f"case m={m} n={n} mb={mb} tree={tree}", flush=True)
-    if tree == tl.TREE_XCD:
+    print(f"case m={m} n={n} mb={mb} tree={tree} domains={domains}", flush=True)
+    if domains:
+        # the load-balanced partition: the oracle factors over the library's
+        # domains, which must be its own equal-power apportionment
+        parts = tl.partition(m, n, tl.opts(domains=domains))
+        P, chunk, _ = tl.plan_info(m, n, tl.opts(domains=domains))
+        assert parts == oracle.partition_weighted(m, n, P, chunk)
+        sched = tl.tree_schedule(P, tree) if tree == tl.TREE_XCD else None
+        orc = oracle.TSQR(A, parts=parts, tree=tree, sched=sched)
+    elif tree == tl.TREE_XCD:
         # the oracle runs the hierarchical schedule over its own domains (for
         # n > 64 the GPU's first panel merges a short last domain by its own
         # width, so the counts can differ; R, Q and x do not depend on it)
@@ -81,7 +89,7 @@ def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True):
     else:
         orc = oracle.TSQR(A, mb=mb, tree=tree)
     Ad = dev(A)
-    f = tl.factor(Ad, row_block=mb, tree=tree)
+    f = tl.factor(Ad, domains=domains, tree=tree) if domains else tl.factor(Ad, row_block=mb, tree=tree)
     R = host(f.R())
     Ro = orc.R()
     assert np.all(np.tril(R, -1) == 0.0)
@@ -167,6 +175,52 @@ SHAPES = [
 def test_shapes(tl, m, n, mb, tree):
     A = synth.gaussian(m, n, seed=m + n)
     check_all(tl, A, mb, tree)
+
+
+# (m, n, domains, tree): the load-balanced partition (opts.domains, Sec. 3):
+# one domain per compute unit with a remainder of chunks spread over the
+# first domains, the narrow leaves' two per unit (-1), every tree, a tiny
+# ragged case and two 64-column panels balanced one by one
+BALANCED_SHAPES = [
+    (300_000, 64, 256, 2),
+    (100_003, 20, -1, 2),
+    (70_001, 32, 300, 4),
+    (50_000, 48, 100, 0),
+    (200_000, 8, 256, 8),
+    (5003, 13, 7, 2),
+    (20_000, 100, 16, 2),
+]
+
+
+@pytest.mark.parametrize("m,n,domains,tree", BALANCED_SHAPES)
+def test_balanced_domains(tl, m, n, domains, tree):
+    A = synth.gaussian(m, n, seed=m + 3 * n)
+    check_all(tl, A, 0, tree, domains=domains)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_balanced_domains_factor_solve(tl, prec):
+    """tsqr_factor_solve over balanced domains (the forked FP64 schedule, or
+    the mixed path's refinement) against the oracle's solution."""
+    m, n, domains = 150_001, 64, 256
+    print(f"case balanced factor_solve m={m} n={n} domains={domains} {prec}", flush=True)
+    A = synth.gaussian(m, n, seed=41)
+    b = np.random.default_rng(42).standard_normal((m, 1))
+    o = tl.opts(domains=domains, lsq_max_rhs=1, prec=tl.MIXED if prec == "mixed" else tl.F64)
+    Q = tl.empty_colmajor(m, n, device="cuda")
+    F, X, r, info = tl.factor_solve(dev(A), dev(b), o, Q=Q)
+    torch.cuda.synchronize()
+    parts = tl.partition(m, n, o)
+    orc = oracle.TSQR(A, parts=parts)
+    xo, ro, _ = orc.lsq(b)
+    assert int(info.item()) == 0
+    colwise(host(X), xo, 1e-12, scale=np.linalg.norm(xo, axis=0))
+    assert abs(host(r)[0] - ro[0]) <= 1e-11 * ro[0]
+    Qh = host(Q)
+    assert np.linalg.norm(Qh.T @ Qh - np.eye(n)) <= (1e-13 if prec == "f64" else 1e-5)
+    if prec == "f64":
+        colwise(Qh, orc.form_q(), 1e-12)
+    r_entrywise(host(F.R()), orc.R())
 
 
 def strided_view(A, row_off, extra_rows):
