@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--row-block", type=int, default=4096)
+    ap.add_argument("--domains", type=int, default=0,
+                    help="single workload: load-balanced partition into this many domains (-1: one per "
+                         "resident leaf workgroup) instead of --row-block")
     ap.add_argument("--tree", default="binary", choices=["binary", "quad", "flat", "xcd"],
                     help="single workload: reduction tree (xcd: each XCD's domains first)")
     ap.add_argument("--cpu-passes", type=int, default=7)
@@ -144,7 +147,7 @@ def counted_traffic(kernel: str, m: int, n: int, mb: int, tree: str):
 
 
 def run_single(args):
-    line = measure_single(args, args.m, args.n, args.row_block, args.steps, args.warmup)
+    line = measure_single(args, args.m, args.n, args.row_block, args.steps, args.warmup, domains=args.domains)
     if not args.no_sub:
         line["sub_records"] = sub_records(args)
     if not args.no_cpu:
@@ -152,9 +155,10 @@ def run_single(args):
     print(json.dumps(line), flush=True)
 
 
-def measure_single(args, m, n, mb, steps, warmup):
+def measure_single(args, m, n, mb, steps, warmup, domains=0):
     """One tsqr_factor_solve (factor + thin Q + 1-RHS solve) per step on an
-    m x n N(0,1) matrix; returns the record of the timed loop."""
+    m x n N(0,1) matrix; returns the record of the timed loop.  domains != 0:
+    the load-balanced partition (opts.domains) instead of mb-row domains."""
     import torch
     import paper_0912_2572_amd as tl
     import synth
@@ -165,7 +169,9 @@ def measure_single(args, m, n, mb, steps, warmup):
     tree_name = getattr(args, "tree", "binary")
     tree = {"binary": tl.TREE_BINARY, "quad": tl.TREE_QUAD, "flat": tl.TREE_FLAT,
             "xcd": tl.TREE_XCD}[tree_name]
-    o = tl.opts(row_block=mb, tree=tree, keep_q=True, lsq_max_rhs=1)
+    if domains:
+        mb = 0
+    o = tl.opts(row_block=mb, tree=tree, keep_q=True, lsq_max_rhs=1, domains=domains)
     work = torch.empty(tl.workspace_bytes(m, n, o), dtype=torch.uint8, device=dev)
     Q = tl.empty_colmajor(m, n, device=dev)
     X = tl.empty_colmajor(n, 1, device=dev)
@@ -270,7 +276,9 @@ def measure_single(args, m, n, mb, steps, warmup):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic iid N(0,1), seed 0",
-        "config": {"workload": f"tsqr_factor_formq_lsq {m}x{n}", "m": m, "n": n, "row_block": mb,
+        "config": {"workload": f"tsqr_factor_formq_lsq {m}x{n}", "m": m, "n": n,
+                   "row_block": mb if not domains else None,
+                   "partition": "balanced" if domains else "row_block",
                    "domains": P, "chunk_rows": chunk, "tree": tree_name, "rhs": 1,
                    "parallelism": "single GPU",
                    "streams": ("one tsqr_factor_solve call: the solve's leaf pass beside the tree, its tree "
@@ -319,7 +327,22 @@ def sub_records(args):
     t4 = time.perf_counter()
     ob = measure_orth(args, steps=3, warmup=1)
     t5 = time.perf_counter()
+    # a row count where 4096-row domains (293 of them) leave a second, mostly
+    # idle wave of leaf workgroups on the 256 compute units, against the
+    # load-balanced partition (one domain of 18-19 chunks per unit)
+    mr = 1_200_000
+    uni = measure_single(args, mr, 64, 4096, 10, 2)
+    bal = measure_single(args, mr, 64, 0, 10, 2, domains=-1)
+    t6 = time.perf_counter()
     return {
+        "balanced_domains": {
+            "workload": f"tsqr_factor_formq_lsq {mr}x64",
+            "row_block_4096": {"domains": uni["config"]["domains"], "ms_per_step": uni["ms_per_step"],
+                               "gflops": uni["value"],
+                               "leaf_ms": uni["kernels_ms_per_step"].get("leaf_factor")},
+            "balanced": {"domains": bal["config"]["domains"], "ms_per_step": bal["ms_per_step"],
+                         "gflops": bal["value"], "leaf_ms": bal["kernels_ms_per_step"].get("leaf_factor")},
+            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5, 1)},
         "mixed_kappa1e6": {
             "workload": mx["config"]["workload"],
             "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
