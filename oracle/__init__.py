@@ -78,6 +78,10 @@ def lib():
         L.or_lsq_refined.argtypes = [vp, dp, i64, dp, dp, ctypes.c_int]
         L.or_lsq_refined.restype = i64
         L.or_max_threads.restype = ctypes.c_int
+        L.or_cond1.argtypes = [i64, dp, i64]
+        L.or_cond1.restype = ctypes.c_double
+        L.or_cond1_est.argtypes = [i64, dp, i64]
+        L.or_cond1_est.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -158,6 +162,19 @@ def partition_weighted(m: int, n: int, P: int, granule: int, weights=None):
     if got < 1:
         raise ValueError("no such partition (a domain gets no granule or fewer than n rows)")
     return list(zip(r0.tolist(), nr.tolist()))
+
+
+def cond1(R) -> float:
+    """kappa_1(R) = ||R||_1 ||R^{-1}||_1 of an upper-triangular R, exactly
+    (R^{-1} by back substitution); +inf for a zero diagonal."""
+    R = _fortran(R)
+    return float(lib().or_cond1(R.shape[0], _dp(R), R.shape[0]))
+
+
+def cond1_est(R) -> float:
+    """The cheap lower-bound estimate of kappa_1(R) (Hager 1984, Higham 1988)."""
+    R = _fortran(R)
+    return float(lib().or_cond1_est(R.shape[0], _dp(R), R.shape[0]))
 
 
 def schedule(P: int, tree: int):

@@ -616,6 +616,119 @@ ORACLE_API int64_t or_lsq_refined(const or_tsqr *f, const double *A, int64_t lda
     return it;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Condition of R in the 1-norm, kappa_1(R) = ||R||_1 ||R^{-1}||_1, for     */
+/* routing ill-conditioned mixed-precision problems to FP64 (the paper is  */
+/* FP64 only; this is the definition, written out).  R: n x n upper         */
+/* triangular, column-major.  R^{-1} is formed column by column by back     */
+/* substitution on the unit vectors.  Returns +inf for a zero diagonal.     */
+/* ------------------------------------------------------------------------ */
+static double or_norm1_tri(int64_t n, const double *R, int64_t ldr)
+{
+    double best = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int64_t i = 0; i <= j; ++i) s += fabs(R[i + j * ldr]);
+        if (s > best) best = s;
+    }
+    return best;
+}
+
+/* y <- R^{-1} y (back substitution). */
+static void or_solve_r(int64_t n, const double *R, int64_t ldr, double *y)
+{
+    for (int64_t j = n - 1; j >= 0; --j) {
+        y[j] /= R[j + j * ldr];
+        for (int64_t i = 0; i < j; ++i) y[i] -= R[i + j * ldr] * y[j];
+    }
+}
+
+/* y <- R^{-T} y (forward substitution with the transpose). */
+static void or_solve_rt(int64_t n, const double *R, int64_t ldr, double *y)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < j; ++i) y[j] -= R[i + j * ldr] * y[i];
+        y[j] /= R[j + j * ldr];
+    }
+}
+
+ORACLE_API double or_cond1(int64_t n, const double *R, int64_t ldr)
+{
+    for (int64_t j = 0; j < n; ++j)
+        if (R[j + j * ldr] == 0.0) return INFINITY;
+    double *e = (double *)malloc(sizeof(double) * (size_t)n);
+    double inv = 0.0;
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t i = 0; i < n; ++i) e[i] = (i == c) ? 1.0 : 0.0;
+        or_solve_r(n, R, ldr, e);
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += fabs(e[i]);
+        if (s > inv) inv = s;
+    }
+    free(e);
+    return or_norm1_tri(n, R, ldr) * inv;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The cheap estimate of kappa_1(R): ||R||_1 times a lower bound on         */
+/* ||R^{-1}||_1 from Hager's method (1984) with Higham's refinements (1988: */
+/* at most five iterations, stop when the sign vector repeats or the       */
+/* estimate stops growing, then compare with the alternating-sign vector   */
+/* x_i = (-1)^i (1 + i / (n - 1)), i = 0..n-1, divided by its 1-norm 3n/2). */
+/* Each iteration costs one solve with R and one with R^T.  Ties in the    */
+/* argmax go to the lower index; sgn(0) = +1.  Returns +inf for a zero     */
+/* diagonal.                                                               */
+/* ------------------------------------------------------------------------ */
+ORACLE_API double or_cond1_est(int64_t n, const double *R, int64_t ldr)
+{
+    for (int64_t j = 0; j < n; ++j)
+        if (R[j + j * ldr] == 0.0) return INFINITY;
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xi = (double *)malloc(sizeof(double) * (size_t)n);
+    double est;
+    for (int64_t i = 0; i < n; ++i) x[i] = 1.0 / (double)n;
+    or_solve_r(n, R, ldr, x);
+    if (n == 1) {
+        est = fabs(x[0]);
+    } else {
+        est = 0.0;
+        for (int64_t i = 0; i < n; ++i) { est += fabs(x[i]); xi[i] = x[i] >= 0.0 ? 1.0 : -1.0; }
+        for (int64_t i = 0; i < n; ++i) x[i] = xi[i];
+        or_solve_rt(n, R, ldr, x);
+        int64_t j = 0;
+        for (int64_t i = 1; i < n; ++i) if (fabs(x[i]) > fabs(x[j])) j = i;
+        for (int iter = 2; iter <= 5; ++iter) {
+            for (int64_t i = 0; i < n; ++i) x[i] = (i == j) ? 1.0 : 0.0;
+            or_solve_r(n, R, ldr, x);
+            double old = est, nrm = 0.0;
+            int same = 1;
+            for (int64_t i = 0; i < n; ++i) {
+                nrm += fabs(x[i]);
+                double sg = x[i] >= 0.0 ? 1.0 : -1.0;
+                if (sg != xi[i]) same = 0;
+                xi[i] = sg;
+            }
+            est = nrm;
+            if (same || est <= old) { if (est < old) est = old; break; }
+            for (int64_t i = 0; i < n; ++i) x[i] = xi[i];
+            or_solve_rt(n, R, ldr, x);
+            int64_t jl = j;
+            j = 0;
+            for (int64_t i = 1; i < n; ++i) if (fabs(x[i]) > fabs(x[j])) j = i;
+            if (fabs(x[jl]) == fabs(x[j])) break;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = ((i % 2) ? -1.0 : 1.0) * (1.0 + (double)i / (double)(n - 1));
+        or_solve_r(n, R, ldr, x);
+        double t = 0.0;
+        for (int64_t i = 0; i < n; ++i) t += fabs(x[i]);
+        t = 2.0 * t / (3.0 * (double)n);
+        if (t > est) est = t;
+    }
+    free(x); free(xi);
+    return or_norm1_tri(n, R, ldr) * est;
+}
+
 /* Number of OpenMP threads the oracle will use when asked for nthreads<=0. */
 ORACLE_API int or_max_threads(void)
 {

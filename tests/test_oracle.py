@@ -229,6 +229,59 @@ def test_factor_over_a_partition_rejects_gaps():
         oracle.TSQR(A, parts=[(0, 299), (299, 1)])        # a domain shorter than n
 
 
+# ------------------------------------------------- condition of R (routing)
+
+def _graded_r(n, decades, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((3 * n + 5, n)) @ np.diag(10.0 ** np.linspace(0, -decades, n))
+    return signfix(np.linalg.qr(A)[1])
+
+
+@pytest.mark.parametrize("n,decades", [(1, 0), (2, 3), (7, 1), (16, 4), (64, 6), (129, 2), (256, 5)])
+def test_cond1_is_numpys_one_norm_condition(n, decades):
+    R = _graded_r(n, decades, n)
+    assert oracle.cond1(R) == pytest.approx(np.linalg.cond(R, 1), rel=1e-9)
+
+
+def test_cond1_special_cases():
+    d = np.array([4.0, 0.5, 2.0, 8.0])
+    assert oracle.cond1(np.diag(d)) == 8.0 / 0.5
+    # a unit upper bidiagonal with -1 above the diagonal: R^{-1} is the
+    # all-ones upper triangle, so ||R||_1 = 2 and ||R^{-1}||_1 = n
+    n = 9
+    R = np.eye(n) - np.diag(np.ones(n - 1), 1)
+    assert oracle.cond1(R) == 2.0 * n
+    R[3, 3] = 0.0
+    assert oracle.cond1(R) == math.inf and oracle.cond1_est(R) == math.inf
+
+
+@pytest.mark.parametrize("n,decades,seed", [(2, 3, 1), (5, 2, 2), (16, 4, 3), (64, 6, 4), (64, 0, 5),
+                                             (100, 3, 6), (256, 5, 7)])
+def test_cond1_estimate_is_a_lower_bound_at_least_lapacks(n, decades, seed):
+    """The estimate never exceeds kappa_1 (it is ||R||_1 times ||R^{-1} x||_1
+    for unit 1-norm vectors x) and is at least LAPACK's dtrcon estimate, the
+    same method with the cycling test keeping the last value instead of the
+    larger one; in practice it is within a small factor of kappa_1."""
+    R = _graded_r(n, decades, seed)
+    est, ex = oracle.cond1_est(R), oracle.cond1(R)
+    rc, info = lapack.dtrcon(R, norm="1", uplo="U", diag="N")
+    assert info == 0
+    assert est <= ex * (1 + 1e-12)
+    assert est >= (1.0 / rc) * (1 - 1e-12)
+    assert est >= ex / 3
+
+
+def test_cond1_estimate_exact_cases():
+    # diagonal: the first sign vector is all +1, R^{-T} of it peaks at the
+    # smallest |r_jj|, and that unit vector attains ||R^{-1}||_1
+    d = np.array([3.0, 0.25, 7.0, 0.5, 2.0])
+    assert oracle.cond1_est(np.diag(d)) == oracle.cond1(np.diag(d)) == 7.0 / 0.25
+    assert oracle.cond1_est(np.array([[-2.5]])) == 1.0
+    n = 12
+    R = np.eye(n) - np.diag(np.ones(n - 1), 1)
+    assert oracle.cond1_est(R) == oracle.cond1(R)
+
+
 def _depth(sched, P):
     d = [0] * P
     for l, r in sched:
