@@ -348,6 +348,9 @@ def sub_records(args):
             "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
             "speedup_mixed_over_f64": mx["speedup_mixed_over_f64"],
             "mixed_sweeps": mx["mixed"]["sweeps"],
+            "mixed_routed_ms": round(mx["mixed_routed"]["ms"], 3),
+            "mixed_routed_kappa_estimate": mx["mixed_routed"]["kappa_estimate"],
+            "eta_mixed_routed": mx["mixed_routed"]["eta"],
             "eta_f64": mx["f64"]["eta"], "eta_mixed": mx["mixed"]["eta"],
             "mixed_info": mx["mixed"]["info"], "wall_s": round(t1 - t0, 1)},
         "batch_512": {
@@ -404,8 +407,10 @@ def measure_mixed(args, steps, warmup):
     B = torch.stack([b, bc], dim=1).t().contiguous().t()
     flops = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0 + 2 * (4.0 * m * n + n * n)
     out = {}
-    for name, prec in (("f64", tl.F64), ("mixed", tl.MIXED)):
-        o = tl.opts(row_block=4096, prec=prec, lsq_max_rhs=2)
+    # "mixed_routed": the mixed path with route_kappa 1e4, which finds
+    # kappa_1(R) ~ 1e6 and solves in FP64 instead of refining
+    for name, prec, route in (("f64", tl.F64, 0.0), ("mixed", tl.MIXED, 0.0), ("mixed_routed", tl.MIXED, 1e4)):
+        o = tl.opts(row_block=4096, prec=prec, lsq_max_rhs=2, route_kappa=route)
         work = torch.empty(tl.workspace_bytes(m, n, o), dtype=torch.uint8, device=dev)
         X = tl.empty_colmajor(n, 2, device=dev)
         res = torch.empty(2, dtype=torch.float64, device=dev)
@@ -431,8 +436,11 @@ def measure_mixed(args, steps, warmup):
         kern = tl.prof_query()
         tl.prof_enable(False)
         e1 = [_eta(A, X[:, c], B[:, c]) for c in range(2)]
+        rprec, rkappa = f.route_info()
         out[name] = {"ms": ms, "gflops": flops / (ms * 1e-3) / 1e9, "eta": e1, "sweeps": sweeps,
                      "info": int(info.item()), "x": X.clone(),
+                     "routed_to_f64": bool(prec == tl.MIXED and rprec == tl.F64),
+                     "kappa_estimate": rkappa,
                      "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()}}
         del work
     xf, xm = out["f64"]["x"], out["mixed"]["x"]
@@ -450,6 +458,7 @@ def measure_mixed(args, steps, warmup):
                    "tree": "binary", "rhs": 2, "kappa": 1e6},
         "f64": {k: v for k, v in out["f64"].items() if k != "x"},
         "mixed": {k: v for k, v in out["mixed"].items() if k != "x"},
+        "mixed_routed": {k: v for k, v in out["mixed_routed"].items() if k != "x"},
         "mixed_vs_f64_rel_x": e2,
         "mixed_consistent_rhs_rel_err_x_true": e_true,
         "speedup_mixed_over_f64": round(out["f64"]["ms"] / out["mixed"]["ms"], 3),

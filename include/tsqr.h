@@ -105,6 +105,14 @@ typedef struct {
     double refine_tol;       /* stop when the error left, estimated as
                                 ||dx|| times the sweep-to-sweep contraction
                                 ||dx|| / ||dx_prev||, is <= tol ||x||       */
+    double route_kappa;      /* mixed: the first tsqr_lsq_solve of a factor
+                                estimates kappa_1(R) (tsqr_cond_estimate);
+                                above route_kappa (or not finite) it factors
+                                A again in FP64 in the same workspace, and
+                                that solve and every later call on the
+                                handle use the FP64 factor, so an
+                                ill-conditioned problem skips a long
+                                refinement.  0 = never (default); >= 0.    */
 } tsqr_opts;
 
 /* Opaque host handle describing one factorization.  It points into the
@@ -114,7 +122,7 @@ typedef struct tsqr_factors_s *tsqr_factors;
 
 /* Fill *o with the defaults: row_block 0 (library default), binary tree,
    FP64, keep_q 1, lsq_max_rhs 8, refine_max_iter 30, domains 0,
-   refine_tol 1e-14. */
+   refine_tol 1e-14, route_kappa 0. */
 TSQR_API void tsqr_default_opts(tsqr_opts *o);
 
 /* Bytes of device workspace tsqr_factor needs for an m x n problem with
@@ -276,6 +284,23 @@ TSQR_API size_t tsqr_block_orth_workspace_bytes(int64_t m, int64_t nv, int64_t b
 TSQR_API int tsqr_block_orth(int64_t m, int64_t nv, const double *V, int64_t ldv, int64_t b, double *W,
                              int64_t ldw, double *H, int64_t ldh, double *R, int64_t ldr, const tsqr_opts *o,
                              void *dwork, size_t work_bytes, void *stream);
+
+/* Estimate of the 1-norm condition number kappa_1(R) = ||R||_1 ||R^{-1}||_1
+   of the factor's R (= kappa_1 of A up to the factorization's rounding),
+   written to *kappa (device, one double) on `stream`: ||R||_1 times Hager's
+   lower bound on ||R^{-1}||_1 with Higham's refinements (at most five pairs
+   of triangular solves, then an alternating-sign test vector), so it never
+   exceeds kappa_1(R) and is usually within a factor of 3 of it; +inf when R
+   has an exactly zero diagonal entry.  One wave of 64 lanes, n <= 256.
+   The paper's method is FP64 only; the estimate serves the mixed-precision
+   routing (opts.route_kappa).  Errors: -1 handle, -2 kappa NULL. */
+TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream);
+
+/* Host only: the precision the handle's reflectors are now in (*prec:
+   TSQR_F64 after a mixed factor was routed to FP64 by opts.route_kappa) and
+   the condition estimate that decided it (*kappa_est, 0 when no routing
+   check ran).  Either pointer may be NULL.  Errors: -1 handle. */
+TSQR_API int tsqr_route_info(tsqr_factors f, int32_t *prec, double *kappa_est);
 
 /* Number of sweeps (the first solve included) the last mixed-precision
    tsqr_lsq_solve on this handle ran, the largest over its groups of 8
@@ -439,6 +464,10 @@ typedef struct {
                             /* yet lets younger requests that fit be         */
                             /* admitted past it until it has waited this     */
                             /* long (ms); 0 = 100 ms, < 0 = strict FIFO       */
+    int32_t reserved;
+    double route_kappa;     /* TSQR_MIXED: a request whose R has a condition */
+                            /* estimate above this is solved in FP64        */
+                            /* (opts.route_kappa); default 1e4, 0 = never    */
 } tsqr_server_opts;
 
 typedef struct {

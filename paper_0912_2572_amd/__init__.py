@@ -38,6 +38,7 @@ class Opts(ctypes.Structure):
         ("refine_max_iter", ctypes.c_int32),
         ("domains", ctypes.c_int32),
         ("refine_tol", ctypes.c_double),
+        ("route_kappa", ctypes.c_double),
     ]
 
 
@@ -79,6 +80,8 @@ class ServerOpts(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("tree", ctypes.c_int32),
         ("bypass_ms", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("route_kappa", ctypes.c_double),
     ]
 
 
@@ -146,6 +149,10 @@ def lib():
         L.tsqr_factor_solve_noalloc.restype = ctypes.c_int
         L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(i64)]
+        L.tsqr_cond_estimate.argtypes = [vp, vp, vp]
+        L.tsqr_cond_estimate.restype = ctypes.c_int
+        L.tsqr_route_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+        L.tsqr_route_info.restype = ctypes.c_int
         L.tsqr_partition.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
         L.tsqr_partition.restype = i64
         L.tsqr_tree_schedule.argtypes = [i64, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
@@ -211,13 +218,16 @@ def _check(code: int, what: str):
 
 def opts(row_block: int = 0, tree: int = TREE_BINARY, prec: int = F64, keep_q: bool = True,
          lsq_max_rhs: int = 8, refine_max_iter: int = 30, refine_tol: float = 1e-14,
-         domains: int = 0) -> Opts:
+         domains: int = 0, route_kappa: float = 0.0) -> Opts:
     """domains > 0 (or -1: one per resident leaf workgroup) selects the
-    load-balanced partition in place of row_block (see tsqr.h)."""
+    load-balanced partition in place of row_block; route_kappa > 0 sends a
+    mixed-precision solve whose R is estimated worse conditioned to FP64
+    (see tsqr.h)."""
     o = Opts()
     lib().tsqr_default_opts(ctypes.byref(o))
     o.row_block = row_block
     o.domains = domains
+    o.route_kappa = route_kappa
     o.tree = tree
     o.prec = prec
     o.keep_q = 1 if keep_q else 0
@@ -401,6 +411,20 @@ class Factors:
 
     def last_refine_iters(self, stream=None) -> int:
         return int(lib().tsqr_last_refine_iters(self._h, _stream(stream)))
+
+    def cond_estimate(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """kappa_1(R) estimate (tsqr_cond_estimate) as a one-element device tensor."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.work.device)
+        _check(lib().tsqr_cond_estimate(self._h, ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "tsqr_cond_estimate")
+        return out
+
+    def route_info(self):
+        """(precision of the reflectors now, condition estimate that routed it or 0)."""
+        prec, kap = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().tsqr_route_info(self._h, ctypes.byref(prec), ctypes.byref(kap)), "tsqr_route_info")
+        return prec.value, kap.value
 
 
 def factor_solve(A: torch.Tensor, B: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = None,
@@ -655,11 +679,14 @@ class Server:
     the server keeps references to them."""
 
     def __init__(self, hbm_budget: int = 8 << 30, streams: int = 4, max_inflight: int = 16,
-                 cache: bool = True, prec: int = F64, tree: int = TREE_BINARY, bypass_ms: int = 0):
+                 cache: bool = True, prec: int = F64, tree: int = TREE_BINARY, bypass_ms: int = 0,
+                 route_kappa: float | None = None):
         o = ServerOpts()
         lib().tsqr_server_default_opts(ctypes.byref(o))
         o.hbm_budget, o.streams, o.max_inflight = hbm_budget, streams, max_inflight
         o.cache, o.prec, o.tree, o.bypass_ms = 1 if cache else 0, prec, tree, bypass_ms
+        if route_kappa is not None:
+            o.route_kappa = route_kappa
         h = ctypes.c_void_p()
         _check(lib().tsqr_server_create(ctypes.byref(o), ctypes.byref(h)), "tsqr_server_create")
         self._h = h

@@ -173,6 +173,8 @@ int tsqr::factor_into(tsqr_factors_s *f, int64_t m, int64_t n, const double *A, 
     f->keep_q = o->keep_q ? 1 : 0;
     f->last_refine = 0;
     f->last_k = 0;
+    f->route_checked = 0;
+    f->kappa_est = 0.0;
     return factor_enqueue(f, A, lda, st);
 }
 
@@ -444,6 +446,56 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
     return apply_q_impl(f, f->plan.n, Q, ldq, false, true, st);
 }
 
+TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream) {
+    int rc = validate_handle(f, false);
+    if (rc) return rc;
+    if (!kappa) return -2;
+    hipError_t e = tsqr::launch_cond_est(at<double>(f, f->plan.off_r), (int)f->plan.n, kappa,
+                                         static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
+TSQR_API int tsqr_route_info(tsqr_factors f, int32_t *prec, double *kappa_est) {
+    int rc = validate_handle(f, false);
+    if (rc) return rc;
+    if (prec) *prec = f->plan.opts.prec;
+    if (kappa_est) *kappa_est = f->kappa_est;
+    return 0;
+}
+
+}  // extern "C"
+
+// Mixed-precision routing (opts.route_kappa): at the first solve of a mixed
+// factor, estimate kappa_1(R) (for n <= 64 R is exact to FP64 rounding, for
+// wider matrices to FP32 rounding, plenty for an estimate); above the
+// threshold, or not finite, factor A again in FP64 into the same workspace
+// (the FP64 plan is the mixed one without its FP32 reflectors and refinement
+// scratch, so it fits) and the handle becomes an FP64 factor.
+static int route_mixed(tsqr_factors_s *f, const double *A, int64_t lda, hipStream_t st, bool *routed) {
+    *routed = false;
+    const Plan &P = f->plan;
+    if (!(P.opts.route_kappa > 0.0) || f->route_checked) return 0;
+    f->route_checked = 1;
+    double *kd = at<double>(f, P.off_cond);
+    TRY(tsqr::launch_cond_est(at<double>(f, P.off_r), (int)P.n, kd, st));
+    double kh = 0.0;
+    TRY(hipMemcpyAsync(&kh, kd, sizeof(double), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    f->kappa_est = kh;
+    if (kh <= P.opts.route_kappa) return 0;
+    tsqr_opts o = P.opts;
+    o.prec = TSQR_F64;
+    Plan p64;
+    if (tsqr::make_plan(P.m, P.n, &o, &p64) != 0 || p64.total > f->ws_bytes) return 0;
+    f->plan = p64;
+    const int rc = factor_enqueue(f, A, lda, st);
+    if (rc) return rc;
+    *routed = true;
+    return 0;
+}
+
+extern "C" {
+
 TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_t k, const double *B,
                             int64_t ldb, double *X, int64_t ldx, double *resid, int32_t *dinfo,
                             void *stream) {
@@ -458,8 +510,12 @@ TSQR_API int tsqr_lsq_solve(tsqr_factors f, const double *A, int64_t lda, int64_
     if (!X) return -7;
     if (ldx < P.n) return -8;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (P.opts.prec == TSQR_MIXED)
-        return lsq_solve_mixed(f, A, lda, k, B, ldb, X, ldx, resid, dinfo, st);
+    if (P.opts.prec == TSQR_MIXED) {
+        bool routed = false;
+        rc = route_mixed(f, A, lda, st, &routed);
+        if (rc) return rc;
+        if (!routed) return lsq_solve_mixed(f, A, lda, k, B, ldb, X, ldx, resid, dinfo, st);
+    }
     double *C = at<double>(f, P.off_lsq);
     hipError_t e = tsqr::launch_copy(B, ldb, C, P.m, P.m, k, st);
     if (e != hipSuccess) return hip_code(e);

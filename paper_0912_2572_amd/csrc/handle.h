@@ -16,6 +16,8 @@ struct tsqr_factors_s {
     int keep_q = 1;
     int last_refine = 0;
     int64_t last_k = 0;   // right-hand sides of the last mixed solve
+    int route_checked = 0;  // mixed: the condition estimate of routing has run
+    double kappa_est = 0.0; // ... and its value
 };
 
 namespace tsqr {

@@ -180,6 +180,9 @@ hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, 
 hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t st);
 hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
                        int64_t cols, hipStream_t st);
+// kappa_1(R) estimate of an n x n upper-triangular R (ld n, n <= 256) into
+// *kappa (device): one wave.
+hipError_t launch_cond_est(const double *R, int n, double *kappa, hipStream_t st);
 hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ldc, int64_t m, int64_t k,
                              double *X, int64_t ldx, double *resid, int32_t *dinfo, double *partial,
                              hipStream_t st);

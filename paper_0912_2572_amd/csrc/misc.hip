@@ -107,6 +107,129 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
     }
 }
 
+// Largest value over the 64 lanes, identical in every lane.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) v = fmax(v, __shfl_xor(v, s));
+    return v;
+}
+
+// Index (< n) of the entry of largest magnitude of the wave's vector (lane l
+// holds entries l + 64 q in x[q]); ties go to the lower index.  Identical in
+// every lane.
+__device__ __forceinline__ int wave_argmax_abs(const double (&x)[4], int n) {
+    const int lane = threadIdx.x & 63;
+    double best = -1.0;
+    int bi = n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        const double a = fabs(x[q]);
+        if (i < n && a > best) {
+            best = a;
+            bi = i;
+        }
+    }
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const double ob = __shfl_xor(best, s);
+        const int oi = __shfl_xor(bi, s);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    return bi;
+}
+
+// The 1-norm condition estimate of R: ||R||_1 times a lower bound on
+// ||R^{-1}||_1 by Hager's method (1984) with Higham's refinements (1988):
+// y = R^{-1} (e / n); then up to four times: xi = sgn(y), z = R^{-T} xi,
+// j = argmax |z_j|, y = R^{-1} e_j, stopping when the sign vector repeats,
+// the estimate ||y||_1 stops growing (the larger of the last two is kept) or
+// the argmax repeats; finally the alternating vector x_i = (-1)^i (1 + i /
+// (n - 1)) gives the bound 2 ||R^{-1} x||_1 / (3n) when that is larger.
+// sgn(0) = +1.  One wave, no barrier; the solves are the one-wave ones.
+__global__ __launch_bounds__(64) void k_cond_est(const double *R, int n, double *kappa) {
+    const int lane = threadIdx.x;
+    double cmax = 0.0;
+    bool zero = false;
+    for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        if (j < n) {
+            double s = 0.0;
+            for (int i = 0; i <= j; ++i) s += fabs(R[i + (int64_t)j * n]);
+            cmax = fmax(cmax, s);
+            zero = zero || R[j + (int64_t)j * n] == 0.0;
+        }
+    }
+    const double norm = wave_max(cmax);
+    if (__ballot(zero)) {
+        if (lane == 0) *kappa = INFINITY;
+        return;
+    }
+    auto l1 = [&](const double (&v)[4]) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += fabs(v[q]);   // entries past n are zero
+        return wave_sum(s);
+    };
+    double x[4], xi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = (lane + 64 * q < n) ? 1.0 / (double)n : 0.0;
+    wave_backsub(R, n, x);
+    double est;
+    if (n == 1) {
+        est = fabs(wave_bcast(x[0], 0));
+    } else {
+        est = l1(x);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xi[q] = (lane + 64 * q < n) ? (x[q] >= 0.0 ? 1.0 : -1.0) : 0.0;
+            x[q] = xi[q];
+        }
+        wave_fwdsub_t(R, n, x);
+        int j = wave_argmax_abs(x, n);
+        for (int iter = 2; iter <= 5; ++iter) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = (lane + 64 * q == j) ? 1.0 : 0.0;
+            wave_backsub(R, n, x);
+            const double old = est;
+            est = l1(x);
+            bool diff = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (lane + 64 * q < n) {
+                    const double sg = x[q] >= 0.0 ? 1.0 : -1.0;
+                    diff = diff || sg != xi[q];
+                    xi[q] = sg;
+                }
+            }
+            if (!__ballot(diff) || est <= old) {
+                est = fmax(est, old);
+                break;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = xi[q];
+            wave_fwdsub_t(R, n, x);
+            const int jl = j;
+            j = wave_argmax_abs(x, n);
+            const double ajl = fabs(wave_bcast(pick4(x, jl >> 6), jl & 63));
+            const double aj = fabs(wave_bcast(pick4(x, j >> 6), j & 63));
+            if (ajl == aj) break;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = lane + 64 * q;
+            x[q] = (i < n) ? ((i & 1) ? -1.0 : 1.0) * (1.0 + (double)i / (double)(n - 1)) : 0.0;
+        }
+        wave_backsub(R, n, x);
+        const double t = 2.0 * l1(x) / (3.0 * (double)n);
+        if (t > est) est = t;
+    }
+    if (lane == 0) *kappa = norm * est;
+}
+
 __global__ void k_info_clear(int32_t *dinfo) {
     if (threadIdx.x == 0) *dinfo = 0;
 }
@@ -131,6 +254,13 @@ hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd,
     if (rows <= 0 || cols <= 0) return hipSuccess;
     ProfScope ps("copy", st);
     hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, st, src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_cond_est(const double *R, int n, double *kappa, hipStream_t st) {
+    if (n < 1 || n > 256) return hipErrorInvalidValue;
+    ProfScope ps("cond_est", st);
+    hipLaunchKernelGGL(k_cond_est, dim3(1), dim3(64), 0, st, R, n, kappa);
     return hipGetLastError();
 }
 

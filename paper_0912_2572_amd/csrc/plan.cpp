@@ -126,6 +126,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     if (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) return -5;
     if (o->row_block != 0 && o->row_block < n) return -5;
     if (o->domains < -1 || (o->domains != 0 && o->row_block != 0)) return -5;
+    if (!(o->route_kappa >= 0.0)) return -5;
     if (o->lsq_max_rhs < 1 || o->refine_max_iter < 0) return -5;
     Plan P;
     P.m = m;
@@ -181,6 +182,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     }
     // small scratch: per-block partial sums (4096 blocks x rhs), a few
     // n x rhs vectors, info words and counters
+    P.off_cond = take(sizeof(double));
     P.small_bytes = sizeof(double) * (size_t)(4096 + 8 * n) * o->lsq_max_rhs + 4096;
     P.off_small = take(P.small_bytes);
     P.total = off;

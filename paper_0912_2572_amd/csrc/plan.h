@@ -94,6 +94,7 @@ struct Plan {
     size_t off_lsq = 0;     // m x lsq_max_rhs scratch (Q^T B)
     size_t off_lsq2 = 0;    // m x lsq_max_rhs scratch (refinement residual)
     size_t off_ref = 0;     // refinement scratch (mixed only): x, partial sums, flags
+    size_t off_cond = 0;    // one double: the condition estimate of mixed-precision routing
     size_t off_small = 0;   // small scratch: partial sums, x corrections, info words
     size_t small_bytes = 0;
     size_t total = 0;

@@ -155,6 +155,7 @@ tsqr_opts factor_opts(const tsqr_server_s *S) {
     o.prec = S->o.prec;
     o.tree = S->o.tree;
     o.lsq_max_rhs = 8;
+    o.route_kappa = S->o.route_kappa;
     return o;
 }
 
@@ -456,6 +457,7 @@ TSQR_API void tsqr_server_default_opts(tsqr_server_opts *o) {
     o->cache = 1;
     o->prec = TSQR_F64;
     o->tree = TSQR_TREE_BINARY;
+    o->route_kappa = 1e4;
 }
 
 TSQR_API int tsqr_server_create(const tsqr_server_opts *o, tsqr_server *out) {
@@ -465,7 +467,7 @@ TSQR_API int tsqr_server_create(const tsqr_server_opts *o, tsqr_server *out) {
     tsqr_server_default_opts(&d);
     if (!o) o = &d;
     if (o->hbm_budget < ((size_t)1 << 20) || o->streams < 1 || o->streams > 64 || o->max_inflight < 1 ||
-        (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) ||
+        (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) || !(o->route_kappa >= 0.0) ||
         (o->tree != TSQR_TREE_FLAT && o->tree != TSQR_TREE_BINARY && o->tree != TSQR_TREE_QUAD &&
          o->tree != TSQR_TREE_XCD))
         return -1;

@@ -151,7 +151,8 @@ def test_invalid_arguments_rejected_on_host(tl):
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
     bad = tl.opts(tree=3)
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
-    for bad in (tl.opts(domains=-2), tl.opts(domains=4, row_block=64)):
+    for bad in (tl.opts(domains=-2), tl.opts(domains=4, row_block=64), tl.opts(route_kappa=-1.0),
+                tl.opts(route_kappa=float("nan"))):
         assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(bad), dummy, 1 << 30, None, ctypes.byref(h)) == -5
         assert L.tsqr_partition(100, 4, ctypes.byref(bad), None, None, 0) == -5
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(o), None, 1 << 30, None,
@@ -196,6 +197,19 @@ def test_batch_create_rejects_on_host(tl):
                                ctypes.byref(h)) == -5
     assert not h.value
     assert L.tsqr_autotune(1, items, 0, None, 0, None, None, 0) == -3
+
+
+def test_routing_calls_check_their_handle(tl):
+    L = tl.lib()
+    prec, kap = ctypes.c_int32(), ctypes.c_double()
+    assert L.tsqr_route_info(None, ctypes.byref(prec), ctypes.byref(kap)) == -1
+    assert L.tsqr_cond_estimate(None, ctypes.c_void_p(256), None) == -1
+    o = tl.ServerOpts()
+    L.tsqr_server_default_opts(ctypes.byref(o))
+    assert o.route_kappa == 1e4
+    o.route_kappa = -1.0
+    h = ctypes.c_void_p()
+    assert L.tsqr_server_create(ctypes.byref(o), ctypes.byref(h)) == -1 and not h.value
 
 
 def test_server_options_checked_on_host(tl):

@@ -135,7 +135,11 @@ def test_server_budget_forces_waits_and_evictions(tl, stream_reqs):
         assert eta(A, X.numpy()[:, 0], B[:, 0]) <= 1e-12
 
 
-def test_server_mixed_precision(tl):
+@pytest.mark.parametrize("route_kappa", [None, 0.0])
+def test_server_mixed_precision(tl, route_kappa):
+    """A mixed-precision server; by default the kappa = 1e6 request is routed
+    to FP64 by its condition estimate (route_kappa 1e4), with routing off it
+    is refined; every solution reaches eta <= 1e-12 either way."""
     reqs = [
         {"id": 0, "matrix_id": 0, "m": 6000, "n": 32, "k": 2, "ill": False, "rhs_seed": 1},
         {"id": 1, "matrix_id": 1, "m": 9000, "n": 128, "k": 1, "ill": True, "rhs_seed": 2},
@@ -143,8 +147,9 @@ def test_server_mixed_precision(tl):
     ]
     mats = {0: synth.request_matrix(6000, 32, False, 0), 1: synth.request_matrix(9000, 128, True, 1)}
     rhs = {r["id"]: synth.request_rhs(r["m"], r["k"], r["rhs_seed"]) for r in reqs}
-    print("case server mixed precision", flush=True)
-    out, st = run(tl, reqs, mats, rhs, hbm_budget=256 << 20, prec=tl.MIXED)
+    print(f"case server mixed precision route_kappa={route_kappa}", flush=True)
+    kw = {} if route_kappa is None else {"route_kappa": route_kappa}
+    out, st = run(tl, reqs, mats, rhs, hbm_budget=256 << 20, prec=tl.MIXED, **kw)
     assert st["cache_hits"] == 1
     for r in reqs:
         X, res, info = out[r["id"]]
