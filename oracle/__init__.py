@@ -78,6 +78,9 @@ def lib():
         L.or_lsq_refined.argtypes = [vp, dp, i64, dp, dp, ctypes.c_int]
         L.or_lsq_refined.restype = i64
         L.or_max_threads.restype = ctypes.c_int
+        L.or_tslu.argtypes = [i64, i64, dp, i64, i64, ip, ip, i64, i64, i64, ip, ip, ctypes.c_int,
+                              ip, dp, i64, dp, i64]
+        L.or_tslu.restype = i64
         L.or_cond1.argtypes = [i64, dp, i64]
         L.or_cond1.restype = ctypes.c_double
         L.or_cond1_est.argtypes = [i64, dp, i64]
@@ -162,6 +165,33 @@ def partition_weighted(m: int, n: int, P: int, granule: int, weights=None):
     if got < 1:
         raise ValueError("no such partition (a domain gets no granule or fewer than n rows)")
     return list(zip(r0.tolist(), nr.tolist()))
+
+
+def tslu(A, parts, first: int, stage: int, tree: int = TREE_BINARY, sched=None, nthreads: int = 0):
+    """LU with tournament pivoting (TSQR's tree applied to LU, the paper's
+    conclusion): each domain (row0, nrows) of `parts` selects b pivot rows by
+    partial-pivoting elimination over stages (its first `first` rows, then
+    its selection stacked on the next `stage` rows), the domains' selections
+    are combined along the tree, and A = L U with U the LU of A[ipiv] and
+    l_i = a_i U^{-1}.  Returns (ipiv, L, U, info)."""
+    A = _fortran(A)
+    m, b = A.shape
+    P = len(parts)
+    if sched is None:
+        sched = schedule(P, tree)
+    r0 = np.array([p[0] for p in parts], dtype=np.int64)
+    nr = np.array([p[1] for p in parts], dtype=np.int64)
+    sl = np.array([s[0] for s in sched] or [0], dtype=np.int64)
+    sr = np.array([s[1] for s in sched] or [0], dtype=np.int64)
+    ipiv = np.zeros(b, dtype=np.int64)
+    L = np.zeros((m, b), order="F")
+    U = np.zeros((b, b), order="F")
+    nt = nthreads if nthreads > 0 else max_threads()
+    info = int(lib().or_tslu(m, b, _dp(A), m, P, _ip(r0), _ip(nr), first, stage, len(sched), _ip(sl),
+                             _ip(sr), nt, _ip(ipiv), _dp(L), m, _dp(U), b))
+    if info < 0:
+        raise ValueError("oracle TSLU rejected its arguments")
+    return ipiv, L, U, info
 
 
 def cond1(R) -> float:

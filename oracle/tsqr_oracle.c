@@ -729,6 +729,152 @@ ORACLE_API double or_cond1_est(int64_t n, const double *R, int64_t ldr)
     return or_norm1_tri(n, R, ldr) * est;
 }
 
+/* ------------------------------------------------------------------------ */
+/* TSLU: LU of a tall-skinny matrix with tournament pivoting, the extension */
+/* the paper names in its conclusion (TSQR's reduction tree carries over  */
+/* to LU, CALU's panel factorization).  The tree selects b pivot rows:     */
+/*   - a node takes a stack of original rows of A (its children's selected */
+/*     rows, or raw rows of A) and runs Gaussian elimination with partial  */
+/*     pivoting on it; the b rows chosen as pivots, in order, are its      */
+/*     selection (the original rows, not their eliminated values);        */
+/*   - inside a domain the rows are taken in stages, a flat tree: the first */
+/*     `first` rows, then repeatedly the current selection stacked on the  */
+/*     next `stage` rows;                                                  */
+/*   - across domains the selections are combined along the schedule       */
+/*     (left, right): the left's selection stacked on the right's.         */
+/* The root's selection gives ipiv (global row indices, pivot order).  U    */
+/* and the unit lower L11 are the LU factors of A[ipiv, :] without further */
+/* pivoting, and every other row i gets l_i = a_i U^{-1}, so A = L U with  */
+/* L (m x b) in A's row order (rows ipiv[k] hold L11's rows).  Ties in a  */
+/* pivot search go to the lowest stack position (stacks keep their order, */
+/* no rows are swapped); a zero pivot column takes its first active row,  */
+/* eliminates nothing, and the solve for l_i leaves l_k = 0 where U_kk = 0.*/
+/* Returns 0, j + 1 for the first U_jj = 0, or -1 for bad arguments.      */
+/* ------------------------------------------------------------------------ */
+
+/* Partial-pivoting elimination on the r x b stack S (column-major, ld r,  */
+/* overwritten); sel receives the stack positions of the min(b, r) pivots. */
+static void or_gepp_select(int64_t r, int64_t b, double *S, int64_t *sel)
+{
+    char *act = (char *)malloc((size_t)r);
+    for (int64_t i = 0; i < r; ++i) act[i] = 1;
+    int64_t kb = b < r ? b : r;
+    for (int64_t j = 0; j < kb; ++j) {
+        int64_t p = -1;
+        double best = -1.0;
+        for (int64_t i = 0; i < r; ++i)
+            if (act[i] && fabs(S[i + j * r]) > best) { best = fabs(S[i + j * r]); p = i; }
+        if (p < 0)   /* a column of NaNs: its first active row */
+            for (int64_t i = r - 1; i >= 0; --i) if (act[i]) p = i;
+        if (p < 0) break;    /* not reached: r - j >= 1 rows are active */
+        sel[j] = p;
+        act[p] = 0;
+        double piv = S[p + j * r];
+        if (piv == 0.0) continue;
+        for (int64_t i = 0; i < r; ++i) {
+            if (!act[i]) continue;
+            double l = S[i + j * r] / piv;
+            S[i + j * r] = l;
+            for (int64_t k = j + 1; k < b; ++k) S[i + k * r] -= l * S[p + k * r];
+        }
+    }
+    free(act);
+}
+
+/* Selection of the stack made of the rows idx[0..r-1] of A. */
+static int64_t or_select_rows(int64_t b, const double *A, int64_t lda, int64_t r, const int64_t *idx,
+                              int64_t *out)
+{
+    double *S = (double *)malloc(sizeof(double) * (size_t)r * b);
+    int64_t *sel = (int64_t *)malloc(sizeof(int64_t) * (size_t)b);
+    for (int64_t k = 0; k < b; ++k)
+        for (int64_t i = 0; i < r; ++i) S[i + k * r] = A[idx[i] + k * lda];
+    or_gepp_select(r, b, S, sel);
+    int64_t kb = b < r ? b : r;
+    for (int64_t j = 0; j < kb; ++j) out[j] = idx[sel[j]];
+    free(S); free(sel);
+    return kb;
+}
+
+ORACLE_API int64_t or_tslu(int64_t m, int64_t b, const double *A, int64_t lda, int64_t P,
+                           const int64_t *row0, const int64_t *nrows, int64_t first, int64_t stage,
+                           int64_t nnodes, const int64_t *sl, const int64_t *sr, int nthreads,
+                           int64_t *ipiv, double *L, int64_t ldl, double *U, int64_t ldu)
+{
+    if (b < 1 || m < b || lda < m || ldl < m || ldu < b || P < 1 || first < b || stage < 1 ||
+        nnodes != P - 1)
+        return -1;
+    for (int64_t d = 0, r = 0; d < P; r += nrows[d], ++d)
+        if (row0[d] != r || nrows[d] < b || (d == P - 1 && r + nrows[d] != m)) return -1;
+    int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)P * b);
+    int nt = nthreads > 0 ? nthreads : 1;
+    (void)nt;
+#pragma omp parallel for schedule(dynamic) num_threads(nt)
+    for (int64_t d = 0; d < P; ++d) {
+        int64_t *cur = cand + d * b;
+        int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(b + (first > stage ? first : stage)));
+        int64_t end = row0[d] + nrows[d];
+        int64_t pos = row0[d], nc = 0, r = 0;
+        int64_t take = nrows[d] < first ? nrows[d] : first;
+        for (int64_t i = 0; i < take; ++i) idx[r++] = pos + i;
+        pos += take;
+        nc = or_select_rows(b, A, lda, r, idx, cur);
+        while (pos < end) {
+            take = end - pos < stage ? end - pos : stage;
+            r = 0;
+            for (int64_t i = 0; i < nc; ++i) idx[r++] = cur[i];
+            for (int64_t i = 0; i < take; ++i) idx[r++] = pos + i;
+            pos += take;
+            nc = or_select_rows(b, A, lda, r, idx, cur);
+        }
+        free(idx);
+    }
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)2 * b);
+    for (int64_t q = 0; q < nnodes; ++q) {
+        for (int64_t i = 0; i < b; ++i) { idx[i] = cand[sl[q] * b + i]; idx[b + i] = cand[sr[q] * b + i]; }
+        or_select_rows(b, A, lda, 2 * b, idx, cand + sl[q] * b);
+    }
+    free(idx);
+    for (int64_t k = 0; k < b; ++k) ipiv[k] = cand[k];
+    free(cand);
+
+    /* U and L11: LU of A[ipiv, :] without pivoting */
+    double *M = (double *)malloc(sizeof(double) * (size_t)b * b);
+    for (int64_t k = 0; k < b; ++k)
+        for (int64_t i = 0; i < b; ++i) M[i + k * b] = A[ipiv[i] + k * lda];
+    int64_t info = 0;
+    for (int64_t j = 0; j < b; ++j) {
+        double piv = M[j + j * b];
+        if (piv == 0.0) { if (!info) info = j + 1; continue; }
+        for (int64_t i = j + 1; i < b; ++i) {
+            double l = M[i + j * b] / piv;
+            M[i + j * b] = l;
+            for (int64_t k = j + 1; k < b; ++k) M[i + k * b] -= l * M[j + k * b];
+        }
+    }
+    for (int64_t k = 0; k < b; ++k)
+        for (int64_t i = 0; i < b; ++i) U[i + k * ldu] = (i <= k) ? M[i + k * b] : 0.0;
+    /* L: the pivot rows from L11, every other row by l U = a */
+    char *isp = (char *)calloc((size_t)m, 1);
+    for (int64_t k = 0; k < b; ++k) isp[ipiv[k]] = 1;
+    for (int64_t k = 0; k < b; ++k)
+        for (int64_t i = 0; i < m; ++i) L[i + k * ldl] = 0.0;
+    for (int64_t i = 0; i < b; ++i)
+        for (int64_t k = 0; k < b; ++k)
+            L[ipiv[i] + k * ldl] = (k < i) ? M[i + k * b] : (k == i ? 1.0 : 0.0);
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t i = 0; i < m; ++i) {
+        if (isp[i]) continue;
+        for (int64_t k = 0; k < b; ++k) {
+            double s = A[i + k * lda];
+            for (int64_t j = 0; j < k; ++j) s -= L[i + j * ldl] * U[j + k * ldu];
+            L[i + k * ldl] = (U[k + k * ldu] == 0.0) ? 0.0 : s / U[k + k * ldu];
+        }
+    }
+    free(isp); free(M);
+    return info;
+}
+
 /* Number of OpenMP threads the oracle will use when asked for nthreads<=0. */
 ORACLE_API int or_max_threads(void)
 {

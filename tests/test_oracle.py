@@ -14,6 +14,7 @@ from fractions import Fraction
 
 import numpy as np
 import pytest
+import scipy.linalg
 import scipy.linalg.lapack as lapack
 
 import oracle
@@ -227,6 +228,93 @@ def test_factor_over_a_partition_rejects_gaps():
         oracle.TSQR(A, parts=[(0, 100), (100, 150)])      # stops short of m
     with pytest.raises(ValueError):
         oracle.TSQR(A, parts=[(0, 299), (299, 1)])        # a domain shorter than n
+
+
+# ------------------------------------------------------------------- TSLU
+
+def _lapack_pivot_rows(A):
+    """The rows LAPACK's dgetrf picks as pivots, in order (its swaps replayed)."""
+    lu, piv = scipy.linalg.lu_factor(A)
+    perm = np.arange(A.shape[0])
+    for i, p in enumerate(piv):
+        perm[i], perm[p] = perm[p], perm[i]
+    return perm[:A.shape[1]], lu
+
+
+@pytest.mark.parametrize("m,b", [(1000, 8), (300, 1), (64, 64), (5000, 33)])
+def test_tslu_one_stage_is_partial_pivoting(m, b):
+    """One domain taken in one stage: the selection is GEPP's pivot sequence
+    and U, L are dgetrf's (L's rows in A's order)."""
+    A = np.random.default_rng(m + b).standard_normal((m, b))
+    ipiv, L, U, info = oracle.tslu(A, [(0, m)], first=m, stage=1)
+    pr, lu = _lapack_pivot_rows(A)
+    assert info == 0
+    assert ipiv.tolist() == pr.tolist()
+    assert rel(U, np.triu(lu[:b])) <= 1e-13
+    Ll = np.tril(lu, -1)[:, :b] + np.eye(m, b)
+    perm = np.arange(m)
+    _, piv = scipy.linalg.lu_factor(A)
+    for i, p in enumerate(piv):
+        perm[i], perm[p] = perm[p], perm[i]
+    assert rel(L[perm], Ll) <= 1e-13
+
+
+def test_tslu_every_node_selects_by_partial_pivoting():
+    """Two domains in stages and a root: each stage's and the root's
+    selection equal dgetrf's pivot rows on the stacked original rows."""
+    rng = np.random.default_rng(3)
+    m, b = 50, 3
+    A = rng.standard_normal((m, b))
+    parts = [(0, 20), (20, 30)]
+    first, stage = 8, 5
+    sel = []
+    for r0, nr in parts:
+        rows = list(range(r0, r0 + first))
+        cur = [rows[i] for i in _lapack_pivot_rows(A[rows])[0]]
+        pos = r0 + first
+        while pos < r0 + nr:
+            rows = cur + list(range(pos, min(pos + stage, r0 + nr)))
+            cur = [rows[i] for i in _lapack_pivot_rows(A[rows])[0]]
+            pos += stage
+        sel.append(cur)
+    rows = sel[0] + sel[1]
+    root = [rows[i] for i in _lapack_pivot_rows(A[rows])[0]]
+    ipiv, L, U, info = oracle.tslu(A, parts, first=first, stage=stage)
+    assert ipiv.tolist() == root
+
+
+@pytest.mark.parametrize("m,b,mb,first,stage,tree", [(20000, 16, 4096, 256, 240, oracle.TREE_BINARY),
+                                                     (9001, 64, 1000, 256, 192, oracle.TREE_QUAD),
+                                                     (3000, 5, 700, 100, 95, oracle.TREE_FLAT)])
+def test_tslu_factorization_invariants(m, b, mb, first, stage, tree):
+    """A = L U, L unit lower trapezoidal in the pivot order, |L| small
+    (tournament pivoting keeps multipliers bounded in practice)."""
+    A = np.random.default_rng(m).standard_normal((m, b))
+    ipiv, L, U, info = oracle.tslu(A, oracle.partition(m, b, mb), first=first, stage=stage, tree=tree)
+    assert info == 0 and len(set(ipiv.tolist())) == b
+    assert np.linalg.norm(A - L @ U) <= 1e-14 * math.sqrt(m) * np.linalg.norm(A)
+    assert np.all(np.tril(U, -1) == 0.0)
+    L11 = L[ipiv]
+    assert np.all(np.triu(L11, 1) == 0.0) and np.all(np.diag(L11) == 1.0)
+    assert np.max(np.abs(L)) <= 20.0
+    # the pivots of the root's stack came first: its U is the LU of A[ipiv]
+    assert rel(L11 @ U, A[ipiv]) <= 1e-14
+
+
+def test_tslu_exact_zero_column_info():
+    A = np.random.default_rng(4).standard_normal((400, 6))
+    A[:, 2] = 0.0
+    ipiv, L, U, info = oracle.tslu(A, oracle.partition(400, 6, 100), first=50, stage=44)
+    assert info == 3 and U[2, 2] == 0.0 and np.all(L[:, 2][np.setdiff1d(np.arange(400), ipiv)] == 0.0)
+
+
+def test_tslu_integer_ties_go_to_the_lowest_row():
+    # every |entry| of the first column equal: each search takes its first
+    # active stack position, so the domain heads win
+    A = np.ones((12, 2))
+    A[:, 1] = np.arange(12) % 5
+    ipiv, L, U, info = oracle.tslu(A, [(0, 6), (6, 6)], first=6, stage=1)
+    assert ipiv[0] == 0
 
 
 # ------------------------------------------------- condition of R (routing)
