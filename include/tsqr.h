@@ -285,6 +285,34 @@ TSQR_API int tsqr_block_orth(int64_t m, int64_t nv, const double *V, int64_t ldv
                              int64_t ldw, double *H, int64_t ldh, double *R, int64_t ldr, const tsqr_opts *o,
                              void *dwork, size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+   TSLU: LU of a tall-skinny matrix with tournament pivoting, the extension
+   of TSQR's reduction tree to LU that the paper's conclusion names (CALU's
+   panel factorization).  The rows are split into domains as for tsqr_factor
+   (opts.row_block or opts.domains, opts.tree for the tree); each domain
+   picks b candidate pivot rows by Gaussian elimination with partial
+   pivoting over stacks of 256 rows (its first 256 rows, then its
+   candidates on the next 256 - b rows), and the tree combines candidate
+   sets the same way (the left's stacked on the right's).  With ipiv the
+   root's rows in pivot order:
+     U (b x b, device, ldu >= b): upper triangular, A[ipiv, :] = L11 U
+       without further pivoting;
+     L (m x b, device, ldl >= m): rows ipiv[k] hold row k of the unit lower
+       L11, every other row l_i = a_i U^{-1}; so A = L U with L a row
+       permutation of a unit lower trapezoidal matrix;
+     ipiv (b, device, int64): the pivot rows of A, in order;
+     dinfo (device, one int32, may be NULL): 0, or j + 1 for the first
+       U_jj = 0 (that column's l entries are then 0).
+   A pivot search takes the largest |entry| of the live rows, ties to the
+   earlier stack position; NaNs rank last.  A (m x b, device, lda >= m) is
+   not modified.  b <= 64.  Errors: -1 m, -2 b, -3 A NULL, -4 lda, -5 opts,
+   -6 L NULL or ldl, -7 U NULL or ldu, -8 ipiv NULL, TSQR_ERR_WORKSPACE,
+   TSQR_ERR_UNSUPPORTED for b > 64, -1000-e on a HIP error. */
+TSQR_API size_t tsqr_tslu_workspace_bytes(int64_t m, int64_t b, const tsqr_opts *o);
+TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const tsqr_opts *o,
+                       void *dwork, size_t work_bytes, double *L, int64_t ldl, double *U, int64_t ldu,
+                       int64_t *ipiv, int32_t *dinfo, void *stream);
+
 /* Estimate of the 1-norm condition number kappa_1(R) = ||R||_1 ||R^{-1}||_1
    of the factor's R (= kappa_1 of A up to the factorization's rounding),
    written to *kappa (device, one double) on `stream`: ||R||_1 times Hager's

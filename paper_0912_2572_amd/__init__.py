@@ -149,6 +149,10 @@ def lib():
         L.tsqr_factor_solve_noalloc.restype = ctypes.c_int
         L.tsqr_plan_info.argtypes = [i64, i64, op, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(i64)]
+        L.tsqr_tslu_workspace_bytes.argtypes = [i64, i64, op]
+        L.tsqr_tslu_workspace_bytes.restype = sz
+        L.tsqr_tslu.argtypes = [i64, i64, vp, i64, op, vp, sz, vp, i64, vp, i64, vp, vp, vp]
+        L.tsqr_tslu.restype = ctypes.c_int
         L.tsqr_cond_estimate.argtypes = [vp, vp, vp]
         L.tsqr_cond_estimate.restype = ctypes.c_int
         L.tsqr_route_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -461,6 +465,35 @@ def factor_solve(A: torch.Tensor, B: torch.Tensor, o: Opts | None = None, work: 
     F = Factors.__new__(Factors)
     F.m, F.n, F.opts, F.work, F._h = m, n, o, work, h
     return F, X, resid, info
+
+
+def tslu(A: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = None, L: torch.Tensor | None = None,
+         U: torch.Tensor | None = None, stream=None):
+    """LU with tournament pivoting over the TSQR partition and tree
+    (tsqr_tslu): returns (ipiv, L, U, info) with A = L U, ipiv the pivot rows
+    of A in order and L a row permutation of a unit lower trapezoidal matrix."""
+    m, b = A.shape
+    o = o if o is not None else opts()
+    dev = A.device
+    need = int(lib().tsqr_tslu_workspace_bytes(m, b, ctypes.byref(o)))
+    if need == 0:
+        raise ValueError(f"invalid TSLU problem {m} x {b} for the given options")
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    if L is None:
+        L = empty_colmajor(m, b, device=dev)
+    if U is None:
+        U = empty_colmajor(b, b, device=dev)
+    ipiv = torch.empty(b, dtype=torch.int64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    pa, lda = _col_major(A, m, "A")
+    pl, ldl = _col_major(L, m, "L")
+    pu, ldu = _col_major(U, b, "U")
+    _check(lib().tsqr_tslu(m, b, ctypes.c_void_p(pa), lda, ctypes.byref(o), ctypes.c_void_p(work.data_ptr()),
+                           work.numel(), ctypes.c_void_p(pl), ldl, ctypes.c_void_p(pu), ldu,
+                           ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(info.data_ptr()), _stream(stream)),
+           "tsqr_tslu")
+    return ipiv, L, U, info
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

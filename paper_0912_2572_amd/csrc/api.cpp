@@ -446,6 +446,52 @@ TSQR_API int tsqr_form_q(tsqr_factors f, double *Q, int64_t ldq, void *stream) {
     return apply_q_impl(f, f->plan.n, Q, ldq, false, true, st);
 }
 
+namespace {
+
+// TSLU's workspace: the candidate rows of every domain (P x b, int32) and a
+// 64 x 64 block for L11.
+size_t tslu_bytes(const Plan &p, int64_t b) {
+    const size_t cand = ((size_t)p.panels[0].P * (size_t)b * sizeof(int32_t) + tsqr::kAlign - 1) /
+                        tsqr::kAlign * tsqr::kAlign;
+    return cand + sizeof(double) * 64 * 64;
+}
+
+}  // namespace
+
+TSQR_API size_t tsqr_tslu_workspace_bytes(int64_t m, int64_t b, const tsqr_opts *o) {
+    if (b < 1 || b > tsqr::kMaxPanel) return 0;
+    Plan p;
+    if (tsqr::make_plan(m, b, o, &p) != 0) return 0;
+    return tslu_bytes(p, b);
+}
+
+TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const tsqr_opts *o, void *dwork,
+                       size_t work_bytes, double *L, int64_t ldl, double *U, int64_t ldu, int64_t *ipiv,
+                       int32_t *dinfo, void *stream) {
+    if (b > tsqr::kMaxPanel) return TSQR_ERR_UNSUPPORTED;
+    if (b < 1) return -2;
+    Plan p;
+    const int rc = tsqr::make_plan(m, b, o, &p);
+    if (rc) return rc;
+    if (!A) return -3;
+    if (lda < m) return -4;
+    if (!L || ldl < m) return -6;
+    if (!U || ldu < b) return -7;
+    if (!ipiv) return -8;
+    const size_t need = tslu_bytes(p, b);
+    if (!dwork || work_bytes < need || (reinterpret_cast<uintptr_t>(dwork) % tsqr::kAlign))
+        return TSQR_ERR_WORKSPACE;
+    const Panel &pp = p.panels[0];
+    std::vector<TreeArgs> levels;
+    for (const auto &Lv : tsqr::tree_levels(pp.P, pp.tree)) levels.push_back(TreeArgs{Lv.stride, Lv.span, Lv.chains, Lv.width});
+    char *w = static_cast<char *>(dwork);
+    int32_t *cand = reinterpret_cast<int32_t *>(w);
+    double *L11 = reinterpret_cast<double *>(w + need - sizeof(double) * 64 * 64);
+    hipError_t e = tsqr::launch_tslu(A, lda, panel_args(pp), levels, (int)b, cand, L11, L, ldl, U, ldu, ipiv,
+                                     dinfo, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
 TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream) {
     int rc = validate_handle(f, false);
     if (rc) return rc;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace tsqr {
 
@@ -180,6 +181,13 @@ hipError_t launch_fill_identity_signs(double *Q, int64_t ldq, int64_t m, int n, 
 hipError_t launch_fill(double *p, int64_t count, double value, hipStream_t st);
 hipError_t launch_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
                        int64_t cols, hipStream_t st);
+// TSLU (tslu.hip): candidate rows per domain into cand (P x b, int32), the
+// tree levels, then ipiv, U (b x b), L (m x b) and dinfo; L11 is a 64 x 64
+// scratch block.
+hipError_t launch_tslu(const double *A, int64_t lda, const PanelArgs &pa, const std::vector<TreeArgs> &levels,
+                       int b, int32_t *cand, double *L11, double *L, int64_t ldl, double *U, int64_t ldu,
+                       int64_t *ipiv, int32_t *dinfo, hipStream_t st);
+
 // kappa_1(R) estimate of an n x n upper-triangular R (ld n, n <= 256) into
 // *kappa (device): one wave.
 hipError_t launch_cond_est(const double *R, int n, double *kappa, hipStream_t st);

@@ -199,6 +199,24 @@ def test_batch_create_rejects_on_host(tl):
     assert L.tsqr_autotune(1, items, 0, None, 0, None, None, 0) == -3
 
 
+def test_tslu_arguments_checked_on_host(tl):
+    L = tl.lib()
+    o = tl.opts(row_block=1000)
+    d = ctypes.c_void_p(256)
+    w = tl.lib().tsqr_tslu_workspace_bytes(10000, 16, ctypes.byref(o))
+    assert w >= 10 * 16 * 4
+    assert L.tsqr_tslu_workspace_bytes(10000, 65, ctypes.byref(o)) == 0
+    args = lambda m, b, lda, ldl, ldu: (m, b, d, lda, ctypes.byref(o), d, 1 << 30, d, ldl, d, ldu, d, None, None)
+    assert L.tsqr_tslu(*args(10000, 65, 10000, 10000, 65)) == tl.ERR_UNSUPPORTED
+    assert L.tsqr_tslu(*args(10000, 0, 10000, 10000, 1)) == -2
+    assert L.tsqr_tslu(*args(10, 16, 10, 10, 16)) == -1
+    assert L.tsqr_tslu(*args(10000, 16, 9999, 10000, 16)) == -4
+    assert L.tsqr_tslu(*args(10000, 16, 10000, 9999, 16)) == -6
+    assert L.tsqr_tslu(*args(10000, 16, 10000, 10000, 15)) == -7
+    small = (10000, 16, d, 10000, ctypes.byref(o), d, 16, d, 10000, d, 16, d, None, None)
+    assert L.tsqr_tslu(*small) == tl.ERR_WORKSPACE
+
+
 def test_routing_calls_check_their_handle(tl):
     L = tl.lib()
     prec, kap = ctypes.c_int32(), ctypes.c_double()
