@@ -93,7 +93,7 @@ def cpu_baseline(m: int, n: int, mb: int, passes: int, samples: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="single",
-                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "copy"])
+                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -119,7 +119,7 @@ def main():
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
-     "sweep": run_sweep, "orth": run_orth, "copy": run_copy}[args.workload](args)
+     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "copy": run_copy}[args.workload](args)
 
 
 def counter_record(kernel: str, m: int, n: int, mb: int, tree: str, kind: str):
@@ -327,6 +327,8 @@ def sub_records(args):
     t4 = time.perf_counter()
     ob = measure_orth(args, steps=3, warmup=1)
     t5 = time.perf_counter()
+    lu = measure_tslu(args, steps=5, warmup=1)
+    t5b = time.perf_counter()
     # a row count where 4096-row domains (293 of them) leave a second, mostly
     # idle wave of leaf workgroups on the 256 compute units, against the
     # load-balanced partition (one domain of 18-19 chunks per unit)
@@ -342,7 +344,7 @@ def sub_records(args):
                                "leaf_ms": uni["kernels_ms_per_step"].get("leaf_factor")},
             "balanced": {"domains": bal["config"]["domains"], "ms_per_step": bal["ms_per_step"],
                          "gflops": bal["value"], "leaf_ms": bal["kernels_ms_per_step"].get("leaf_factor")},
-            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5, 1)},
+            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5b, 1)},
         "mixed_kappa1e6": {
             "workload": mx["config"]["workload"],
             "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
@@ -366,6 +368,10 @@ def sub_records(args):
             "mixed_p99_ms_saturated": round(sv["mixed_saturated"]["p99_ms"], 2),
             "sampled_eta_max": sv["sampled_eta_max"], "wall_s": round(t3 - t2, 1)},
         "n_sweep_m2p20": {**sw["by_n"], "wall_s": round(t4 - t3, 1)},
+        "tslu_1048576x64": {
+            "ms": lu["ms_per_step"], "gflops": lu["value"], "leaf_ms": lu["leaf_ms"],
+            "rel_residual": lu["rel_residual_A_minus_LU"], "max_abs_L": lu["max_abs_L"],
+            "wall_s": round(t5b - t5, 1)},
         "block_krylov_orth": {
             "workload": ob["config"]["workload"], "ms_per_loop": ob["ms_per_step"], "gflops": ob["value"],
             "roofline_frac_hbm": ob["roofline"]["frac"], "proj_update_gbs": ob["proj_update_gbs"],
@@ -696,6 +702,55 @@ def measure_serve(args, requests, loads, mixed_pass):
         "sampled_eta_max": worst,
     }
     return line
+
+
+def run_tslu(args):
+    print(json.dumps(measure_tslu(args, args.steps, args.warmup)), flush=True)
+
+
+def measure_tslu(args, steps, warmup, m=1 << 20, b=64):
+    """TSLU (LU with tournament pivoting over the TSQR partition and binary
+    tree) of an m x b N(0,1) matrix with 4096-row domains; useful flops
+    m b^2 - b^3/3 (the LU of the panel)."""
+    import torch
+    import paper_0912_2572_amd as tl
+    import synth
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(synth.config_large(m, b, seed=0)).t().contiguous().t().to(dev)
+    o = tl.opts(row_block=4096)
+    work = torch.empty(tl.lib().tsqr_tslu_workspace_bytes(m, b, ctypes_ref(o)), dtype=torch.uint8, device=dev)
+    L = tl.empty_colmajor(m, b, device=dev)
+    U = tl.empty_colmajor(b, b, device=dev)
+
+    def step():
+        return tl.tslu(A, o, work=work, L=L, U=U)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tl.prof_enable(True)
+    step()
+    torch.cuda.synchronize()
+    kern = tl.prof_query()
+    tl.prof_enable(False)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        ipiv, _, _, info = step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    flops = m * b * b - b ** 3 / 3.0
+    res = float(torch.linalg.norm(A - L @ U) / torch.linalg.norm(A))
+    lmax = float(L.abs().max())
+    leaf_ms = kern.get("tslu_leaf", (1, 0.0))[1]
+    return {"metric": "TSLU Gflop/s (LU with tournament pivoting)", "value": round(flops / (ms * 1e-3) / 1e9, 2),
+            "unit": "Gflop/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic iid N(0,1), seed 0",
+            "config": {"workload": f"tsqr_tslu {m}x{b}", "m": m, "b": b, "row_block": 4096, "tree": "binary",
+                       "stack_rows": 256},
+            "info": int(info.item()), "rel_residual_A_minus_LU": res, "max_abs_L": lmax,
+            "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()},
+            "leaf_ms": round(leaf_ms, 4)}
 
 
 def run_orth(args):

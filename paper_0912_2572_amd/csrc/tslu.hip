@@ -16,12 +16,13 @@
 //   k_tslu_l      l_i = a_i U^{-1} for every row (one row per thread);
 //   k_tslu_scatter  rows ipiv[k] of L <- row k of L11.
 //
-// Stack layout (256 threads): thread t holds the 16 stack rows 16 (t & 15)
-// .. +15 of the four columns 4 (t >> 4) .. +3, so the 16 lanes holding a
-// column sit in one 16-lane segment of one wave: the pivot search is a
-// 16-lane shuffle reduction, the pivot row's entries come from a lane of the
-// thread's own segment, and only the multipliers of the step go through LDS
-// (double-buffered: one barrier per elimination step).
+// Stack layout (256 threads): thread t holds the stack positions 16 i +
+// (t & 15), i = 0..15, of the four columns 4 (t >> 4) .. +3, so the 16 lanes
+// holding a column form one 16-lane row of one wave: the pivot search is a
+// DPP reduction in that row, the pivot row's entries come from a lane of the
+// thread's own row by DPP broadcast, and only the multipliers of the step
+// go through LDS (double-buffered: one barrier per elimination step).
+#include "common.h"
 #include "kernels.h"
 #include "prof.h"
 
@@ -40,12 +41,65 @@ struct TsluSmem {
 
 typedef double Rows16[16];   // the 16 stack rows one thread holds of one column
 
-// The pivot search and the multipliers of column j (this lane's column jc of
-// four) in the 16 lanes holding it; the column index is a template argument
-// so that every register access is static.
+// Lane l of a 16-lane row <- lane N of that row (DPP row_newbcast).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+    return dpp_f64<0x150 + N>(v);
+}
+
+// (value, position) pairs: the larger value wins, equal values go to the
+// lower position.
+__device__ __forceinline__ void argmax_take(double &best, int &bp, double &bv, double ob, int op, double ov) {
+    if (ob > best || (ob == best && op < bp)) {
+        best = ob;
+        bp = op;
+        bv = ov;
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double &best, int &bp, double &bv) {
+    argmax_take(best, bp, bv, dpp_f64<CTRL>(best), __builtin_amdgcn_update_dpp(0, bp, CTRL, 0xf, 0xf, false),
+                dpp_f64<CTRL>(bv));
+}
+
+// Loads the stack: position q = 16 i + r (r = lane in its 16-lane row, i =
+// slot) holds row gidx[q] of A for q < rows, so the 16 lanes of a row read
+// 16 consecutive positions of a column per load; columns past b and
+// positions past rows are zero.  act: bit i set when slot i is live.  Every
+// load is issued before any is used (addresses clamped into A).
+__device__ __forceinline__ void load_stack(const TsluSmem &sm, const double *__restrict__ A, int64_t lda,
+                                           int rows, int b, Rows16 (&a)[4], uint32_t &act) {
+    const int t = threadIdx.x, cg = t >> 4, r = t & 15;
+    int64_t g[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = 16 * i + r;
+        g[i] = q < rows ? sm.gidx[q] : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int64_t co = (int64_t)(4 * cg + c < b ? 4 * cg + c : 0) * lda;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[c][i] = A[g[i] + co];
+    }
+    act = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const bool live = 16 * i + r < rows;
+        if (live) act |= 1u << i;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (!live || 4 * cg + c >= b) a[c][i] = 0.0;
+    }
+}
+
+// The pivot search and the multipliers of column j (column JC of this
+// lane's four) in the 16 lanes holding it; the column index is a template
+// argument so that every register access is static.
 template <int JC>
 __device__ __forceinline__ void pivot_column(TsluSmem &sm, const Rows16 (&a)[4], uint32_t act, int j, int par) {
-    const int rb = threadIdx.x & 15;
+    const int r = threadIdx.x & 15;
     double best = -1.0, bv = 0.0;
     int bp = 1 << 30;
 #pragma unroll
@@ -54,59 +108,37 @@ __device__ __forceinline__ void pivot_column(TsluSmem &sm, const Rows16 (&a)[4],
         if (key != key) key = -0.5;
         if (((act >> i) & 1u) && key > best) {
             best = key;
-            bp = 16 * rb + i;
+            bp = 16 * i + r;
             bv = a[JC][i];
         }
     }
-#pragma unroll
-    for (int s = 1; s < 16; s <<= 1) {
-        const double ob = __shfl_xor(best, s, 16);
-        const int op = __shfl_xor(bp, s, 16);
-        const double ov = __shfl_xor(bv, s, 16);
-        if (ob > best || (ob == best && op < bp)) {
-            best = ob;
-            bp = op;
-            bv = ov;
-        }
-    }
+    argmax_step<kDppXor1>(best, bp, bv);
+    argmax_step<kDppXor2>(best, bp, bv);
+    argmax_step<0x124>(best, bp, bv);   // row_ror:4: the next quad's winner
+    argmax_step<kDppRowRor8>(best, bp, bv);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const int q = 16 * rb + i;
+        const int q = 16 * i + r;
         const bool live = ((act >> i) & 1u) && q != bp && bv != 0.0;
         sm.l[par][q] = live ? a[JC][i] / bv : 0.0;
     }
-    if (rb == 0) {
+    if (r == 0) {
         sm.piv[par] = bp;
         sm.sel[j] = bp;
     }
 }
 
-// u[c] = a[c][K]: one case of a branch on the wave-uniform row index.
+// u[c] = a[c][K]: one case of a branch on the wave-uniform slot index.
 template <int K>
-__device__ __forceinline__ void take_row(const Rows16 (&a)[4], double (&u)[4]) {
+__device__ __forceinline__ void take_slot(const Rows16 (&a)[4], double (&u)[4]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) u[c] = a[c][K];
 }
 
-// Loads the stack: position q holds row gidx[q] of A for q < rows (columns
-// past b and positions past rows are zero).  act: this thread's live rows.
-__device__ __forceinline__ void load_stack(const TsluSmem &sm, const double *__restrict__ A, int64_t lda,
-                                           int rows, int b, Rows16 (&a)[4], uint32_t &act) {
-    const int t = threadIdx.x, cg = t >> 4, rb = t & 15;
-    act = 0;
+template <int N>
+__device__ __forceinline__ void bcast_from(double (&u)[4]) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int q = 16 * rb + i;
-        const bool live = q < rows;
-        if (live) act |= 1u << i;
-        const int64_t g = live ? sm.gidx[q] : 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int col = 4 * cg + c;
-            const double v = A[g + (int64_t)(col < b ? col : 0) * lda];
-            a[c][i] = (live && col < b) ? v : 0.0;
-        }
-    }
+    for (int c = 0; c < 4; ++c) u[c] = row_bcast<N>(u[c]);
 }
 
 // min(b, rows) steps of partial-pivoting elimination on the stack; the
@@ -114,9 +146,12 @@ __device__ __forceinline__ void load_stack(const TsluSmem &sm, const double *__r
 // NaN ranks below every number (a column of NaNs takes its first live row);
 // a zero pivot eliminates nothing.  Entries of columns <= j keep being
 // updated after their step (never read again), so every column takes the
-// same update and no lane branches on its column.
+// same update and no lane branches on its column.  The pivot row's entries
+// come from the lane of the thread's own 16-lane row that holds it: a
+// branch on the (wave-uniform) slot picks the register, a DPP broadcast
+// moves it.
 __device__ __forceinline__ void gepp_steps(TsluSmem &sm, Rows16 (&a)[4], uint32_t act, int rows, int b) {
-    const int t = threadIdx.x, cg = t >> 4, rb = t & 15;
+    const int t = threadIdx.x, cg = t >> 4, r = t & 15;
     const int kb = b < rows ? b : rows;
     for (int j = 0; j < kb; ++j) {
         const int par = j & 1;
@@ -130,32 +165,48 @@ __device__ __forceinline__ void gepp_steps(TsluSmem &sm, Rows16 (&a)[4], uint32_
         }
         __syncthreads();
         const int p = __builtin_amdgcn_readfirstlane(sm.piv[par]);
-        const int ip = p & 15, src = p >> 4;
+        const int slot = p >> 4, src = p & 15;
         double u[4];
-        switch (ip) {
-            case 0: take_row<0>(a, u); break;
-            case 1: take_row<1>(a, u); break;
-            case 2: take_row<2>(a, u); break;
-            case 3: take_row<3>(a, u); break;
-            case 4: take_row<4>(a, u); break;
-            case 5: take_row<5>(a, u); break;
-            case 6: take_row<6>(a, u); break;
-            case 7: take_row<7>(a, u); break;
-            case 8: take_row<8>(a, u); break;
-            case 9: take_row<9>(a, u); break;
-            case 10: take_row<10>(a, u); break;
-            case 11: take_row<11>(a, u); break;
-            case 12: take_row<12>(a, u); break;
-            case 13: take_row<13>(a, u); break;
-            case 14: take_row<14>(a, u); break;
-            default: take_row<15>(a, u); break;
+        switch (slot) {
+            case 0: take_slot<0>(a, u); break;
+            case 1: take_slot<1>(a, u); break;
+            case 2: take_slot<2>(a, u); break;
+            case 3: take_slot<3>(a, u); break;
+            case 4: take_slot<4>(a, u); break;
+            case 5: take_slot<5>(a, u); break;
+            case 6: take_slot<6>(a, u); break;
+            case 7: take_slot<7>(a, u); break;
+            case 8: take_slot<8>(a, u); break;
+            case 9: take_slot<9>(a, u); break;
+            case 10: take_slot<10>(a, u); break;
+            case 11: take_slot<11>(a, u); break;
+            case 12: take_slot<12>(a, u); break;
+            case 13: take_slot<13>(a, u); break;
+            case 14: take_slot<14>(a, u); break;
+            default: take_slot<15>(a, u); break;
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) u[c] = __shfl(u[c], src, 16);
-        if (src == rb) act &= ~(1u << ip);
+        switch (src) {
+            case 0: bcast_from<0>(u); break;
+            case 1: bcast_from<1>(u); break;
+            case 2: bcast_from<2>(u); break;
+            case 3: bcast_from<3>(u); break;
+            case 4: bcast_from<4>(u); break;
+            case 5: bcast_from<5>(u); break;
+            case 6: bcast_from<6>(u); break;
+            case 7: bcast_from<7>(u); break;
+            case 8: bcast_from<8>(u); break;
+            case 9: bcast_from<9>(u); break;
+            case 10: bcast_from<10>(u); break;
+            case 11: bcast_from<11>(u); break;
+            case 12: bcast_from<12>(u); break;
+            case 13: bcast_from<13>(u); break;
+            case 14: bcast_from<14>(u); break;
+            default: bcast_from<15>(u); break;
+        }
+        if (src == r) act &= ~(1u << slot);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const double li = sm.l[par][16 * rb + i];
+            const double li = sm.l[par][16 * i + r];
 #pragma unroll
             for (int c = 0; c < 4; ++c) a[c][i] = fma(-li, u[c], a[c][i]);
         }
