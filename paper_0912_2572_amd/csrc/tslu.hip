@@ -116,11 +116,14 @@ __device__ __forceinline__ void pivot_column(TsluSmem &sm, const Rows16 (&a)[4],
     argmax_step<kDppXor2>(best, bp, bv);
     argmax_step<0x124>(best, bp, bv);   // row_ror:4: the next quad's winner
     argmax_step<kDppRowRor8>(best, bp, bv);
+    // the multipliers only steer the selection (U and L are computed from
+    // the chosen rows afterwards): one reciprocal instead of 16 divisions
+    const double rv = (bv != 0.0) ? 1.0 / bv : 0.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int q = 16 * i + r;
-        const bool live = ((act >> i) & 1u) && q != bp && bv != 0.0;
-        sm.l[par][q] = live ? a[JC][i] / bv : 0.0;
+        const bool live = ((act >> i) & 1u) && q != bp;
+        sm.l[par][q] = live ? a[JC][i] * rv : 0.0;
     }
     if (r == 0) {
         sm.piv[par] = bp;
