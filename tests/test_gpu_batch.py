@@ -125,8 +125,9 @@ def test_batch_replays_and_plain_launches_agree(tl, small_batch):
 def test_batch_equals_single_calls(tl, small_batch):
     """Each matrix's R equals (bitwise) a single tsqr_factor with the same
     plan: the batched factor runs the same per-domain and per-chain code.
-    The solves apply Q^T in different work splits (chunk chain in one
-    workgroup vs. chunk-parallel passes), so x agrees to rounding."""
+    An FP64 matrix's x equals the single call's bitwise too (the batched
+    apply passes run the single-matrix bodies); a mixed matrix's refinement
+    runs a fixed, device-gated sweep schedule, so its x agrees to rounding."""
     shapes, mats = small_batch
     print("case batch vs single calls", flush=True)
     B = make(tl, shapes, mats)
@@ -138,7 +139,10 @@ def test_batch_equals_single_calls(tl, small_batch):
         assert np.array_equal(host(f.R()), host(B.R(i))), f"matrix {i}"
         X, res, info = f.lsq(dev(b.reshape(-1, 1)), A=dev(A))
         torch.cuda.synchronize()
-        assert rel(host(X)[:, 0], host(B.x(i))) <= 1e-13
+        if prec == tl.F64:
+            assert np.array_equal(host(X)[:, 0], host(B.x(i))), f"matrix {i}"
+        else:
+            assert rel(host(X)[:, 0], host(B.x(i))) <= 1e-13
 
 
 def test_batch_tuned_plans(tl, small_batch):
