@@ -113,6 +113,22 @@ typedef struct {
                                 handle use the FP64 factor, so an
                                 ill-conditioned problem skips a long
                                 refinement.  0 = never (default); >= 0.    */
+    const int64_t *domain_weights; /* NULL (default), or num_weights      */
+    int64_t num_weights;     /* integer powers >= 1 (host memory, read    */
+                             /* while planning): that many domains, the   */
+                             /* rows apportioned to the powers in whole   */
+                             /* leaf chunks (C = ceil(m / chunk) chunks;  */
+                             /* floor(C w_d / W) each, the rest one each  */
+                             /* to the largest remainders C w_d mod W,    */
+                             /* ties to the lower index), the last domain */
+                             /* ending at row m: Sec. 3's rows in         */
+                             /* proportion to each domain's processing    */
+                             /* power, e.g. the share of its XCD (domain  */
+                             /* d runs on XCD d mod 8) other work leaves. */
+                             /* Every domain must get a chunk and at least*/
+                             /* n rows, else -5.  Needs row_block = 0 and */
+                             /* domains = 0.  Not accepted by             */
+                             /* tsqr_factor_solve_noalloc.                */
 } tsqr_opts;
 
 /* Opaque host handle describing one factorization.  It points into the
@@ -122,7 +138,7 @@ typedef struct tsqr_factors_s *tsqr_factors;
 
 /* Fill *o with the defaults: row_block 0 (library default), binary tree,
    FP64, keep_q 1, lsq_max_rhs 8, refine_max_iter 30, domains 0,
-   refine_tol 1e-14, route_kappa 0. */
+   refine_tol 1e-14, route_kappa 0, no domain weights. */
 TSQR_API void tsqr_default_opts(tsqr_opts *o);
 
 /* Bytes of device workspace tsqr_factor needs for an m x n problem with
@@ -240,7 +256,8 @@ TSQR_API int tsqr_factor_solve(int64_t m, int64_t n, const double *A, int64_t ld
    return TSQR_ERR_WORKSPACE.  Every call on one GPU shares that array, so
    calls that overlap on one GPU race: order them (one stream, or events).
    Errors: -1 m, -2 n, -3 A NULL, -4 lda, -5 opts, TSQR_ERR_UNSUPPORTED for
-   a precision other than TSQR_F64, TSQR_ERR_STATE for keep_q = 0,
+   a precision other than TSQR_F64 or for domain weights (their table would
+   be copied from host memory), TSQR_ERR_STATE for keep_q = 0,
    TSQR_ERR_WORKSPACE (too large), -6 k, -7 B NULL, -8 ldb, -9 X NULL,
    -10 ldx, -14 ldq, -16 ldr, -1000-e on a HIP error. */
 TSQR_API int tsqr_factor_solve_noalloc(int64_t m, int64_t n, const double *A, int64_t lda,

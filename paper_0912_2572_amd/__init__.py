@@ -39,6 +39,8 @@ class Opts(ctypes.Structure):
         ("domains", ctypes.c_int32),
         ("refine_tol", ctypes.c_double),
         ("route_kappa", ctypes.c_double),
+        ("domain_weights", ctypes.POINTER(ctypes.c_int64)),
+        ("num_weights", ctypes.c_int64),
     ]
 
 
@@ -222,9 +224,10 @@ def _check(code: int, what: str):
 
 def opts(row_block: int = 0, tree: int = TREE_BINARY, prec: int = F64, keep_q: bool = True,
          lsq_max_rhs: int = 8, refine_max_iter: int = 30, refine_tol: float = 1e-14,
-         domains: int = 0, route_kappa: float = 0.0) -> Opts:
+         domains: int = 0, route_kappa: float = 0.0, weights=None) -> Opts:
     """domains > 0 (or -1: one per resident leaf workgroup) selects the
-    load-balanced partition in place of row_block; route_kappa > 0 sends a
+    load-balanced partition in place of row_block; weights (one integer
+    power >= 1 per domain) the weighted one; route_kappa > 0 sends a
     mixed-precision solve whose R is estimated worse conditioned to FP64
     (see tsqr.h)."""
     o = Opts()
@@ -232,6 +235,11 @@ def opts(row_block: int = 0, tree: int = TREE_BINARY, prec: int = F64, keep_q: b
     o.row_block = row_block
     o.domains = domains
     o.route_kappa = route_kappa
+    if weights is not None:
+        w = (ctypes.c_int64 * len(weights))(*[int(x) for x in weights])
+        o._weights = w          # keeps the array alive as long as the options
+        o.domain_weights = ctypes.cast(w, ctypes.POINTER(ctypes.c_int64))
+        o.num_weights = len(weights)
     o.tree = tree
     o.prec = prec
     o.keep_q = 1 if keep_q else 0

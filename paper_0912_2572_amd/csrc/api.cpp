@@ -5,6 +5,7 @@
 // allocated here: the workspace, inputs and outputs belong to the caller.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -30,8 +31,18 @@ PanelArgs panel_args(const Panel &p) {
     a.cpd = p.cpd;
     a.chunk = p.chunk;
     a.extra = p.extra;
+    a.wtab = nullptr;
+    a.maxch = p.maxch;
     a.n = p.n;
     a.ns = p.ns;
+    return a;
+}
+
+// PanelArgs of a panel of the factor in workspace ws: a weighted partition's
+// table is the workspace copy.
+PanelArgs panel_args(const Panel &p, const char *ws) {
+    PanelArgs a = panel_args(p);
+    if (!p.wchunk0.empty()) a.wtab = reinterpret_cast<const int64_t *>(ws + p.off_wtab);
     return a;
 }
 
@@ -54,7 +65,7 @@ inline bool is_mixed(const tsqr_factors_s *f) { return f->plan.opts.prec == TSQR
 hipError_t leaf_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int64_t ldbs, double *B,
                       int64_t ldb, int64_t k, int trans, hipStream_t st) {
     const Plan &P = f->plan;
-    const PanelArgs pa = panel_args(p);
+    const PanelArgs pa = panel_args(p, f->ws);
     const int64_t off = p.row_off + (int64_t)p.col_off * P.m;
     const double *Tc = at<double>(f, p.off_tc);
     if (k <= tsqr::kApply3MaxCols && Bsrc == B && p.off_pz) {
@@ -76,7 +87,7 @@ hipError_t leaf_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsr
 
 int panel_apply(const tsqr_factors_s *f, const Panel &p, const double *Bsrc, int64_t ldbs, double *B,
                 int64_t ldb, int64_t k, int trans, hipStream_t st) {
-    const PanelArgs pa = panel_args(p);
+    const PanelArgs pa = panel_args(p, f->ws);
     const double *Rdom = at<double>(f, p.off_rdom);
     const double *Tnode = at<double>(f, p.off_tnode);
     auto levels = tsqr::tree_levels(p.P, p.tree);
@@ -213,7 +224,17 @@ static int factor_enqueue(tsqr_factors_s *f, const double *A, int64_t lda, hipSt
     }
     for (int q = 0; q < np && !err; ++q) {
         const Panel &p = plan.panels[q];
-        const PanelArgs pa = panel_args(p);
+        const PanelArgs pa = panel_args(p, f->ws);
+        if (!p.wchunk0.empty()) {
+            // the weighted partition's table, for this and every later call
+            // on the factor (copied from host memory before the call returns)
+            hipError_t e = hipMemcpyAsync(f->ws + p.off_wtab, p.wchunk0.data(), sizeof(int64_t) * p.wchunk0.size(),
+                                          hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) {
+                err = hip_code(e);
+                break;
+            }
+        }
         const double *src = (q == 0) ? A : W;
         const int64_t lds = (q == 0) ? lda : m;
         const double *src_p = src + p.row_off + (int64_t)p.col_off * lds;
@@ -392,7 +413,7 @@ static int form_q_single_panel(tsqr_factors_s *f, double *Q, int64_t ldq, hipStr
     const double *dsign = at<double>(f, f->plan.off_d);
     {
         const Panel &p = f->plan.panels[0];
-        const PanelArgs pa = panel_args(p);
+        const PanelArgs pa = panel_args(p, f->ws);
         double *S = at<double>(f, p.off_s);
         const auto levels = tsqr::tree_levels(p.P, p.tree);
         const int nlev = (int)levels.size();
@@ -450,10 +471,14 @@ namespace {
 
 // TSLU's workspace: the candidate rows of every domain (P x b, int32) and a
 // 64 x 64 block for L11.
+size_t tslu_up(size_t x) { return (x + tsqr::kAlign - 1) / tsqr::kAlign * tsqr::kAlign; }
+
+// TSLU's workspace: the candidate rows of every domain (P x b, int32), a
+// 64 x 64 block for L11 and a weighted partition's table.
 size_t tslu_bytes(const Plan &p, int64_t b) {
-    const size_t cand = ((size_t)p.panels[0].P * (size_t)b * sizeof(int32_t) + tsqr::kAlign - 1) /
-                        tsqr::kAlign * tsqr::kAlign;
-    return cand + sizeof(double) * 64 * 64;
+    const Panel &pp = p.panels[0];
+    return tslu_up((size_t)pp.P * (size_t)b * sizeof(int32_t)) + tslu_up(sizeof(double) * 64 * 64) +
+           sizeof(int64_t) * pp.wchunk0.size();
 }
 
 }  // namespace
@@ -486,9 +511,18 @@ TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const
     for (const auto &Lv : tsqr::tree_levels(pp.P, pp.tree)) levels.push_back(TreeArgs{Lv.stride, Lv.span, Lv.chains, Lv.width});
     char *w = static_cast<char *>(dwork);
     int32_t *cand = reinterpret_cast<int32_t *>(w);
-    double *L11 = reinterpret_cast<double *>(w + need - sizeof(double) * 64 * 64);
-    hipError_t e = tsqr::launch_tslu(A, lda, panel_args(pp), levels, (int)b, cand, L11, L, ldl, U, ldu, ipiv,
-                                     dinfo, static_cast<hipStream_t>(stream));
+    const size_t off_l11 = tslu_up((size_t)pp.P * (size_t)b * sizeof(int32_t));
+    double *L11 = reinterpret_cast<double *>(w + off_l11);
+    PanelArgs pa = panel_args(pp);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!pp.wchunk0.empty()) {
+        int64_t *tab = reinterpret_cast<int64_t *>(w + off_l11 + tslu_up(sizeof(double) * 64 * 64));
+        hipError_t e = hipMemcpyAsync(tab, pp.wchunk0.data(), sizeof(int64_t) * pp.wchunk0.size(),
+                                      hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_code(e);
+        pa.wtab = tab;
+    }
+    hipError_t e = tsqr::launch_tslu(A, lda, pa, levels, (int)b, cand, L11, L, ldl, U, ldu, ipiv, dinfo, st);
     return e == hipSuccess ? 0 : hip_code(e);
 }
 
@@ -618,13 +652,16 @@ int factor_solve_forked(tsqr_factors_s *f, const double *A, int64_t lda, int64_t
                         int64_t ldq, hipStream_t st, const ForkJoin &fj) {
     const Plan &P = f->plan;
     const Panel &p = P.panels[0];
-    const PanelArgs pa = panel_args(p);
+    const PanelArgs pa = panel_args(p, f->ws);
     double *W = at<double>(f, P.off_w);
     double *Rdom = at<double>(f, p.off_rdom);
     double *Tnode = at<double>(f, p.off_tnode);
     double *C = at<double>(f, P.off_lsq);
     const auto levels = tsqr::tree_levels(p.P, p.tree);
     double *Tc = at<double>(f, p.off_tc);
+    if (!p.wchunk0.empty())
+        TRY(hipMemcpyAsync(f->ws + p.off_wtab, p.wchunk0.data(), sizeof(int64_t) * p.wchunk0.size(),
+                           hipMemcpyHostToDevice, st));
     TRY(tsqr::launch_leaf(A, lda, W, P.m, Tc, Rdom, pa, 2, st));
     TRY(hipEventRecord(fj.leaf, st));
     TRY(hipStreamWaitEvent(fj.aux, fj.leaf, 0));

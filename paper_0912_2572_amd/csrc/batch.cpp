@@ -348,6 +348,8 @@ TSQR_API int tsqr_batch_create(int count, const tsqr_batch_item *items, const ts
         M.pa.cpd = p.cpd;
         M.pa.chunk = p.chunk;
         M.pa.extra = p.extra;
+        M.pa.wtab = nullptr;
+        M.pa.maxch = p.maxch;
         M.pa.n = p.n;
         M.pa.ns = p.ns;
         M.prec = it.prec;

@@ -17,6 +17,9 @@ struct PanelArgs {
     int64_t chunk;  // rows per chunk
     int64_t extra;  // load-balanced partition: domains 0 .. extra-1 hold one
                     // chunk more than mb (then mb = cpd chunks); 0 otherwise
+    const int64_t *wtab;  // weighted partition: first chunk of every domain
+                          // (P + 1 entries, device), else nullptr
+    int64_t maxch;  // most chunks of any domain
     int n;          // columns (<= 64)
     int ns;         // column slots per thread of the leaf kernel
 };
@@ -25,30 +28,42 @@ struct PanelArgs {
 // and its chunks' T factors sit in slots dom_chunk0(d), ... of the panel's
 // chunk array.  The last domain ends at row m (it may be shorter than mb, or
 // longer when a short remainder was merged into it).
+// (Device code only for a weighted partition, whose table is in device
+// memory.)
 __host__ __device__ inline int64_t dom_row0(const PanelArgs &pa, int64_t d) {
+    if (pa.wtab) return pa.wtab[d] * pa.chunk;
     return d * pa.mb + (d < pa.extra ? d : pa.extra) * pa.chunk;
 }
 __host__ __device__ inline int64_t dom_rows(const PanelArgs &pa, int64_t d) {
-    return (d == pa.P - 1) ? pa.m - dom_row0(pa, d) : pa.mb + (d < pa.extra ? pa.chunk : 0);
+    if (d == pa.P - 1) return pa.m - dom_row0(pa, d);
+    if (pa.wtab) return (pa.wtab[d + 1] - pa.wtab[d]) * pa.chunk;
+    return pa.mb + (d < pa.extra ? pa.chunk : 0);
 }
 __host__ __device__ inline int64_t dom_chunk0(const PanelArgs &pa, int64_t d) {
+    if (pa.wtab) return pa.wtab[d];
     return d * pa.cpd + (d < pa.extra ? d : pa.extra);
 }
 
 // The domain holding chunk slot g of the panel and the chunk's index in it.
 __host__ __device__ inline void dom_of_chunk(const PanelArgs &pa, int64_t g, int64_t &dom, int64_t &ch) {
-    const int64_t big = pa.extra * (pa.cpd + 1);   // slots of the longer domains
-    dom = g < big ? g / (pa.cpd + 1) : pa.extra + (g - big) / pa.cpd;
-    if (dom > pa.P - 1) dom = pa.P - 1;            // a merged last domain
+    if (pa.wtab) {
+        int64_t lo = 0, hi = pa.P - 1;   // the last d with wtab[d] <= g
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (pa.wtab[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        dom = lo;
+    } else {
+        const int64_t big = pa.extra * (pa.cpd + 1);   // slots of the longer domains
+        dom = g < big ? g / (pa.cpd + 1) : pa.extra + (g - big) / pa.cpd;
+        if (dom > pa.P - 1) dom = pa.P - 1;            // a merged last domain
+    }
     ch = g - dom_chunk0(pa, dom);
 }
 
-// Most chunks any domain has.
-inline int64_t max_domain_chunks(const PanelArgs &pa) {
-    const int64_t last = (dom_rows(pa, pa.P - 1) + pa.chunk - 1) / pa.chunk;
-    const int64_t full = pa.cpd + (pa.extra > 0 ? 1 : 0);
-    return last > full ? last : full;
-}
+// Most chunks any domain has (from the plan).
+inline int64_t max_domain_chunks(const PanelArgs &pa) { return pa.maxch; }
 
 // One tree level: chain c = 0..chains-1 starts at
 //     left = (c / width) * span + c % width

@@ -68,7 +68,7 @@ TSQR_API int tsqr_factor_solve_noalloc(int64_t m, int64_t n, const double *A, in
     if (rc) return rc;
     if (!A) return -3;
     if (lda < m) return -4;
-    if (o->prec != TSQR_F64) return TSQR_ERR_UNSUPPORTED;
+    if (o->prec != TSQR_F64 || o->domain_weights) return TSQR_ERR_UNSUPPORTED;
     if (!o->keep_q) return TSQR_ERR_STATE;
     if (plan.total > kScratchBytes) return TSQR_ERR_WORKSPACE;
     if (k < 1 || k > o->lsq_max_rhs) return -6;

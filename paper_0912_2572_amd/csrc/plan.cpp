@@ -109,6 +109,47 @@ static void balance_panel(Panel &pa, int64_t want) {
     pa.cpd = q;
 }
 
+// Weighted partition (Sec. 3: rows per domain in proportion to the
+// processing power behind it): the panel's C = ceil(m / chunk) chunks are
+// apportioned to the integer powers w by largest remainders -- domain d gets
+// floor(C w_d / W) chunks, and the chunks left over go one each to the
+// domains with the largest C w_d mod W, ties to the lower index.  Returns
+// false when a domain would get no chunk or fewer than n rows.
+static bool weigh_panel(Panel &pa, const int64_t *w, int64_t P) {
+    const int64_t C = (pa.m + pa.chunk - 1) / pa.chunk;
+    int64_t W = 0;
+    for (int64_t d = 0; d < P; ++d) {
+        if (w[d] < 1) return false;
+        W += w[d];
+    }
+    std::vector<int64_t> k(P), rem(P);
+    int64_t given = 0;
+    for (int64_t d = 0; d < P; ++d) {
+        k[d] = C * w[d] / W;
+        rem[d] = C * w[d] % W;
+        given += k[d];
+    }
+    // the leftover chunks, largest remainder first (a stable order keeps
+    // equal remainders in index order)
+    std::vector<int64_t> order(P);
+    for (int64_t d = 0; d < P; ++d) order[d] = d;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return rem[a] > rem[b]; });
+    for (int64_t i = 0; i < C - given; ++i) k[order[i]] += 1;
+    pa.wchunk0.assign(P + 1, 0);
+    for (int64_t d = 0; d < P; ++d) {
+        if (k[d] < 1) return false;
+        pa.wchunk0[d + 1] = pa.wchunk0[d] + k[d];
+    }
+    pa.P = P;
+    pa.mb = k[0] * pa.chunk;
+    pa.cpd = 0;
+    for (int64_t d = 0; d < P; ++d) pa.cpd = std::max(pa.cpd, k[d]);
+    pa.extra = 0;
+    for (int64_t d = 0; d < P; ++d)
+        if (pa.domain_rows(d) < pa.n) return false;
+    return true;
+}
+
 // Leaf workgroups one compute unit holds at once: two for panels of up to 32
 // columns (their leaf fits two in registers and LDS), one for wider ones.
 static int64_t leaf_residency(int n) { return n <= 32 ? 2 : 1; }
@@ -127,6 +168,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     if (o->row_block != 0 && o->row_block < n) return -5;
     if (o->domains < -1 || (o->domains != 0 && o->row_block != 0)) return -5;
     if (!(o->route_kappa >= 0.0)) return -5;
+    if (o->domain_weights && (o->num_weights < 1 || o->row_block != 0 || o->domains != 0)) return -5;
     if (o->lsq_max_rhs < 1 || o->refine_max_iter < 0) return -5;
     Plan P;
     P.m = m;
@@ -152,7 +194,9 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         pa.m = m - pa.row_off;
         pa.ns = slots_for(pa.n);
         pa.chunk = chunk_rows_for(pa.n);
-        if (o->domains != 0) {
+        if (o->domain_weights) {
+            if (!weigh_panel(pa, o->domain_weights, o->num_weights)) return -5;
+        } else if (o->domains != 0) {
             balance_panel(pa, o->domains > 0 ? o->domains : kComputeUnits * leaf_residency(pa.n));
         } else {
             pa.mb = P.mb;
@@ -162,6 +206,9 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
             pa.cpd = (pa.mb + pa.chunk - 1) / pa.chunk;
         }
         pa.total_chunks = pa.domain_chunk0(pa.P - 1) + pa.domain_chunks(pa.P - 1);
+        pa.maxch = std::max(pa.domain_chunks(pa.P - 1), pa.P > 1 ? pa.domain_chunks(0) : (int64_t)0);
+        for (int64_t d = 1; d + 1 < pa.P && !pa.wchunk0.empty(); ++d)
+            pa.maxch = std::max(pa.maxch, pa.domain_chunks(d));
         pa.tree = o->tree;
         size_t nn = (size_t)pa.n * pa.n * sizeof(double);
         pa.off_tc = take(nn * (size_t)pa.total_chunks);
@@ -169,6 +216,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         pa.off_tnode = take(nn * (size_t)pa.P);
         pa.off_s = take(nn * (size_t)pa.P);
         if (o->keep_q) pa.off_pz = take(2 * sizeof(double) * (size_t)pa.n * 16 * (size_t)pa.total_chunks);
+        if (!pa.wchunk0.empty()) pa.off_wtab = take(sizeof(int64_t) * pa.wchunk0.size());
         P.panels.push_back(pa);
     }
     P.off_lsq = take(sizeof(double) * (size_t)m * o->lsq_max_rhs);

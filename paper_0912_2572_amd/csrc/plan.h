@@ -43,6 +43,7 @@ struct Panel {
     int64_t chunk = 0;              // rows per chunk of the leaf kernel
     int64_t cpd = 0;                // chunks in a full domain
     int64_t total_chunks = 0;
+    int64_t maxch = 0;              // most chunks of any domain
     int tree = TSQR_TREE_BINARY;
     // workspace offsets (bytes from the workspace base)
     size_t off_tc = 0;              // total_chunks x n x n   (chunk T factors)
@@ -50,12 +51,25 @@ struct Panel {
     size_t off_tnode = 0;           // P x n x n              (node T, by right child)
     size_t off_s = 0;               // P x n x n              (top-down blocks)
     size_t off_pz = 0;              // 2 x total_chunks x n x 16 (few-column apply: P_c, Z_c)
+    // weighted partition (opts.domain_weights): first chunk of every domain,
+    // P + 1 entries (the last = the panel's chunk count), on the host and,
+    // copied there by the factorization, in the workspace
+    std::vector<int64_t> wchunk0;
+    size_t off_wtab = 0;
 
-    int64_t domain_row0(int64_t i) const { return i * mb + (i < extra ? i : extra) * chunk; }
-    int64_t domain_rows(int64_t i) const {
-        return (i == P - 1) ? m - domain_row0(i) : mb + (i < extra ? chunk : 0);
+    int64_t domain_row0(int64_t i) const {
+        if (!wchunk0.empty()) return wchunk0[i] * chunk;
+        return i * mb + (i < extra ? i : extra) * chunk;
     }
-    int64_t domain_chunk0(int64_t i) const { return i * cpd + (i < extra ? i : extra); }
+    int64_t domain_rows(int64_t i) const {
+        if (i == P - 1) return m - domain_row0(i);
+        if (!wchunk0.empty()) return (wchunk0[i + 1] - wchunk0[i]) * chunk;
+        return mb + (i < extra ? chunk : 0);
+    }
+    int64_t domain_chunk0(int64_t i) const {
+        if (!wchunk0.empty()) return wchunk0[i];
+        return i * cpd + (i < extra ? i : extra);
+    }
     int64_t domain_chunks(int64_t i) const { return (domain_rows(i) + chunk - 1) / chunk; }
 };
 

@@ -86,6 +86,37 @@ def test_balanced_partition_is_the_oracle_equal_power_partition(tl, m, n, want):
     assert not sizes or max(sizes) - min(sizes) <= chunk
 
 
+@pytest.mark.parametrize("m,n,weights", [
+    (100_000, 64, [1, 2, 3, 4]),
+    (1_200_000, 64, [2, 1] * 128),              # half the power on every other domain
+    (300_001, 20, [5, 5, 1, 1, 1, 3, 2] * 10),  # ties among the remainders
+    (5003, 13, [1, 1, 1]),
+    (70_000, 130, [4, 3, 2, 1]),                # three panels, each weighted over its rows
+])
+def test_weighted_partition_is_the_oracle_apportionment(tl, m, n, weights):
+    o = tl.opts(weights=weights)
+    P, chunk, _ = tl.plan_info(m, n, o)
+    assert P == len(weights)
+    assert tl.partition(m, n, o) == oracle.partition_weighted(m, n, P, chunk, weights)
+    assert tl.workspace_bytes(m, n, o) > 8 * m * n
+
+
+def test_weighted_partition_rejected_cases(tl):
+    L = tl.lib()
+    for bad in (tl.opts(weights=[1, 0, 2]),                    # a domain of no power
+                tl.opts(weights=[1, 2], row_block=4096),       # with row_block
+                tl.opts(weights=[1, 2], domains=8),            # with domains
+                tl.opts(weights=[1000, 1])):                   # a domain without a chunk
+        assert L.tsqr_partition(100_000, 16, ctypes.byref(bad), None, None, 0) == -5
+    o = tl.opts(weights=[1, 1])
+    o.num_weights = 0
+    assert L.tsqr_partition(100_000, 16, ctypes.byref(o), None, None, 0) == -5
+    d = ctypes.c_void_p(256)
+    o = tl.opts(weights=[1, 1])
+    assert L.tsqr_factor_solve_noalloc(1000, 8, d, 1000, ctypes.byref(o), 1, d, 1000, d, 8, None, None,
+                                       None, 1000, None, 8, None) == tl.ERR_UNSUPPORTED
+
+
 def test_balanced_partition_defaults_to_one_domain_per_resident_leaf(tl):
     for n, per_cu in [(8, 2), (16, 2), (32, 2), (33, 1), (64, 1), (128, 1)]:
         P, chunk, _ = tl.plan_info(1 << 22, n, tl.opts(domains=-1))

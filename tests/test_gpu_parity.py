@@ -67,15 +67,16 @@ def r_entrywise(R, Ro, tol=1e-12):
         float(np.max(np.abs(R - Ro) / np.maximum(cn, 1e-300)[None, :]))
 
 
-def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True, domains=0):
+def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True, domains=0, weights=None):
     m, n = A.shape
-    print(f"case m={m} n={n} mb={mb} tree={tree} domains={domains}", flush=True)
-    if domains:
-        # the load-balanced partition: the oracle factors over the library's
-        # domains, which must be its own equal-power apportionment
-        parts = tl.partition(m, n, tl.opts(domains=domains))
-        P, chunk, _ = tl.plan_info(m, n, tl.opts(domains=domains))
-        assert parts == oracle.partition_weighted(m, n, P, chunk)
+    print(f"case m={m} n={n} mb={mb} tree={tree} domains={domains} weights={weights is not None}", flush=True)
+    if domains or weights is not None:
+        # the load-balanced or weighted partition: the oracle factors over the
+        # library's domains, which must be its own apportionment
+        po = tl.opts(domains=domains) if domains else tl.opts(weights=weights)
+        parts = tl.partition(m, n, po)
+        P, chunk, _ = tl.plan_info(m, n, po)
+        assert parts == oracle.partition_weighted(m, n, P, chunk, weights)
         sched = tl.tree_schedule(P, tree) if tree == tl.TREE_XCD else None
         orc = oracle.TSQR(A, parts=parts, tree=tree, sched=sched)
     elif tree == tl.TREE_XCD:
@@ -89,7 +90,12 @@ def check_all(tl, A, mb, tree=2, nrhs=2, seed=0, full_q=True, domains=0):
     else:
         orc = oracle.TSQR(A, mb=mb, tree=tree)
     Ad = dev(A)
-    f = tl.factor(Ad, domains=domains, tree=tree) if domains else tl.factor(Ad, row_block=mb, tree=tree)
+    if weights is not None:
+        f = tl.factor(Ad, weights=weights, tree=tree)
+    elif domains:
+        f = tl.factor(Ad, domains=domains, tree=tree)
+    else:
+        f = tl.factor(Ad, row_block=mb, tree=tree)
     R = host(f.R())
     Ro = orc.R()
     assert np.all(np.tril(R, -1) == 0.0)
@@ -196,6 +202,49 @@ BALANCED_SHAPES = [
 def test_balanced_domains(tl, m, n, domains, tree):
     A = synth.gaussian(m, n, seed=m + 3 * n)
     check_all(tl, A, 0, tree, domains=domains)
+
+
+# (m, n, weights, tree): rows in proportion to per-domain powers (Sec. 3)
+WEIGHTED_SHAPES = [
+    (300_000, 64, [1, 2, 3, 4] * 64, 2),
+    (100_003, 20, [3, 1] * 50, 4),
+    (50_000, 48, [5, 1, 2, 7, 3], 0),
+    (200_000, 8, [2, 1, 1, 1] * 16, 8),
+    (20_000, 100, [1, 2, 3], 2),
+]
+
+
+@pytest.mark.parametrize("m,n,weights,tree", WEIGHTED_SHAPES)
+def test_weighted_domains(tl, m, n, weights, tree):
+    A = synth.gaussian(m, n, seed=m + 5 * n)
+    check_all(tl, A, 0, tree, weights=weights)
+
+
+def test_weighted_domains_factor_solve_and_tslu(tl):
+    """tsqr_factor_solve (the forked FP64 schedule) and TSLU over weighted
+    domains against the oracle on the same domains."""
+    m, n = 150_001, 64
+    w = [3, 1] * 64
+    print(f"case weighted factor_solve and TSLU m={m} n={n}", flush=True)
+    A = synth.gaussian(m, n, seed=51)
+    b = np.random.default_rng(52).standard_normal((m, 1))
+    o = tl.opts(weights=w, lsq_max_rhs=1)
+    Q = tl.empty_colmajor(m, n, device="cuda")
+    F, X, r, info = tl.factor_solve(dev(A), dev(b), o, Q=Q)
+    torch.cuda.synchronize()
+    parts = tl.partition(m, n, o)
+    orc = oracle.TSQR(A, parts=parts)
+    xo, ro, _ = orc.lsq(b)
+    assert int(info.item()) == 0
+    colwise(host(X), xo, 1e-12, scale=np.linalg.norm(xo, axis=0))
+    colwise(host(Q), orc.form_q(), 1e-12)
+    r_entrywise(host(F.R()), orc.R())
+    ipiv, L, U, linfo = tl.tslu(dev(A), o)
+    torch.cuda.synchronize()
+    ipo, Lo, Uo, _ = oracle.tslu(A, parts, first=256, stage=256 - n)
+    assert host(ipiv).tolist() == ipo.tolist()
+    assert np.max(np.abs(host(U) - Uo)) <= 1e-13 * np.abs(Uo).max()
+    assert np.max(np.abs(host(L) - Lo)) <= 1e-12 * max(1.0, np.abs(Lo).max())
 
 
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
