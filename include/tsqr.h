@@ -127,8 +127,11 @@ typedef struct {
                              /* d runs on XCD d mod 8) other work leaves. */
                              /* Every domain must get a chunk and at least*/
                              /* n rows, else -5.  Needs row_block = 0 and */
-                             /* domains = 0.  Not accepted by             */
-                             /* tsqr_factor_solve_noalloc.                */
+                             /* domains = 0.  The factorization copies    */
+                             /* the domain table (8 (P + 1) bytes) from   */
+                             /* host memory on its stream, so it cannot   */
+                             /* be captured in a HIP graph; not accepted  */
+                             /* by tsqr_factor_solve_noalloc.             */
 } tsqr_opts;
 
 /* Opaque host handle describing one factorization.  It points into the
