@@ -117,18 +117,25 @@ __device__ __forceinline__ void householder_scalars(double alpha, double sig2, d
         return;
     }
     const double sgn = (alpha < 0.0) ? -1.0 : 1.0;
-    beta = -sgn * sqrt(fma(alpha, alpha, sig2));
-    // s = 1 / (alpha - beta) and tau = (beta - alpha) / beta = -(alpha - beta) / beta
-    // from two independent reciprocals, each v_rcp_f64 refined by two Newton
-    // steps r <- r + r (1 - x r) (within an ulp of the quotient)
+    // r = 1 / sqrt(alpha^2 + sig2) from v_rsq_f64 and two Newton steps
+    // r <- r (3 - x r^2) / 2, so that |beta| = x r and 1 / beta = -sgn r come
+    // from one short chain (no square root expansion, no reciprocal of beta)
+    const double x = fma(alpha, alpha, sig2);
+    // (x is a normal number over the library's supported magnitudes,
+    // 2^-400 .. 2^400, so r^2 stays finite)
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = r * fma(-hx, r * r, 1.5);
+    r = r * fma(-hx, r * r, 1.5);
+    beta = -sgn * (x * r);
+    // s = 1 / (alpha - beta): v_rcp_f64 and two Newton steps r <- r + r (1 - d r);
+    // tau = (beta - alpha) / beta = -(alpha - beta) / beta = sgn (alpha - beta) r
     const double d = alpha - beta;
-    double rd = __builtin_amdgcn_rcp(d), rb = __builtin_amdgcn_rcp(beta);
+    double rd = __builtin_amdgcn_rcp(d);
     rd = fma(rd, fma(-d, rd, 1.0), rd);
-    rb = fma(rb, fma(-beta, rb, 1.0), rb);
     rd = fma(rd, fma(-d, rd, 1.0), rd);
-    rb = fma(rb, fma(-beta, rb, 1.0), rb);
     s = rd;
-    tau = -d * rb;
+    tau = sgn * (d * r);
 }
 
 // ---- one-wave triangular solves for n <= 256 (column-major R, ld n) ----

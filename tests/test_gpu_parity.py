@@ -272,6 +272,18 @@ def test_balanced_domains_factor_solve(tl, prec):
     r_entrywise(host(F.R()), orc.R())
 
 
+@pytest.mark.parametrize("scale_exp", [-400, -250, 400])
+def test_extreme_scales(tl, scale_exp):
+    """Entries at the ends of the supported magnitudes, 2^-400 and 2^400
+    (sums of squares near 2^-800 and 2^800, the range the Householder
+    scalars' reciprocal square root covers), and in between: R, Q and x
+    against the oracle (plain FP64 sums, as the paper's norms)."""
+    m, n, mb = 20000, 64, 4096
+    print(f"case scale 2^{scale_exp}", flush=True)
+    A = np.ldexp(synth.gaussian(m, n, seed=77), scale_exp)
+    check_all(tl, A, mb, 2, nrhs=1)
+
+
 def strided_view(A, row_off, extra_rows):
     """A as a view into a taller column-major device matrix: leading
     dimension m + extra_rows, first row at row_off (row_off odd: the view's
