@@ -114,7 +114,8 @@ typedef struct {
                                 ill-conditioned problem skips a long
                                 refinement.  0 = never (default); >= 0.    */
     const int64_t *domain_weights; /* NULL (default), or num_weights      */
-    int64_t num_weights;     /* integer powers >= 1 (host memory, read    */
+    int64_t num_weights;     /* integer powers 1 .. 2^31 (host memory,    */
+                             /* read while planning; at most 2^31 of them)*/
                              /* while planning): that many domains, the   */
                              /* rows apportioned to the powers in whole   */
                              /* leaf chunks (C = ceil(m / chunk) chunks;  */

@@ -201,7 +201,7 @@ ORACLE_API int64_t or_partition_weighted(int64_t m, int64_t n, int64_t P, int64_
     int64_t C = (m + g - 1) / g, W = 0;
     for (int64_t d = 0; d < P; ++d) {
         int64_t wd = w ? w[d] : 1;
-        if (wd < 1) return -1;
+        if (wd < 1 || wd > ((int64_t)1 << 31)) return -1;   /* C w_d stays in 64 bits */
         W += wd;
     }
     int64_t *k = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);

@@ -119,7 +119,7 @@ static bool weigh_panel(Panel &pa, const int64_t *w, int64_t P) {
     const int64_t C = (pa.m + pa.chunk - 1) / pa.chunk;
     int64_t W = 0;
     for (int64_t d = 0; d < P; ++d) {
-        if (w[d] < 1) return false;
+        if (w[d] < 1 || w[d] > kMaxWeight) return false;   // C w_d and W stay in 64 bits
         W += w[d];
     }
     std::vector<int64_t> k(P), rem(P);
@@ -168,7 +168,9 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
     if (o->row_block != 0 && o->row_block < n) return -5;
     if (o->domains < -1 || (o->domains != 0 && o->row_block != 0)) return -5;
     if (!(o->route_kappa >= 0.0)) return -5;
-    if (o->domain_weights && (o->num_weights < 1 || o->row_block != 0 || o->domains != 0)) return -5;
+    if (o->domain_weights &&
+        (o->num_weights < 1 || o->num_weights > kMaxWeight || o->row_block != 0 || o->domains != 0))
+        return -5;
     if (o->lsq_max_rhs < 1 || o->refine_max_iter < 0) return -5;
     Plan P;
     P.m = m;

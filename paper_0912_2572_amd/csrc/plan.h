@@ -19,6 +19,7 @@ constexpr int kThreads = 256;     // threads per workgroup of the leaf kernel
 constexpr size_t kAlign = 256;
 constexpr int kRefineBlocks = 1024;   // workgroups of the refinement's residual pass
 constexpr int64_t kComputeUnits = 256;  // compute units of one gfx950 GPU (MI355X)
+constexpr int64_t kMaxWeight = (int64_t)1 << 31;  // largest domain weight, and weight count
 
 // Column slots per thread of the leaf kernel for a panel of width w: 16
 // column groups x ns slots must cover w (ns = 1, 2 or 4).  Rows per chunk

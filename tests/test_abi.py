@@ -106,7 +106,8 @@ def test_weighted_partition_rejected_cases(tl):
     for bad in (tl.opts(weights=[1, 0, 2]),                    # a domain of no power
                 tl.opts(weights=[1, 2], row_block=4096),       # with row_block
                 tl.opts(weights=[1, 2], domains=8),            # with domains
-                tl.opts(weights=[1000, 1])):                   # a domain without a chunk
+                tl.opts(weights=[1000, 1]),                    # a domain without a chunk
+                tl.opts(weights=[1, 1 << 40])):                # a weight past 2^31
         assert L.tsqr_partition(100_000, 16, ctypes.byref(bad), None, None, 0) == -5
     o = tl.opts(weights=[1, 1])
     o.num_weights = 0
