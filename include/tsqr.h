@@ -28,7 +28,11 @@
  *     style); TSQR_ERR_WORKSPACE when the workspace is too small;
  *     -1000 - e for a HIP runtime error e.
  *
- * Scope limits: 1 <= n <= 256, n <= m <= 2^31 - 1, domain rows >= n.
+ * Scope limits: 1 <= n <= 1024 (TSQR_MIXED and tsqr_cond_estimate:
+ * n <= 256), n <= m <= 2^31 - 1, domain rows >= n.  Wider than 64 columns,
+ * the matrix is factored in 64-column panels (Sec. 2.3's CAQR structure:
+ * each panel a TSQR of the rows below the previous ones, its Q^T applied to
+ * the columns to its right), so square matrices up to 1024 are covered.
  */
 #ifndef TSQR_H_
 #define TSQR_H_
@@ -340,7 +344,8 @@ TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const
    lower bound on ||R^{-1}||_1 with Higham's refinements (at most five pairs
    of triangular solves, then an alternating-sign test vector), so it never
    exceeds kappa_1(R) and is usually within a factor of 3 of it; +inf when R
-   has an exactly zero diagonal entry.  One wave of 64 lanes, n <= 256.
+   has an exactly zero diagonal entry.  One wave of 64 lanes, n <= 256
+   (TSQR_ERR_UNSUPPORTED beyond).
    The paper's method is FP64 only; the estimate serves the mixed-precision
    routing (opts.route_kappa).  Errors: -1 handle, -2 kappa NULL. */
 TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream);

@@ -530,6 +530,7 @@ TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream) {
     int rc = validate_handle(f, false);
     if (rc) return rc;
     if (!kappa) return -2;
+    if (f->plan.n > tsqr::kMaxMixedN) return TSQR_ERR_UNSUPPORTED;
     hipError_t e = tsqr::launch_cond_est(at<double>(f, f->plan.off_r), (int)f->plan.n, kappa,
                                          static_cast<hipStream_t>(stream));
     return e == hipSuccess ? 0 : hip_code(e);
@@ -865,7 +866,7 @@ TSQR_API const char *tsqr_strerror(int code) {
     if (code == 0) return "success";
     if (code == TSQR_ERR_WORKSPACE) return "workspace missing, misaligned or too small";
     if (code == TSQR_ERR_STATE) return "factor handle cannot serve this call (keep_q = 0?)";
-    if (code == TSQR_ERR_UNSUPPORTED) return "shape outside the supported scope (n <= 256)";
+    if (code == TSQR_ERR_UNSUPPORTED) return "shape outside the supported scope (n <= 1024; mixed precision and the condition estimate n <= 256)";
     if (code <= -1000) return "HIP runtime error (code = -1000 - hipError_t)";
     if (code < 0) return "invalid argument (code = -index of the argument)";
     return "unknown";

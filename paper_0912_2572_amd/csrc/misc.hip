@@ -64,8 +64,59 @@ __global__ __launch_bounds__(256) void k_resid_partial(const double *C, int64_t 
     }
 }
 
+// Back substitution R x = b for 256 < n <= 64 Q (lane l holds entries
+// l + 64 q, q < Q): the one-wave scheme of wave_backsub with Q slots per lane.
+template <int Q>
+__device__ __forceinline__ double pick_slot(const double (&xr)[Q], int q) {
+    double v = xr[0];
+#pragma unroll
+    for (int u = 1; u < Q; ++u) v = (q == u) ? xr[u] : v;
+    return v;
+}
+
+template <int Q>
+__device__ __forceinline__ void wide_backsub(const double *__restrict__ R, int n, double (&xr)[Q]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int D = kSolveAhead;
+    double col[D][Q], dg[D];
+    auto fetch = [&](int j, double (&cc)[Q], double &d) {
+        const int jj = j < 0 ? 0 : j;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = lane + 64 * q;
+            const double v = R[(i < jj ? i : 0) + (int64_t)jj * n];
+            cc[q] = (i < jj) ? v : 0.0;
+        }
+        d = R[jj + (int64_t)jj * n];
+    };
+    auto step = [&](int j, const double (&cc)[Q], double d) {
+        const int qj = j >> 6, lj = j & 63;
+        const double xj = wave_bcast(pick_slot<Q>(xr, qj), lj) / d;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            xr[q] = fma(-cc[q], xj, xr[q]);
+            if (q == qj && lane == lj) xr[q] = xj;
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch(n - 1 - u, col[u], dg[u]);
+    int j0 = n - 1;
+    for (; j0 - (D - 1) >= 0; j0 -= D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            step(j0 - u, col[u], dg[u]);
+            fetch(j0 - u - D, col[u], dg[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < D - 1; ++u)
+        if (j0 - u >= 0) step(j0 - u, col[u], dg[u]);
+}
+
 // One wave per right-hand side: info from the diagonal of R, the residual
-// norm from the partials, then X = R^{-1} C[0:n] by back substitution.
+// norm from the partials, then X = R^{-1} C[0:n] by back substitution
+// (Q = 4 slots per lane for n <= 256, 16 for n <= 1024).
+template <int Q>
 __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const double *C, int64_t ldc,
                                                   int64_t k, double *X, int64_t ldx, double *resid,
                                                   int32_t *dinfo, const double *partial, int nparts) {
@@ -73,9 +124,9 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
     const int64_t c = blockIdx.x;
     // the right-hand side and the residual partials are loaded before the
     // diagonal test, so the three groups of loads overlap
-    double xr[4];
+    double xr[Q];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < Q; ++q) {
         const int i = lane + 64 * q;
         xr[q] = (i < n) ? C[i + c * ldc] : 0.0;
     }
@@ -99,9 +150,10 @@ __global__ __launch_bounds__(64) void k_lsq_final(const double *R, int n, const 
         }
     }
     if (info) return;
-    wave_backsub(R, n, xr);
+    if constexpr (Q == 4) wave_backsub(R, n, xr);
+    else wide_backsub<Q>(R, n, xr);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < Q; ++q) {
         const int i = lane + 64 * q;
         if (i < n) X[i + c * ldx] = xr[q];
     }
@@ -267,6 +319,7 @@ hipError_t launch_cond_est(const double *R, int n, double *kappa, hipStream_t st
 hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ldc, int64_t m, int64_t k,
                              double *X, int64_t ldx, double *resid, int32_t *dinfo, double *partial,
                              hipStream_t st) {
+    if (n < 1 || n > 1024) return hipErrorInvalidValue;
     int blocks = kResidBlocks;
     if (m - n < (int64_t)blocks * 256) blocks = (int)((m - n + 255) / 256);
     if (blocks < 1) blocks = 1;
@@ -277,8 +330,12 @@ hipError_t launch_lsq_finish(const double *R, int n, const double *C, int64_t ld
         blocks = 0;
         if (dinfo) hipLaunchKernelGGL(k_info_clear, dim3(1), dim3(64), 0, st, dinfo);
     }
-    hipLaunchKernelGGL(k_lsq_final, dim3((unsigned)k), dim3(64), 0, st, R, n, C, ldc, k, X, ldx, resid, dinfo,
-                       partial, blocks);
+    if (n > 256)
+        hipLaunchKernelGGL(k_lsq_final<16>, dim3((unsigned)k), dim3(64), 0, st, R, n, C, ldc, k, X, ldx, resid,
+                           dinfo, partial, blocks);
+    else
+        hipLaunchKernelGGL(k_lsq_final<4>, dim3((unsigned)k), dim3(64), 0, st, R, n, C, ldc, k, X, ldx, resid,
+                           dinfo, partial, blocks);
     return hipGetLastError();
 }
 

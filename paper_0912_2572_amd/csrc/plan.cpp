@@ -165,6 +165,7 @@ int make_plan(int64_t m, int64_t n, const tsqr_opts *o, Plan *p) {
         o->tree != TSQR_TREE_XCD)
         return -5;
     if (o->prec != TSQR_F64 && o->prec != TSQR_MIXED) return -5;
+    if (o->prec == TSQR_MIXED && n > kMaxMixedN) return TSQR_ERR_UNSUPPORTED;
     if (o->row_block != 0 && o->row_block < n) return -5;
     if (o->domains < -1 || (o->domains != 0 && o->row_block != 0)) return -5;
     if (!(o->route_kappa >= 0.0)) return -5;

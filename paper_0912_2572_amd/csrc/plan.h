@@ -14,7 +14,8 @@
 namespace tsqr {
 
 constexpr int kMaxPanel = 64;     // columns handled by one leaf/tree kernel
-constexpr int kMaxN = 256;        // documented scope
+constexpr int kMaxN = 1024;       // documented scope (FP64)
+constexpr int kMaxMixedN = 256;   // mixed precision (the refinement's one-wave solves)
 constexpr int kThreads = 256;     // threads per workgroup of the leaf kernel
 constexpr size_t kAlign = 256;
 constexpr int kRefineBlocks = 1024;   // workgroups of the refinement's residual pass

@@ -166,7 +166,9 @@ def test_workspace_bytes(tl):
     assert w >= 8 * m * n + 8 * chunks * (n * n + 2 * n * 16)
     assert w < 8 * m * n * 1.6
     assert tl.workspace_bytes(10, 20, o) == 0          # m < n
-    assert tl.workspace_bytes(100, 300, o) == 0        # n above scope
+    assert tl.workspace_bytes(2000, 1100, o) == 0      # n above scope
+    assert tl.workspace_bytes(2000, 1024, o) > 8 * 2000 * 1024
+    assert tl.workspace_bytes(2000, 300, tl.opts(row_block=4096, prec=tl.MIXED)) == 0   # mixed: n <= 256
 
 
 def test_invalid_arguments_rejected_on_host(tl):
@@ -191,7 +193,10 @@ def test_invalid_arguments_rejected_on_host(tl):
                          ctypes.byref(h)) == tl.ERR_WORKSPACE
     assert L.tsqr_factor(100, 4, dummy, 100, ctypes.byref(o), dummy, 16, None,
                          ctypes.byref(h)) == tl.ERR_WORKSPACE
-    assert L.tsqr_factor(1000, 300, dummy, 1000, ctypes.byref(o), dummy, 1 << 30, None,
+    assert L.tsqr_factor(2000, 1100, dummy, 2000, ctypes.byref(o), dummy, 1 << 30, None,
+                         ctypes.byref(h)) == tl.ERR_UNSUPPORTED
+    mixed = tl.opts(row_block=4096, prec=tl.MIXED)
+    assert L.tsqr_factor(2000, 300, dummy, 2000, ctypes.byref(mixed), dummy, 1 << 30, None,
                          ctypes.byref(h)) == tl.ERR_UNSUPPORTED
     assert not h.value
     assert L.tsqr_strerror(-900).decode().startswith("workspace")

@@ -346,7 +346,11 @@ def test_nonfinite_input_info(tl, bad, prec):
 
 
 @pytest.mark.parametrize("m,n,mb,tree", [(5000, 65, 1024, 2), (3000, 128, 512, 2), (4096, 200, 1024, 2),
-                                         (2048, 256, 512, 2), (40000, 100, 1024, 8)])
+                                         (2048, 256, 512, 2), (40000, 100, 1024, 8),
+                                         # past 256 columns (the 16-slot final solve), up to
+                                         # square: 5 to 16 panels
+                                         (20000, 300, 4096, 2), (8000, 512, 2048, 2), (5000, 777, 1024, 4),
+                                         (1024, 1024, 1024, 2)])
 def test_wide_panels(tl, m, n, mb, tree):
     A = synth.gaussian(m, n, seed=m * 3 + n)
     check_all(tl, A, mb, tree)
