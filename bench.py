@@ -93,7 +93,7 @@ def cpu_baseline(m: int, n: int, mb: int, passes: int, samples: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="single",
-                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "copy"])
+                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "wide", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -119,7 +119,7 @@ def main():
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
-     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "copy": run_copy}[args.workload](args)
+     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "wide": run_wide, "copy": run_copy}[args.workload](args)
 
 
 def counter_record(kernel: str, m: int, n: int, mb: int, tree: str, kind: str):
@@ -329,6 +329,8 @@ def sub_records(args):
     t5 = time.perf_counter()
     lu = measure_tslu(args, steps=5, warmup=1)
     t5b = time.perf_counter()
+    wd = measure_wide(args, steps=3, warmup=1, domains=-1)
+    t5c = time.perf_counter()
     # a row count where 4096-row domains (293 of them) leave a second, mostly
     # idle wave of leaf workgroups on the 256 compute units, against the
     # load-balanced partition (one domain of 18-19 chunks per unit)
@@ -344,7 +346,7 @@ def sub_records(args):
                                "leaf_ms": uni["kernels_ms_per_step"].get("leaf_factor")},
             "balanced": {"domains": bal["config"]["domains"], "ms_per_step": bal["ms_per_step"],
                          "gflops": bal["value"], "leaf_ms": bal["kernels_ms_per_step"].get("leaf_factor")},
-            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5b, 1)},
+            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5c, 1)},
         "mixed_kappa1e6": {
             "workload": mx["config"]["workload"],
             "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
@@ -372,6 +374,11 @@ def sub_records(args):
             "ms": lu["ms_per_step"], "gflops": lu["value"], "leaf_ms": lu["leaf_ms"],
             "rel_residual": lu["rel_residual_A_minus_LU"], "max_abs_L": lu["max_abs_L"],
             "wall_s": round(t5b - t5, 1)},
+        "panels_262144x1024": {
+            "ms": wd["ms_per_step"], "gflops": wd["value"], "eta": wd["eta"], "info": wd["info"],
+            "domains": wd["config"]["domains"],
+            "trailing_update_ms": wd["kernels_ms_per_step"].get("leaf_apply_qt"),
+            "wall_s": round(t5c - t5b, 1)},
         "block_krylov_orth": {
             "workload": ob["config"]["workload"], "ms_per_loop": ob["ms_per_step"], "gflops": ob["value"],
             "roofline_frac_hbm": ob["roofline"]["frac"], "proj_update_gbs": ob["proj_update_gbs"],
@@ -751,6 +758,58 @@ def measure_tslu(args, steps, warmup, m=1 << 20, b=64):
             "info": int(info.item()), "rel_residual_A_minus_LU": res, "max_abs_L": lmax,
             "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()},
             "leaf_ms": round(leaf_ms, 4)}
+
+
+def run_wide(args):
+    print(json.dumps(measure_wide(args, args.steps, args.warmup, domains=args.domains)), flush=True)
+
+
+def measure_wide(args, steps, warmup, m=262144, n=1024, domains=0):
+    """Wider than 64 columns: FP64 factor + 1-RHS least squares of an m x n
+    N(0,1) matrix in 64-column panels (each a TSQR of the rows below the
+    previous ones, its Q^T applied to the columns to its right); useful
+    flops 2mn^2 - 2n^3/3 (R) + 4mn + n^2 (the solve)."""
+    import torch
+    import paper_0912_2572_amd as tl
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    A = torch.randn((n, m), generator=g, device=dev, dtype=torch.float64).t()
+    b = torch.randn((m, 1), generator=g, device=dev, dtype=torch.float64)
+    o = tl.opts(row_block=0 if domains else 4096, lsq_max_rhs=1, domains=domains)
+    work = torch.empty(tl.workspace_bytes(m, n, o), dtype=torch.uint8, device=dev)
+    X = tl.empty_colmajor(n, 1, device=dev)
+    res = torch.empty(1, dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def step():
+        f, _, _, _ = tl.factor_solve(A, b, o, work=work, X=X, resid=res, info=info)
+        return f
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tl.prof_enable(True)
+    step()
+    torch.cuda.synchronize()
+    kern = tl.prof_query()
+    tl.prof_enable(False)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    fl = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0 + 4.0 * m * n + n * n
+    eta = _eta(A, X[:, 0], b[:, 0])
+    return {"metric": "TSQR/CAQR Gflop/s (factor + LSQ), FP64, 64-column panels", "value": round(fl / (ms * 1e-3) / 1e9, 2),
+            "unit": "Gflop/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic N(0,1), torch Philox seed 3",
+            "config": {"workload": f"tsqr_panels_lsq {m}x{n}", "m": m, "n": n,
+                       "row_block": None if domains else 4096, "domains": tl.plan_info(m, n, o)[0],
+                       "partition": "balanced" if domains else "row_block", "panels": n // 64},
+            "info": int(info.item()), "eta": eta,
+            "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()}}
 
 
 def run_orth(args):
