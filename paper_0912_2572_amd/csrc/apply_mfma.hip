@@ -141,18 +141,23 @@ __device__ __forceinline__ void chunk_apply_m(ApplyMSmem<Tile> &sm, const typena
         sm.Wp[1][m][j] = s;   // W: each entry read and written by one thread
     }
     __syncthreads();
-    // Z = op(T) W (W in Wp[1]), written over the partial buffer of wave 0
-    for (int e = tid; e < 64 * KBM; e += 256) {
-        const int i = e >> 4, j = e & 15;
-        T z = 0;
-        if (i < n) {
-            if (trans) {
-                for (int q = 0; q <= i; ++q) z = fma(sm.Tm[q * kLdsStride + i], sm.Wp[1][q][j], z);
-            } else {
-                for (int q = i; q < n; ++q) z = fma(sm.Tm[i * kLdsStride + q], sm.Wp[1][q][j], z);
-            }
+    // Z = op(T) W (W in Wp[1]) on the matrix cores, written over the
+    // partial buffer of wave 0: wave w computes rows 16 w .. 16 w + 15 (T is
+    // zero outside its upper triangle and past n, so the full 64-wide sum is
+    // op(T) W; W rows past n are not formed and enter as zeros)
+    {
+        Acc acc = Acc{0, 0, 0, 0};
+        const int i = 16 * w + l16;
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) {
+            if (4 * kb >= n) break;
+            const int q = 4 * kb + l4;
+            const T a = trans ? sm.Tm[q * kLdsStride + i] : sm.Tm[i * kLdsStride + q];
+            const T b = (q < n) ? sm.Wp[1][q][l16] : T(0);
+            acc = Tile::mfma(a, b, acc);
         }
-        sm.Wp[0][i][j] = z;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sm.Wp[0][16 * w + Tile::drow(r, lane)][l16] = acc[r];
     }
     __syncthreads();
     if (!first)
