@@ -85,6 +85,8 @@ def lib():
         L.or_cond1.restype = ctypes.c_double
         L.or_cond1_est.argtypes = [i64, dp, i64]
         L.or_cond1_est.restype = ctypes.c_double
+        L.or_cholesky.argtypes = [i64, dp, i64, dp, i64, ctypes.c_int]
+        L.or_cholesky.restype = i64
         _lib = L
     return _lib
 
@@ -205,6 +207,25 @@ def cond1_est(R) -> float:
     """The cheap lower-bound estimate of kappa_1(R) (Hager 1984, Higham 1988)."""
     R = _fortran(R)
     return float(lib().or_cond1_est(R.shape[0], _dp(R), R.shape[0]))
+
+
+def cholesky(A, nthreads: int = 0):
+    """Cholesky factor of a symmetric positive definite A (the one-sided
+    factorization the paper names beside QR and LU), from the definition
+    column by column; only the lower triangle of A is read.  Returns (L,
+    info): L lower triangular with zeros above, info = 0 or j + 1 for the
+    first leading minor of order j + 1 that is not positive definite
+    (columns 0..j-1 of L final, the rest zero)."""
+    A = _fortran(A)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    L = np.zeros((n, n), order="F")
+    nt = nthreads if nthreads > 0 else max_threads()
+    info = int(lib().or_cholesky(n, _dp(A), max(n, 1), _dp(L), max(n, 1), nt))
+    if info < 0:
+        raise ValueError("oracle Cholesky rejected its arguments")
+    return L, info
 
 
 def schedule(P: int, tree: int):

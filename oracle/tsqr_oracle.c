@@ -54,6 +54,7 @@
 
 #define ORACLE_API __attribute__((visibility("default")))
 
+
 /* ------------------------------------------------------------------------ */
 /* Householder reflector (Sec. 2.2: H = I - tau v v^T).                      */
 /* In: *alpha = x_1, x[0..nx-1] = x_2 (stride incx).                         */
@@ -872,6 +873,50 @@ ORACLE_API int64_t or_tslu(int64_t m, int64_t b, const double *A, int64_t lda, i
         }
     }
     free(isp); free(M);
+    return info;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cholesky factorization A = L L^T of a symmetric positive definite n x n  */
+/* matrix, the third one-sided factorization the paper's introduction and   */
+/* conclusion name beside QR and LU.  This is the definition written out    */
+/* column by column (Cholesky-Crout order):                                 */
+/*   l_jj = sqrt(a_jj - sum_{k<j} l_jk^2),                                  */
+/*   l_ij = (a_ij - sum_{k<j} l_ik l_jk) / l_jj   for i > j,                */
+/* each sum taken in increasing k.  Only the lower triangle of A is read.   */
+/* L (ldl >= n) receives L with zeros above the diagonal.  Returns 0, or     */
+/* j + 1 when the leading minor of order j + 1 is not positive definite     */
+/* (a_jj - sum <= 0 or NaN): columns 0..j-1 of L are then final and the     */
+/* rest are zero.  The rows of a column are independent and run in         */
+/* parallel with OpenMP; L is kept row by row inside so the sums read       */
+/* consecutive memory.                                                      */
+/* ------------------------------------------------------------------------ */
+ORACLE_API int64_t or_cholesky(int64_t n, const double *A, int64_t lda, double *L, int64_t ldl, int nthreads)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || ldl < (n > 1 ? n : 1)) return -1;
+    const int nt = nthreads > 0 ? nthreads : 1;
+    double *Lr = (double *)calloc((size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1), sizeof(double));
+    int64_t info = 0;
+    for (int64_t j = 0; j < n && !info; ++j) {
+        const double *lj = Lr + j * n;
+        double d = A[j + j * lda];
+        for (int64_t k = 0; k < j; ++k) d -= lj[k] * lj[k];
+        if (!(d > 0.0)) { info = j + 1; break; }
+        const double ljj = sqrt(d);
+        Lr[j * n + j] = ljj;
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t i = j + 1; i < n; ++i) {
+            const double *li = Lr + i * n;
+            double s = A[i + j * lda];
+            for (int64_t k = 0; k < j; ++k) s -= li[k] * lj[k];
+            Lr[i * n + j] = s / ljj;
+        }
+    }
+    const int64_t done = info ? info - 1 : n;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i)
+            L[i + j * ldl] = (i >= j && j < done) ? Lr[i * n + j] : 0.0;
+    free(Lr);
     return info;
 }
 

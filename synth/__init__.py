@@ -140,3 +140,24 @@ def request_matrix(m: int, n: int, ill: bool, matrix_id: int, lo_exp: float = -6
 def request_rhs(m: int, k: int, seed: int):
     rng = np.random.default_rng(seed)
     return np.asfortranarray(rng.standard_normal((m, k)))
+
+
+def spd_gram(n: int, seed: int = 0, k: int = 0) -> np.ndarray:
+    """Symmetric positive definite n x n Gram matrix A = G G^T / k of an
+    n x k iid N(0,1) matrix G (k = 2n by default: eigenvalues in about
+    [(1 - 1/sqrt 2)^2, (1 + 1/sqrt 2)^2], condition number about 34),
+    column-major float64.  The Gram matrix of a block of vectors is what a
+    Cholesky-based orthogonalisation factors."""
+    k = 2 * n if k <= 0 else k
+    G = np.random.default_rng(seed).standard_normal((n, k))
+    A = (G @ G.T) / k
+    A = 0.5 * (A + A.T)
+    return np.asfortranarray(A)
+
+
+def spd_gram_factor(n: int, seed: int = 0, k: int = 0) -> np.ndarray:
+    """The G of spd_gram (n x k, C order), for callers that form G G^T / k
+    on the device."""
+    k = 2 * n if k <= 0 else k
+    return np.random.default_rng(seed).standard_normal((n, k))
+

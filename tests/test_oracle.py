@@ -767,3 +767,82 @@ def test_block_orth_of_a_block_in_the_complement():
     assert np.linalg.norm(V.T @ Q2) <= 1e-13
     assert rel(V @ H2 + Q2 @ R2, W2) <= 1e-14
 
+
+
+# ---------------------------------------------------------------- Cholesky
+
+def test_cholesky_pascal_closed_form():
+    # The symmetric Pascal matrix S_ij = C(i + j, i) has the lower Pascal
+    # matrix L_ij = C(i, j) as its Cholesky factor (a unit diagonal, so every
+    # step is integer arithmetic, exact in FP64 while the entries stay below
+    # 2^53).  A dropped term, a transposed index or a wrong sign changes some
+    # binomial.
+    n = 20
+    S = np.array([[math.comb(i + j, i) for j in range(n)] for i in range(n)], dtype=np.float64)
+    L, info = oracle.cholesky(S)
+    assert info == 0
+    want = np.array([[math.comb(i, j) if j <= i else 0 for j in range(n)] for i in range(n)], dtype=np.float64)
+    assert np.array_equal(L, want)
+
+
+def test_cholesky_small_closed_forms():
+    L, info = oracle.cholesky(np.array([[9.0]]))
+    assert info == 0 and L[0, 0] == 3.0
+    L, info = oracle.cholesky(np.array([[4.0, 2.0], [2.0, 5.0]]))
+    assert info == 0 and np.array_equal(L, np.array([[2.0, 0.0], [1.0, 2.0]]))
+    # 3 x 3 with L = [[2,0,0],[6,1,0],[-8,5,3]] (a textbook example)
+    Lw = np.array([[2.0, 0, 0], [6, 1, 0], [-8, 5, 3]])
+    L, info = oracle.cholesky(Lw @ Lw.T)
+    assert info == 0 and np.array_equal(L, Lw)
+
+
+@pytest.mark.parametrize("n", [1, 7, 50, 130])
+def test_cholesky_backward_error_and_lapack(n):
+    A = synth.spd_gram(n, seed=300 + n)
+    L, info = oracle.cholesky(A)
+    assert info == 0
+    assert np.array_equal(L, np.tril(L)) and np.all(np.diag(L) > 0)
+    # backward stability: L L^T = A + E with |E| <= gamma_{n+1} |L| |L^T|
+    E = np.abs(L @ L.T - A)
+    bound = (n + 1) * U / (1 - (n + 1) * U) * (np.abs(L) @ np.abs(L.T))
+    assert np.all(E <= 2.0 * bound + 1e-300)
+    # LAPACK's dpotrf (through SciPy) factors the same matrix: kappa ~ 34
+    Ll = scipy.linalg.cholesky(A, lower=True)
+    assert np.max(np.abs(L - Ll)) <= 64 * n * U * 34 * np.max(np.abs(Ll))
+
+
+def test_cholesky_reads_lower_triangle_only():
+    n = 40
+    A = synth.spd_gram(n, seed=7)
+    B = A.copy(order="F")
+    B[np.triu_indices(n, 1)] = np.random.default_rng(8).standard_normal(n * (n - 1) // 2) * 1e3
+    assert np.array_equal(oracle.cholesky(A)[0], oracle.cholesky(B)[0])
+
+
+def test_cholesky_power_of_two_scaling_is_exact():
+    # chol(D A D) = D chol(A) for D = diag(2^e_i): every operation scales by
+    # an exact power of two.
+    n = 60
+    A = synth.spd_gram(n, seed=9)
+    e = np.random.default_rng(10).integers(-30, 31, n)
+    D = np.ldexp(1.0, e)
+    L, info = oracle.cholesky(D[:, None] * A * D[None, :])
+    L0, _ = oracle.cholesky(A)
+    assert info == 0 and np.array_equal(L, D[:, None] * L0)
+
+
+def test_cholesky_info_on_indefinite_and_singular():
+    # diag(1, 1, -1, 1): the leading minor of order 3 is negative
+    L, info = oracle.cholesky(np.diag([1.0, 1.0, -1.0, 1.0]))
+    assert info == 3
+    assert np.array_equal(L[:, :2], np.eye(4)[:, :2]) and not L[:, 2:].any()
+    # a singular leading 2 x 2 block: the second pivot is exactly zero
+    L, info = oracle.cholesky(np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 0.0], [0.0, 0.0, 1.0]]))
+    assert info == 2 and L[0, 0] == 1.0 and L[1, 0] == 1.0
+    # a NaN on the diagonal fails at once
+    A = synth.spd_gram(5, seed=1)
+    A[0, 0] = np.nan
+    assert oracle.cholesky(A)[1] == 1
+    # a rank-deficient Gram matrix (k < n) fails somewhere past column k
+    A = synth.spd_gram(30, seed=2, k=10)
+    assert oracle.cholesky(A)[1] > 10
