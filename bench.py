@@ -93,7 +93,7 @@ def cpu_baseline(m: int, n: int, mb: int, passes: int, samples: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="single",
-                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "wide", "copy"])
+                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "wide", "chol", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -119,7 +119,7 @@ def main():
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
-     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "wide": run_wide, "copy": run_copy}[args.workload](args)
+     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "wide": run_wide, "chol": run_chol, "copy": run_copy}[args.workload](args)
 
 
 def counter_record(kernel: str, m: int, n: int, mb: int, tree: str, kind: str):
@@ -331,6 +331,8 @@ def sub_records(args):
     t5b = time.perf_counter()
     wd = measure_wide(args, steps=3, warmup=1, domains=-1)
     t5c = time.perf_counter()
+    ch = measure_chol(args, steps=5, warmup=1)
+    t5d = time.perf_counter()
     # a row count where 4096-row domains (293 of them) leave a second, mostly
     # idle wave of leaf workgroups on the 256 compute units, against the
     # load-balanced partition (one domain of 18-19 chunks per unit)
@@ -346,7 +348,7 @@ def sub_records(args):
                                "leaf_ms": uni["kernels_ms_per_step"].get("leaf_factor")},
             "balanced": {"domains": bal["config"]["domains"], "ms_per_step": bal["ms_per_step"],
                          "gflops": bal["value"], "leaf_ms": bal["kernels_ms_per_step"].get("leaf_factor")},
-            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5c, 1)},
+            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5d, 1)},
         "mixed_kappa1e6": {
             "workload": mx["config"]["workload"],
             "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
@@ -379,6 +381,12 @@ def sub_records(args):
             "domains": wd["config"]["domains"],
             "trailing_update_ms": wd["kernels_ms_per_step"].get("leaf_apply_qt"),
             "wall_s": round(t5c - t5b, 1)},
+        "cholesky_8192": {
+            "ms": ch["ms_per_step"], "gflops": ch["value"], "info": ch["info"],
+            "torch_linalg_cholesky_ms": ch["torch_linalg_cholesky_ms"], "speedup_vs_torch": ch["speedup_vs_torch"],
+            "syrk_ms": ch["kernels_ms_per_step"].get("chol_syrk"), "syrk_tflops": ch["syrk_tflops"],
+            "panel_ms": ch["kernels_ms_per_step"].get("chol_panel"),
+            "sampled_backward_error": ch["sampled_backward_error"], "wall_s": round(t5d - t5c, 1)},
         "block_krylov_orth": {
             "workload": ob["config"]["workload"], "ms_per_loop": ob["ms_per_step"], "gflops": ob["value"],
             "roofline_frac_hbm": ob["roofline"]["frac"], "proj_update_gbs": ob["proj_update_gbs"],
@@ -758,6 +766,91 @@ def measure_tslu(args, steps, warmup, m=1 << 20, b=64):
             "info": int(info.item()), "rel_residual_A_minus_LU": res, "max_abs_L": lmax,
             "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()},
             "leaf_ms": round(leaf_ms, 4)}
+
+
+def run_chol(args):
+    print(json.dumps(measure_chol(args, args.steps, args.warmup)), flush=True)
+
+
+def chol_update_flops(n, outer=256):
+    """Flops of the 256-column block columns' trailing updates (the lower
+    triangle of each trailing matrix, 2 K flops per entry)."""
+    f = 0.0
+    for j in range(0, n, outer):
+        jend = min(j + outer, n)
+        t = n - jend
+        f += 2.0 * (jend - j) * t * (t + 1) / 2.0
+    return f
+
+
+def measure_chol(args, steps, warmup, n=8192):
+    """In-place Cholesky of an n x n SPD Gram matrix G G^T / 2n (G iid
+    N(0,1), n x 2n); useful flops n^3/3.  torch.linalg.cholesky on the same
+    matrix is timed beside it for context.  Each step restores A by a device
+    copy outside the timed interval."""
+    import numpy as np
+    import torch
+    import paper_0912_2572_amd as tl
+    import synth
+    dev = torch.device("cuda:0")
+    g = torch.as_tensor(synth.spd_gram_factor(n, seed=0)).to(dev)
+    A0 = (g @ g.t()) / (2 * n)
+    A0 = (0.5 * (A0 + A0.t())).t().contiguous().t()
+    del g
+    A = torch.empty_like(A0).t().contiguous().t()
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+
+    def step():
+        A.copy_(A0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        tl.cholesky(A, info)
+        e1.record(st)
+        return e0, e1
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tl.prof_enable(True)
+    step()
+    torch.cuda.synchronize()
+    kern = tl.prof_query()
+    tl.prof_enable(False)
+    evs = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    flops = n ** 3 / 3.0
+    L = torch.tril(A)
+    rng = np.random.default_rng(1)
+    ii = torch.as_tensor(rng.integers(0, n, 2000), device=dev)
+    jj = torch.as_tensor(rng.integers(0, n, 2000), device=dev)
+    rec = (L[ii] * L[jj]).sum(dim=1)
+    back = float(((rec - A0[ii, jj]).abs() / (L[ii].abs() * L[jj].abs()).sum(dim=1)).max())
+    # torch's own Cholesky (rocSOLVER) on the same matrix, for context
+    for _ in range(warmup):
+        torch.linalg.cholesky(A0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        Lt = torch.linalg.cholesky(A0)
+    e1.record()
+    torch.cuda.synchronize()
+    torch_ms = e0.elapsed_time(e1) / steps
+    diff = float((Lt - L).abs().max() / L.abs().max())
+    syrk_ms = kern.get("chol_syrk", (1, 0.0))[1]
+    syrk_tf = chol_update_flops(n) / (syrk_ms * 1e-3) / 1e12 if syrk_ms > 0 else None
+    return {"metric": "Cholesky Gflop/s (n^3/3 useful flops)", "value": round(flops / (ms * 1e-3) / 1e9, 2),
+            "unit": "Gflop/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic SPD Gram G G^T/2n, G iid N(0,1), seed 0",
+            "config": {"workload": f"tsqr_cholesky {n}x{n}", "n": n, "block_column": 256, "panel": 64},
+            "info": int(info.item()), "sampled_backward_error": back, "max_rel_diff_vs_torch": diff,
+            "torch_linalg_cholesky_ms": round(torch_ms, 4),
+            "speedup_vs_torch": round(torch_ms / ms, 3),
+            "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()},
+            "launches": {k: v[0] for k, v in kern.items()},
+            "syrk_tflops": None if syrk_tf is None else round(syrk_tf, 2),
+            "syrk_frac_fp64_mfma_peak": None if syrk_tf is None else round(syrk_tf / 78.6, 4)}
 
 
 def run_wide(args):

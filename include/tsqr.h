@@ -338,6 +338,29 @@ TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const
                        void *dwork, size_t work_bytes, double *L, int64_t ldl, double *U, int64_t ldu,
                        int64_t *ipiv, int32_t *dinfo, void *stream);
 
+/* ------------------------------------------------------------------------
+   Cholesky factorization A = L L^T of a symmetric positive definite n x n
+   matrix: the third one-sided factorization, beside QR and LU, that the
+   paper's introduction and conclusion carry the approach over to.
+   Blocked right-looking, communication-avoiding in the sequential sense of
+   the Cholesky work the conclusion cites: block columns of 256 columns,
+   whose trailing update A22 -= L21 L21^T runs on the FP64 matrix cores (the
+   trailing matrix is read and written once per block column), each factored
+   in 64-column panels (the 64 x 64 diagonal block in one wave, the rows
+   below solved against it, 64 rows per workgroup).
+   A (n x n, device, column-major, lda >= max(1, n)): in, the lower triangle
+   of the SPD matrix (the strict upper triangle is neither read nor
+   written); out, L in the lower triangle.
+   dinfo (device, one int32, required): 0, or j > 0 when the leading minor
+   of order j is not positive definite (its pivot is <= 0 or NaN, LAPACK's
+   dpotrf convention).  The columns of L before the 64-column panel that
+   holds column j - 1 are then final; the rest of the lower triangle is
+   left part-way.
+   Runs on `stream`, allocates nothing.  n = 0 only clears dinfo.  Errors:
+   -1 n < 0, -2 A NULL, -3 lda, -4 dinfo NULL, TSQR_ERR_UNSUPPORTED for
+   n >= 2^31, -1000-e on a HIP error. */
+TSQR_API int tsqr_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, void *stream);
+
 /* Estimate of the 1-norm condition number kappa_1(R) = ||R||_1 ||R^{-1}||_1
    of the factor's R (= kappa_1 of A up to the factorization's rounding),
    written to *kappa (device, one double) on `stream`: ||R||_1 times Hager's

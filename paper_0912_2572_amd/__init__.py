@@ -156,6 +156,8 @@ def lib():
         L.tsqr_tslu.argtypes = [i64, i64, vp, i64, op, vp, sz, vp, i64, vp, i64, vp, vp, vp]
         L.tsqr_tslu.restype = ctypes.c_int
         L.tsqr_cond_estimate.argtypes = [vp, vp, vp]
+        L.tsqr_cholesky.argtypes = [i64, vp, i64, vp, vp]
+        L.tsqr_cholesky.restype = ctypes.c_int
         L.tsqr_cond_estimate.restype = ctypes.c_int
         L.tsqr_route_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         L.tsqr_route_info.restype = ctypes.c_int
@@ -502,6 +504,23 @@ def tslu(A: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = Non
                            ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(info.data_ptr()), _stream(stream)),
            "tsqr_tslu")
     return ipiv, L, U, info
+
+
+def cholesky(A: torch.Tensor, info: torch.Tensor | None = None, stream=None):
+    """In-place Cholesky factorization A = L L^T of a symmetric positive
+    definite matrix (tsqr_cholesky): reads the lower triangle of the
+    column-major A, overwrites it with L and leaves the strict upper
+    triangle alone.  Returns the device info word (0, or the order of the
+    first leading minor that is not positive definite)."""
+    n = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != n:
+        raise ValueError("A must be square")
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    pa, lda = _col_major(A, n, "A") if n > 0 else (0, 1)
+    _check(lib().tsqr_cholesky(n, ctypes.c_void_p(pa), lda, ctypes.c_void_p(info.data_ptr()), _stream(stream)),
+           "tsqr_cholesky")
+    return info
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

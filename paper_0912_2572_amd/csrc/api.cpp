@@ -526,6 +526,16 @@ TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const
     return e == hipSuccess ? 0 : hip_code(e);
 }
 
+TSQR_API int tsqr_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, void *stream) {
+    if (n < 0) return -1;
+    if (n > INT32_MAX) return TSQR_ERR_UNSUPPORTED;
+    if (!A && n > 0) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (!dinfo) return -4;
+    hipError_t e = tsqr::launch_cholesky(n, A, lda, dinfo, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : hip_code(e);
+}
+
 TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream) {
     int rc = validate_handle(f, false);
     if (rc) return rc;

@@ -203,6 +203,11 @@ hipError_t launch_tslu(const double *A, int64_t lda, const PanelArgs &pa, const 
                        int b, int32_t *cand, double *L11, double *L, int64_t ldl, double *U, int64_t ldu,
                        int64_t *ipiv, int32_t *dinfo, hipStream_t st);
 
+// In-place Cholesky A = L L^T of the lower triangle of an n x n SPD matrix
+// (lda >= n); *dinfo (device) <- 0 or the order of the first leading minor
+// that is not positive definite.
+hipError_t launch_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, hipStream_t st);
+
 // kappa_1(R) estimate of an n x n upper-triangular R (ld n, n <= 256) into
 // *kappa (device): one wave.
 hipError_t launch_cond_est(const double *R, int n, double *kappa, hipStream_t st);

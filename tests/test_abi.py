@@ -254,6 +254,17 @@ def test_tslu_arguments_checked_on_host(tl):
     assert L.tsqr_tslu(*small) == tl.ERR_WORKSPACE
 
 
+def test_cholesky_arguments_checked_on_host(tl):
+    L = tl.lib()
+    d = ctypes.c_void_p(256)
+    assert L.tsqr_cholesky(-1, d, 1, d, None) == -1
+    assert L.tsqr_cholesky(10, None, 10, d, None) == -2
+    assert L.tsqr_cholesky(10, d, 9, d, None) == -3
+    assert L.tsqr_cholesky(0, None, 0, d, None) == -3
+    assert L.tsqr_cholesky(10, d, 10, None, None) == -4
+    assert L.tsqr_cholesky(1 << 31, d, 1 << 31, d, None) == tl.ERR_UNSUPPORTED
+
+
 def test_routing_calls_check_their_handle(tl):
     L = tl.lib()
     prec, kap = ctypes.c_int32(), ctypes.c_double()
