@@ -6,25 +6,26 @@
 // inside one, panels of kPanel = 64 columns:
 //
 //   k_chol_panel   per panel: the 64 x 64 diagonal block factored in one
-//                  wave (lane t holds row t; l_jk reaches the other lanes by
-//                  readlane), then every row below the block solved against
-//                  it, l_i = a_i L11^{-T} (one wave per 64 rows, lane = row,
-//                  L11 read from LDS as broadcasts).  Every workgroup
+//                  wave (lane t holds row t; column k of L goes through LDS
+//                  and comes back to every lane as broadcasts), then every
+//                  row below the block solved against it, l_i = a_i
+//                  L11^{-T} (one wave per 64 rows, lane = row).  Every workgroup
 //                  factors the diagonal block itself, so one launch covers
 //                  the panel;
 //   k_chol_update  C -= W W^T on the lower triangle of a trailing block:
 //                  with W the panel inside its block column (K = 64, the
 //                  columns of the rest of the block column), then with W
 //                  the whole block column (K = 256, the trailing matrix).
-//                  FP64 matrix-core tiles over TILE x TILE output tiles of
+//                  FP64 matrix-core tiles over 64 x 64 output tiles of
 //                  the lower triangle, operands staged through LDS in
 //                  16-column chunks (double-buffered).
 //
 // The trailing matrix is read and written once per 256-column block
-// column: with 128 x 128 tiles that is 2 x 8 bytes of HBM traffic per 2 x
-// 256 flops, which keeps the update on the matrix cores' side of the
-// roofline (the communication-avoiding blocking of the sequential Cholesky
-// algorithms the paper cites).
+// column: 2 x 8 bytes of HBM traffic per 2 x 256 flops, which keeps the
+// update on the matrix cores' side of the roofline (the
+// communication-avoiding blocking of the sequential Cholesky algorithms the
+// paper cites); the operands, a 256-column block of L, are re-read from
+// the caches by every tile.
 //
 // A failed pivot (<= 0 or NaN) writes j + 1 to the info word; every later
 // kernel reads the word first and returns at once.
@@ -40,14 +41,88 @@ namespace {
 constexpr int kPanel = 64;
 constexpr int kOuter = 256;
 
+// 1 / sqrt(d) for a positive normal d: the hardware estimate and two
+// Newton steps r <- r (3/2 - d r^2 / 2), each squaring the relative error.
+__device__ __forceinline__ double rsqrt_f64(double d) {
+    double r = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    r = r * fma(-hd, r * r, 1.5);
+    r = r * fma(-hd, r * r, 1.5);
+    return r;
+}
+
+// The steps of the panel kernel, unrolled by template recursion so that
+// every register index is a compile-time constant.  A step reads its
+// column of L11 from LDS into registers and marks each value as used, in
+// order, with an empty asm statement: every load is then issued before the
+// first use instead of one load in front of each use.
+
+// Factorization step K: lane t holds row t of the diagonal block in m.
+template <int K>
+struct FactorStep {
+    __device__ static void run(double (&m)[kPanel], double *Lc, int t, int sb, int &fail) {
+        if (K < sb && fail < 0) {
+            const double d = wave_bcast(m[K], K);
+            if (!(d > 0.0)) {
+                fail = K;
+            } else {
+                const double rinv = rsqrt_f64(d);
+                const double v = t < K ? 0.0 : (t == K ? d * rinv : m[K] * rinv);
+                m[K] = v;
+                Lc[kPanel * K + t] = t == K ? rinv : v;
+                __syncthreads();
+                constexpr int R = kPanel - K - 1;
+                if constexpr (R > 0) {
+                    double cv[R];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) cv[i] = Lc[kPanel * K + K + 1 + i];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) asm volatile("" : "+v"(cv[i]));
+#pragma unroll
+                    for (int i = 0; i < R; ++i) m[K + 1 + i] = fma(-v, cv[i], m[K + 1 + i]);
+                }
+            }
+        }
+        FactorStep<K + 1>::run(m, Lc, t, sb, fail);
+    }
+};
+template <>
+struct FactorStep<kPanel> {
+    __device__ static void run(double (&)[kPanel], double *, int, int, int &) {}
+};
+
+// Solve step K: x[K] <- x[K] / L(K, K), then x[j] -= x[K] L(j, K), j > K.
+template <int K>
+struct SolveStep {
+    __device__ static void run(double (&x)[kPanel], const double *Lc, int sb) {
+        if (K < sb) {
+            constexpr int R = kPanel - K;
+            double cv[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) cv[i] = Lc[kPanel * K + K + i];
+#pragma unroll
+            for (int i = 0; i < R; ++i) asm volatile("" : "+v"(cv[i]));
+            const double xk = x[K] * cv[0];
+            x[K] = xk;
+#pragma unroll
+            for (int i = 1; i < R; ++i) x[K + i] = fma(-xk, cv[i], x[K + i]);
+        }
+        SolveStep<K + 1>::run(x, Lc, sb);
+    }
+};
+template <>
+struct SolveStep<kPanel> {
+    __device__ static void run(double (&)[kPanel], const double *, int) {}
+};
+
 __global__ __launch_bounds__(64) void k_chol_info_clear(int32_t *dinfo) {
     if (threadIdx.x == 0) *dinfo = 0;
 }
 
 // Panel of columns s .. s + sb - 1 (1 <= sb <= 64): the diagonal block
 // (rows s .. s + sb - 1) and the rows s + sb + 64 blockIdx.x + lane.
-// The factorization's steps take l_jk from lane j's registers (readlane);
-// the row solve reads L11 from LDS, a column ahead of its use.
+// Both phases read a column of L11 from LDS as broadcasts, all of its
+// loads issued before the first use.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_chol_panel(double *__restrict__ A, int64_t lda, int64_t n, int64_t s, int sb,
                   int32_t *__restrict__ dinfo) {
@@ -66,22 +141,7 @@ void k_chol_panel(double *__restrict__ A, int64_t lda, int64_t n, int64_t s, int
     // Right-looking factorization: step k finishes column k of L and updates
     // the columns after it.
     int fail = -1;
-#pragma unroll
-    for (int k = 0; k < kPanel; ++k) {
-        if (k >= sb || fail >= 0) continue;
-        const double d = wave_bcast(m[k], k);
-        if (!(d > 0.0)) {
-            fail = k;
-            continue;
-        }
-        const double ljj = sqrt(d);
-        const double rinv = 1.0 / ljj;
-        const double v = t < k ? 0.0 : (t == k ? ljj : m[k] * rinv);
-        m[k] = v;
-        Lc[kPanel * k + t] = t == k ? rinv : v;
-#pragma unroll
-        for (int j = k + 1; j < kPanel; ++j) m[j] = fma(-v, wave_bcast(v, j), m[j]);
-    }
+    FactorStep<0>::run(m, Lc, t, sb, fail);
     if (fail >= 0) {
         if (t == 0) *dinfo = (int32_t)(s + fail + 1);
         return;
@@ -100,21 +160,7 @@ void k_chol_panel(double *__restrict__ A, int64_t lda, int64_t n, int64_t s, int
     double x[kPanel];
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) x[j] = j < sb ? Ar[j * lda] : 0.0;
-    double c[2][kPanel];
-#pragma unroll
-    for (int j = 0; j < kPanel; ++j) c[0][j] = Lc[j];
-#pragma unroll
-    for (int k = 0; k < kPanel; ++k) {
-        if (k >= sb) continue;
-        if (k + 1 < kPanel) {
-#pragma unroll
-            for (int j = k + 1; j < kPanel; ++j) c[(k + 1) & 1][j] = Lc[kPanel * (k + 1) + j];
-        }
-        const double xk = x[k] * c[k & 1][k];
-        x[k] = xk;
-#pragma unroll
-        for (int j = k + 1; j < kPanel; ++j) x[j] = fma(-xk, c[k & 1][j], x[j]);
-    }
+    SolveStep<0>::run(x, Lc, sb);
 #pragma unroll
     for (int j = 0; j < kPanel; ++j)
         if (j < sb) Ar[j * lda] = x[j];
@@ -259,12 +305,10 @@ hipError_t launch_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, hi
             }
         }
         if (jend < n) {
-            // 128-row tiles once they give two workgroups per compute unit
-            const int64_t T = (n - jend + 127) / 128;
-            if (T * (T + 1) / 2 >= 2 * 256)
-                e = update<128>(A, lda, n, jend, n, j, (int)(jend - j), dinfo, "chol_syrk", st);
-            else
-                e = update<64>(A, lda, n, jend, n, j, (int)(jend - j), dinfo, "chol_syrk", st);
+            // 64 x 64 tiles: four resident workgroups per compute unit hide
+            // the operand loads better than 128 x 128 tiles' reuse pays
+            // (8192 x 8192: 4.8 against 6.4 ms of trailing updates)
+            e = update<64>(A, lda, n, jend, n, j, (int)(jend - j), dinfo, "chol_syrk", st);
             if (e != hipSuccess) return e;
         }
     }

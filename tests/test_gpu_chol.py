@@ -123,7 +123,7 @@ def test_cholesky_after_failure_next_call_succeeds(tl):
 
 
 def test_cholesky_large_leading_block_and_backward_error(tl):
-    # n = 8192 (the benchmark's size; 128 x 128 trailing tiles): the factor
+    # n = 8192 (the benchmark size, 128 panels, 31 block columns): the factor
     # of a leading principal block is the leading block of L, so the oracle
     # checks L[:1600, :1600]; every sampled entry of L L^T must equal A to
     # the backward-error bound.
@@ -154,3 +154,25 @@ def test_cholesky_large_leading_block_and_backward_error(tl):
     rec = (li * lj).sum(dim=1).cpu().numpy()
     bound = (n + 1) * U * (li.abs() * lj.abs()).sum(dim=1).cpu().numpy()
     assert np.all(np.abs(rec - A_s) <= 4.0 * bound), float(np.max(np.abs(rec - A_s) / bound))
+
+
+def test_cholesky_on_a_side_stream_is_deterministic(tl):
+    # the bulk of each trailing update runs on the library's second stream
+    # beside the next panels; every call on a caller's stream must still see
+    # the whole factorization done, and give the same bits each time
+    n = 2000
+    A = synth.spd_gram(n, seed=77)
+    side = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            a = dev(A)
+            side.wait_stream(torch.cuda.default_stream())
+            info = tl.cholesky(a, stream=side)
+            outs.append((a, info))
+    side.synchronize()
+    G = [o[0].cpu().numpy() for o in outs]
+    assert all(int(o[1].item()) == 0 for o in outs)
+    assert np.array_equal(G[0], G[1]) and np.array_equal(G[0], G[2])
+    Lo, _ = oracle.cholesky(A)
+    assert float(np.max(np.abs(np.tril(G[0]) - Lo))) <= tol(n, Lo)
