@@ -87,6 +87,8 @@ def lib():
         L.or_cond1_est.restype = ctypes.c_double
         L.or_cholesky.argtypes = [i64, dp, i64, dp, i64, ctypes.c_int]
         L.or_cholesky.restype = i64
+        L.or_calu.argtypes = [i64, i64, dp, i64, i64, ctypes.c_int, ctypes.c_int, ip]
+        L.or_calu.restype = i64
         _lib = L
     return _lib
 
@@ -226,6 +228,24 @@ def cholesky(A, nthreads: int = 0):
     if info < 0:
         raise ValueError("oracle Cholesky rejected its arguments")
     return L, info
+
+
+def calu(A, mb: int, tree: int = TREE_BINARY, nthreads: int = 0):
+    """LU with tournament pivoting of an m x n matrix (m >= n; CALU, the LU
+    counterpart of CAQR named in the conclusion): 64-column panels, each
+    pivoted by TSLU over or_partition(m - k, b, mb) and the tree, the pivots
+    applied as LAPACK-style row interchanges.  Returns (LU, ipiv, info) in
+    dgetrf's layout: P A = L U with L unit lower (strictly below the
+    diagonal of LU) and U upper, ipiv[i] = the row swapped with row i
+    (0-based), info = 0 or the first j + 1 with U_jj == 0."""
+    LU = _fortran(A)
+    m, n = LU.shape
+    ipiv = np.zeros(n, dtype=np.int64)
+    nt = nthreads if nthreads > 0 else max_threads()
+    info = int(lib().or_calu(m, n, _dp(LU), m, mb, tree, nt, _ip(ipiv)))
+    if info < 0:
+        raise ValueError("oracle CALU rejected its arguments")
+    return LU, ipiv, info
 
 
 def schedule(P: int, tree: int):

@@ -920,6 +920,96 @@ ORACLE_API int64_t or_cholesky(int64_t n, const double *A, int64_t lda, double *
     return info;
 }
 
+/* ------------------------------------------------------------------------ */
+/* CALU: LU of an m x n matrix (m >= n) with tournament pivoting, the LU    */
+/* counterpart of CAQR that the conclusion names beside TSLU.  Panels of    */
+/* b = 64 columns (the last one narrower); panel k:                         */
+/*   1. TSLU (or_tslu) of the m - k rows below the diagonal, over the       */
+/*      domains of or_partition(m - k, b, mb) and the or_schedule tree,     */
+/*      stacks of 256 rows;                                                 */
+/*   2. the tournament's pivot rows become b row interchanges in LAPACK's   */
+/*      style: interchange i swaps rows k + i and k + swp[i], where swp[i]  */
+/*      is where the i-th pivot row sits after interchanges 0..i-1;         */
+/*      ipiv[k + i] = k + swp[i];                                           */
+/*   3. the interchanges are applied to every column outside the panel, and */
+/*      the panel's columns take L and U in the permuted row order (U in    */
+/*      and above the diagonal block's diagonal, the unit lower L11 below   */
+/*      it, L21 under the block);                                           */
+/*   4. U12 = L11^{-1} A12 (forward substitution, unit diagonal) and        */
+/*      A22 -= L21 U12.                                                     */
+/* A is overwritten LAPACK-style (dgetrf's packed L\U).  Returns 0, or the  */
+/* first k + j + 1 whose U_jj is exactly zero (that column's l entries are  */
+/* zero and the factorization goes on), or -1 on bad arguments.             */
+/* ------------------------------------------------------------------------ */
+ORACLE_API int64_t or_calu(int64_t m, int64_t n, double *A, int64_t lda, int64_t mb, int tree, int nthreads,
+                           int64_t *ipiv)
+{
+    if (n < 1 || m < n || lda < m || mb < 1) return -1;
+    const int64_t bw = 64;
+    int64_t info = 0;
+    int64_t *row0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *nrows = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *sl = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *sr = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *rowat = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *posof = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    double *Lp = (double *)malloc(sizeof(double) * (size_t)m * (size_t)bw);
+    double *Up = (double *)malloc(sizeof(double) * (size_t)bw * (size_t)bw);
+    int64_t piv[64], swp[64];
+    for (int64_t k = 0; k < n; k += bw) {
+        const int64_t b = (n - k < bw) ? n - k : bw;
+        const int64_t mr = m - k;
+        /* 1. the panel's tournament */
+        const int64_t P = or_partition(mr, b, mb, row0, nrows);
+        const int64_t nn = or_schedule(P, tree, sl, sr);
+        const int64_t ik = or_tslu(mr, b, A + k + k * lda, lda, P, row0, nrows, 256, 256 - b, nn, sl, sr,
+                                   nthreads, piv, Lp, mr, Up, b);
+        if (ik > 0 && !info) info = k + ik;
+        /* 2. pivot rows -> interchanges */
+        for (int64_t r = 0; r < mr; ++r) { rowat[r] = r; posof[r] = r; }
+        for (int64_t i = 0; i < b; ++i) {
+            const int64_t r = piv[i], p = posof[r], ri = rowat[i];
+            swp[i] = p;
+            rowat[i] = r; rowat[p] = ri;
+            posof[r] = i; posof[ri] = p;
+            ipiv[k + i] = k + p;
+        }
+        /* 3. interchanges outside the panel; the panel's L and U */
+        for (int64_t c = 0; c < n; ++c) {
+            if (c >= k && c < k + b) continue;
+            double *col = A + c * lda + k;
+            for (int64_t i = 0; i < b; ++i) {
+                const double t = col[i];
+                col[i] = col[swp[i]];
+                col[swp[i]] = t;
+            }
+        }
+        for (int64_t j = 0; j < b; ++j)
+            for (int64_t rel = 0; rel < mr; ++rel)
+                A[k + rel + (k + j) * lda] = (rel < b && j >= rel) ? Up[rel + j * b] : Lp[rowat[rel] + j * mr];
+        /* 4. U12 and the trailing update */
+        for (int64_t c = k + b; c < n; ++c) {
+            double *col = A + c * lda;
+            for (int64_t i = 0; i < b; ++i) {
+                double t = col[k + i];
+                for (int64_t l = 0; l < i; ++l) t -= A[k + i + (k + l) * lda] * col[k + l];
+                col[k + i] = t;
+            }
+        }
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+        for (int64_t c = k + b; c < n; ++c) {
+            double *col = A + c * lda;
+            for (int64_t i = k + b; i < m; ++i) {
+                double t = col[i];
+                for (int64_t l = 0; l < b; ++l) t -= A[i + (k + l) * lda] * col[k + l];
+                col[i] = t;
+            }
+        }
+    }
+    free(row0); free(nrows); free(sl); free(sr); free(rowat); free(posof); free(Lp); free(Up);
+    return info;
+}
+
 /* Number of OpenMP threads the oracle will use when asked for nthreads<=0. */
 ORACLE_API int or_max_threads(void)
 {

@@ -846,3 +846,67 @@ def test_cholesky_info_on_indefinite_and_singular():
     # a rank-deficient Gram matrix (k < n) fails somewhere past column k
     A = synth.spd_gram(30, seed=2, k=10)
     assert oracle.cholesky(A)[1] > 10
+
+
+# ---------------------------------------------------------------- CALU
+
+def _calu_parts(LU, ipiv):
+    m, n = LU.shape
+    L = np.tril(LU, -1)[:, :n] + np.eye(m, n)
+    U = np.triu(LU[:n, :])
+    perm = np.arange(m)
+    for i, p in enumerate(ipiv):
+        perm[[i, p]] = perm[[p, i]]
+    return L, U, perm
+
+
+@pytest.mark.parametrize("m,n", [(5, 5), (64, 64), (100, 100), (200, 64), (256, 130), (130, 70), (90, 1)])
+def test_calu_is_lapack_getrf_when_one_stack_holds_each_panel(m, n):
+    # m <= 256: every panel's tournament is one stack, i.e. Gaussian
+    # elimination with partial pivoting, so the pivots are LAPACK's dgetrf's
+    # exactly and the factors agree to rounding
+    A = synth.gaussian(m, n, seed=600 + m + n)
+    LU, ipiv, info = oracle.calu(A, mb=4096)
+    lu, piv = scipy.linalg.lu_factor(A)
+    assert info == 0
+    assert ipiv.tolist() == piv.tolist()
+    assert np.max(np.abs(LU - lu)) <= 1e-12 * max(1.0, np.abs(lu).max())
+
+
+@pytest.mark.parametrize("m,n,mb,tree", [(3000, 200, 512, oracle.TREE_BINARY), (2500, 130, 600, oracle.TREE_QUAD),
+                                         (1500, 64, 256, oracle.TREE_FLAT), (800, 800, 300, oracle.TREE_BINARY)])
+def test_calu_reconstructs_a_and_keeps_multipliers_bounded(m, n, mb, tree):
+    A = synth.gaussian(m, n, seed=7 + m)
+    LU, ipiv, info = oracle.calu(A, mb=mb, tree=tree)
+    assert info == 0
+    L, U, perm = _calu_parts(LU, ipiv)
+    assert sorted(perm.tolist()) == list(range(m))
+    assert np.all(ipiv >= np.arange(n)) and np.all(ipiv < m)
+    res = np.linalg.norm(A[perm] - L @ U) / np.linalg.norm(A)
+    assert res <= 1e-14 * np.sqrt(n)
+    # tournament pivoting keeps the multipliers small (|l| = 1 only for
+    # partial pivoting; the tournament's bound is looser but far from growth)
+    assert np.abs(L).max() <= 16.0
+
+
+def test_calu_single_column_is_the_argmax():
+    A = synth.gaussian(5000, 1, seed=3)
+    LU, ipiv, info = oracle.calu(A, mb=700)
+    p = int(np.argmax(np.abs(A[:, 0])))
+    assert info == 0 and ipiv[0] == p
+    assert LU[0, 0] == A[p, 0]
+    rest = np.delete(np.arange(5000), [p])
+    # row p came to the top; the old top row went to position p
+    col = A[:, 0].copy()
+    col[[0, p]] = col[[p, 0]]
+    assert np.array_equal(LU[1:, 0], col[1:] / A[p, 0])
+
+
+def test_calu_zero_column_sets_info_and_goes_on():
+    A = synth.gaussian(400, 100, seed=4)
+    A[:, 70] = 0.0
+    LU, ipiv, info = oracle.calu(A, mb=128)
+    assert info == 71
+    L, U, perm = _calu_parts(LU, ipiv)
+    assert U[70, 70] == 0.0 and not np.tril(LU, -1)[:, 70].any()
+    assert np.linalg.norm(A[perm] - L @ U) / np.linalg.norm(A) <= 1e-14 * 10
