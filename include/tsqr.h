@@ -339,6 +339,32 @@ TSQR_API int tsqr_tslu(int64_t m, int64_t b, const double *A, int64_t lda, const
                        int64_t *ipiv, int32_t *dinfo, void *stream);
 
 /* ------------------------------------------------------------------------
+   CALU: LU of an m x n matrix (m >= n) with tournament pivoting, the LU
+   counterpart of CAQR that the conclusion names with TSLU.  Panels of 64
+   columns; each panel's pivot rows come from TSLU (above: the domains of
+   opts for the m - k rows below the diagonal, opts.tree, 256-row stacks),
+   become LAPACK-style row interchanges applied to the whole rows, and are
+   followed by U12 = L11^{-1} A12 and the trailing update A22 -= L21 U12 on
+   the FP64 matrix cores.
+   A (m x n, device, column-major, lda >= m): in, the matrix; out, dgetrf's
+     packed factors: U on and above the diagonal, the unit lower L strictly
+     below, so that P A = L U with P the interchanges;
+   ipiv (n, device, int64): row i was interchanged with row ipiv[i]
+     (0-based, ipiv[i] >= i), in order i = 0, 1, ...;
+   dinfo (device, one int32, required): 0, or j + 1 for the first U_jj that
+     is exactly zero (that column's l entries are zero; the factorization
+     goes on).
+   opts: row_block or domains and tree as for tsqr_factor (weighted domains
+   are TSQR_ERR_UNSUPPORTED).  dwork: >= tsqr_calu_workspace_bytes (0 for
+   invalid arguments), 256-byte aligned.  Runs on `stream`; allocates
+   nothing.  Errors: -1 m < n, -2 n < 1, -3 A NULL, -4 lda, -5 opts, -8
+   ipiv NULL, -9 dinfo NULL, TSQR_ERR_WORKSPACE, TSQR_ERR_UNSUPPORTED for
+   m >= 2^31 or weighted domains, -1000-e on a HIP error. */
+TSQR_API size_t tsqr_calu_workspace_bytes(int64_t m, int64_t n, const tsqr_opts *o);
+TSQR_API int tsqr_calu(int64_t m, int64_t n, double *A, int64_t lda, const tsqr_opts *o, void *dwork,
+                       size_t work_bytes, int64_t *ipiv, int32_t *dinfo, void *stream);
+
+/* ------------------------------------------------------------------------
    Cholesky factorization A = L L^T of a symmetric positive definite n x n
    matrix: the third one-sided factorization, beside QR and LU, that the
    paper's introduction and conclusion carry the approach over to.

@@ -157,6 +157,10 @@ def lib():
         L.tsqr_tslu.restype = ctypes.c_int
         L.tsqr_cond_estimate.argtypes = [vp, vp, vp]
         L.tsqr_cholesky.argtypes = [i64, vp, i64, vp, vp]
+        L.tsqr_calu_workspace_bytes.argtypes = [i64, i64, op]
+        L.tsqr_calu_workspace_bytes.restype = sz
+        L.tsqr_calu.argtypes = [i64, i64, vp, i64, op, vp, sz, vp, vp, vp]
+        L.tsqr_calu.restype = ctypes.c_int
         L.tsqr_cholesky.restype = ctypes.c_int
         L.tsqr_cond_estimate.restype = ctypes.c_int
         L.tsqr_route_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -504,6 +508,30 @@ def tslu(A: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = Non
                            ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(info.data_ptr()), _stream(stream)),
            "tsqr_tslu")
     return ipiv, L, U, info
+
+
+def calu(A: torch.Tensor, o: Opts | None = None, work: torch.Tensor | None = None,
+         ipiv: torch.Tensor | None = None, info: torch.Tensor | None = None, stream=None):
+    """In-place LU with tournament pivoting (tsqr_calu) of a column-major
+    m x n A (m >= n): A becomes dgetrf's packed L\\U with P A = L U.
+    Returns (ipiv, info): ipiv[i] the row interchanged with row i (0-based)."""
+    m, n = A.shape
+    o = o if o is not None else opts()
+    dev = A.device
+    need = int(lib().tsqr_calu_workspace_bytes(m, n, ctypes.byref(o)))
+    if need == 0:
+        raise ValueError(f"invalid CALU problem {m} x {n} for the given options")
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    if ipiv is None:
+        ipiv = torch.empty(n, dtype=torch.int64, device=dev)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+    pa, lda = _col_major(A, m, "A")
+    _check(lib().tsqr_calu(m, n, ctypes.c_void_p(pa), lda, ctypes.byref(o), ctypes.c_void_p(work.data_ptr()),
+                           work.numel(), ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(info.data_ptr()),
+                           _stream(stream)), "tsqr_calu")
+    return ipiv, info
 
 
 def cholesky(A: torch.Tensor, info: torch.Tensor | None = None, stream=None):

@@ -536,6 +536,91 @@ TSQR_API int tsqr_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, vo
     return e == hipSuccess ? 0 : hip_code(e);
 }
 
+namespace {
+
+// CALU's workspace: the first panel's TSLU workspace (the most domains),
+// then L (m x 64), U (64 x 64), the pivot rows (64 int64), the interchanges
+// (64 int32) and the panel's info word.
+struct CaluLayout {
+    size_t tslu = 0, l = 0, u = 0, piv = 0, swp = 0, pinfo = 0, total = 0;
+};
+int calu_layout(int64_t m, int64_t n, const tsqr_opts *o, CaluLayout *out) {
+    // the TSLU workspace of the panel that needs the most (every panel's
+    // plan is made again when it is factored)
+    size_t tsb = 0;
+    for (int64_t k = 0; k < n; k += 64) {
+        const int64_t b = n - k < 64 ? n - k : 64;
+        Plan p;
+        const int rc = tsqr::make_plan(m - k, b, o, &p);
+        if (rc) return rc;
+        if (!p.panels[0].wchunk0.empty()) return TSQR_ERR_UNSUPPORTED;
+        tsb = std::max(tsb, tslu_bytes(p, b));
+    }
+    CaluLayout L;
+    L.tslu = 0;
+    L.l = tslu_up(tsb);
+    L.u = L.l + tslu_up(sizeof(double) * (size_t)m * 64);
+    L.piv = L.u + tslu_up(sizeof(double) * 64 * 64);
+    L.swp = L.piv + tslu_up(sizeof(int64_t) * 64);
+    L.pinfo = L.swp + tslu_up(sizeof(int32_t) * 64);
+    L.total = L.pinfo + tslu_up(sizeof(int32_t));
+    *out = L;
+    return 0;
+}
+
+}  // namespace
+
+TSQR_API size_t tsqr_calu_workspace_bytes(int64_t m, int64_t n, const tsqr_opts *o) {
+    if (n < 1 || m < n) return 0;
+    CaluLayout L;
+    if (calu_layout(m, n, o, &L) != 0) return 0;
+    return L.total;
+}
+
+TSQR_API int tsqr_calu(int64_t m, int64_t n, double *A, int64_t lda, const tsqr_opts *o, void *dwork,
+                       size_t work_bytes, int64_t *ipiv, int32_t *dinfo, void *stream) {
+    if (n < 1) return -2;
+    if (m < n) return -1;
+    if (m > INT32_MAX) return TSQR_ERR_UNSUPPORTED;
+    if (!A) return -3;
+    if (lda < m) return -4;
+    CaluLayout Lw;
+    const int rc = calu_layout(m, n, o, &Lw);
+    if (rc) return rc;
+    if (!ipiv) return -8;
+    if (!dinfo) return -9;
+    if (!dwork || work_bytes < Lw.total || (reinterpret_cast<uintptr_t>(dwork) % tsqr::kAlign))
+        return TSQR_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(dwork);
+    double *Lp = reinterpret_cast<double *>(w + Lw.l);
+    double *Up = reinterpret_cast<double *>(w + Lw.u);
+    int64_t *piv = reinterpret_cast<int64_t *>(w + Lw.piv);
+    int32_t *swp = reinterpret_cast<int32_t *>(w + Lw.swp);
+    int32_t *pinfo = reinterpret_cast<int32_t *>(w + Lw.pinfo);
+    hipError_t e = tsqr::launch_calu_clear(dinfo, st);
+    if (e != hipSuccess) return hip_code(e);
+    for (int64_t k = 0; k < n; k += 64) {
+        const int b = (int)(n - k < 64 ? n - k : 64);
+        const int64_t mr = m - k;
+        Plan p;
+        const int prc = tsqr::make_plan(mr, b, o, &p);
+        if (prc) return prc;
+        const Panel &pp = p.panels[0];
+        std::vector<TreeArgs> levels;
+        for (const auto &Lv : tsqr::tree_levels(pp.P, pp.tree))
+            levels.push_back(TreeArgs{Lv.stride, Lv.span, Lv.chains, Lv.width});
+        int32_t *cand = reinterpret_cast<int32_t *>(w);
+        double *L11 = reinterpret_cast<double *>(w + tslu_up((size_t)pp.P * (size_t)b * sizeof(int32_t)));
+        double *Ak = A + k + k * lda;
+        e = tsqr::launch_tslu(Ak, lda, panel_args(pp), levels, b, cand, L11, Lp, mr, Up, 64, piv, pinfo, st);
+        if (e != hipSuccess) return hip_code(e);
+        e = tsqr::launch_calu_panel_rest(A, lda, m, n, k, b, piv, swp, ipiv, pinfo, dinfo, Lp, mr, Up, 64, st);
+        if (e != hipSuccess) return hip_code(e);
+    }
+    return 0;
+}
+
 TSQR_API int tsqr_cond_estimate(tsqr_factors f, double *kappa, void *stream) {
     int rc = validate_handle(f, false);
     if (rc) return rc;

@@ -1,0 +1,257 @@
+// calu.hip -- LU of an m x n matrix (m >= n) with tournament pivoting
+// (CALU), the LU counterpart of CAQR that the paper's conclusion names
+// beside TSLU.  Panels of 64 columns; panel k:
+//
+//   TSLU (tslu.hip) of the m - k rows below the diagonal: the tournament's
+//     pivot rows, U11 and L = A U11^{-1} in the panel's row order;
+//   k_calu_swaps   one lane turns the pivot rows into LAPACK-style row
+//                  interchanges (interchange i swaps rows k + i and
+//                  k + swp[i], swp[i] = where the i-th pivot row sits after
+//                  interchanges 0..i-1) and merges the panel's info word;
+//   k_calu_rowswap the interchanges on every column outside the panel (one
+//                  thread per column);
+//   k_calu_pack    the panel's columns in the permuted row order: U on and
+//                  above the diagonal block's diagonal, L below (row rel
+//                  takes the L row of the original row that the interchanges
+//                  brought there);
+//   k_calu_trsm    U12 = L11^{-1} A12 by forward substitution (unit
+//                  diagonal), one thread per column, L11 in LDS;
+//   k_lu_update    A22 -= L21 U12 on the FP64 matrix cores, 64 x 64 tiles,
+//                  operands staged through LDS in 16-deep chunks.
+#include "common.h"
+#include "kernels.h"
+#include "mfma.h"
+#include "prof.h"
+
+namespace tsqr {
+
+namespace {
+
+constexpr int kLuPanel = 64;
+
+__global__ __launch_bounds__(64) void k_calu_clear(int32_t *dinfo) {
+    if (threadIdx.x == 0) *dinfo = 0;
+}
+
+// swp[i] from the pivot rows piv (relative to row k): the row piv[i] starts
+// at position piv[i] and moves whenever an earlier interchange l touches its
+// position.  ipiv_out[i] = k + swp[i].  dinfo <- k + pinfo on the first
+// panel whose U has an exactly zero diagonal entry.
+__global__ __launch_bounds__(64) void k_calu_swaps(const int64_t *__restrict__ piv, int b, int64_t k,
+                                                   int32_t *__restrict__ swp, int64_t *__restrict__ ipiv_out,
+                                                   const int32_t *__restrict__ pinfo, int32_t *__restrict__ dinfo) {
+    if (threadIdx.x != 0) return;
+    int32_t s[kLuPanel];
+    for (int i = 0; i < b; ++i) {
+        int64_t p = piv[i];
+        for (int l = 0; l < i; ++l) {
+            if (p == l) p = s[l];
+            else if (p == s[l]) p = l;
+        }
+        s[i] = (int32_t)p;
+        swp[i] = (int32_t)p;
+        ipiv_out[i] = k + p;
+    }
+    const int32_t pi = *pinfo;
+    if (pi > 0 && *dinfo == 0) *dinfo = (int32_t)(k + pi);
+}
+
+// Columns outside [k, k + b): rows k + i and k + swp[i] exchanged, i = 0..b-1.
+__global__ __launch_bounds__(256) void k_calu_rowswap(double *__restrict__ A, int64_t lda, int64_t n, int64_t k,
+                                                      int b, const int32_t *__restrict__ swp) {
+    __shared__ int32_t s[kLuPanel];
+    if (threadIdx.x < b) s[threadIdx.x] = swp[threadIdx.x];
+    __syncthreads();
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n - b) return;
+    if (c >= k) c += b;
+    double *col = A + c * lda + k;
+    for (int i = 0; i < b; ++i) {
+        const int p = s[i];
+        if (p != i) {
+            const double t = col[i];
+            col[i] = col[p];
+            col[p] = t;
+        }
+    }
+}
+
+// Panel columns, row rel = 0 .. mr - 1 below row k: the original row o that
+// the interchanges brought to rel (walk them backwards), then U11[rel][j]
+// for rel < b, j >= rel, else L[o][j] (L: mr x b, ld ldl).
+__global__ __launch_bounds__(256) void k_calu_pack(double *__restrict__ A, int64_t lda, int64_t mr, int64_t k,
+                                                   int b, const int32_t *__restrict__ swp,
+                                                   const double *__restrict__ L, int64_t ldl,
+                                                   const double *__restrict__ U, int64_t ldu) {
+    __shared__ int32_t s[kLuPanel];
+    if (threadIdx.x < b) s[threadIdx.x] = swp[threadIdx.x];
+    __syncthreads();
+    const int64_t rel = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rel >= mr) return;
+    int64_t o = rel;
+    for (int i = b - 1; i >= 0; --i) {
+        if (o == i) o = s[i];
+        else if (o == s[i]) o = i;
+    }
+    double *dst = A + (k + rel) + k * lda;
+    for (int j = 0; j < b; ++j)
+        dst[j * lda] = (rel < b && j >= rel) ? U[rel + j * ldu] : L[o + j * ldl];
+}
+
+// U12 = L11^{-1} A12 for columns c in [k + b, n): one thread per column,
+// L11 (unit lower, rows/columns k .. k + b - 1 of the packed A) in LDS.
+__global__ __launch_bounds__(64) void k_calu_trsm(double *__restrict__ A, int64_t lda, int64_t n, int64_t k,
+                                                  int b) {
+    __shared__ double Ls[kLuPanel * kLuPanel];   // Ls[64 l + i] = L11(i, l)
+    const int t = threadIdx.x;
+    for (int l = 0; l < b; ++l) Ls[kLuPanel * l + t] = t < b ? A[(k + t) + (k + l) * lda] : 0.0;
+    __syncthreads();
+    const int64_t c = k + b + (int64_t)blockIdx.x * kLuPanel + t;
+    if (c >= n) return;
+    double *col = A + c * lda + k;
+    double y[kLuPanel];
+#pragma unroll
+    for (int i = 0; i < kLuPanel; ++i) y[i] = i < b ? col[i] : 0.0;
+#pragma unroll
+    for (int l = 0; l < kLuPanel; ++l) {
+        if (l >= b) continue;
+#pragma unroll
+        for (int i = l + 1; i < kLuPanel; ++i) y[i] = fma(-y[l], Ls[kLuPanel * l + i], y[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kLuPanel; ++i)
+        if (i < b) col[i] = y[i];
+}
+
+// A(i, c) -= sum_{kk < K} A(i, k + kk) A(k + kk, c) for i in [r0, m),
+// c in [r0, n), r0 = k + K: 64 x 64 tiles (bi = id mod Tr, bc = id / Tr),
+// four waves in a 2 x 2 grid of 32 x 32 sub-tiles.
+__global__ __launch_bounds__(256) void k_lu_update(double *__restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                   int64_t k, int K, int64_t Tr) {
+    constexpr int TILE = 64, WT = 2;
+    __shared__ double As[2][16][TILE];
+    __shared__ double Bs[2][16][TILE];
+    const int64_t r0 = k + K;
+    const int64_t bi = (int64_t)blockIdx.x % Tr, bc = (int64_t)blockIdx.x / Tr;
+    const int64_t i0 = r0 + bi * TILE, c0 = r0 + bc * TILE;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wi = w >> 1, wj = w & 1;
+
+    // A operand: row i0 + (tid & 63), depth (tid >> 6) + 4 q; B operand:
+    // depth tid & 15 (16 consecutive rows of U12), column c0 + (tid >> 4) + 16 q
+    const int arow = tid & 63, ak = tid >> 6;
+    const int bk = tid & 15, bcol = tid >> 4;
+    const bool aok = i0 + arow < m;
+    const double *__restrict__ Aa = A + (aok ? i0 + arow : 0) + k * lda;
+    double ra[4], rb[4];
+    auto load = [&](int ch) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = 16 * ch + ak + 4 * q;
+            ra[q] = (aok && kk < K) ? Aa[kk * lda] : 0.0;
+            const int kb = 16 * ch + bk;
+            const int64_t c = c0 + bcol + 16 * q;
+            rb[q] = (kb < K && c < n) ? A[(k + kb) + c * lda] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[buf][ak + 4 * q][arow] = ra[q];
+            Bs[buf][bk][bcol + 16 * q] = rb[q];
+        }
+    };
+    d4 acc[WT][WT];
+#pragma unroll
+    for (int I = 0; I < WT; ++I)
+#pragma unroll
+        for (int J = 0; J < WT; ++J) acc[I][J] = d4_zero();
+    const int nch = (K + 15) / 16;
+    load(0);
+    stash(0);
+    __syncthreads();
+    const int ri = wi * (TILE / 2) + (lane & 15), rj = wj * (TILE / 2) + (lane & 15);
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) load(ch + 1);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = 4 * ks + (lane >> 4);
+            double a[WT], bv[WT];
+#pragma unroll
+            for (int I = 0; I < WT; ++I) a[I] = As[buf][kk][ri + 16 * I];
+#pragma unroll
+            for (int J = 0; J < WT; ++J) bv[J] = Bs[buf][kk][rj + 16 * J];
+#pragma unroll
+            for (int I = 0; I < WT; ++I)
+#pragma unroll
+                for (int J = 0; J < WT; ++J) acc[I][J] = mfma_f64(a[I], bv[J], acc[I][J]);
+        }
+        if (ch + 1 < nch) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int I = 0; I < WT; ++I)
+#pragma unroll
+        for (int J = 0; J < WT; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = i0 + wi * (TILE / 2) + 16 * I + d_row(r, lane);
+                const int64_t col = c0 + wj * (TILE / 2) + 16 * J + d_col(lane);
+                if (row < m && col < n) A[row + col * lda] -= acc[I][J][r];
+            }
+}
+
+}  // namespace
+
+hipError_t launch_calu_clear(int32_t *dinfo, hipStream_t st) {
+    hipLaunchKernelGGL(k_calu_clear, dim3(1), dim3(64), 0, st, dinfo);
+    return hipGetLastError();
+}
+
+hipError_t launch_calu_panel_rest(double *A, int64_t lda, int64_t m, int64_t n, int64_t k, int b,
+                                  const int64_t *piv, int32_t *swp, int64_t *ipiv_out, const int32_t *pinfo,
+                                  int32_t *dinfo, const double *L, int64_t ldl, const double *U, int64_t ldu,
+                                  hipStream_t st) {
+    if (b < 1 || b > kLuPanel) return hipErrorInvalidValue;
+    {
+        ProfScope ps("calu_swaps", st);
+        hipLaunchKernelGGL(k_calu_swaps, dim3(1), dim3(64), 0, st, piv, b, k, swp, ipiv_out + k, pinfo, dinfo);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n > b) {
+        ProfScope ps("calu_rowswap", st);
+        hipLaunchKernelGGL(k_calu_rowswap, dim3((unsigned)((n - b + 255) / 256)), dim3(256), 0, st, A, lda, n, k,
+                           b, swp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    {
+        ProfScope ps("calu_pack", st);
+        const int64_t mr = m - k;
+        hipLaunchKernelGGL(k_calu_pack, dim3((unsigned)((mr + 255) / 256)), dim3(256), 0, st, A, lda, mr, k, b,
+                           swp, L, ldl, U, ldu);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (k + b < n) {
+        {
+            ProfScope ps("calu_trsm", st);
+            const int64_t cols = n - k - b;
+            hipLaunchKernelGGL(k_calu_trsm, dim3((unsigned)((cols + kLuPanel - 1) / kLuPanel)), dim3(kLuPanel), 0,
+                               st, A, lda, n, k, b);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const int64_t Tr = (m - k - b + 63) / 64, Tc = (n - k - b + 63) / 64;
+        if (Tr * Tc > INT32_MAX) return hipErrorInvalidValue;
+        ProfScope ps("calu_update", st);
+        hipLaunchKernelGGL(k_lu_update, dim3((unsigned)(Tr * Tc)), dim3(256), 0, st, A, lda, m, n, k, b, Tr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace tsqr

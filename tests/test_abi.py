@@ -254,6 +254,28 @@ def test_tslu_arguments_checked_on_host(tl):
     assert L.tsqr_tslu(*small) == tl.ERR_WORKSPACE
 
 
+def test_calu_arguments_checked_on_host(tl):
+    L = tl.lib()
+    o = tl.opts(row_block=512)
+    d = ctypes.c_void_p(256)
+    w = L.tsqr_calu_workspace_bytes(3000, 200, ctypes.byref(o))
+    assert w >= 3000 * 64 * 8
+    assert L.tsqr_calu_workspace_bytes(100, 200, ctypes.byref(o)) == 0
+    assert L.tsqr_calu_workspace_bytes(100, 0, ctypes.byref(o)) == 0
+    args = lambda m, n, A, lda, ipiv, info, wb: (m, n, A, lda, ctypes.byref(o), d, wb, ipiv, info, None)
+    assert L.tsqr_calu(*args(100, 200, d, 100, d, d, w)) == -1
+    assert L.tsqr_calu(*args(3000, 0, d, 3000, d, d, w)) == -2
+    assert L.tsqr_calu(*args(3000, 200, None, 3000, d, d, w)) == -3
+    assert L.tsqr_calu(*args(3000, 200, d, 2999, d, d, w)) == -4
+    assert L.tsqr_calu(*args(3000, 200, d, 3000, None, d, w)) == -8
+    assert L.tsqr_calu(*args(3000, 200, d, 3000, d, None, w)) == -9
+    assert L.tsqr_calu(*args(3000, 200, d, 3000, d, d, 16)) == tl.ERR_WORKSPACE
+    wts = np.array([1, 2, 3], dtype=np.int64)
+    ow = tl.opts(weights=wts)
+    assert L.tsqr_calu_workspace_bytes(3000, 200, ctypes.byref(ow)) == 0
+    assert L.tsqr_calu(3000, 200, d, 3000, ctypes.byref(ow), d, w, d, d, None) == tl.ERR_UNSUPPORTED
+
+
 def test_cholesky_arguments_checked_on_host(tl):
     L = tl.lib()
     d = ctypes.c_void_p(256)
