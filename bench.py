@@ -93,7 +93,7 @@ def cpu_baseline(m: int, n: int, mb: int, passes: int, samples: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="single",
-                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "wide", "chol", "copy"])
+                    choices=["single", "mixed", "batch", "serve", "sweep", "orth", "tslu", "wide", "chol", "calu", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -119,7 +119,7 @@ def main():
               "(DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
-     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "wide": run_wide, "chol": run_chol, "copy": run_copy}[args.workload](args)
+     "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "wide": run_wide, "chol": run_chol, "calu": run_calu, "copy": run_copy}[args.workload](args)
 
 
 def counter_record(kernel: str, m: int, n: int, mb: int, tree: str, kind: str):
@@ -333,6 +333,8 @@ def sub_records(args):
     t5c = time.perf_counter()
     ch = measure_chol(args, steps=5, warmup=1)
     t5d = time.perf_counter()
+    cl = measure_calu(args, steps=3, warmup=1)
+    t5e = time.perf_counter()
     # a row count where 4096-row domains (293 of them) leave a second, mostly
     # idle wave of leaf workgroups on the 256 compute units, against the
     # load-balanced partition (one domain of 18-19 chunks per unit)
@@ -348,7 +350,7 @@ def sub_records(args):
                                "leaf_ms": uni["kernels_ms_per_step"].get("leaf_factor")},
             "balanced": {"domains": bal["config"]["domains"], "ms_per_step": bal["ms_per_step"],
                          "gflops": bal["value"], "leaf_ms": bal["kernels_ms_per_step"].get("leaf_factor")},
-            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5d, 1)},
+            "speedup": round(uni["ms_per_step"] / bal["ms_per_step"], 3), "wall_s": round(t6 - t5e, 1)},
         "mixed_kappa1e6": {
             "workload": mx["config"]["workload"],
             "f64_ms": round(mx["f64"]["ms"], 3), "mixed_ms": round(mx["mixed"]["ms"], 3),
@@ -387,6 +389,13 @@ def sub_records(args):
             "syrk_ms": ch["kernels_ms_per_step"].get("chol_syrk"), "syrk_tflops": ch["syrk_tflops"],
             "panel_ms": ch["kernels_ms_per_step"].get("chol_panel"),
             "sampled_backward_error": ch["sampled_backward_error"], "wall_s": round(t5d - t5c, 1)},
+        "calu_4096": {
+            "ms": cl["ms_per_step"], "gflops": cl["value"], "info": cl["info"],
+            "torch_linalg_lu_factor_ms": cl["torch_linalg_lu_factor_ms"], "speedup_vs_torch": cl["speedup_vs_torch"],
+            "tslu_ms": round(sum(v for k, v in cl["kernels_ms_per_step"].items() if k.startswith("tslu")), 3),
+            "update_ms": cl["kernels_ms_per_step"].get("calu_update"),
+            "rel_residual": cl["rel_residual_PA_minus_LU"], "max_abs_L": cl["max_abs_L"],
+            "wall_s": round(t5e - t5d, 1)},
         "block_krylov_orth": {
             "workload": ob["config"]["workload"], "ms_per_loop": ob["ms_per_step"], "gflops": ob["value"],
             "roofline_frac_hbm": ob["roofline"]["frac"], "proj_update_gbs": ob["proj_update_gbs"],
@@ -851,6 +860,76 @@ def measure_chol(args, steps, warmup, n=8192):
             "launches": {k: v[0] for k, v in kern.items()},
             "syrk_tflops": None if syrk_tf is None else round(syrk_tf, 2),
             "syrk_frac_fp64_mfma_peak": None if syrk_tf is None else round(syrk_tf / 78.6, 4)}
+
+
+def run_calu(args):
+    print(json.dumps(measure_calu(args, args.steps, args.warmup)), flush=True)
+
+
+def measure_calu(args, steps, warmup, n=4096, row_block=256):
+    """CALU (LU with tournament-pivoted 64-column panels) of an n x n N(0,1)
+    matrix; each panel's TSLU uses row_block-row domains and the binary
+    tree.  Useful flops 2n^3/3.  torch.linalg.lu_factor (partial pivoting)
+    on the same matrix is timed beside it for context.  Each step restores
+    A by a device copy outside the timed interval."""
+    import torch
+    import paper_0912_2572_amd as tl
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    A0 = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64).t()
+    A = torch.empty((n, n), device=dev, dtype=torch.float64).t()
+    o = tl.opts(row_block=row_block)
+    work = torch.empty(tl.lib().tsqr_calu_workspace_bytes(n, n, ctypes_ref(o)), dtype=torch.uint8, device=dev)
+    ipiv = torch.empty(n, dtype=torch.int64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+
+    def step():
+        A.copy_(A0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        tl.calu(A, o, work=work, ipiv=ipiv, info=info)
+        e1.record(st)
+        return e0, e1
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tl.prof_enable(True)
+    step()
+    torch.cuda.synchronize()
+    kern = tl.prof_query()
+    tl.prof_enable(False)
+    evs = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    # P A = L U on the device
+    L = torch.tril(A, -1) + torch.eye(n, device=dev, dtype=torch.float64)
+    U = torch.triu(A)
+    perm = list(range(n))
+    for i, p in enumerate(ipiv.cpu().tolist()):
+        perm[i], perm[p] = perm[p], perm[i]
+    res = float(torch.linalg.norm(A0[torch.as_tensor(perm, device=dev)] - L @ U) / torch.linalg.norm(A0))
+    lmax = float(L.abs().max())
+    for _ in range(warmup):
+        torch.linalg.lu_factor(A0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        torch.linalg.lu_factor(A0)
+    e1.record()
+    torch.cuda.synchronize()
+    torch_ms = e0.elapsed_time(e1) / steps
+    flops = 2.0 * n ** 3 / 3.0
+    return {"metric": "CALU Gflop/s (2n^3/3 useful flops)", "value": round(flops / (ms * 1e-3) / 1e9, 2),
+            "unit": "Gflop/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic iid N(0,1), torch Philox seed 5",
+            "config": {"workload": f"tsqr_calu {n}x{n}", "n": n, "panel": 64, "row_block": row_block,
+                       "tree": "binary", "stack_rows": 256},
+            "info": int(info.item()), "rel_residual_PA_minus_LU": res, "max_abs_L": lmax,
+            "torch_linalg_lu_factor_ms": round(torch_ms, 4), "speedup_vs_torch": round(torch_ms / ms, 3),
+            "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kern.items()}}
 
 
 def run_wide(args):

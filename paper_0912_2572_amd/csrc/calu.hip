@@ -4,7 +4,7 @@
 //
 //   TSLU (tslu.hip) of the m - k rows below the diagonal: the tournament's
 //     pivot rows, U11 and L = A U11^{-1} in the panel's row order;
-//   k_calu_swaps   one lane turns the pivot rows into LAPACK-style row
+//   k_calu_swaps   one wave turns the pivot rows into LAPACK-style row
 //                  interchanges (interchange i swaps rows k + i and
 //                  k + swp[i], swp[i] = where the i-th pivot row sits after
 //                  interchanges 0..i-1) and merges the panel's info word;
@@ -33,27 +33,64 @@ __global__ __launch_bounds__(64) void k_calu_clear(int32_t *dinfo) {
     if (threadIdx.x == 0) *dinfo = 0;
 }
 
-// swp[i] from the pivot rows piv (relative to row k): the row piv[i] starts
-// at position piv[i] and moves whenever an earlier interchange l touches its
-// position.  ipiv_out[i] = k + swp[i].  dinfo <- k + pinfo on the first
-// panel whose U has an exactly zero diagonal entry.
+// swp[i] from the pivot rows piv (relative to row k), on one wave.  Lane t
+// tracks the row at position t < b (top) and one position at or past b that
+// an interchange has filled with another row (the displaced list, nd
+// entries); every other position holds its own row.  Step i finds where
+// piv[i] sits by a ballot over both, exchanges it with position i and
+// records the row it displaces.  ipiv_out[i] = k + swp[i].  dinfo <- k +
+// pinfo on the first panel whose U has an exactly zero diagonal entry.
 __global__ __launch_bounds__(64) void k_calu_swaps(const int64_t *__restrict__ piv, int b, int64_t k,
                                                    int32_t *__restrict__ swp, int64_t *__restrict__ ipiv_out,
                                                    const int32_t *__restrict__ pinfo, int32_t *__restrict__ dinfo) {
-    if (threadIdx.x != 0) return;
-    int32_t s[kLuPanel];
+    const int t = threadIdx.x;
+    __shared__ int64_t pv[kLuPanel];
+    if (t < b) pv[t] = piv[t];
+    __syncthreads();
+    int64_t top = t, dpos = -1, drow = -1;
+    int nd = 0;
+    int64_t mine = 0;   // swp[t], kept by lane t
     for (int i = 0; i < b; ++i) {
-        int64_t p = piv[i];
-        for (int l = 0; l < i; ++l) {
-            if (p == l) p = s[l];
-            else if (p == s[l]) p = l;
+        const int64_t r = pv[i];
+        const uint64_t m1 = __ballot(t >= i && t < b && top == r);
+        const uint64_t m2 = __ballot(t < nd && drow == r);
+        int64_t p;
+        int dl = -1;
+        if (m1) {
+            p = __builtin_ctzll(m1);
+        } else if (m2) {
+            dl = __builtin_ctzll(m2);
+            const int64_t dp = dpos;
+            p = (int64_t)__shfl(dp, dl);
+        } else {
+            p = r;
         }
-        s[i] = (int32_t)p;
-        swp[i] = (int32_t)p;
-        ipiv_out[i] = k + p;
+        const int64_t tp = top;
+        const int64_t ri = __shfl(tp, i);   // the row at position i, displaced to p
+        if (t == i) {
+            top = r;
+            mine = p;
+        }
+        if (p < b) {
+            if (t == p && p != i) top = ri;
+        } else if (dl >= 0) {
+            if (t == dl) drow = ri;
+        } else {
+            if (t == nd) {
+                dpos = p;
+                drow = ri;
+            }
+            ++nd;
+        }
     }
-    const int32_t pi = *pinfo;
-    if (pi > 0 && *dinfo == 0) *dinfo = (int32_t)(k + pi);
+    if (t < b) {
+        swp[t] = (int32_t)mine;
+        ipiv_out[t] = k + mine;
+    }
+    if (t == 0) {
+        const int32_t pi = *pinfo;
+        if (pi > 0 && *dinfo == 0) *dinfo = (int32_t)(k + pi);
+    }
 }
 
 // Columns outside [k, k + b): rows k + i and k + swp[i] exchanged, i = 0..b-1.
