@@ -538,9 +538,9 @@ TSQR_API int tsqr_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, vo
 
 namespace {
 
-// CALU's workspace: the first panel's TSLU workspace (the most domains),
-// then L (m x 64), U (64 x 64), the pivot rows (64 int64), the interchanges
-// (64 int32) and the panel's info word.
+// CALU's workspace: the TSLU workspace of the panel that needs the most,
+// then L (m x 64), U (64 x 64), the pivot rows (64 int64), the interchange
+// record (kCaluMetaWords int32) and the panel's info word.
 struct CaluLayout {
     size_t tslu = 0, l = 0, u = 0, piv = 0, swp = 0, pinfo = 0, total = 0;
 };
@@ -562,7 +562,7 @@ int calu_layout(int64_t m, int64_t n, const tsqr_opts *o, CaluLayout *out) {
     L.u = L.l + tslu_up(sizeof(double) * (size_t)m * 64);
     L.piv = L.u + tslu_up(sizeof(double) * 64 * 64);
     L.swp = L.piv + tslu_up(sizeof(int64_t) * 64);
-    L.pinfo = L.swp + tslu_up(sizeof(int32_t) * 64);
+    L.pinfo = L.swp + tslu_up(sizeof(int32_t) * tsqr::kCaluMetaWords);
     L.total = L.pinfo + tslu_up(sizeof(int32_t));
     *out = L;
     return 0;

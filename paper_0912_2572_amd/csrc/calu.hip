@@ -8,8 +8,8 @@
 //                  interchanges (interchange i swaps rows k + i and
 //                  k + swp[i], swp[i] = where the i-th pivot row sits after
 //                  interchanges 0..i-1) and merges the panel's info word;
-//   k_calu_rowswap the interchanges on every column outside the panel (one
-//                  thread per column);
+//   k_calu_rowswap the interchanges on every column outside the panel, as
+//                  one gather per column over the touched positions;
 //   k_calu_pack    the panel's columns in the permuted row order: U on and
 //                  above the diagonal block's diagonal, L below (row rel
 //                  takes the L row of the original row that the interchanges
@@ -29,6 +29,12 @@ namespace {
 
 constexpr int kLuPanel = 64;
 
+// Per-panel interchange record (int32 words): swp[0..63], then the touched
+// positions (at most 128: the top b and the displaced ones), the row each
+// ends up holding (its position before the panel's interchanges), and their
+// count.
+constexpr int kMetaSwp = 0, kMetaPos = 64, kMetaSrc = 192, kMetaCount = 320;
+
 __global__ __launch_bounds__(64) void k_calu_clear(int32_t *dinfo) {
     if (threadIdx.x == 0) *dinfo = 0;
 }
@@ -38,11 +44,14 @@ __global__ __launch_bounds__(64) void k_calu_clear(int32_t *dinfo) {
 // an interchange has filled with another row (the displaced list, nd
 // entries); every other position holds its own row.  Step i finds where
 // piv[i] sits by a ballot over both, exchanges it with position i and
-// records the row it displaces.  ipiv_out[i] = k + swp[i].  dinfo <- k +
-// pinfo on the first panel whose U has an exactly zero diagonal entry.
+// records the row it displaces.  ipiv_out[i] = k + swp[i].  The touched
+// positions and the rows they end up holding go to meta (see CaluMeta) for
+// the row exchange.  dinfo <- k + pinfo on the first panel whose U has an
+// exactly zero diagonal entry.
 __global__ __launch_bounds__(64) void k_calu_swaps(const int64_t *__restrict__ piv, int b, int64_t k,
-                                                   int32_t *__restrict__ swp, int64_t *__restrict__ ipiv_out,
+                                                   int32_t *__restrict__ meta, int64_t *__restrict__ ipiv_out,
                                                    const int32_t *__restrict__ pinfo, int32_t *__restrict__ dinfo) {
+    int32_t *__restrict__ swp = meta + kMetaSwp;
     const int t = threadIdx.x;
     __shared__ int64_t pv[kLuPanel];
     if (t < b) pv[t] = piv[t];
@@ -86,42 +95,50 @@ __global__ __launch_bounds__(64) void k_calu_swaps(const int64_t *__restrict__ p
     if (t < b) {
         swp[t] = (int32_t)mine;
         ipiv_out[t] = k + mine;
+        meta[kMetaPos + t] = t;
+        meta[kMetaSrc + t] = (int32_t)top;
     }
+    if (t < nd) {
+        meta[kMetaPos + b + t] = (int32_t)dpos;
+        meta[kMetaSrc + b + t] = (int32_t)drow;
+    }
+    if (t == 0) meta[kMetaCount] = b + nd;
     if (t == 0) {
         const int32_t pi = *pinfo;
         if (pi > 0 && *dinfo == 0) *dinfo = (int32_t)(k + pi);
     }
 }
 
-// Columns outside [k, k + b): rows k + i and k + swp[i] exchanged, i = 0..b-1.
+// Columns outside [k, k + b): the interchanges as one gather per column
+// (the touched positions take the rows recorded for them; all loads of a
+// column are issued before its stores).  Four columns per workgroup, one
+// wave each, two touched positions per lane.
 __global__ __launch_bounds__(256) void k_calu_rowswap(double *__restrict__ A, int64_t lda, int64_t n, int64_t k,
-                                                      int b, const int32_t *__restrict__ swp) {
-    __shared__ int32_t s[kLuPanel];
-    if (threadIdx.x < b) s[threadIdx.x] = swp[threadIdx.x];
-    __syncthreads();
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n - b) return;
+                                                      int b, const int32_t *__restrict__ meta) {
+    const int lane = threadIdx.x & 63;
+    int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int cnt = meta[kMetaCount];
+    const bool live = c < n - b;
     if (c >= k) c += b;
-    double *col = A + c * lda + k;
-    for (int i = 0; i < b; ++i) {
-        const int p = s[i];
-        if (p != i) {
-            const double t = col[i];
-            col[i] = col[p];
-            col[p] = t;
-        }
-    }
+    double *col = A + (live ? c : 0) * lda + k;
+    const bool q0 = live && lane < cnt, q1 = live && lane + 64 < cnt;
+    const int p0 = q0 ? meta[kMetaPos + lane] : 0, p1 = q1 ? meta[kMetaPos + lane + 64] : 0;
+    const double v0 = q0 ? col[meta[kMetaSrc + lane]] : 0.0;
+    const double v1 = q1 ? col[meta[kMetaSrc + lane + 64]] : 0.0;
+    __syncthreads();
+    if (q0) col[p0] = v0;
+    if (q1) col[p1] = v1;
 }
 
 // Panel columns, row rel = 0 .. mr - 1 below row k: the original row o that
 // the interchanges brought to rel (walk them backwards), then U11[rel][j]
 // for rel < b, j >= rel, else L[o][j] (L: mr x b, ld ldl).
 __global__ __launch_bounds__(256) void k_calu_pack(double *__restrict__ A, int64_t lda, int64_t mr, int64_t k,
-                                                   int b, const int32_t *__restrict__ swp,
+                                                   int b, const int32_t *__restrict__ meta,
                                                    const double *__restrict__ L, int64_t ldl,
                                                    const double *__restrict__ U, int64_t ldu) {
     __shared__ int32_t s[kLuPanel];
-    if (threadIdx.x < b) s[threadIdx.x] = swp[threadIdx.x];
+    if (threadIdx.x < b) s[threadIdx.x] = meta[kMetaSwp + threadIdx.x];
     __syncthreads();
     const int64_t rel = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (rel >= mr) return;
@@ -135,10 +152,37 @@ __global__ __launch_bounds__(256) void k_calu_pack(double *__restrict__ A, int64
         dst[j * lda] = (rel < b && j >= rel) ? U[rel + j * ldu] : L[o + j * ldl];
 }
 
+// Step L of the unit-lower forward substitution: y[i] -= y[L] L11(i, L),
+// i > L, with column L of L11 read from LDS into registers, every load
+// issued before the first use (empty asm statements mark the values used
+// in order).  Unrolled by template recursion: every index is a constant.
+template <int L>
+struct UnitSolveStep {
+    __device__ static void run(double (&y)[kLuPanel], const double *Ls, int b) {
+        if (L < b) {
+            constexpr int R = kLuPanel - L - 1;
+            if constexpr (R > 0) {
+                double cv[R];
+#pragma unroll
+                for (int i = 0; i < R; ++i) cv[i] = Ls[kLuPanel * L + L + 1 + i];
+#pragma unroll
+                for (int i = 0; i < R; ++i) asm volatile("" : "+v"(cv[i]));
+#pragma unroll
+                for (int i = 0; i < R; ++i) y[L + 1 + i] = fma(-y[L], cv[i], y[L + 1 + i]);
+            }
+        }
+        UnitSolveStep<L + 1>::run(y, Ls, b);
+    }
+};
+template <>
+struct UnitSolveStep<kLuPanel> {
+    __device__ static void run(double (&)[kLuPanel], const double *, int) {}
+};
+
 // U12 = L11^{-1} A12 for columns c in [k + b, n): one thread per column,
 // L11 (unit lower, rows/columns k .. k + b - 1 of the packed A) in LDS.
-__global__ __launch_bounds__(64) void k_calu_trsm(double *__restrict__ A, int64_t lda, int64_t n, int64_t k,
-                                                  int b) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_calu_trsm(double *__restrict__ A, int64_t lda, int64_t n, int64_t k, int b) {
     __shared__ double Ls[kLuPanel * kLuPanel];   // Ls[64 l + i] = L11(i, l)
     const int t = threadIdx.x;
     for (int l = 0; l < b; ++l) Ls[kLuPanel * l + t] = t < b ? A[(k + t) + (k + l) * lda] : 0.0;
@@ -149,12 +193,7 @@ __global__ __launch_bounds__(64) void k_calu_trsm(double *__restrict__ A, int64_
     double y[kLuPanel];
 #pragma unroll
     for (int i = 0; i < kLuPanel; ++i) y[i] = i < b ? col[i] : 0.0;
-#pragma unroll
-    for (int l = 0; l < kLuPanel; ++l) {
-        if (l >= b) continue;
-#pragma unroll
-        for (int i = l + 1; i < kLuPanel; ++i) y[i] = fma(-y[l], Ls[kLuPanel * l + i], y[i]);
-    }
+    UnitSolveStep<0>::run(y, Ls, b);
 #pragma unroll
     for (int i = 0; i < kLuPanel; ++i)
         if (i < b) col[i] = y[i];
@@ -247,20 +286,20 @@ hipError_t launch_calu_clear(int32_t *dinfo, hipStream_t st) {
 }
 
 hipError_t launch_calu_panel_rest(double *A, int64_t lda, int64_t m, int64_t n, int64_t k, int b,
-                                  const int64_t *piv, int32_t *swp, int64_t *ipiv_out, const int32_t *pinfo,
+                                  const int64_t *piv, int32_t *meta, int64_t *ipiv_out, const int32_t *pinfo,
                                   int32_t *dinfo, const double *L, int64_t ldl, const double *U, int64_t ldu,
                                   hipStream_t st) {
     if (b < 1 || b > kLuPanel) return hipErrorInvalidValue;
     {
         ProfScope ps("calu_swaps", st);
-        hipLaunchKernelGGL(k_calu_swaps, dim3(1), dim3(64), 0, st, piv, b, k, swp, ipiv_out + k, pinfo, dinfo);
+        hipLaunchKernelGGL(k_calu_swaps, dim3(1), dim3(64), 0, st, piv, b, k, meta, ipiv_out + k, pinfo, dinfo);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n > b) {
         ProfScope ps("calu_rowswap", st);
-        hipLaunchKernelGGL(k_calu_rowswap, dim3((unsigned)((n - b + 255) / 256)), dim3(256), 0, st, A, lda, n, k,
-                           b, swp);
+        hipLaunchKernelGGL(k_calu_rowswap, dim3((unsigned)((n - b + 3) / 4)), dim3(256), 0, st, A, lda, n, k, b,
+                           meta);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -268,7 +307,7 @@ hipError_t launch_calu_panel_rest(double *A, int64_t lda, int64_t m, int64_t n, 
         ProfScope ps("calu_pack", st);
         const int64_t mr = m - k;
         hipLaunchKernelGGL(k_calu_pack, dim3((unsigned)((mr + 255) / 256)), dim3(256), 0, st, A, lda, mr, k, b,
-                           swp, L, ldl, U, ldu);
+                           meta, L, ldl, U, ldu);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

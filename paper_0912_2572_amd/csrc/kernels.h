@@ -205,11 +205,13 @@ hipError_t launch_tslu(const double *A, int64_t lda, const PanelArgs &pa, const 
 
 // CALU pieces: clear the info word; after a panel's TSLU (pivot rows piv,
 // L (mr x b, ld ldl), U (b x b, ld ldu), its info word pinfo): the row
-// interchanges (swp, ipiv_out[k..k+b-1]), their application outside the
-// panel, the packed panel, U12 and the trailing update.
+// interchanges (meta: kCaluMetaWords int32 of device scratch;
+// ipiv_out[k..k+b-1]), their application outside the panel, the packed
+// panel, U12 and the trailing update.
+constexpr int kCaluMetaWords = 324;
 hipError_t launch_calu_clear(int32_t *dinfo, hipStream_t st);
 hipError_t launch_calu_panel_rest(double *A, int64_t lda, int64_t m, int64_t n, int64_t k, int b,
-                                  const int64_t *piv, int32_t *swp, int64_t *ipiv_out, const int32_t *pinfo,
+                                  const int64_t *piv, int32_t *meta, int64_t *ipiv_out, const int32_t *pinfo,
                                   int32_t *dinfo, const double *L, int64_t ldl, const double *U, int64_t ldu,
                                   hipStream_t st);
 
