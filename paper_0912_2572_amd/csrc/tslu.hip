@@ -281,32 +281,70 @@ __global__ __launch_bounds__(256) void k_tslu_tree(const double *__restrict__ A,
 // U and the unit lower L11 of A[ipiv, :] by elimination without pivoting:
 // thread i owns row i; row j is final after step j - 1.  info: the first
 // zero U_jj (1-based), else 0.
-__global__ __launch_bounds__(64) void k_tslu_u(const double *__restrict__ A, int64_t lda, int b,
-                                               const int32_t *__restrict__ cand, int64_t *__restrict__ ipiv,
-                                               double *__restrict__ U, int64_t ldu, double *__restrict__ L11,
-                                               int32_t *__restrict__ dinfo) {
-    __shared__ double M[64][65];
+// Step J of the no-pivot LU of the pivot block: lane i holds row i in m;
+// lane J publishes row J's entries past J in LDS (double-buffered by step
+// parity) and every lane reads them back in one batch (all loads issued
+// before the first use); rows below J divide by the pivot and update their
+// entries past J.  A zero pivot skips the step and records info.  Unrolled
+// by template recursion so that every register index is a constant.
+template <int J>
+struct NoPivotStep {
+    __device__ static void run(double (&m)[64], double (&row)[2][64], int i, int b, int &info) {
+        if (J < b) {
+            const double piv = wave_bcast(m[J], J);
+            if (piv == 0.0) {
+                if (!info) info = J + 1;
+            } else {
+                constexpr int R = 63 - J;
+                if (i == J) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) row[J & 1][J + 1 + q] = m[J + 1 + q];
+                }
+                __syncthreads();
+                const bool below = i > J && i < b;
+                const double l = below ? m[J] / piv : 0.0;
+                if (below) m[J] = l;
+                if constexpr (R > 0) {
+                    double cv[R];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) cv[q] = row[J & 1][J + 1 + q];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) asm volatile("" : "+v"(cv[q]));
+                    if (below) {
+#pragma unroll
+                        for (int q = 0; q < R; ++q) m[J + 1 + q] = fma(-l, cv[q], m[J + 1 + q]);
+                    }
+                }
+            }
+        }
+        NoPivotStep<J + 1>::run(m, row, i, b, info);
+    }
+};
+template <>
+struct NoPivotStep<64> {
+    __device__ static void run(double (&)[64], double (&)[2][64], int, int, int &) {}
+};
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_tslu_u(const double *__restrict__ A, int64_t lda, int b, const int32_t *__restrict__ cand,
+              int64_t *__restrict__ ipiv, double *__restrict__ U, int64_t ldu, double *__restrict__ L11,
+              int32_t *__restrict__ dinfo) {
+    __shared__ double row[2][64];
     const int i = threadIdx.x;
     const int32_t gi = (i < b) ? cand[i] : 0;
     if (i < b) ipiv[i] = gi;
-    for (int k = 0; k < b; ++k) M[i][k] = (i < b) ? A[gi + (int64_t)k * lda] : 0.0;
-    __syncthreads();
+    double m[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) m[k] = (i < b && k < b) ? A[gi + (int64_t)k * lda] : 0.0;
     int info = 0;
-    for (int j = 0; j < b; ++j) {
-        const double piv = M[j][j];
-        if (piv == 0.0) {
-            if (!info) info = j + 1;
-        } else if (i > j && i < b) {
-            const double l = M[i][j] / piv;
-            M[i][j] = l;
-            for (int k = j + 1; k < b; ++k) M[i][k] = fma(-l, M[j][k], M[i][k]);
-        }
-        __syncthreads();
-    }
+    NoPivotStep<0>::run(m, row, i, b, info);
     if (i < b) {
-        for (int k = 0; k < b; ++k) {
-            U[i + (int64_t)k * ldu] = (i <= k) ? M[i][k] : 0.0;
-            L11[i + (int64_t)k * 64] = (k < i) ? M[i][k] : (k == i ? 1.0 : 0.0);
+#pragma unroll
+        for (int k = 0; k < 64; ++k) {
+            if (k < b) {
+                U[i + (int64_t)k * ldu] = (i <= k) ? m[k] : 0.0;
+                L11[i + (int64_t)k * 64] = (k < i) ? m[k] : (k == i ? 1.0 : 0.0);
+            }
         }
     }
     if (i == 0 && dinfo) *dinfo = info;
