@@ -11,7 +11,8 @@
 //                 candidates on the next 256 - b rows), the flat tree of
 //                 the TSQR leaf's chunks;
 //   k_tslu_tree   one workgroup per chain of a tree level (the TSQR tree's
-//                 shapes): the left's candidates stacked on each right's;
+//                 shapes): the left's candidates stacked on each right's,
+//                 one thread per stack row (two waves);
 //   k_tslu_u      U and the unit lower L11 of A[ipiv, :] without pivoting;
 //   k_tslu_l      l_i = a_i U^{-1} for every row (one row per thread);
 //   k_tslu_scatter  rows ipiv[k] of L <- row k of L11.
@@ -254,26 +255,128 @@ __global__ __launch_bounds__(256) void k_tslu_leaf(const double *__restrict__ A,
     if (t < b) cand[dom * b + t] = sm.gidx[t];
 }
 
-__global__ __launch_bounds__(256) void k_tslu_tree(const double *__restrict__ A, int64_t lda, PanelArgs pa,
-                                                   TreeArgs ta, int b, int32_t *__restrict__ cand) {
-    __shared__ TsluSmem sm;
+// The tree's stacks hold two candidate sets (2b <= 128 rows): one thread
+// per stack row, two waves, the row's 64 entries in registers.  Step J:
+//   each wave's argmax of |a_iJ| over its live rows (a NaN ranks below
+//   every number, ties go to the lower position: the pivot_column rules)
+//   by DPP inside each 16-lane row and lane reads across the four rows; the
+//   wave's winner puts its row past J in LDS (one buffer per wave, double-
+//   buffered by step parity) with its key; one barrier; every thread takes
+//   the better of the two waves' winners, reads that row in one batch and
+//   updates its entries past J with l = a_iJ / a_pJ (one reciprocal, as in
+//   pivot_column: the multipliers only steer the selection).
+struct TreeSelSmem {
+    double prow[2][2][64];   // [wave][parity][column]
+    double key[2][2];        // [wave][parity]
+    double val[2][2];
+    int32_t pos[2][2];
+    int32_t gidx[128];
+    int32_t sel[64];
+};
+
+template <int J>
+struct TreeSelStep {
+    __device__ __forceinline__ static void run(TreeSelSmem &sm, double (&m)[64], bool &live, int b) {
+        if (J < b) {
+            const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+            constexpr int par = J & 1;
+            double best = -1.0, bv = 0.0;
+            int bp = 1 << 30;
+            if (live) {
+                double key = fabs(m[J]);
+                if (key != key) key = -0.5;
+                best = key;
+                bp = t;
+                bv = m[J];
+            }
+            argmax_step<kDppXor1>(best, bp, bv);
+            argmax_step<kDppXor2>(best, bp, bv);
+            argmax_step<0x124>(best, bp, bv);
+            argmax_step<kDppRowRor8>(best, bp, bv);
+            // the four 16-lane rows' winners, lowest position first on ties
+#pragma unroll
+            for (int rr = 1; rr < 4; ++rr) {
+                const double ok = wave_bcast(best, 16 * rr);
+                const int op = __builtin_amdgcn_readlane(bp, 16 * rr);
+                const double ov = wave_bcast(bv, 16 * rr);
+                argmax_take(best, bp, bv, ok, op, ov);
+            }
+            best = wave_bcast(best, 0);
+            bp = __builtin_amdgcn_readfirstlane(bp);
+            bv = wave_bcast(bv, 0);
+            constexpr int R = 63 - J;
+            if (t == bp) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) sm.prow[w][par][J + 1 + q] = m[J + 1 + q];
+            }
+            if (lane == 0) {
+                sm.key[w][par] = best;
+                sm.val[w][par] = bv;
+                sm.pos[w][par] = bp;
+            }
+            __syncthreads();
+            const double k1 = sm.key[1][par];
+            const int p1 = sm.pos[1][par];
+            const double v1 = sm.val[1][par];
+            double kb = sm.key[0][par], vb = sm.val[0][par];
+            int pb = sm.pos[0][par];
+            argmax_take(kb, pb, vb, k1, p1, v1);
+            const int src = pb >> 6;
+            if (t == 0) sm.sel[J] = pb;
+            const double rv = (vb != 0.0) ? 1.0 / vb : 0.0;
+            const bool upd = live && t != pb;
+            const double l = upd ? m[J] * rv : 0.0;
+            if (t == pb) live = false;
+            // the pivot row in batches of at most 32 entries (registers)
+            const double *pr = sm.prow[src][par];
+            constexpr int R1 = R < 32 ? R : 32, R2 = R - R1;
+            if constexpr (R1 > 0) {
+                double cv[R1];
+#pragma unroll
+                for (int q = 0; q < R1; ++q) cv[q] = pr[J + 1 + q];
+#pragma unroll
+                for (int q = 0; q < R1; ++q) asm volatile("" : "+v"(cv[q]));
+#pragma unroll
+                for (int q = 0; q < R1; ++q) m[J + 1 + q] = fma(-l, cv[q], m[J + 1 + q]);
+            }
+            if constexpr (R2 > 0) {
+                double cv[R2];
+#pragma unroll
+                for (int q = 0; q < R2; ++q) cv[q] = pr[J + 1 + R1 + q];
+#pragma unroll
+                for (int q = 0; q < R2; ++q) asm volatile("" : "+v"(cv[q]));
+#pragma unroll
+                for (int q = 0; q < R2; ++q) m[J + 1 + R1 + q] = fma(-l, cv[q], m[J + 1 + R1 + q]);
+            }
+        }
+        TreeSelStep<J + 1>::run(sm, m, live, b);
+    }
+};
+template <>
+struct TreeSelStep<64> {
+    __device__ __forceinline__ static void run(TreeSelSmem &, double (&)[64], bool &, int) {}
+};
+
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_tslu_tree(const double *__restrict__ A, int64_t lda, PanelArgs pa, TreeArgs ta, int b,
+                 int32_t *__restrict__ cand) {
+    __shared__ TreeSelSmem sm;
     const int64_t g = blockIdx.x;
     const int64_t left = (g / ta.width) * ta.span + g % ta.width;
     if (left >= pa.P) return;
     const int t = threadIdx.x;
-    double a[4][16];
-    uint32_t act;
     for (int64_t q = 1; q * ta.stride < ta.span && left + q * ta.stride < pa.P; ++q) {
         const int64_t right = left + q * ta.stride;
-        if (t < b) {
-            sm.gidx[t] = cand[left * b + t];
-            sm.gidx[b + t] = cand[right * b + t];
-        }
+        if (t < 2 * b) sm.gidx[t] = (t < b) ? cand[left * b + t] : cand[right * b + (t - b)];
         __syncthreads();
-        load_stack(sm, A, lda, 2 * b, b, a, act);
-        gepp_steps(sm, a, act, 2 * b, b);
-        keep_selection(sm, 2 * b, b);
-        if (t < b) cand[left * b + t] = sm.gidx[t];
+        bool live = t < 2 * b;
+        const double *src = A + (live ? sm.gidx[t] : 0);
+        double m[64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) m[k] = (live && k < b) ? src[(int64_t)k * lda] : 0.0;
+        TreeSelStep<0>::run(sm, m, live, b);
+        __syncthreads();
+        if (t < b) cand[left * b + t] = sm.gidx[sm.sel[t]];
         __syncthreads();
     }
 }
@@ -400,7 +503,7 @@ hipError_t launch_tslu(const double *A, int64_t lda, const PanelArgs &pa, const 
     }
     for (const TreeArgs &ta : levels) {
         ProfScope ps("tslu_tree", st);
-        hipLaunchKernelGGL(k_tslu_tree, dim3((unsigned)ta.chains), dim3(256), 0, st, A, lda, pa, ta, b, cand);
+        hipLaunchKernelGGL(k_tslu_tree, dim3((unsigned)ta.chains), dim3(128), 0, st, A, lda, pa, ta, b, cand);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
