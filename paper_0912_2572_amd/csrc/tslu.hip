@@ -9,7 +9,7 @@
 //   k_tslu_leaf   one workgroup per domain: the domain's rows in stages of
 //                 one 256-row stack each (its first 256 rows, then its b
 //                 candidates on the next 256 - b rows), the flat tree of
-//                 the TSQR leaf's chunks;
+//                 the TSQR leaf's chunks, one thread per stack row;
 //   k_tslu_tree   one workgroup per chain of a tree level (the TSQR tree's
 //                 shapes): the left's candidates stacked on each right's,
 //                 one thread per stack row (two waves);
@@ -17,12 +17,13 @@
 //   k_tslu_l      l_i = a_i U^{-1} for every row (one row per thread);
 //   k_tslu_scatter  rows ipiv[k] of L <- row k of L11.
 //
-// Stack layout (256 threads): thread t holds the stack positions 16 i +
-// (t & 15), i = 0..15, of the four columns 4 (t >> 4) .. +3, so the 16 lanes
-// holding a column form one 16-lane row of one wave: the pivot search is a
-// DPP reduction in that row, the pivot row's entries come from a lane of the
-// thread's own row by DPP broadcast, and only the multipliers of the step
-// go through LDS (double-buffered: one barrier per elimination step).
+// Stack layout: thread t holds stack position t (row gidx[t] of A), its b
+// entries in registers; a 256-row stack takes four waves, a tree node's
+// 2b-row stack two.  An elimination step: each wave's pivot search by DPP
+// and lane reads, the waves' winners (key, position, value and the pivot
+// row past the step's column) through LDS with one barrier, then every
+// live row's multiplier and the update of its entries past the column, the
+// pivot row read back in batches of 32 entries.
 #include "common.h"
 #include "kernels.h"
 #include "prof.h"
@@ -32,21 +33,6 @@ namespace tsqr {
 namespace {
 
 constexpr int kStack = 256;
-
-struct TsluSmem {
-    double l[2][kStack];     // multipliers of the step (by step parity)
-    int32_t gidx[kStack];    // row of A at each stack position
-    int32_t sel[64];         // stack positions of the pivots, in order
-    int32_t piv[2];          // pivot position of the step (by step parity)
-};
-
-typedef double Rows16[16];   // the 16 stack rows one thread holds of one column
-
-// Lane l of a 16-lane row <- lane N of that row (DPP row_newbcast).
-template <int N>
-__device__ __forceinline__ double row_bcast(double v) {
-    return dpp_f64<0x150 + N>(v);
-}
 
 // (value, position) pairs: the larger value wins, equal values go to the
 // lower position.
@@ -64,219 +50,30 @@ __device__ __forceinline__ void argmax_step(double &best, int &bp, double &bv) {
                 dpp_f64<CTRL>(bv));
 }
 
-// Loads the stack: position q = 16 i + r (r = lane in its 16-lane row, i =
-// slot) holds row gidx[q] of A for q < rows, so the 16 lanes of a row read
-// 16 consecutive positions of a column per load; columns past b and
-// positions past rows are zero.  act: bit i set when slot i is live.  Every
-// load is issued before any is used (addresses clamped into A).
-__device__ __forceinline__ void load_stack(const TsluSmem &sm, const double *__restrict__ A, int64_t lda,
-                                           int rows, int b, Rows16 (&a)[4], uint32_t &act) {
-    const int t = threadIdx.x, cg = t >> 4, r = t & 15;
-    int64_t g[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int q = 16 * i + r;
-        g[i] = q < rows ? sm.gidx[q] : 0;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int64_t co = (int64_t)(4 * cg + c < b ? 4 * cg + c : 0) * lda;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) a[c][i] = A[g[i] + co];
-    }
-    act = 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const bool live = 16 * i + r < rows;
-        if (live) act |= 1u << i;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (!live || 4 * cg + c >= b) a[c][i] = 0.0;
-    }
-}
-
-// The pivot search and the multipliers of column j (column JC of this
-// lane's four) in the 16 lanes holding it; the column index is a template
-// argument so that every register access is static.
-template <int JC>
-__device__ __forceinline__ void pivot_column(TsluSmem &sm, const Rows16 (&a)[4], uint32_t act, int j, int par) {
-    const int r = threadIdx.x & 15;
-    double best = -1.0, bv = 0.0;
-    int bp = 1 << 30;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        double key = fabs(a[JC][i]);
-        if (key != key) key = -0.5;
-        if (((act >> i) & 1u) && key > best) {
-            best = key;
-            bp = 16 * i + r;
-            bv = a[JC][i];
-        }
-    }
-    argmax_step<kDppXor1>(best, bp, bv);
-    argmax_step<kDppXor2>(best, bp, bv);
-    argmax_step<0x124>(best, bp, bv);   // row_ror:4: the next quad's winner
-    argmax_step<kDppRowRor8>(best, bp, bv);
-    // the multipliers only steer the selection (U and L are computed from
-    // the chosen rows afterwards): one reciprocal instead of 16 divisions
-    const double rv = (bv != 0.0) ? 1.0 / bv : 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int q = 16 * i + r;
-        const bool live = ((act >> i) & 1u) && q != bp;
-        sm.l[par][q] = live ? a[JC][i] * rv : 0.0;
-    }
-    if (r == 0) {
-        sm.piv[par] = bp;
-        sm.sel[j] = bp;
-    }
-}
-
-// u[c] = a[c][K]: one case of a branch on the wave-uniform slot index.
-template <int K>
-__device__ __forceinline__ void take_slot(const Rows16 (&a)[4], double (&u)[4]) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) u[c] = a[c][K];
-}
-
-template <int N>
-__device__ __forceinline__ void bcast_from(double (&u)[4]) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) u[c] = row_bcast<N>(u[c]);
-}
-
-// min(b, rows) steps of partial-pivoting elimination on the stack; the
-// pivot positions go to sm.sel.  Ties go to the lower stack position; a
-// NaN ranks below every number (a column of NaNs takes its first live row);
-// a zero pivot eliminates nothing.  Entries of columns <= j keep being
-// updated after their step (never read again), so every column takes the
-// same update and no lane branches on its column.  The pivot row's entries
-// come from the lane of the thread's own 16-lane row that holds it: a
-// branch on the (wave-uniform) slot picks the register, a DPP broadcast
-// moves it.
-__device__ __forceinline__ void gepp_steps(TsluSmem &sm, Rows16 (&a)[4], uint32_t act, int rows, int b) {
-    const int t = threadIdx.x, cg = t >> 4, r = t & 15;
-    const int kb = b < rows ? b : rows;
-    for (int j = 0; j < kb; ++j) {
-        const int par = j & 1;
-        if (cg == (j >> 2)) {
-            switch (j & 3) {
-                case 0: pivot_column<0>(sm, a, act, j, par); break;
-                case 1: pivot_column<1>(sm, a, act, j, par); break;
-                case 2: pivot_column<2>(sm, a, act, j, par); break;
-                default: pivot_column<3>(sm, a, act, j, par); break;
-            }
-        }
-        __syncthreads();
-        const int p = __builtin_amdgcn_readfirstlane(sm.piv[par]);
-        const int slot = p >> 4, src = p & 15;
-        double u[4];
-        switch (slot) {
-            case 0: take_slot<0>(a, u); break;
-            case 1: take_slot<1>(a, u); break;
-            case 2: take_slot<2>(a, u); break;
-            case 3: take_slot<3>(a, u); break;
-            case 4: take_slot<4>(a, u); break;
-            case 5: take_slot<5>(a, u); break;
-            case 6: take_slot<6>(a, u); break;
-            case 7: take_slot<7>(a, u); break;
-            case 8: take_slot<8>(a, u); break;
-            case 9: take_slot<9>(a, u); break;
-            case 10: take_slot<10>(a, u); break;
-            case 11: take_slot<11>(a, u); break;
-            case 12: take_slot<12>(a, u); break;
-            case 13: take_slot<13>(a, u); break;
-            case 14: take_slot<14>(a, u); break;
-            default: take_slot<15>(a, u); break;
-        }
-        switch (src) {
-            case 0: bcast_from<0>(u); break;
-            case 1: bcast_from<1>(u); break;
-            case 2: bcast_from<2>(u); break;
-            case 3: bcast_from<3>(u); break;
-            case 4: bcast_from<4>(u); break;
-            case 5: bcast_from<5>(u); break;
-            case 6: bcast_from<6>(u); break;
-            case 7: bcast_from<7>(u); break;
-            case 8: bcast_from<8>(u); break;
-            case 9: bcast_from<9>(u); break;
-            case 10: bcast_from<10>(u); break;
-            case 11: bcast_from<11>(u); break;
-            case 12: bcast_from<12>(u); break;
-            case 13: bcast_from<13>(u); break;
-            case 14: bcast_from<14>(u); break;
-            default: bcast_from<15>(u); break;
-        }
-        if (src == r) act &= ~(1u << slot);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const double li = sm.l[par][16 * i + r];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) a[c][i] = fma(-li, u[c], a[c][i]);
-        }
-    }
-}
-
-// After gepp_steps: gidx[0 .. kb-1] <- the chosen rows in pivot order.
-__device__ __forceinline__ int keep_selection(TsluSmem &sm, int rows, int b) {
-    const int kb = b < rows ? b : rows;
-    __syncthreads();
-    const int t = threadIdx.x;
-    const int32_t g = (t < kb) ? sm.gidx[sm.sel[t]] : 0;
-    __syncthreads();
-    if (t < kb) sm.gidx[t] = g;
-    return kb;
-}
-
-}  // namespace
-
-__global__ __launch_bounds__(256) void k_tslu_leaf(const double *__restrict__ A, int64_t lda, PanelArgs pa,
-                                                   int b, int32_t *__restrict__ cand) {
-    __shared__ TsluSmem sm;
-    const int64_t dom = blockIdx.x;
-    const int64_t row0 = dom_row0(pa, dom), end = row0 + dom_rows(pa, dom);
-    const int t = threadIdx.x;
-    double a[4][16];
-    uint32_t act;
-    int64_t pos = row0;
-    int nc = 0;
-    while (pos < end) {
-        const int room = kStack - (nc ? b : 0);
-        const int take = (int)((end - pos < room) ? end - pos : room);
-        if (t >= nc && t < nc + take) sm.gidx[t] = (int32_t)(pos + (t - nc));
-        __syncthreads();
-        const int rows = nc + take;
-        load_stack(sm, A, lda, rows, b, a, act);
-        gepp_steps(sm, a, act, rows, b);
-        nc = keep_selection(sm, rows, b);
-        pos += take;
-        __syncthreads();
-    }
-    if (t < b) cand[dom * b + t] = sm.gidx[t];
-}
-
-// The tree's stacks hold two candidate sets (2b <= 128 rows): one thread
-// per stack row, two waves, the row's 64 entries in registers.  Step J:
+// Step J of partial-pivoting elimination on a stack of W waves, one thread
+// per stack row, the row's entries in m:
 //   each wave's argmax of |a_iJ| over its live rows (a NaN ranks below
-//   every number, ties go to the lower position: the pivot_column rules)
-//   by DPP inside each 16-lane row and lane reads across the four rows; the
-//   wave's winner puts its row past J in LDS (one buffer per wave, double-
-//   buffered by step parity) with its key; one barrier; every thread takes
-//   the better of the two waves' winners, reads that row in one batch and
-//   updates its entries past J with l = a_iJ / a_pJ (one reciprocal, as in
-//   pivot_column: the multipliers only steer the selection).
-struct TreeSelSmem {
-    double prow[2][2][64];   // [wave][parity][column]
-    double key[2][2];        // [wave][parity]
-    double val[2][2];
-    int32_t pos[2][2];
-    int32_t gidx[128];
+//   every number, ties go to the lower stack position) by DPP inside each
+//   16-lane row and lane reads across the four rows; the wave's winner puts
+//   its row past J in LDS (one buffer per wave, double-buffered by step
+//   parity) with its key; one barrier; every thread takes the best of the W
+//   winners, reads that row back and updates its entries past J with
+//   l = a_iJ * (1 / a_pJ) (one reciprocal: the multipliers only steer the
+//   selection; U and L are computed from the chosen rows afterwards); a
+//   zero pivot eliminates nothing.
+template <int W>
+struct RowSelSmem {
+    double prow[W][2][64];   // [wave][parity][column]
+    double key[W][2];        // [wave][parity]
+    double val[W][2];
+    int32_t pos[W][2];
+    int32_t gidx[64 * W];
     int32_t sel[64];
 };
 
-template <int J>
-struct TreeSelStep {
-    __device__ __forceinline__ static void run(TreeSelSmem &sm, double (&m)[64], bool &live, int b) {
+template <int W, int J>
+struct RowSelStep {
+    __device__ __forceinline__ static void run(RowSelSmem<W> &sm, double (&m)[64], bool &live, int b) {
         if (J < b) {
             const int t = threadIdx.x, w = t >> 6, lane = t & 63;
             constexpr int par = J & 1;
@@ -315,12 +112,10 @@ struct TreeSelStep {
                 sm.pos[w][par] = bp;
             }
             __syncthreads();
-            const double k1 = sm.key[1][par];
-            const int p1 = sm.pos[1][par];
-            const double v1 = sm.val[1][par];
             double kb = sm.key[0][par], vb = sm.val[0][par];
             int pb = sm.pos[0][par];
-            argmax_take(kb, pb, vb, k1, p1, v1);
+#pragma unroll
+            for (int u = 1; u < W; ++u) argmax_take(kb, pb, vb, sm.key[u][par], sm.pos[u][par], sm.val[u][par]);
             const int src = pb >> 6;
             if (t == 0) sm.sel[J] = pb;
             const double rv = (vb != 0.0) ? 1.0 / vb : 0.0;
@@ -349,18 +144,61 @@ struct TreeSelStep {
                 for (int q = 0; q < R2; ++q) m[J + 1 + R1 + q] = fma(-l, cv[q], m[J + 1 + R1 + q]);
             }
         }
-        TreeSelStep<J + 1>::run(sm, m, live, b);
+        RowSelStep<W, J + 1>::run(sm, m, live, b);
     }
 };
-template <>
-struct TreeSelStep<64> {
-    __device__ __forceinline__ static void run(TreeSelSmem &, double (&)[64], bool &, int) {}
+template <int W>
+struct RowSelStep<W, 64> {
+    __device__ __forceinline__ static void run(RowSelSmem<W> &, double (&)[64], bool &, int) {}
 };
+
+// One stack of `rows` rows (sm.gidx) on W waves, one thread per row: the
+// kb = min(b, rows) selection steps, then gidx[0 .. kb-1] <- the chosen
+// rows in pivot order.  Returns kb.
+template <int W>
+__device__ __forceinline__ int select_stack(RowSelSmem<W> &sm, const double *__restrict__ A, int64_t lda,
+                                            int rows, int b) {
+    const int t = threadIdx.x;
+    bool live = t < rows;
+    const double *src = A + (live ? sm.gidx[t] : 0);
+    double m[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) m[k] = (live && k < b) ? src[(int64_t)k * lda] : 0.0;
+    const int kb = b < rows ? b : rows;
+    RowSelStep<W, 0>::run(sm, m, live, kb);
+    __syncthreads();
+    const int32_t g = (t < kb) ? sm.gidx[sm.sel[t]] : 0;
+    __syncthreads();
+    if (t < kb) sm.gidx[t] = g;
+    return kb;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_tslu_leaf(const double *__restrict__ A, int64_t lda, PanelArgs pa, int b, int32_t *__restrict__ cand) {
+    __shared__ RowSelSmem<4> sm;
+    const int64_t dom = blockIdx.x;
+    const int64_t row0 = dom_row0(pa, dom), end = row0 + dom_rows(pa, dom);
+    const int t = threadIdx.x;
+    int64_t pos = row0;
+    int nc = 0;
+    while (pos < end) {
+        const int room = kStack - (nc ? b : 0);
+        const int take = (int)((end - pos < room) ? end - pos : room);
+        if (t >= nc && t < nc + take) sm.gidx[t] = (int32_t)(pos + (t - nc));
+        __syncthreads();
+        nc = select_stack<4>(sm, A, lda, nc + take, b);
+        pos += take;
+        __syncthreads();
+    }
+    if (t < b) cand[dom * b + t] = sm.gidx[t];
+}
 
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_tslu_tree(const double *__restrict__ A, int64_t lda, PanelArgs pa, TreeArgs ta, int b,
                  int32_t *__restrict__ cand) {
-    __shared__ TreeSelSmem sm;
+    __shared__ RowSelSmem<2> sm;
     const int64_t g = blockIdx.x;
     const int64_t left = (g / ta.width) * ta.span + g % ta.width;
     if (left >= pa.P) return;
@@ -369,14 +207,8 @@ void k_tslu_tree(const double *__restrict__ A, int64_t lda, PanelArgs pa, TreeAr
         const int64_t right = left + q * ta.stride;
         if (t < 2 * b) sm.gidx[t] = (t < b) ? cand[left * b + t] : cand[right * b + (t - b)];
         __syncthreads();
-        bool live = t < 2 * b;
-        const double *src = A + (live ? sm.gidx[t] : 0);
-        double m[64];
-#pragma unroll
-        for (int k = 0; k < 64; ++k) m[k] = (live && k < b) ? src[(int64_t)k * lda] : 0.0;
-        TreeSelStep<0>::run(sm, m, live, b);
-        __syncthreads();
-        if (t < b) cand[left * b + t] = sm.gidx[sm.sel[t]];
+        select_stack<2>(sm, A, lda, 2 * b, b);
+        if (t < b) cand[left * b + t] = sm.gidx[t];
         __syncthreads();
     }
 }
