@@ -44,6 +44,32 @@ __device__ __forceinline__ void argmax_take(double &best, int &bp, double &bv, d
     }
 }
 
+// (best, bp, bv) of lanes l and l ^ 16 (permlane16_swap returns both of a
+// pair's values to each lane), the better kept by both.
+__device__ __forceinline__ void argmax_swap16(double &best, int &bp, double &bv) {
+    const auto kl = __builtin_amdgcn_permlane16_swap(__double2loint(best), __double2loint(best), false, false);
+    const auto kh = __builtin_amdgcn_permlane16_swap(__double2hiint(best), __double2hiint(best), false, false);
+    const auto pp = __builtin_amdgcn_permlane16_swap(bp, bp, false, false);
+    const auto vl = __builtin_amdgcn_permlane16_swap(__double2loint(bv), __double2loint(bv), false, false);
+    const auto vh = __builtin_amdgcn_permlane16_swap(__double2hiint(bv), __double2hiint(bv), false, false);
+    best = __hiloint2double(kh[0], kl[0]);
+    bp = (int)pp[0];
+    bv = __hiloint2double(vh[0], vl[0]);
+    argmax_take(best, bp, bv, __hiloint2double(kh[1], kl[1]), (int)pp[1], __hiloint2double(vh[1], vl[1]));
+}
+// The same for lanes l and l ^ 32.
+__device__ __forceinline__ void argmax_swap32(double &best, int &bp, double &bv) {
+    const auto kl = __builtin_amdgcn_permlane32_swap(__double2loint(best), __double2loint(best), false, false);
+    const auto kh = __builtin_amdgcn_permlane32_swap(__double2hiint(best), __double2hiint(best), false, false);
+    const auto pp = __builtin_amdgcn_permlane32_swap(bp, bp, false, false);
+    const auto vl = __builtin_amdgcn_permlane32_swap(__double2loint(bv), __double2loint(bv), false, false);
+    const auto vh = __builtin_amdgcn_permlane32_swap(__double2hiint(bv), __double2hiint(bv), false, false);
+    best = __hiloint2double(kh[0], kl[0]);
+    bp = (int)pp[0];
+    bv = __hiloint2double(vh[0], vl[0]);
+    argmax_take(best, bp, bv, __hiloint2double(kh[1], kl[1]), (int)pp[1], __hiloint2double(vh[1], vl[1]));
+}
+
 template <int CTRL>
 __device__ __forceinline__ void argmax_step(double &best, int &bp, double &bv) {
     argmax_take(best, bp, bv, dpp_f64<CTRL>(best), __builtin_amdgcn_update_dpp(0, bp, CTRL, 0xf, 0xf, false),
@@ -54,7 +80,7 @@ __device__ __forceinline__ void argmax_step(double &best, int &bp, double &bv) {
 // per stack row, the row's entries in m:
 //   each wave's argmax of |a_iJ| over its live rows (a NaN ranks below
 //   every number, ties go to the lower stack position) by DPP inside each
-//   16-lane row and lane reads across the four rows; the wave's winner puts
+//   16-lane row and lane-pair exchanges across the rows; the wave's winner puts
 //   its row past J in LDS (one buffer per wave, double-buffered by step
 //   parity) with its key; one barrier; every thread takes the best of the W
 //   winners, reads that row back and updates its entries past J with
@@ -90,17 +116,12 @@ struct RowSelStep {
             argmax_step<kDppXor2>(best, bp, bv);
             argmax_step<0x124>(best, bp, bv);
             argmax_step<kDppRowRor8>(best, bp, bv);
-            // the four 16-lane rows' winners, lowest position first on ties
-#pragma unroll
-            for (int rr = 1; rr < 4; ++rr) {
-                const double ok = wave_bcast(best, 16 * rr);
-                const int op = __builtin_amdgcn_readlane(bp, 16 * rr);
-                const double ov = wave_bcast(bv, 16 * rr);
-                argmax_take(best, bp, bv, ok, op, ov);
-            }
-            best = wave_bcast(best, 0);
+            // the four 16-lane rows' winners: rows 0|1 and 2|3 exchanged, then
+            // the two halves (the take is symmetric, so every lane ends with
+            // the wave's winner)
+            argmax_swap16(best, bp, bv);
+            argmax_swap32(best, bp, bv);
             bp = __builtin_amdgcn_readfirstlane(bp);
-            bv = wave_bcast(bv, 0);
             constexpr int R = 63 - J;
             if (t == bp) {
 #pragma unroll
