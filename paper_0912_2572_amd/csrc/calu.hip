@@ -148,8 +148,13 @@ __global__ __launch_bounds__(256) void k_calu_pack(double *__restrict__ A, int64
         else if (o == s[i]) o = i;
     }
     double *dst = A + (k + rel) + k * lda;
-    for (int j = 0; j < b; ++j)
-        dst[j * lda] = (rel < b && j >= rel) ? U[rel + j * ldu] : L[o + j * ldl];
+    double v[kLuPanel];
+#pragma unroll
+    for (int j = 0; j < kLuPanel; ++j)
+        v[j] = (j < b) ? ((rel < b && j >= rel) ? U[rel + j * ldu] : L[o + j * ldl]) : 0.0;
+#pragma unroll
+    for (int j = 0; j < kLuPanel; ++j)
+        if (j < b) dst[j * lda] = v[j];
 }
 
 // Step L of the unit-lower forward substitution: y[i] -= y[L] L11(i, L),
