@@ -190,7 +190,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_calu_trsm(double *__restrict__ A, int64_t lda, int64_t n, int64_t k, int b) {
     __shared__ double Ls[kLuPanel * kLuPanel];   // Ls[64 l + i] = L11(i, l)
     const int t = threadIdx.x;
-    for (int l = 0; l < b; ++l) Ls[kLuPanel * l + t] = t < b ? A[(k + t) + (k + l) * lda] : 0.0;
+    {
+        // every load in flight before the LDS stores
+        double v[kLuPanel];
+#pragma unroll
+        for (int l = 0; l < kLuPanel; ++l) v[l] = (t < b && l < b) ? A[(k + t) + (k + l) * lda] : 0.0;
+#pragma unroll
+        for (int l = 0; l < kLuPanel; ++l)
+            if (l < b) Ls[kLuPanel * l + t] = v[l];
+    }
     __syncthreads();
     const int64_t c = k + b + (int64_t)blockIdx.x * kLuPanel + t;
     if (c >= n) return;

@@ -312,9 +312,16 @@ __global__ __launch_bounds__(256) void k_tslu_l(const double *__restrict__ A, in
                                                 const double *__restrict__ U, int64_t ldu, double *__restrict__ L,
                                                 int64_t ldl) {
     __shared__ double Us[64 * 64];
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        Us[e] = (r < b && c < b) ? U[r + (int64_t)c * ldu] : 0.0;
+    {
+        // every load in flight before the LDS stores
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = threadIdx.x + 256 * u, r = e & 63, c = e >> 6;
+            v[u] = (r < b && c < b) ? U[r + (int64_t)c * ldu] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Us[threadIdx.x + 256 * u] = v[u];
     }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
