@@ -9,7 +9,8 @@
 //                  wave (lane t holds row t; column k of L goes through LDS
 //                  and comes back to every lane as broadcasts), then every
 //                  row below the block solved against it, l_i = a_i
-//                  L11^{-T} (one wave per 64 rows, lane = row).  Every workgroup
+//                  L11^{-T} (one wave per 32 rows, a lane pair per row
+//                  splitting its columns by parity).  Every workgroup
 //                  factors the diagonal block itself, so one launch covers
 //                  the panel;
 //   k_chol_update  C -= W W^T on the lower triangle of a trailing block:
@@ -57,10 +58,15 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 // order, with an empty asm statement: every load is then issued before the
 // first use instead of one load in front of each use.
 
+// Column K of L11 in LDS: L(i, K), i != K, at lc_at(K, i) (the even rows,
+// then the odd ones, so that a lane pair's halves are contiguous); 1 /
+// L(K, K) at 64 * 64 + K.
+__host__ __device__ constexpr int lc_at(int K, int i) { return kPanel * K + 32 * (i & 1) + (i >> 1); }
+
 // Factorization step K: lane t holds row t of the diagonal block in m.
 template <int K>
 struct FactorStep {
-    __device__ static void run(double (&m)[kPanel], double *Lc, int t, int sb, int &fail) {
+    __device__ __forceinline__ static void run(double (&m)[kPanel], double *Lc, int t, int sb, int &fail) {
         if (K < sb && fail < 0) {
             const double d = wave_bcast(m[K], K);
             if (!(d > 0.0)) {
@@ -69,13 +75,14 @@ struct FactorStep {
                 const double rinv = rsqrt_f64(d);
                 const double v = t < K ? 0.0 : (t == K ? d * rinv : m[K] * rinv);
                 m[K] = v;
-                Lc[kPanel * K + t] = t == K ? rinv : v;
+                if (t == K) Lc[kPanel * kPanel + K] = rinv;
+                else Lc[lc_at(K, t)] = v;
                 __syncthreads();
                 constexpr int R = kPanel - K - 1;
                 if constexpr (R > 0) {
                     double cv[R];
 #pragma unroll
-                    for (int i = 0; i < R; ++i) cv[i] = Lc[kPanel * K + K + 1 + i];
+                    for (int i = 0; i < R; ++i) cv[i] = Lc[lc_at(K, K + 1 + i)];
 #pragma unroll
                     for (int i = 0; i < R; ++i) asm volatile("" : "+v"(cv[i]));
 #pragma unroll
@@ -88,31 +95,42 @@ struct FactorStep {
 };
 template <>
 struct FactorStep<kPanel> {
-    __device__ static void run(double (&)[kPanel], double *, int, int, int &) {}
+    __device__ __forceinline__ static void run(double (&)[kPanel], double *, int, int, int &) {}
 };
 
-// Solve step K: x[K] <- x[K] / L(K, K), then x[j] -= x[K] L(j, K), j > K.
+// Solve step K on a lane pair: lane h = lane & 1 of the pair holds the
+// columns j = 2 q + h of its row in xh[q].  The owner of column K (h = K & 1)
+// forms x_K = x_K / L(K, K) and passes it to its partner by DPP; each lane
+// then updates its columns past K with column K of L11, its half read from
+// LDS in one batch.
 template <int K>
-struct SolveStep {
-    __device__ static void run(double (&x)[kPanel], const double *Lc, int sb) {
+struct PairSolveStep {
+    __device__ __forceinline__ static void run(double (&xh)[kPanel / 2], const double *Lc, int h, int sb) {
         if (K < sb) {
-            constexpr int R = kPanel - K;
+            constexpr int hK = K & 1, qK = K >> 1, Q0 = K >> 1, R = kPanel / 2 - Q0;
+            const double own = xh[qK] * Lc[kPanel * kPanel + K];
+            // the exchange runs on the whole wave before the select (inside
+            // a branch on the non-owners it would read lanes that are off)
+            double other = dpp_f64<kDppXor1>(own);
+            asm volatile("" : "+v"(other));
+            const double xk = (h == hK) ? own : other;
+            if (h == hK) xh[qK] = xk;
             double cv[R];
+            const double *col = Lc + kPanel * K + 32 * h;
 #pragma unroll
-            for (int i = 0; i < R; ++i) cv[i] = Lc[kPanel * K + K + i];
+            for (int q = 0; q < R; ++q) cv[q] = col[Q0 + q];
 #pragma unroll
-            for (int i = 0; i < R; ++i) asm volatile("" : "+v"(cv[i]));
-            const double xk = x[K] * cv[0];
-            x[K] = xk;
+            for (int q = 0; q < R; ++q) asm volatile("" : "+v"(cv[q]));
 #pragma unroll
-            for (int i = 1; i < R; ++i) x[K + i] = fma(-xk, cv[i], x[K + i]);
+            for (int q = 0; q < R; ++q)
+                if (2 * (Q0 + q) + h > K) xh[Q0 + q] = fma(-xk, cv[q], xh[Q0 + q]);
         }
-        SolveStep<K + 1>::run(x, Lc, sb);
+        PairSolveStep<K + 1>::run(xh, Lc, h, sb);
     }
 };
 template <>
-struct SolveStep<kPanel> {
-    __device__ static void run(double (&)[kPanel], const double *, int) {}
+struct PairSolveStep<kPanel> {
+    __device__ __forceinline__ static void run(double (&)[kPanel / 2], const double *, int, int) {}
 };
 
 __global__ __launch_bounds__(64) void k_chol_info_clear(int32_t *dinfo) {
@@ -120,16 +138,16 @@ __global__ __launch_bounds__(64) void k_chol_info_clear(int32_t *dinfo) {
 }
 
 // Panel of columns s .. s + sb - 1 (1 <= sb <= 64): the diagonal block
-// (rows s .. s + sb - 1) and the rows s + sb + 64 blockIdx.x + lane.
+// (rows s .. s + sb - 1) and the rows s + sb + 32 blockIdx.x + lane / 2.
 // Both phases read a column of L11 from LDS as broadcasts, all of its
 // loads issued before the first use.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_chol_panel(double *__restrict__ A, int64_t lda, int64_t n, int64_t s, int sb,
                   int32_t *__restrict__ dinfo) {
     if (*(volatile int32_t *)dinfo != 0) return;
-    // Lc[64 k + i] = L(i, k) of the diagonal block for i > k (rows >= sb are
-    // zero) and 1 / L(k, k) at i = k
-    __shared__ double Lc[kPanel * kPanel];
+    // column k of L11 at lc_at(k, i) (rows >= sb zero), 1 / L(k, k) at
+    // 64 * 64 + k
+    __shared__ double Lc[kPanel * kPanel + kPanel];
     const int t = threadIdx.x;
     double *__restrict__ Ad = A + s + s * lda;
 
@@ -153,17 +171,20 @@ void k_chol_panel(double *__restrict__ A, int64_t lda, int64_t n, int64_t s, int
     }
     __syncthreads();
 
-    // Rows below: x L11^T = a by forward substitution, lane = row.
-    const int64_t r = s + sb + (int64_t)blockIdx.x * kPanel + t;
-    if (r >= n) return;
-    double *__restrict__ Ar = A + r + s * lda;
-    double x[kPanel];
+    // Rows below: x L11^T = a by forward substitution, a lane pair per row
+    // (32 rows per workgroup), lane h of the pair on the columns 2 q + h.
+    const int h = t & 1;
+    const int64_t r = s + sb + (int64_t)blockIdx.x * (kPanel / 2) + (t >> 1);
+    const bool rok = r < n;
+    double *__restrict__ Ar = A + (rok ? r : 0) + s * lda;
+    double xh[kPanel / 2];
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j) x[j] = j < sb ? Ar[j * lda] : 0.0;
-    SolveStep<0>::run(x, Lc, sb);
+    for (int q = 0; q < kPanel / 2; ++q) xh[q] = (rok && 2 * q + h < sb) ? Ar[(2 * q + h) * lda] : 0.0;
+    PairSolveStep<0>::run(xh, Lc, h, sb);
+    if (!rok) return;
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j)
-        if (j < sb) Ar[j * lda] = x[j];
+    for (int q = 0; q < kPanel / 2; ++q)
+        if (2 * q + h < sb) Ar[(2 * q + h) * lda] = xh[q];
 }
 
 // C(i, c) -= sum_{k < K} A(i, kc + k) A(c, kc + k) for t0 <= c < cend,
@@ -292,7 +313,7 @@ hipError_t launch_cholesky(int64_t n, double *A, int64_t lda, int32_t *dinfo, hi
         for (int64_t s = j; s < jend; s += kPanel) {
             const int sb = (int)(jend - s < kPanel ? jend - s : kPanel);
             const int64_t below = n - s - sb;
-            const int64_t grid = below > 0 ? (below + kPanel - 1) / kPanel : 1;
+            const int64_t grid = below > 0 ? (below + kPanel / 2 - 1) / (kPanel / 2) : 1;
             {
                 ProfScope ps("chol_panel", st);
                 hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)grid), dim3(kPanel), 0, st, A, lda, n, s, sb, dinfo);

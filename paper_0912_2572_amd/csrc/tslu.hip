@@ -52,10 +52,14 @@ __device__ __forceinline__ void argmax_swap16(double &best, int &bp, double &bv)
     const auto pp = __builtin_amdgcn_permlane16_swap(bp, bp, false, false);
     const auto vl = __builtin_amdgcn_permlane16_swap(__double2loint(bv), __double2loint(bv), false, false);
     const auto vh = __builtin_amdgcn_permlane16_swap(__double2hiint(bv), __double2hiint(bv), false, false);
-    best = __hiloint2double(kh[0], kl[0]);
-    bp = (int)pp[0];
-    bv = __hiloint2double(vh[0], vl[0]);
-    argmax_take(best, bp, bv, __hiloint2double(kh[1], kl[1]), (int)pp[1], __hiloint2double(vh[1], vl[1]));
+    double k0 = __hiloint2double(kh[0], kl[0]), k1 = __hiloint2double(kh[1], kl[1]);
+    double v0 = __hiloint2double(vh[0], vl[0]), v1 = __hiloint2double(vh[1], vl[1]);
+    int p0 = (int)pp[0], p1 = (int)pp[1];
+    asm volatile("" : "+v"(k0), "+v"(k1), "+v"(v0), "+v"(v1), "+v"(p0), "+v"(p1));
+    best = k0;
+    bp = p0;
+    bv = v0;
+    argmax_take(best, bp, bv, k1, p1, v1);
 }
 // The same for lanes l and l ^ 32.
 __device__ __forceinline__ void argmax_swap32(double &best, int &bp, double &bv) {
@@ -64,16 +68,25 @@ __device__ __forceinline__ void argmax_swap32(double &best, int &bp, double &bv)
     const auto pp = __builtin_amdgcn_permlane32_swap(bp, bp, false, false);
     const auto vl = __builtin_amdgcn_permlane32_swap(__double2loint(bv), __double2loint(bv), false, false);
     const auto vh = __builtin_amdgcn_permlane32_swap(__double2hiint(bv), __double2hiint(bv), false, false);
-    best = __hiloint2double(kh[0], kl[0]);
-    bp = (int)pp[0];
-    bv = __hiloint2double(vh[0], vl[0]);
-    argmax_take(best, bp, bv, __hiloint2double(kh[1], kl[1]), (int)pp[1], __hiloint2double(vh[1], vl[1]));
+    double k0 = __hiloint2double(kh[0], kl[0]), k1 = __hiloint2double(kh[1], kl[1]);
+    double v0 = __hiloint2double(vh[0], vl[0]), v1 = __hiloint2double(vh[1], vl[1]);
+    int p0 = (int)pp[0], p1 = (int)pp[1];
+    asm volatile("" : "+v"(k0), "+v"(k1), "+v"(v0), "+v"(v1), "+v"(p0), "+v"(p1));
+    best = k0;
+    bp = p0;
+    bv = v0;
+    argmax_take(best, bp, bv, k1, p1, v1);
 }
 
+// The lane exchanges below run on the whole wave before any comparison:
+// empty asm statements keep the compiler from moving them into the
+// conditional assignments, where they would read lanes that are off.
 template <int CTRL>
 __device__ __forceinline__ void argmax_step(double &best, int &bp, double &bv) {
-    argmax_take(best, bp, bv, dpp_f64<CTRL>(best), __builtin_amdgcn_update_dpp(0, bp, CTRL, 0xf, 0xf, false),
-                dpp_f64<CTRL>(bv));
+    double ob = dpp_f64<CTRL>(best), ov = dpp_f64<CTRL>(bv);
+    int op = __builtin_amdgcn_update_dpp(0, bp, CTRL, 0xf, 0xf, false);
+    asm volatile("" : "+v"(ob), "+v"(op), "+v"(ov));
+    argmax_take(best, bp, bv, ob, op, ov);
 }
 
 // Step J of partial-pivoting elimination on a stack of W waves, one thread
