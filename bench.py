@@ -115,8 +115,8 @@ def main():
                          "(the thin Q and the solve on two streams) instead of one tsqr_factor_solve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU; multi-GPU sharding of TSQR is a design "
-              "(DESIGN.md), not part of this build", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: this library factors on one GPU; sharding the rows "
+              "over several GPUs (one more combine level across them) is not implemented", file=sys.stderr)
         sys.exit(2)
     {"single": run_single, "mixed": run_mixed, "batch": run_batch, "serve": run_serve,
      "sweep": run_sweep, "orth": run_orth, "tslu": run_tslu, "wide": run_wide, "chol": run_chol, "calu": run_calu, "copy": run_copy}[args.workload](args)

@@ -24,7 +24,7 @@
  *     factors (the paper mentions QR as the first step toward least squares
  *     only in its draft text; the solve is the textbook one).
  *
- * Readings where the paper is silent (each is listed in the design doc too):
+ * Readings where the paper is silent:
  *   - reflector convention is LAPACK's: beta = -sgn(alpha) sqrt(alpha^2 +
  *     sigma^2), tau = (beta - alpha) / beta, v = [1; x / (alpha - beta)];
  *     tau = 0 when the subcolumn below alpha is exactly zero;

@@ -1,7 +1,7 @@
 """GPU parity: the HIP library against the FP64 CPU oracle, element by
 element on the same seeded inputs.
 
-Tolerances (stated in the benchmark spec and derived in the design doc):
+Tolerances (the FP64 accuracy targets of the least-squares workloads):
   R:   ||R_gpu - R_oracle||_F / ||R_oracle||_F <= 1e-12 after both are
        sign-normalised (R with diag >= 0 is unique, Sec. 2.2);
   Q:   ||A - Q R||_F / ||A||_F <= 1e-13 and ||Q^T Q - I||_F <= 1e-13;
