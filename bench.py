@@ -25,7 +25,7 @@ Other workloads, one JSON line each:
                     latency at 0.5, 0.8 and 0.95 of it;
   --workload copy   a plain 1 GiB device copy (calibrates HBM counters).
 
---gpus N > 1 is refused: this build runs on one GPU.
+--gpus N > 1 is refused: the library factors on one GPU.
 """
 from __future__ import annotations
 
