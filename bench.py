@@ -23,7 +23,16 @@ Other workloads, one JSON line each:
                     10 % at kappa 1e6, 25 % repeated matrices) through the
                     request server: saturated throughput, then p50/p99
                     latency at 0.5, 0.8 and 0.95 of it;
+  --workload sweep  the single-matrix path at m = 2^20 for n in {8, 16, 32, 64};
+  --workload orth   a block Krylov loop: TSQR-based block orthogonalisation;
+  --workload tslu   LU with tournament pivoting of 1,048,576 x 64 (TSLU);
+  --workload wide   262,144 x 1,024 in 64-column panels (factor + solve);
+  --workload chol   8,192 x 8,192 Cholesky of an SPD Gram matrix, beside
+                    torch.linalg.cholesky;
+  --workload calu   4,096 x 4,096 LU with tournament-pivoted panels (CALU),
+                    beside torch.linalg.lu_factor;
   --workload copy   a plain 1 GiB device copy (calibrates HBM counters).
+The default run also appends compact records of these workloads.
 
 --gpus N > 1 is refused: the library factors on one GPU.
 """
